@@ -84,10 +84,12 @@ double oracle_log(double x)
     double s = f / (2.0 + f);
     double z = s * s;
     /* R = sum_{k=1..10} z^k / (2k+1), Horner from the highest term. */
+    /* Each Horner step and the final product-sum are single fused
+     * multiply-adds (C99 fma, one rounding each). */
     double poly = 1.0 / 21.0;
     for (int k = 9; k >= 1; --k) {
         double ck = 1.0 / (double)(2 * k + 1);
-        poly = ck + z * poly;
+        poly = fma(z, poly, ck);
     }
     double R = z * poly;
     double R2 = R + R;
@@ -95,7 +97,7 @@ double oracle_log(double x)
     const double ln2_hi = 6.93147180369123816490e-01; /* ln 2 with 20 trailing zero bits */
     const double ln2_lo = 1.90821492927058770002e-10; /* ln 2 - ln2_hi */
     double ed = (double)e;
-    return ed * ln2_hi - ((hfsq - (s * (hfsq + R2) + ed * ln2_lo)) - f);
+    return ed * ln2_hi - ((hfsq - fma(s, hfsq + R2, ed * ln2_lo)) - f);
 }
 
 static inline double u53_open0_closed1(uint32_t a, uint32_t b)
