@@ -1,0 +1,208 @@
+/*
+ * smc.h -- C ABI of libsmc: on-the-fly statistical model checking of
+ * mass-action reaction networks on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Ballarini, Forlin, Mazza, Prandi, "Efficient Parallel Statistical
+ * Model Checking of Biochemical Networks" (PDMC 2009):
+ *   - trajectories are drawn with Gillespie's direct method (Sec. 2.2,
+ *     eqs. 1, 2a, 2b and the five-step SSA template);
+ *   - each trajectory is checked against a BLTLc formula (Sec. 3.1) while it
+ *     is generated and stops as soon as the formula is decided (Sec. 3.2);
+ *   - the verdicts are Bernoulli samples; the estimate is their mean with the
+ *     Wilson score interval (eq. 3), and the number of trajectories is chosen
+ *     by the iterative Wilson procedure (eq. 4, Fig. 2) or fixed by the caller.
+ *
+ * Conventions (all entry points):
+ *   - Return value: SMC_OK (0) or a negative SMC_E_* code.  No C++ exception
+ *     crosses this interface.  The message of the last failure on a context
+ *     is returned by smc_last_error().
+ *   - Ownership: the caller owns every array it passes in or out; the library
+ *     copies what it keeps.  The library owns the handles it creates; they are
+ *     released with the matching *_destroy function.
+ *   - Pointers are host pointers unless stated otherwise.
+ *   - One context per host thread.  Work on a context is ordered on its HIP
+ *     stream; every entry point returns after its results are on the host.
+ *   - Randomness is a pure function of (seed, model_id, trajectory index,
+ *     event index) through Philox4x32-10, so results do not depend on the
+ *     launch configuration.
+ */
+#ifndef SMC_H
+#define SMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define SMC_OK 0
+#define SMC_E_INVALID (-1)     /* bad argument, network or parameter          */
+#define SMC_E_PARSE (-2)       /* formula text does not parse                 */
+#define SMC_E_UNSUPPORTED (-3) /* formula outside the GPU monitor classes     */
+#define SMC_E_HIP (-4)         /* HIP runtime error                           */
+#define SMC_E_NOMEM (-5)       /* device or host allocation failed            */
+#define SMC_E_CANCELLED (-6)   /* stopped by smc_cancel()                     */
+#define SMC_E_TIMEOUT (-7)     /* exceeded the context's watchdog time        */
+
+/* verdict_reason byte written per trajectory: verdict | reason << 1 */
+#define SMC_REASON_STATE 0   /* decided by the state just entered             */
+#define SMC_REASON_TIME 1    /* decided when a time bound passed              */
+#define SMC_REASON_ABSORB 2  /* total propensity zero: no further event       */
+#define SMC_REASON_CAP 3     /* undecided after max_events events: FALSE      */
+#define SMC_REASON_TMAX 4    /* undecided past t_max: FALSE (Sec. 3.2 rule)   */
+
+/* smc_params.flags */
+#define SMC_CONSERVATIVE_START 1u /* first sample from eq. 4 at p = 0.5 (Sec. 3.3.2)  */
+#define SMC_PAPER_ROUNDING 2u     /* Fig. 2 rounding exactly as printed: p +- eps may
+                                     step across 0.5 (default: the step stops at 0.5) */
+
+typedef struct smc_ctx smc_ctx;
+typedef struct smc_net smc_net;
+typedef struct smc_formula smc_formula;
+
+/* ---- context ----------------------------------------------------------- */
+/* Create a context on HIP device `hip_device`.  `hip_stream` is a hipStream_t
+ * to order work on (e.g. torch.cuda.current_stream().cuda_stream), or NULL for
+ * a stream owned by the context.  Errors: SMC_E_INVALID (no such device),
+ * SMC_E_HIP. */
+int smc_ctx_create(int hip_device, void *hip_stream, smc_ctx **out);
+void smc_ctx_destroy(smc_ctx *ctx);
+/* Message of the last failure on ctx ("" if none); valid until the next call
+ * on ctx.  With ctx == NULL: the last failure of smc_ctx_create on this
+ * thread. */
+const char *smc_last_error(const smc_ctx *ctx);
+/* Watchdog: a call whose kernels run longer than `seconds` is stopped and
+ * returns SMC_E_TIMEOUT (default 300 s; <= 0 disables). */
+int smc_set_watchdog(smc_ctx *ctx, double seconds);
+/* Launch shape of the SSA kernel: waves per compute unit (1..32, 0 = tuned
+ * default).  Results do not depend on it. */
+int smc_set_waves_per_cu(smc_ctx *ctx, int waves_per_cu);
+/* Ask a running call on ctx (from another thread) to stop: it returns
+ * SMC_E_CANCELLED. */
+void smc_cancel(smc_ctx *ctx);
+/* Number of compute units of the context's device. */
+int smc_device_cus(const smc_ctx *ctx);
+
+/* ---- reaction networks (Sec. 2.2) -------------------------------------- */
+/* Mass-action network with S species and M reaction channels.  Reaction j has
+ * rate constant c_j = rate[j] >= 0, reactants reactants[2j], reactants[2j+1]
+ * (species index or -1; two equal indices form a homodimer), and a net state
+ * change of change_val[4j+q] on species change_idx[4j+q] (q = 0..3, index -1
+ * = unused entry).  Its propensity is c_j times the number of distinct
+ * reactant combinations: 1, x_a, x_a x_b, or x_a (x_a - 1) / 2.
+ * Errors (SMC_E_INVALID): S < 1, M < 1, a negative count or rate, a species
+ * index out of range, or a change that consumes more of a species than the
+ * reaction's reactants hold (counts could go negative).  names (S strings, or
+ * NULL for X0, X1, ...) are the species names used by formulas. */
+typedef struct {
+    int32_t n_species;
+    int32_t n_reactions;
+    const int32_t *x0;         /* [S] initial counts                       */
+    const double *rate;        /* [M] rate constants                       */
+    const int32_t *reactants;  /* [M][2]                                   */
+    const int32_t *change_idx; /* [M][4]                                   */
+    const int32_t *change_val; /* [M][4]                                   */
+    const char *const *names;  /* [S] or NULL                              */
+} smc_net_desc;
+
+int smc_net_create(smc_ctx *ctx, const smc_net_desc *desc, smc_net **out);
+/* Replace the M rate constants (parameter sweeps). */
+int smc_net_set_rates(smc_net *net, const double *rate);
+void smc_net_destroy(smc_net *net);
+
+/* ---- formulas (Sec. 3.1) ----------------------------------------------- */
+/* Compile BLTLc text over the network's species names:
+ *   phi ::= val op val | !phi | phi & phi | phi '|' phi | X I phi | phi U I phi
+ *           | F I phi | G I phi | (phi) | true | false
+ *   val ::= name | number | val (+ - * /) val | -val | sqrt(val) | (val)
+ *   I   ::= [a,b] | <= b | (omitted: [0, inf))      op: < <= >= > = !=
+ * Precedence: unary (!, X, F, G) > U (right associative) > & > |.
+ * GPU monitor classes: top-level boolean combinations of
+ *   state predicates; F I p; G I p; p U I q; X I p; and the nested until
+ *   p U[0,a] (q U[0,b] r), where p, q, r are boolean combinations of
+ *   predicates.  Other nestings give SMC_E_UNSUPPORTED; text that does not
+ *   parse gives SMC_E_PARSE. */
+int smc_formula_compile(smc_ctx *ctx, const smc_net *net, const char *text, smc_formula **out);
+/* Time span of the path the formula can depend on (+inf if unbounded). */
+double smc_formula_horizon(const smc_formula *f);
+void smc_formula_destroy(smc_formula *f);
+
+/* ---- estimation (Sec. 3.3) --------------------------------------------- */
+typedef struct {
+    double confidence;   /* 1 - alpha in (0,1)                                   */
+    double half_width;   /* epsilon > 0: target interval [p - eps, p + eps]      */
+    double z;            /* > 0: use this z_{1-alpha/2}; 0: derive from confidence */
+    uint64_t fixed_n;    /* 0: iterative Wilson (Fig. 2); > 0: exactly this many  */
+    uint64_t seed;       /* Philox counter words 2..3                            */
+    uint32_t model_id;   /* Philox key word 1                                    */
+    uint32_t max_events; /* 0: no cap; else undecided after this many events: FALSE */
+    double t_max;        /* pessimistic horizon for unbounded formulas (+inf: none) */
+    uint32_t flags;      /* SMC_CONSERVATIVE_START | SMC_PAPER_ROUNDING          */
+} smc_params;
+
+typedef struct {
+    double p_hat;          /* successes / n                                      */
+    double lo, hi;         /* Wilson interval (eq. 3) at confidence              */
+    uint64_t n;            /* trajectories used                                  */
+    uint64_t successes;    /* TRUE verdicts among them                           */
+    uint64_t events;       /* SSA events (applied transitions) over them         */
+    uint64_t truncated;    /* trajectories stopped by max_events                 */
+    uint64_t batches;      /* sample-size iterations (1 with fixed_n)            */
+    double z;              /* z_{1-alpha/2} used                                 */
+    double device_seconds; /* kernel time on the device (HIP events)             */
+    int32_t status;        /* SMC_OK or the failure of this job                  */
+} smc_result;
+
+/* One model: estimate P(formula) to the requested interval.  The trajectory
+ * indices used are 0..n-1.  Errors: SMC_E_INVALID (eps <= 0, confidence
+ * outside (0,1), unbounded formula with neither t_max nor max_events, sample
+ * size above 2^32), SMC_E_UNSUPPORTED, SMC_E_HIP, SMC_E_TIMEOUT,
+ * SMC_E_CANCELLED. */
+int smc_estimate(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_params *p,
+                 smc_result *out);
+
+/* Many models in one persistent launch; each stops at its own interval width.
+ * Networks may differ in size.  out[k] receives job k's result; the return
+ * value is the first failure (all jobs are attempted). */
+typedef struct {
+    const smc_net *net;
+    const smc_formula *formula;
+    smc_params params;
+} smc_job;
+int smc_estimate_batch(smc_ctx *ctx, const smc_job *jobs, size_t n_jobs, smc_result *out);
+
+/* Per-trajectory results for indices first .. first+count-1 (the same
+ * trajectories smc_estimate would draw): events[k] = applied transitions,
+ * verdict_reason[k] = verdict | reason << 1.  Either output may be NULL. */
+int smc_trajectories(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_params *p,
+                     uint64_t first, uint64_t count, uint32_t *events, uint8_t *verdict_reason);
+
+/* SSA probe: the state sigma@T of trajectories first .. first+count-1,
+ * counts[k*S + s] (no formula involved). */
+int smc_sample_state(smc_ctx *ctx, const smc_net *net, const smc_params *p, double T,
+                     uint64_t first, uint64_t count, int32_t *counts);
+
+/* ---- Wilson formulas (host, no context) -------------------------------- */
+/* z_{1-alpha/2} for confidence 1 - alpha. */
+double smc_z_value(double confidence);
+/* Eq. 4 before rounding; smc_wilson_sample rounds it up. */
+double smc_wilson_sample_value(double p, double eps, double z);
+uint64_t smc_wilson_sample(double p, double eps, double z);
+/* Eq. 3 for k successes out of n, clipped to [0,1]. */
+void smc_wilson_interval(uint64_t k, uint64_t n, double z, double *lo, double *hi);
+
+/* The device's step of Fig. 2 for many (successes, n) pairs: out[k] =
+ * ceil(eq. 4 at p = successes[k]/n[k] moved by eps towards 0.5), computed by
+ * the same GPU code the persistent kernel uses to pick the next sample size
+ * (flags: SMC_PAPER_ROUNDING).  For checking device and host arithmetic
+ * against each other.  Errors: SMC_E_INVALID (n[k] == 0, eps outside
+ * (0, 0.5)), SMC_E_HIP. */
+int smc_wilson_next_device(smc_ctx *ctx, const uint64_t *successes, const uint64_t *n, size_t count,
+                           double eps, double z, uint32_t flags, uint64_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SMC_H */

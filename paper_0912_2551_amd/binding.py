@@ -1,0 +1,304 @@
+"""Python binding of libsmc (include/smc.h): argument marshalling only.
+
+Every step of the path runs in the HIP library; this module converts numpy
+arrays and Python values into the C structures and back.  If the library is
+not built, or cannot be loaded, calls fail with LibraryMissing: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsmc.so")
+
+SMC_OK = 0
+SMC_E_INVALID = -1
+SMC_E_PARSE = -2
+SMC_E_UNSUPPORTED = -3
+SMC_E_HIP = -4
+SMC_E_NOMEM = -5
+SMC_E_CANCELLED = -6
+SMC_E_TIMEOUT = -7
+SMC_CONSERVATIVE_START = 1
+SMC_PAPER_ROUNDING = 2
+REASON_STATE, REASON_TIME, REASON_ABSORB, REASON_CAP, REASON_TMAX = range(5)
+
+EXPORTS = [
+    "smc_ctx_create", "smc_ctx_destroy", "smc_last_error", "smc_set_watchdog",
+    "smc_set_waves_per_cu", "smc_cancel", "smc_device_cus", "smc_net_create",
+    "smc_net_set_rates", "smc_net_destroy", "smc_formula_compile", "smc_formula_horizon",
+    "smc_formula_destroy", "smc_estimate", "smc_estimate_batch", "smc_trajectories",
+    "smc_sample_state", "smc_z_value", "smc_wilson_sample_value", "smc_wilson_sample",
+    "smc_wilson_interval", "smc_wilson_next_device",
+]
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class SmcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libsmc error {code}: {msg}")
+        self.code = code
+
+
+class NetDesc(ctypes.Structure):
+    _fields_ = [("n_species", ctypes.c_int32), ("n_reactions", ctypes.c_int32),
+                ("x0", ctypes.POINTER(ctypes.c_int32)), ("rate", ctypes.POINTER(ctypes.c_double)),
+                ("reactants", ctypes.POINTER(ctypes.c_int32)),
+                ("change_idx", ctypes.POINTER(ctypes.c_int32)),
+                ("change_val", ctypes.POINTER(ctypes.c_int32)),
+                ("names", ctypes.POINTER(ctypes.c_char_p))]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("confidence", ctypes.c_double), ("half_width", ctypes.c_double),
+                ("z", ctypes.c_double), ("fixed_n", ctypes.c_uint64), ("seed", ctypes.c_uint64),
+                ("model_id", ctypes.c_uint32), ("max_events", ctypes.c_uint32),
+                ("t_max", ctypes.c_double), ("flags", ctypes.c_uint32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("p_hat", ctypes.c_double), ("lo", ctypes.c_double), ("hi", ctypes.c_double),
+                ("n", ctypes.c_uint64), ("successes", ctypes.c_uint64), ("events", ctypes.c_uint64),
+                ("truncated", ctypes.c_uint64), ("batches", ctypes.c_uint64), ("z", ctypes.c_double),
+                ("device_seconds", ctypes.c_double), ("status", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class JobDesc(ctypes.Structure):
+    _fields_ = [("net", ctypes.c_void_p), ("formula", ctypes.c_void_p), ("params", Params)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsmc.so (built by __graft_entry__.build() or build.py)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LibraryMissing(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        try:
+            L = ctypes.CDLL(LIB_PATH)
+        except OSError as e:
+            raise LibraryMissing(f"cannot load {LIB_PATH}: {e}") from e
+        vp, i32, u64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_double
+        sig = {
+            "smc_ctx_create": (i32, [i32, vp, ctypes.POINTER(vp)]),
+            "smc_ctx_destroy": (None, [vp]),
+            "smc_last_error": (ctypes.c_char_p, [vp]),
+            "smc_set_watchdog": (i32, [vp, dbl]),
+            "smc_set_waves_per_cu": (i32, [vp, i32]),
+            "smc_cancel": (None, [vp]),
+            "smc_device_cus": (i32, [vp]),
+            "smc_net_create": (i32, [vp, ctypes.POINTER(NetDesc), ctypes.POINTER(vp)]),
+            "smc_net_set_rates": (i32, [vp, ctypes.POINTER(ctypes.c_double)]),
+            "smc_net_destroy": (None, [vp]),
+            "smc_formula_compile": (i32, [vp, vp, ctypes.c_char_p, ctypes.POINTER(vp)]),
+            "smc_formula_horizon": (dbl, [vp]),
+            "smc_formula_destroy": (None, [vp]),
+            "smc_estimate": (i32, [vp, vp, vp, ctypes.POINTER(Params), ctypes.POINTER(Result)]),
+            "smc_estimate_batch": (i32, [vp, ctypes.POINTER(JobDesc), ctypes.c_size_t, ctypes.POINTER(Result)]),
+            "smc_trajectories": (i32, [vp, vp, vp, ctypes.POINTER(Params), u64, u64,
+                                       ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint8)]),
+            "smc_sample_state": (i32, [vp, vp, ctypes.POINTER(Params), dbl, u64, u64,
+                                       ctypes.POINTER(ctypes.c_int32)]),
+            "smc_z_value": (dbl, [dbl]),
+            "smc_wilson_sample_value": (dbl, [dbl, dbl, dbl]),
+            "smc_wilson_sample": (u64, [dbl, dbl, dbl]),
+            "smc_wilson_interval": (None, [u64, u64, dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]),
+            "smc_wilson_next_device": (i32, [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                                             ctypes.c_size_t, dbl, dbl, ctypes.c_uint32,
+                                             ctypes.POINTER(ctypes.c_uint64)]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def params(confidence=0.95, half_width=0.01, z=0.0, fixed_n=0, seed=1, model_id=0, max_events=0,
+           t_max=math.inf, conservative=False, paper_rounding=False) -> Params:
+    flags = (SMC_CONSERVATIVE_START if conservative else 0) | (SMC_PAPER_ROUNDING if paper_rounding else 0)
+    return Params(confidence, half_width, z, fixed_n, seed, model_id, max_events, t_max, flags)
+
+
+class Context:
+    """A libsmc context on one HIP device; `stream` may be a torch.cuda.Stream
+    (or its integer handle) so that work is ordered with torch's."""
+
+    def __init__(self, device: int = 0, stream=None):
+        L = lib()
+        handle = None
+        if stream is not None:
+            handle = ctypes.c_void_p(getattr(stream, "cuda_stream", stream))
+        out = ctypes.c_void_p()
+        rc = L.smc_ctx_create(device, handle, ctypes.byref(out))
+        if rc != SMC_OK:
+            raise SmcError(rc, L.smc_last_error(None).decode())
+        self.h = out
+        self._keep = []
+
+    def _check(self, rc):
+        if rc != SMC_OK:
+            raise SmcError(rc, lib().smc_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().smc_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_watchdog(self, seconds: float):
+        self._check(lib().smc_set_watchdog(self.h, float(seconds)))
+
+    def set_waves_per_cu(self, w: int):
+        self._check(lib().smc_set_waves_per_cu(self.h, int(w)))
+
+    def cus(self) -> int:
+        return lib().smc_device_cus(self.h)
+
+    def cancel(self):
+        lib().smc_cancel(self.h)
+
+    # -- handles ------------------------------------------------------------
+    def network(self, net) -> "Network":
+        return Network(self, net)
+
+    def formula(self, network: "Network", text: str) -> "Formula":
+        return Formula(self, network, text)
+
+    # -- estimation ---------------------------------------------------------
+    def estimate(self, network: "Network", formula: "Formula", p: Params) -> dict:
+        r = Result()
+        self._check(lib().smc_estimate(self.h, network.h, formula.h, ctypes.byref(p), ctypes.byref(r)))
+        return r.as_dict()
+
+    def estimate_batch(self, jobs) -> list:
+        """jobs: list of (Network, Formula, Params)."""
+        arr = (JobDesc * len(jobs))()
+        for k, (n, f, p) in enumerate(jobs):
+            arr[k].net = n.h
+            arr[k].formula = f.h
+            arr[k].params = p
+        res = (Result * len(jobs))()
+        self._check(lib().smc_estimate_batch(self.h, arr, len(jobs), res))
+        return [r.as_dict() for r in res]
+
+    def trajectories(self, network, formula, p: Params, first: int, count: int):
+        ev = np.zeros(count, dtype=np.uint32)
+        vr = np.zeros(count, dtype=np.uint8)
+        self._check(lib().smc_trajectories(self.h, network.h, formula.h, ctypes.byref(p), first, count,
+                                           _ptr(ev, ctypes.c_uint32), _ptr(vr, ctypes.c_uint8)))
+        return ev, vr & 1, vr >> 1
+
+    def wilson_next_device(self, successes, n, eps: float, z: float, paper_rounding=False):
+        y = np.ascontiguousarray(successes, dtype=np.uint64)
+        nn = np.ascontiguousarray(n, dtype=np.uint64)
+        out = np.zeros(y.shape[0], dtype=np.uint64)
+        self._check(lib().smc_wilson_next_device(
+            self.h, _ptr(y, ctypes.c_uint64), _ptr(nn, ctypes.c_uint64), y.shape[0], eps, z,
+            SMC_PAPER_ROUNDING if paper_rounding else 0, _ptr(out, ctypes.c_uint64)))
+        return out
+
+    def sample_state(self, network, p: Params, T: float, first: int, count: int):
+        out = np.zeros((count, network.S), dtype=np.int32)
+        self._check(lib().smc_sample_state(self.h, network.h, ctypes.byref(p), float(T), first, count,
+                                           _ptr(out, ctypes.c_int32)))
+        return out
+
+
+class Network:
+    def __init__(self, ctx: Context, net):
+        self.ctx = ctx
+        self.S = int(np.asarray(net.x0).shape[0])
+        self.M = int(np.asarray(net.rate).shape[0])
+        x0 = np.ascontiguousarray(net.x0, dtype=np.int32)
+        rate = np.ascontiguousarray(net.rate, dtype=np.float64)
+        reac = np.ascontiguousarray(net.reactants, dtype=np.int32)
+        ci = np.ascontiguousarray(net.chg_idx, dtype=np.int32)
+        cv = np.ascontiguousarray(net.chg_val, dtype=np.int32)
+        names = list(getattr(net, "names", [f"X{k}" for k in range(self.S)]))
+        cnames = (ctypes.c_char_p * self.S)(*[n.encode() for n in names])
+        d = NetDesc(self.S, self.M, _ptr(x0, ctypes.c_int32), _ptr(rate, ctypes.c_double),
+                    _ptr(reac, ctypes.c_int32), _ptr(ci, ctypes.c_int32), _ptr(cv, ctypes.c_int32), cnames)
+        out = ctypes.c_void_p()
+        ctx._check(lib().smc_net_create(ctx.h, ctypes.byref(d), ctypes.byref(out)))
+        self.h = out
+
+    def set_rates(self, rate):
+        r = np.ascontiguousarray(rate, dtype=np.float64)
+        self.ctx._check(lib().smc_net_set_rates(self.h, _ptr(r, ctypes.c_double)))
+
+    def __del__(self):
+        try:
+            if self.h and self.ctx.h:
+                lib().smc_net_destroy(self.h)
+        except Exception:
+            pass
+
+
+class Formula:
+    def __init__(self, ctx: Context, network: Network, text: str):
+        self.ctx = ctx
+        self.text = text
+        out = ctypes.c_void_p()
+        ctx._check(lib().smc_formula_compile(ctx.h, network.h, text.encode(), ctypes.byref(out)))
+        self.h = out
+
+    @property
+    def horizon(self) -> float:
+        return lib().smc_formula_horizon(self.h)
+
+    def __del__(self):
+        try:
+            if self.h and self.ctx.h:
+                lib().smc_formula_destroy(self.h)
+        except Exception:
+            pass
+
+
+# -- Wilson formulas (host functions of the library) ------------------------
+def z_value(confidence: float) -> float:
+    return lib().smc_z_value(confidence)
+
+
+def wilson_sample(p: float, eps: float, z: float) -> int:
+    return int(lib().smc_wilson_sample(p, eps, z))
+
+
+def wilson_sample_value(p: float, eps: float, z: float) -> float:
+    return lib().smc_wilson_sample_value(p, eps, z)
+
+
+def wilson_interval(k: int, n: int, z: float):
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    lib().smc_wilson_interval(k, n, z, ctypes.byref(lo), ctypes.byref(hi))
+    return lo.value, hi.value

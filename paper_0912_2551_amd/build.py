@@ -1,0 +1,73 @@
+"""Build libsmc.so (HIP kernels for gfx950 + host runtime) in-tree with hipcc.
+
+Device code: -O3, -ffp-contract=off (the numeric contract forbids fused
+multiply-adds the source does not spell out), packed-FP32 instructions off.
+Host code: amdclang++ with the same contraction rule (it computes eqs. 3-4).
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import tempfile
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIB = os.path.join(HERE, "libsmc.so")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+ARCH = os.environ.get("SMC_OFFLOAD_ARCH", "gfx950")
+
+DEVICE_SOURCES = ["ssa_kernel.hip"]
+HOST_SOURCES = ["smc_api.cpp", "formula.cpp"]
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+
+
+def build(verbose: bool = False, jobs: int = 4) -> str:
+    hipcc = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
+    clang = os.path.join(ROCM, "bin", "amdclang++")
+    if not os.path.exists(clang):
+        clang = os.path.join(ROCM, "llvm", "bin", "clang++")
+    inc = ["-I", INCLUDE, "-I", CSRC]
+    tmp = tempfile.mkdtemp(prefix="smc_build_")
+    try:
+        procs, objs = [], []
+        for src in DEVICE_SOURCES:
+            obj = os.path.join(tmp, src + ".o")
+            cmd = [hipcc, "-c", "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+                   "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                   "-Wno-unused-command-line-argument", *inc, os.path.join(CSRC, src), "-o", obj]
+            procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+            objs.append(obj)
+        for src in HOST_SOURCES:
+            obj = os.path.join(tmp, src + ".o")
+            cmd = [clang, "-c", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off",
+                   "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROCM, "include"), *inc,
+                   os.path.join(CSRC, src), "-o", obj]
+            procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+            objs.append(obj)
+        failed = []
+        for cmd, p in procs:
+            out, _ = p.communicate()
+            if verbose or p.returncode:
+                print(out.decode(errors="replace"), flush=True)
+            if p.returncode:
+                failed.append(" ".join(cmd))
+        if failed:
+            raise RuntimeError("compilation failed:\n" + "\n".join(failed))
+        out_tmp = LIB + ".tmp%d" % os.getpid()
+        _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", out_tmp], verbose)
+        os.replace(out_tmp, LIB)
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,671 @@
+// formula.cpp -- BLTLc text -> device monitor program (host side).
+//
+// Syntax (Sec. 3.1): predicates val op val over species counts; !, &, |;
+// X^I, U^I; and the derived F^I p = tt U^I p and G^I p = !F^I !p.
+// Precedence: unary > U (right associative) > & > |.
+//
+// The device evaluates a top-level boolean combination of "atoms", each an
+// O(1)-register monitor of one temporal operator applied to state formulas
+// (boolean combinations of predicates):
+//   p                      decided on the initial state
+//   p U[a,b] q, F, G       one status
+//   X[a,b] p               decided at the first event
+//   p U[0,a] (q U[0,b] r)  status + (left operand held so far, latest start)
+// Decided atoms freeze; the combination is evaluated in three-valued logic
+// after every state and every time step, so a trajectory stops at the first
+// prefix that decides the formula (Sec. 3.2).
+#include <hip/hip_runtime.h>
+
+#include <cctype>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "smc_device.h"
+#include "smc_internal.h"
+
+namespace smc {
+
+namespace {
+
+struct Expr {
+    enum Kind { VAR, CONST, ADD, SUB, MUL, DIV, NEG, SQRT, POW } kind;
+    int var = -1;
+    double c = 0.0;
+    std::unique_ptr<Expr> a, b;
+};
+
+struct Node {
+    enum Kind { TT, FF, PRED, NOT, AND, OR, NEXT, UNTIL, FIN, GLOB } kind;
+    std::unique_ptr<Expr> lhs, rhs;
+    int cmp = 0;
+    double lo = 0.0, hi = INFINITY;
+    std::unique_ptr<Node> a, b;
+};
+
+struct Tok {
+    enum Kind { NUM, NAME, OP, END } kind;
+    std::string s;
+};
+
+class Lexer {
+  public:
+    explicit Lexer(const std::string &text)
+    {
+        size_t i = 0;
+        const size_t n = text.size();
+        while (i < n) {
+            const char ch = text[i];
+            if (std::isspace((unsigned char)ch)) {
+                ++i;
+                continue;
+            }
+            if (std::isdigit((unsigned char)ch) || (ch == '.' && i + 1 < n && std::isdigit((unsigned char)text[i + 1]))) {
+                size_t j = i;
+                while (j < n && (std::isdigit((unsigned char)text[j]) || text[j] == '.')) ++j;
+                if (j < n && (text[j] == 'e' || text[j] == 'E')) {
+                    size_t k = j + 1;
+                    if (k < n && (text[k] == '+' || text[k] == '-')) ++k;
+                    if (k < n && std::isdigit((unsigned char)text[k])) {
+                        j = k;
+                        while (j < n && std::isdigit((unsigned char)text[j])) ++j;
+                    }
+                }
+                toks.push_back({Tok::NUM, text.substr(i, j - i)});
+                i = j;
+                continue;
+            }
+            if (std::isalpha((unsigned char)ch) || ch == '_') {
+                size_t j = i;
+                while (j < n && (std::isalnum((unsigned char)text[j]) || text[j] == '_')) ++j;
+                toks.push_back({Tok::NAME, text.substr(i, j - i)});
+                i = j;
+                continue;
+            }
+            static const char *two[] = {"<=", ">=", "!=", "==", "&&", "||"};
+            bool matched = false;
+            for (const char *t : two) {
+                if (text.compare(i, 2, t) == 0) {
+                    std::string s(t);
+                    if (s == "&&") s = "&";
+                    if (s == "||") s = "|";
+                    toks.push_back({Tok::OP, s});
+                    i += 2;
+                    matched = true;
+                    break;
+                }
+            }
+            if (matched) continue;
+            if (std::strchr("+-*/()<>=!&|[],", ch)) {
+                toks.push_back({Tok::OP, std::string(1, ch)});
+                ++i;
+                continue;
+            }
+            throw ParseFailure(std::string("unexpected character '") + ch + "'");
+        }
+        toks.push_back({Tok::END, ""});
+    }
+    std::vector<Tok> toks;
+};
+
+class Parser {
+  public:
+    Parser(const std::string &text, const std::vector<std::string> &names) : lex_(text)
+    {
+        for (size_t k = 0; k < names.size(); ++k) names_[names[k]] = (int)k;
+    }
+
+    std::unique_ptr<Node> parse()
+    {
+        auto n = disj();
+        if (peek().kind != Tok::END) throw ParseFailure("trailing input at '" + peek().s + "'");
+        return n;
+    }
+
+  private:
+    const Tok &peek(size_t k = 0) const
+    {
+        const size_t j = pos_ + k;
+        return j < lex_.toks.size() ? lex_.toks[j] : lex_.toks.back();
+    }
+    bool is_op(const char *s, size_t k = 0) const { return peek(k).kind == Tok::OP && peek(k).s == s; }
+    Tok take() { return lex_.toks[pos_ < lex_.toks.size() - 1 ? pos_++ : pos_]; }
+    void expect(const char *s)
+    {
+        if (!is_op(s)) throw ParseFailure(std::string("expected '") + s + "' near '" + peek().s + "'");
+        ++pos_;
+    }
+
+    std::unique_ptr<Node> mk(Node::Kind k)
+    {
+        auto n = std::make_unique<Node>();
+        n->kind = k;
+        return n;
+    }
+
+    std::unique_ptr<Node> disj()
+    {
+        auto l = conj();
+        while (is_op("|")) {
+            ++pos_;
+            auto n = mk(Node::OR);
+            n->a = std::move(l);
+            n->b = conj();
+            l = std::move(n);
+        }
+        return l;
+    }
+    std::unique_ptr<Node> conj()
+    {
+        auto l = until();
+        while (is_op("&")) {
+            ++pos_;
+            auto n = mk(Node::AND);
+            n->a = std::move(l);
+            n->b = until();
+            l = std::move(n);
+        }
+        return l;
+    }
+    std::unique_ptr<Node> until()
+    {
+        auto l = unary();
+        if (peek().kind == Tok::NAME && peek().s == "U") {
+            ++pos_;
+            auto n = mk(Node::UNTIL);
+            interval(n->lo, n->hi);
+            n->a = std::move(l);
+            n->b = until();
+            return n;
+        }
+        return l;
+    }
+    double number()
+    {
+        const Tok t = take();
+        if (t.kind == Tok::NAME && (t.s == "inf" || t.s == "Inf" || t.s == "INF")) return INFINITY;
+        if (t.kind != Tok::NUM) throw ParseFailure("expected a number near '" + t.s + "'");
+        return std::strtod(t.s.c_str(), nullptr);
+    }
+    void interval(double &lo, double &hi)
+    {
+        if (is_op("[")) {
+            ++pos_;
+            lo = number();
+            expect(",");
+            hi = number();
+            expect("]");
+        } else if (is_op("<=")) {
+            ++pos_;
+            lo = 0.0;
+            hi = number();
+        } else {
+            lo = 0.0;
+            hi = INFINITY;
+        }
+        if (!(lo >= 0.0 && lo <= hi)) throw ParseFailure("bad time interval");
+    }
+    std::unique_ptr<Node> unary()
+    {
+        const Tok &t = peek();
+        if (t.kind == Tok::OP && t.s == "!") {
+            ++pos_;
+            auto n = mk(Node::NOT);
+            n->a = unary();
+            return n;
+        }
+        if (t.kind == Tok::NAME && (t.s == "F" || t.s == "G" || t.s == "X") &&
+            (names_.count(t.s) == 0 || is_op("[", 1))) {
+            const std::string op = t.s;
+            ++pos_;
+            auto n = mk(op == "F" ? Node::FIN : op == "G" ? Node::GLOB : Node::NEXT);
+            interval(n->lo, n->hi);
+            n->a = unary();
+            return n;
+        }
+        if (t.kind == Tok::NAME && (t.s == "true" || t.s == "tt")) {
+            ++pos_;
+            return mk(Node::TT);
+        }
+        if (t.kind == Tok::NAME && (t.s == "false" || t.s == "ff")) {
+            ++pos_;
+            return mk(Node::FF);
+        }
+        if (is_op("(")) {
+            const size_t save = pos_;
+            try {
+                return predicate();
+            } catch (const ParseFailure &) {
+                pos_ = save;
+            }
+            ++pos_;
+            auto inner = disj();
+            expect(")");
+            return inner;
+        }
+        return predicate();
+    }
+    std::unique_ptr<Node> predicate()
+    {
+        auto n = mk(Node::PRED);
+        n->lhs = sum();
+        const Tok t = take();
+        static const char *ops[] = {"<", "<=", ">=", ">", "=", "!="};
+        int cmp = -1;
+        for (int k = 0; k < 6; ++k)
+            if (t.kind == Tok::OP && t.s == ops[k]) cmp = k;
+        if (t.kind == Tok::OP && t.s == "==") cmp = CMP_EQ;
+        if (cmp < 0) throw ParseFailure("expected a comparison near '" + t.s + "'");
+        n->cmp = cmp;
+        n->rhs = sum();
+        return n;
+    }
+    std::unique_ptr<Expr> ebin(Expr::Kind k, std::unique_ptr<Expr> a, std::unique_ptr<Expr> b)
+    {
+        auto e = std::make_unique<Expr>();
+        e->kind = k;
+        e->a = std::move(a);
+        e->b = std::move(b);
+        return e;
+    }
+    std::unique_ptr<Expr> sum()
+    {
+        auto l = product();
+        while (is_op("+") || is_op("-")) {
+            const bool add = is_op("+");
+            ++pos_;
+            l = ebin(add ? Expr::ADD : Expr::SUB, std::move(l), product());
+        }
+        return l;
+    }
+    std::unique_ptr<Expr> product()
+    {
+        auto l = atom();
+        while (is_op("*") || is_op("/")) {
+            const bool mul = is_op("*");
+            ++pos_;
+            l = ebin(mul ? Expr::MUL : Expr::DIV, std::move(l), atom());
+        }
+        return l;
+    }
+    std::unique_ptr<Expr> atom()
+    {
+        const Tok t = take();
+        auto e = std::make_unique<Expr>();
+        if (t.kind == Tok::NUM) {
+            e->kind = Expr::CONST;
+            e->c = std::strtod(t.s.c_str(), nullptr);
+            return e;
+        }
+        if (t.kind == Tok::OP && t.s == "-") {
+            e->kind = Expr::NEG;
+            e->a = atom();
+            return e;
+        }
+        if (t.kind == Tok::OP && t.s == "(") {
+            auto inner = sum();
+            expect(")");
+            return inner;
+        }
+        if (t.kind == Tok::NAME) {
+            std::string low = t.s;
+            for (auto &ch : low) ch = (char)std::tolower((unsigned char)ch);
+            if ((low == "sqrt" || low == "pow") && is_op("(")) {
+                ++pos_;
+                e->kind = low == "sqrt" ? Expr::SQRT : Expr::POW;
+                e->a = sum();
+                if (e->kind == Expr::POW) {
+                    expect(",");
+                    e->b = sum();
+                }
+                expect(")");
+                return e;
+            }
+            auto it = names_.find(t.s);
+            if (it == names_.end()) throw ParseFailure("unknown species '" + t.s + "'");
+            e->kind = Expr::VAR;
+            e->var = it->second;
+            return e;
+        }
+        throw ParseFailure("unexpected '" + t.s + "'");
+    }
+
+    Lexer lex_;
+    size_t pos_ = 0;
+    std::map<std::string, int> names_;
+};
+
+// ---------------------------------------------------------------------------
+// Compilation to the device program.
+// ---------------------------------------------------------------------------
+bool is_state_formula(const Node *n)
+{
+    switch (n->kind) {
+    case Node::TT:
+    case Node::FF:
+    case Node::PRED: return true;
+    case Node::NOT: return is_state_formula(n->a.get());
+    case Node::AND:
+    case Node::OR: return is_state_formula(n->a.get()) && is_state_formula(n->b.get());
+    default: return false;
+    }
+}
+
+double horizon_of(const Node *n)
+{
+    switch (n->kind) {
+    case Node::TT:
+    case Node::FF:
+    case Node::PRED: return 0.0;
+    case Node::NOT: return horizon_of(n->a.get());
+    case Node::AND:
+    case Node::OR: return std::fmax(horizon_of(n->a.get()), horizon_of(n->b.get()));
+    case Node::NEXT:
+    case Node::FIN:
+    case Node::GLOB: return n->hi + horizon_of(n->a.get());
+    default: return n->hi + std::fmax(horizon_of(n->a.get()), horizon_of(n->b.get()));
+    }
+}
+
+// Exact linear form sum w_s x_s + c with integer coefficients, if any.
+bool linear_form(const Expr *e, std::map<int, double> &w, double &c, double scale)
+{
+    switch (e->kind) {
+    case Expr::VAR: w[e->var] += scale; return true;
+    case Expr::CONST: c += scale * e->c; return true;
+    case Expr::NEG: return linear_form(e->a.get(), w, c, -scale);
+    case Expr::ADD: return linear_form(e->a.get(), w, c, scale) && linear_form(e->b.get(), w, c, scale);
+    case Expr::SUB: return linear_form(e->a.get(), w, c, scale) && linear_form(e->b.get(), w, c, -scale);
+    case Expr::MUL:
+        if (e->a->kind == Expr::CONST) return linear_form(e->b.get(), w, c, scale * e->a->c);
+        if (e->b->kind == Expr::CONST) return linear_form(e->a.get(), w, c, scale * e->b->c);
+        return false;
+    default: return false;
+    }
+}
+
+bool is_small_int(double v, double lim) { return std::fabs(v) <= lim && std::floor(v) == v; }
+
+// Does every evaluation of this expression stay an integer exactly
+// representable in a double?  (Then any evaluation order gives the same value.)
+bool integer_exact(const Expr *e)
+{
+    switch (e->kind) {
+    case Expr::VAR: return true;
+    case Expr::CONST: return is_small_int(e->c, 1048576.0);
+    case Expr::NEG: return integer_exact(e->a.get());
+    case Expr::ADD:
+    case Expr::SUB: return integer_exact(e->a.get()) && integer_exact(e->b.get());
+    case Expr::MUL:
+        return (e->a->kind == Expr::CONST && is_small_int(e->a->c, 1048576.0) && integer_exact(e->b.get())) ||
+               (e->b->kind == Expr::CONST && is_small_int(e->b->c, 1048576.0) && integer_exact(e->a.get()));
+    default: return false;
+    }
+}
+
+class Compiler {
+  public:
+    explicit Compiler(MonProg &p) : p_(p) { std::memset(&p_, 0, sizeof(MonProg)); }
+
+    void compile(const Node *root)
+    {
+        top(root);
+        p_.horizon = horizon_of(root);
+    }
+
+  private:
+    void emit_top(int op, int arg)
+    {
+        if (p_.n_top >= kMaxTopOps) throw Unsupported("formula has too many boolean operators");
+        p_.top_op[p_.n_top] = op;
+        p_.top_arg[p_.n_top] = arg;
+        ++p_.n_top;
+    }
+
+    int new_atom()
+    {
+        if (p_.n_atoms >= kMaxAtoms) throw Unsupported("formula has more than 8 temporal operators");
+        Atom &a = p_.atoms[p_.n_atoms];
+        a.p1 = a.p2 = a.p3 = -1;
+        a.slot = -1;
+        return p_.n_atoms++;
+    }
+
+    void top(const Node *n)
+    {
+        if (is_state_formula(n)) {
+            const int a = new_atom();
+            p_.atoms[a].kind = AK_PROP;
+            p_.atoms[a].p1 = prop(n, false);
+            emit_top(TO_ATOM, a);
+            return;
+        }
+        switch (n->kind) {
+        case Node::NOT:
+            top(n->a.get());
+            emit_top(TO_NOT, 0);
+            return;
+        case Node::AND:
+        case Node::OR:
+            top(n->a.get());
+            top(n->b.get());
+            emit_top(n->kind == Node::AND ? TO_AND : TO_OR, 0);
+            return;
+        case Node::FIN:
+        case Node::GLOB: {
+            if (!is_state_formula(n->a.get()))
+                throw Unsupported("F/G over a temporal formula is outside the GPU monitor classes");
+            const int a = new_atom();
+            Atom &A = p_.atoms[a];
+            A.kind = AK_UNTIL;
+            A.neg = n->kind == Node::GLOB;
+            A.lo = n->lo;
+            A.hi = n->hi;
+            A.p1 = prop_true();
+            A.p2 = prop(n->a.get(), n->kind == Node::GLOB);
+            emit_top(TO_ATOM, a);
+            return;
+        }
+        case Node::NEXT: {
+            if (!is_state_formula(n->a.get()))
+                throw Unsupported("X over a temporal formula is outside the GPU monitor classes");
+            const int a = new_atom();
+            Atom &A = p_.atoms[a];
+            A.kind = AK_NEXT;
+            A.lo = n->lo;
+            A.hi = n->hi;
+            A.p1 = prop(n->a.get(), false);
+            emit_top(TO_ATOM, a);
+            return;
+        }
+        case Node::UNTIL: {
+            const Node *l = n->a.get(), *r = n->b.get();
+            if (!is_state_formula(l))
+                throw Unsupported("the left operand of U must be a state formula on the GPU");
+            if (is_state_formula(r)) {
+                const int a = new_atom();
+                Atom &A = p_.atoms[a];
+                A.kind = AK_UNTIL;
+                A.lo = n->lo;
+                A.hi = n->hi;
+                A.p1 = prop(l, false);
+                A.p2 = prop(r, false);
+                emit_top(TO_ATOM, a);
+                return;
+            }
+            // p U[0,a] (q U[0,b] r)  or  p U[0,a] F[0,b] r
+            const bool inner_until = r->kind == Node::UNTIL && is_state_formula(r->a.get()) &&
+                                     is_state_formula(r->b.get());
+            const bool inner_fin = r->kind == Node::FIN && is_state_formula(r->a.get());
+            if (!(inner_until || inner_fin) || n->lo != 0.0 || r->lo != 0.0)
+                throw Unsupported("nested until needs the form p U[0,a] (q U[0,b] r)");
+            int slot = 0;
+            for (int k = 0; k < p_.n_atoms; ++k)
+                if (p_.atoms[k].kind == AK_NESTED) ++slot;
+            if (slot >= kMaxNested) throw Unsupported("more than two nested untils");
+            const int a = new_atom();
+            Atom &A = p_.atoms[a];
+            A.kind = AK_NESTED;
+            A.slot = slot;
+            A.lo = 0.0;
+            A.hi = n->hi;
+            A.hi2 = r->hi;
+            A.p1 = prop(l, false);
+            if (inner_until) {
+                A.p2 = prop(r->a.get(), false);
+                A.p3 = prop(r->b.get(), false);
+            } else {
+                A.p2 = prop_true();
+                A.p3 = prop(r->a.get(), false);
+            }
+            emit_top(TO_ATOM, a);
+            return;
+        }
+        default: throw Unsupported("formula outside the GPU monitor classes");
+        }
+    }
+
+    void emit_prop(int op, int arg)
+    {
+        if (n_pops_ >= kMaxPropOps) throw Unsupported("state formulas too long");
+        p_.pop[n_pops_] = op;
+        p_.parg[n_pops_] = arg;
+        ++n_pops_;
+    }
+
+    int finish_prop(int off)
+    {
+        if (p_.n_props >= 3 * kMaxAtoms) throw Unsupported("too many state formulas");
+        const int id = p_.n_props++;
+        p_.prop_off[id] = off;
+        p_.prop_len[id] = n_pops_ - off;
+        return id;
+    }
+
+    int prop_true()
+    {
+        const int off = n_pops_;
+        emit_prop(PO_TRUE, 0);
+        return finish_prop(off);
+    }
+
+    int prop(const Node *n, bool negate)
+    {
+        const int off = n_pops_;
+        prop_body(n);
+        if (negate) emit_prop(PO_NOT, 0);
+        return finish_prop(off);
+    }
+
+    void prop_body(const Node *n)
+    {
+        switch (n->kind) {
+        case Node::TT: emit_prop(PO_TRUE, 0); return;
+        case Node::FF: emit_prop(PO_FALSE, 0); return;
+        case Node::PRED: emit_prop(PO_PRED, predicate(n)); return;
+        case Node::NOT:
+            prop_body(n->a.get());
+            emit_prop(PO_NOT, 0);
+            return;
+        default:
+            prop_body(n->a.get());
+            prop_body(n->b.get());
+            emit_prop(n->kind == Node::AND ? PO_AND : PO_OR, 0);
+            return;
+        }
+    }
+
+    int predicate(const Node *n)
+    {
+        if (p_.n_preds >= kMaxPreds) throw Unsupported("more than 16 predicates");
+        const int id = p_.n_preds++;
+        Pred &P = p_.preds[id];
+        P.op = n->cmp;
+        std::map<int, double> w;
+        double c = 0.0;
+        const bool lin = integer_exact(n->lhs.get()) && integer_exact(n->rhs.get()) &&
+                         linear_form(n->lhs.get(), w, c, 1.0) && linear_form(n->rhs.get(), w, c, -1.0);
+        std::vector<std::pair<int, double>> terms;
+        for (auto &kv : w)
+            if (kv.second != 0.0) terms.push_back(kv);
+        bool ok = lin && terms.size() <= 4 && is_small_int(c, 1125899906842624.0);
+        for (auto &tm : terms) ok = ok && is_small_int(tm.second, 1048576.0);
+        if (ok) {
+            P.linear = 1;
+            P.nterm = (int)terms.size();
+            for (int k = 0; k < P.nterm; ++k) {
+                P.var[k] = terms[k].first;
+                P.w[k] = (int64_t)terms[k].second;
+            }
+            P.c = (int64_t)c;
+            return id;
+        }
+        P.linear = 0;
+        P.lhs_off = n_vops_;
+        int depth = 0, maxd = 0;
+        val(n->lhs.get(), depth, maxd);
+        P.lhs_len = n_vops_ - P.lhs_off;
+        P.rhs_off = n_vops_;
+        depth = 0;
+        val(n->rhs.get(), depth, maxd);
+        P.rhs_len = n_vops_ - P.rhs_off;
+        if (maxd > kValStack) throw Unsupported("arithmetic predicate too deep for the GPU");
+        return id;
+    }
+
+    void emit_val(int op, int var, double c, int &depth, int &maxd, int delta)
+    {
+        if (n_vops_ >= kMaxValOps) throw Unsupported("arithmetic predicates too long");
+        p_.vop[n_vops_] = op;
+        p_.vvar[n_vops_] = var;
+        p_.vconst[n_vops_] = c;
+        ++n_vops_;
+        depth += delta;
+        if (depth > maxd) maxd = depth;
+    }
+
+    void val(const Expr *e, int &depth, int &maxd)
+    {
+        switch (e->kind) {
+        case Expr::VAR: emit_val(VO_VAR, e->var, 0.0, depth, maxd, +1); return;
+        case Expr::CONST: emit_val(VO_CONST, 0, e->c, depth, maxd, +1); return;
+        case Expr::NEG:
+            val(e->a.get(), depth, maxd);
+            emit_val(VO_NEG, 0, 0.0, depth, maxd, 0);
+            return;
+        case Expr::SQRT:
+            val(e->a.get(), depth, maxd);
+            emit_val(VO_SQRT, 0, 0.0, depth, maxd, 0);
+            return;
+        case Expr::POW: throw Unsupported("pow() has no bit-reproducible GPU form");
+        default: {
+            val(e->a.get(), depth, maxd);
+            val(e->b.get(), depth, maxd);
+            const int op = e->kind == Expr::ADD ? VO_ADD : e->kind == Expr::SUB ? VO_SUB
+                           : e->kind == Expr::MUL ? VO_MUL : VO_DIV;
+            emit_val(op, 0, 0.0, depth, maxd, -1);
+            return;
+        }
+        }
+    }
+
+    MonProg &p_;
+    int n_pops_ = 0;
+    int n_vops_ = 0;
+};
+
+}  // namespace
+
+void compile_formula(const std::string &text, const std::vector<std::string> &names, MonProg &out)
+{
+    Parser ps(text, names);
+    auto root = ps.parse();
+    Compiler cc(out);
+    cc.compile(root.get());
+}
+
+}  // namespace smc

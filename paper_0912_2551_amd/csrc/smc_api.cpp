@@ -1,0 +1,694 @@
+// smc_api.cpp -- the C ABI declared in include/smc.h (host runtime).
+//
+// Validates inputs, keeps network tables and compiled formulas in device
+// memory, sets up one Job per model, launches the persistent SSA kernel, waits
+// on it under a watchdog, and turns the per-job counts into estimates with
+// the Wilson interval (eq. 3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "smc.h"
+#include "smc_device.h"
+#include "smc_internal.h"
+
+using namespace smc;
+
+struct smc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    int n_cu = 256;
+    int waves_per_cu = 0;
+    double watchdog = 300.0;
+    int32_t *cancel_host = nullptr;   // pinned, read by kernels
+    int32_t *cancel_dev = nullptr;
+    std::atomic<int> cancel_req{0};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // grow-only workspace
+    Job *d_jobs = nullptr;
+    size_t cap_jobs = 0;
+    JobState *d_states = nullptr;
+    size_t cap_states = 0;
+    JobResult *d_results = nullptr;
+    size_t cap_results = 0;
+    Control *d_ctl = nullptr;
+    char *d_rec = nullptr;
+    size_t cap_rec = 0;
+};
+
+struct smc_net {
+    smc_ctx *ctx = nullptr;
+    int S = 0, M = 0;
+    std::vector<int32_t> x0;
+    std::vector<double> rate;
+    std::vector<int2> reac;
+    std::vector<int4> chg;
+    std::vector<std::string> names;
+    int32_t *d_x0 = nullptr;
+    double *d_rate = nullptr;
+    int2 *d_reac = nullptr;
+    int4 *d_chg = nullptr;
+};
+
+struct smc_formula {
+    smc_ctx *ctx = nullptr;
+    MonProg prog;
+    MonProg *d_prog = nullptr;
+    double horizon = 0.0;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+int fail(smc_ctx *ctx, int code, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+int hip_fail(smc_ctx *ctx, hipError_t e, const char *what)
+{
+    return fail(ctx, e == hipErrorOutOfMemory ? SMC_E_NOMEM : SMC_E_HIP,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, call)                                   \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+    } while (0)
+
+template <typename T>
+int ensure(smc_ctx *ctx, T *&ptr, size_t &cap, size_t n)
+{
+    if (n <= cap) return SMC_OK;
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+    const size_t want = std::max(n, cap * 2);
+    HIP_TRY(ctx, hipMalloc((void **)&ptr, want * sizeof(T)));
+    cap = want;
+    return SMC_OK;
+}
+
+// Eq. 4 before rounding, in the contract's operation order.
+double wilson_value(double p, double eps, double z)
+{
+    const double pq = p * (1.0 - p);
+    const double e2 = eps * eps;
+    const double d = p - 0.5;
+    const double rad = pq * pq + (4.0 * e2) * (d * d);
+    const double num = (pq - 2.0 * e2) + std::sqrt(rad);
+    return (z * z) * num / (2.0 * e2);
+}
+
+double resolve_z(const smc_params &p) { return p.z > 0.0 ? p.z : smc_z_value(p.confidence); }
+
+struct Prepared {
+    Job job;
+    int S = 0, M = 0;
+    uint64_t capacity = 0;
+    double z = 0.0;
+};
+
+int prepare(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_params *p,
+            uint64_t first, Prepared &out)
+{
+    if (!net || !f || !p) return fail(ctx, SMC_E_INVALID, "null network, formula or parameters");
+    if (net->ctx != ctx || f->ctx != ctx) return fail(ctx, SMC_E_INVALID, "handle from another context");
+    if (std::isnan(p->t_max) || p->t_max < 0.0) return fail(ctx, SMC_E_INVALID, "t_max must be >= 0");
+    if (std::isinf(f->horizon) && std::isinf(p->t_max) && p->max_events == 0)
+        return fail(ctx, SMC_E_INVALID, "an unbounded formula needs t_max or max_events");
+    const bool iterative = p->fixed_n == 0;
+    double z = 0.0;
+    if (iterative || p->z > 0.0 || (p->confidence > 0.0 && p->confidence < 1.0)) {
+        if (p->z <= 0.0 && !(p->confidence > 0.0 && p->confidence < 1.0))
+            return fail(ctx, SMC_E_INVALID, "confidence must lie in (0, 1)");
+        z = resolve_z(*p);
+    }
+    uint64_t n_first, capacity;
+    if (iterative) {
+        if (!(p->half_width > 0.0 && p->half_width < 0.5))
+            return fail(ctx, SMC_E_INVALID, "half_width must lie in (0, 0.5)");
+        const double start = (p->flags & SMC_CONSERVATIVE_START) ? 0.5 : 1.0;
+        n_first = (uint64_t)std::ceil(wilson_value(start, p->half_width, z));
+        capacity = (uint64_t)std::ceil(wilson_value(0.5, p->half_width, z));
+        if (n_first < 1) n_first = 1;
+        if (capacity < n_first) capacity = n_first;
+    } else {
+        n_first = p->fixed_n;
+        capacity = p->fixed_n;
+    }
+    if (first + capacity > (1ull << 32))
+        return fail(ctx, SMC_E_INVALID, "trajectory indices must stay below 2^32");
+    Job &J = out.job;
+    std::memset(&J, 0, sizeof(J));
+    J.net.S = net->S;
+    J.net.M = net->M;
+    J.net.x0 = net->d_x0;
+    J.net.rate = net->d_rate;
+    J.net.reac = net->d_reac;
+    J.net.chg = net->d_chg;
+    J.mon = f->d_prog;
+    J.seed = p->seed;
+    J.first = first;
+    J.capacity = capacity;
+    J.n_first = n_first;
+    J.model_id = p->model_id;
+    J.max_events = p->max_events;
+    J.t_max = p->t_max;
+    J.iterative = iterative ? 1 : 0;
+    J.literal = (p->flags & SMC_PAPER_ROUNDING) ? 1 : 0;
+    J.eps = p->half_width;
+    J.z = z;
+    out.S = net->S;
+    out.M = net->M;
+    out.capacity = capacity;
+    out.z = z;
+    return SMC_OK;
+}
+
+int pick_waves_per_cu(const smc_ctx *ctx)
+{
+    if (ctx->waves_per_cu > 0) return ctx->waves_per_cu;
+    return 16;
+}
+
+// Run prepared jobs to completion.  rec_base (optional) is a device buffer
+// laid out as [events u32 ...][verdict bytes ...] for job 0.
+int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res, double *seconds)
+{
+    const int n = (int)P.size();
+    if (ensure(ctx, ctx->d_jobs, ctx->cap_jobs, (size_t)n)) return SMC_E_NOMEM;
+    if (ensure(ctx, ctx->d_states, ctx->cap_states, (size_t)n)) return SMC_E_NOMEM;
+    if (ensure(ctx, ctx->d_results, ctx->cap_results, (size_t)n)) return SMC_E_NOMEM;
+    int s_max = 1, m_max = 1, n_iter = 0;
+    std::vector<Job> jobs(n);
+    for (int k = 0; k < n; ++k) {
+        jobs[k] = P[k].job;
+        jobs[k].st = ctx->d_states + k;
+        s_max = std::max(s_max, P[k].S);
+        m_max = std::max(m_max, P[k].M);
+        n_iter += jobs[k].iterative;
+    }
+    hipStream_t s = ctx->stream;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_jobs, jobs.data(), n * sizeof(Job), hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipMemsetAsync(ctx->d_states, 0, n * sizeof(JobState), s));
+    HIP_TRY(ctx, launch_init(s, ctx->d_jobs, n));
+    *ctx->cancel_host = 0;
+    ctx->cancel_req.store(0);
+
+    const size_t lds_wave = (size_t)s_max * kWave * sizeof(int32_t);
+    int wpb = (int)std::min<size_t>(4, std::max<size_t>(1, 65536 / lds_wave));
+    if (lds_wave > 65536) return fail(ctx, SMC_E_INVALID, "network too large for one wave's LDS");
+    const int wpc = pick_waves_per_cu(ctx);
+    const int grid = std::max(1, (ctx->n_cu * wpc + wpb - 1) / wpb);
+    const int nb_variant = m_max <= 4 ? 4 : kBlocks;
+    res.assign(n, JobResult{});
+    double total_ms = 0.0;
+    const auto t_start = std::chrono::steady_clock::now();
+    unsigned long long last_progress = ~0ull;
+    int stalls = 0;
+    for (int launch = 0; launch < 1000; ++launch) {
+        Control c{};
+        int open = 0;
+        if (launch == 0) open = n_iter;
+        else
+            for (int k = 0; k < n; ++k) open += (jobs[k].iterative && !res[k].final_flag);
+        c.open_jobs = open;
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->d_ctl, &c, sizeof(c), hipMemcpyHostToDevice, s));
+        HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
+        HIP_TRY(ctx, launch_persistent(nb_variant, grid, wpb, lds_wave * wpb, s, ctx->d_jobs, n, s_max,
+                                       ctx->d_ctl, ctx->cancel_dev, 1 << 18));
+        HIP_TRY(ctx, launch_finalize(s, ctx->d_jobs, n, ctx->d_results));
+        HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
+        // wait under the watchdog
+        for (;;) {
+            const hipError_t q = hipEventQuery(ctx->ev1);
+            if (q == hipSuccess) break;
+            if (q != hipErrorNotReady) return hip_fail(ctx, q, "kernel");
+            const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+            if ((ctx->watchdog > 0.0 && el > ctx->watchdog) || ctx->cancel_req.load())
+                __atomic_store_n(ctx->cancel_host, 1, __ATOMIC_SEQ_CST);
+            std::this_thread::yield();
+        }
+        float ms = 0.0f;
+        HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        total_ms += ms;
+        HIP_TRY(ctx, hipMemcpyAsync(res.data(), ctx->d_results, n * sizeof(JobResult), hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        if (*ctx->cancel_host) {
+            *seconds = total_ms * 1e-3;
+            return ctx->cancel_req.load() ? fail(ctx, SMC_E_CANCELLED, "cancelled")
+                                          : fail(ctx, SMC_E_TIMEOUT, "watchdog time exceeded");
+        }
+        bool all = true;
+        unsigned long long progress = 0;
+        for (int k = 0; k < n; ++k) {
+            all = all && res[k].final_flag;
+            progress += res[k].issued + (unsigned long long)res[k].final_flag;
+        }
+        if (all) break;
+        // Waves leave when they find no work for a while; a job still open
+        // then needs another launch.  Launches that issue no trajectory and
+        // finish no job would repeat forever: report that.
+        if (progress == last_progress) {
+            if (++stalls > 2) return fail(ctx, SMC_E_HIP, "stopping rule made no progress");
+        } else {
+            stalls = 0;
+        }
+        last_progress = progress;
+    }
+    *seconds = total_ms * 1e-3;
+    for (int k = 0; k < n; ++k)
+        if (!res[k].final_flag) return fail(ctx, SMC_E_HIP, "job did not finish");
+    return SMC_OK;
+}
+
+void fill_result(const JobResult &r, double z, smc_result *out)
+{
+    out->n = r.n;
+    out->successes = r.yes;
+    out->events = r.events;
+    out->truncated = r.trunc;
+    out->batches = (uint64_t)r.batches;
+    out->p_hat = r.n ? (double)r.yes / (double)r.n : 0.0;
+    out->z = z;
+    if (z > 0.0) smc_wilson_interval(r.yes, r.n, z, &out->lo, &out->hi);
+    else {
+        out->lo = 0.0;
+        out->hi = 1.0;
+    }
+    out->status = r.overflow ? SMC_E_INVALID : SMC_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int smc_ctx_create(int hip_device, void *hip_stream, smc_ctx **out)
+{
+    if (!out) return fail(nullptr, SMC_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0) return fail(nullptr, SMC_E_HIP, "no HIP device");
+    if (hip_device < 0 || hip_device >= count) return fail(nullptr, SMC_E_INVALID, "no such device");
+    if ((e = hipSetDevice(hip_device)) != hipSuccess) return fail(nullptr, SMC_E_HIP, hipGetErrorString(e));
+    smc_ctx *c = new smc_ctx();
+    c->device = hip_device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+    if (hip_stream) c->stream = (hipStream_t)hip_stream;
+    else {
+        if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) {
+            delete c;
+            return fail(nullptr, SMC_E_HIP, hipGetErrorString(e));
+        }
+        c->own_stream = true;
+    }
+    if ((e = hipHostMalloc((void **)&c->cancel_host, sizeof(int32_t), hipHostMallocMapped)) != hipSuccess ||
+        (e = hipHostGetDevicePointer((void **)&c->cancel_dev, c->cancel_host, 0)) != hipSuccess ||
+        (e = hipMalloc((void **)&c->d_ctl, sizeof(Control))) != hipSuccess ||
+        (e = hipEventCreate(&c->ev0)) != hipSuccess || (e = hipEventCreate(&c->ev1)) != hipSuccess) {
+        smc_ctx_destroy(c);
+        return fail(nullptr, SMC_E_HIP, hipGetErrorString(e));
+    }
+    *c->cancel_host = 0;
+    *out = c;
+    return SMC_OK;
+}
+
+void smc_ctx_destroy(smc_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->d_jobs) (void)hipFree(c->d_jobs);
+    if (c->d_states) (void)hipFree(c->d_states);
+    if (c->d_results) (void)hipFree(c->d_results);
+    if (c->d_rec) (void)hipFree(c->d_rec);
+    if (c->d_ctl) (void)hipFree(c->d_ctl);
+    if (c->cancel_host) (void)hipHostFree(c->cancel_host);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char *smc_last_error(const smc_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int smc_set_watchdog(smc_ctx *c, double seconds)
+{
+    if (!c) return SMC_E_INVALID;
+    c->watchdog = seconds;
+    return SMC_OK;
+}
+
+int smc_set_waves_per_cu(smc_ctx *c, int w)
+{
+    if (!c) return SMC_E_INVALID;
+    if (w < 0 || w > 32) return fail(c, SMC_E_INVALID, "waves_per_cu must lie in 0..32");
+    c->waves_per_cu = w;
+    return SMC_OK;
+}
+
+void smc_cancel(smc_ctx *c)
+{
+    if (c) c->cancel_req.store(1);
+}
+
+int smc_device_cus(const smc_ctx *c) { return c ? c->n_cu : 0; }
+
+// ---- networks ----------------------------------------------------------------
+static int upload_net(smc_net *n)
+{
+    smc_ctx *c = n->ctx;
+    HIP_TRY(c, hipMalloc((void **)&n->d_x0, n->S * sizeof(int32_t)));
+    HIP_TRY(c, hipMalloc((void **)&n->d_rate, n->M * sizeof(double)));
+    HIP_TRY(c, hipMalloc((void **)&n->d_reac, n->M * sizeof(int2)));
+    HIP_TRY(c, hipMalloc((void **)&n->d_chg, n->M * sizeof(int4)));
+    HIP_TRY(c, hipMemcpy(n->d_x0, n->x0.data(), n->S * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(n->d_rate, n->rate.data(), n->M * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(n->d_reac, n->reac.data(), n->M * sizeof(int2), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(n->d_chg, n->chg.data(), n->M * sizeof(int4), hipMemcpyHostToDevice));
+    return SMC_OK;
+}
+
+int smc_net_create(smc_ctx *c, const smc_net_desc *d, smc_net **out)
+{
+    if (!c || !d || !out) return fail(c, SMC_E_INVALID, "null argument");
+    *out = nullptr;
+    const int S = d->n_species, M = d->n_reactions;
+    if (S < 1 || M < 1 || S > 16384) return fail(c, SMC_E_INVALID, "need 1 <= S <= 16384 and M >= 1");
+    if (!d->x0 || !d->rate || !d->reactants || !d->change_idx || !d->change_val)
+        return fail(c, SMC_E_INVALID, "missing network array");
+    auto *n = new smc_net();
+    n->ctx = c;
+    n->S = S;
+    n->M = M;
+    n->x0.assign(d->x0, d->x0 + S);
+    n->rate.assign(d->rate, d->rate + M);
+    for (int s = 0; s < S; ++s)
+        if (n->x0[s] < 0) {
+            delete n;
+            return fail(c, SMC_E_INVALID, "negative initial count");
+        }
+    n->reac.resize(M);
+    n->chg.resize(M);
+    for (int j = 0; j < M; ++j) {
+        if (!(n->rate[j] >= 0.0) || std::isinf(n->rate[j])) {
+            delete n;
+            return fail(c, SMC_E_INVALID, "rate constants must be finite and >= 0");
+        }
+        int ra = d->reactants[2 * j], rb = d->reactants[2 * j + 1];
+        if (ra < -1 || ra >= S || rb < -1 || rb >= S) {
+            delete n;
+            return fail(c, SMC_E_INVALID, "reactant index out of range");
+        }
+        if (ra < 0 && rb >= 0) std::swap(ra, rb);
+        n->reac[j] = make_int2(ra, rb);
+        int packed[4];
+        std::vector<std::pair<int, int>> net_change;
+        for (int q = 0; q < 4; ++q) {
+            const int s = d->change_idx[4 * j + q], v = d->change_val[4 * j + q];
+            if (s < -1 || s >= S || v < -32768 || v > 32767) {
+                delete n;
+                return fail(c, SMC_E_INVALID, "state change out of range");
+            }
+            packed[q] = s < 0 ? (int)0xFFFF0000u : (int)(((uint32_t)s << 16) | ((uint32_t)v & 0xFFFFu));
+            if (s >= 0) net_change.push_back({s, v});
+        }
+        // a reaction may not remove more molecules of a species than it consumes
+        for (auto &sv : net_change) {
+            int total = 0;
+            for (auto &o : net_change)
+                if (o.first == sv.first) total += o.second;
+            const int consumed = (ra == sv.first) + (rb == sv.first);
+            if (total < -consumed) {
+                delete n;
+                return fail(c, SMC_E_INVALID, "reaction consumes more than its reactants");
+            }
+        }
+        n->chg[j] = make_int4(packed[0], packed[1], packed[2], packed[3]);
+    }
+    for (int s = 0; s < S; ++s)
+        n->names.push_back(d->names && d->names[s] ? std::string(d->names[s]) : "X" + std::to_string(s));
+    const int rc = upload_net(n);
+    if (rc != SMC_OK) {
+        smc_net_destroy(n);
+        return rc;
+    }
+    *out = n;
+    return SMC_OK;
+}
+
+int smc_net_set_rates(smc_net *n, const double *rate)
+{
+    if (!n || !rate) return SMC_E_INVALID;
+    for (int j = 0; j < n->M; ++j)
+        if (!(rate[j] >= 0.0) || std::isinf(rate[j]))
+            return fail(n->ctx, SMC_E_INVALID, "rate constants must be finite and >= 0");
+    n->rate.assign(rate, rate + n->M);
+    HIP_TRY(n->ctx, hipMemcpy(n->d_rate, n->rate.data(), n->M * sizeof(double), hipMemcpyHostToDevice));
+    return SMC_OK;
+}
+
+void smc_net_destroy(smc_net *n)
+{
+    if (!n) return;
+    if (n->d_x0) (void)hipFree(n->d_x0);
+    if (n->d_rate) (void)hipFree(n->d_rate);
+    if (n->d_reac) (void)hipFree(n->d_reac);
+    if (n->d_chg) (void)hipFree(n->d_chg);
+    delete n;
+}
+
+// ---- formulas ----------------------------------------------------------------
+int smc_formula_compile(smc_ctx *c, const smc_net *net, const char *text, smc_formula **out)
+{
+    if (!c || !net || !text || !out) return fail(c, SMC_E_INVALID, "null argument");
+    *out = nullptr;
+    auto *f = new smc_formula();
+    f->ctx = c;
+    try {
+        compile_formula(text, net->names, f->prog);
+    } catch (const ParseFailure &e) {
+        delete f;
+        return fail(c, SMC_E_PARSE, e.what());
+    } catch (const Unsupported &e) {
+        delete f;
+        return fail(c, SMC_E_UNSUPPORTED, e.what());
+    } catch (const std::exception &e) {
+        delete f;
+        return fail(c, SMC_E_INVALID, e.what());
+    }
+    f->horizon = f->prog.horizon;
+    hipError_t e = hipMalloc((void **)&f->d_prog, sizeof(MonProg));
+    if (e == hipSuccess) e = hipMemcpy(f->d_prog, &f->prog, sizeof(MonProg), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        smc_formula_destroy(f);
+        return hip_fail(c, e, "formula upload");
+    }
+    *out = f;
+    return SMC_OK;
+}
+
+double smc_formula_horizon(const smc_formula *f) { return f ? f->horizon : NAN; }
+
+void smc_formula_destroy(smc_formula *f)
+{
+    if (!f) return;
+    if (f->d_prog) (void)hipFree(f->d_prog);
+    delete f;
+}
+
+// ---- estimation --------------------------------------------------------------
+int smc_estimate_batch(smc_ctx *c, const smc_job *jobs, size_t n_jobs, smc_result *out)
+{
+    if (!c || (!jobs && n_jobs) || (!out && n_jobs)) return fail(c, SMC_E_INVALID, "null argument");
+    if (n_jobs == 0) return SMC_OK;
+    if (n_jobs > (1u << 20)) return fail(c, SMC_E_INVALID, "too many jobs");
+    HIP_TRY(c, hipSetDevice(c->device));
+    std::vector<Prepared> P(n_jobs);
+    int first_err = SMC_OK;
+    for (size_t k = 0; k < n_jobs; ++k) {
+        std::memset(&out[k], 0, sizeof(smc_result));
+        const int rc = prepare(c, jobs[k].net, jobs[k].formula, &jobs[k].params, 0, P[k]);
+        if (rc != SMC_OK) {
+            out[k].status = rc;
+            return rc;
+        }
+    }
+    std::vector<JobResult> res;
+    double secs = 0.0;
+    const int rc = run_jobs(c, P, res, &secs);
+    if (rc != SMC_OK) {
+        for (size_t k = 0; k < n_jobs; ++k) out[k].status = rc;
+        return rc;
+    }
+    for (size_t k = 0; k < n_jobs; ++k) {
+        fill_result(res[k], P[k].z, &out[k]);
+        out[k].device_seconds = secs;
+        if (out[k].status != SMC_OK && first_err == SMC_OK) {
+            first_err = out[k].status;
+            c->err = "stopping rule ran out of batch slots";
+        }
+    }
+    return first_err;
+}
+
+int smc_estimate(smc_ctx *c, const smc_net *net, const smc_formula *f, const smc_params *p, smc_result *out)
+{
+    if (!out) return fail(c, SMC_E_INVALID, "out is NULL");
+    smc_job j;
+    j.net = net;
+    j.formula = f;
+    if (p) j.params = *p;
+    else std::memset(&j.params, 0, sizeof(j.params));
+    return p ? smc_estimate_batch(c, &j, 1, out) : fail(c, SMC_E_INVALID, "params is NULL");
+}
+
+int smc_trajectories(smc_ctx *c, const smc_net *net, const smc_formula *f, const smc_params *p,
+                     uint64_t first, uint64_t count, uint32_t *events, uint8_t *verdict_reason)
+{
+    if (!c || !p) return fail(c, SMC_E_INVALID, "null argument");
+    if (count == 0) return SMC_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    smc_params q = *p;
+    q.fixed_n = count;
+    std::vector<Prepared> P(1);
+    int rc = prepare(c, net, f, &q, first, P[0]);
+    if (rc != SMC_OK) return rc;
+    const size_t bytes = count * (sizeof(uint32_t) + sizeof(uint8_t)) + 16;
+    if (ensure(c, c->d_rec, c->cap_rec, bytes)) return SMC_E_NOMEM;
+    auto *d_ev = (uint32_t *)c->d_rec;
+    auto *d_vr = (uint8_t *)(d_ev + count);
+    P[0].job.rec_events = d_ev;
+    P[0].job.rec_vr = d_vr;
+    std::vector<JobResult> res;
+    double secs = 0.0;
+    rc = run_jobs(c, P, res, &secs);
+    if (rc != SMC_OK) return rc;
+    if (events) HIP_TRY(c, hipMemcpyAsync(events, d_ev, count * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    if (verdict_reason) HIP_TRY(c, hipMemcpyAsync(verdict_reason, d_vr, count, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return SMC_OK;
+}
+
+int smc_sample_state(smc_ctx *c, const smc_net *net, const smc_params *p, double T, uint64_t first,
+                     uint64_t count, int32_t *counts)
+{
+    if (!c || !net || !p || !counts) return fail(c, SMC_E_INVALID, "null argument");
+    if (count == 0) return SMC_OK;
+    if (!(T >= 0.0)) return fail(c, SMC_E_INVALID, "T must be >= 0");
+    if (first + count > (1ull << 32)) return fail(c, SMC_E_INVALID, "trajectory indices must stay below 2^32");
+    if ((size_t)net->S * kWave * sizeof(int32_t) > 65536) return fail(c, SMC_E_INVALID, "network too large");
+    HIP_TRY(c, hipSetDevice(c->device));
+    Job J;
+    std::memset(&J, 0, sizeof(J));
+    J.net.S = net->S;
+    J.net.M = net->M;
+    J.net.x0 = net->d_x0;
+    J.net.rate = net->d_rate;
+    J.net.reac = net->d_reac;
+    J.net.chg = net->d_chg;
+    J.seed = p->seed;
+    J.first = first;
+    J.model_id = p->model_id;
+    if (ensure(c, c->d_jobs, c->cap_jobs, 1)) return SMC_E_NOMEM;
+    const size_t bytes = count * (size_t)net->S * sizeof(int32_t);
+    if (ensure(c, c->d_rec, c->cap_rec, bytes)) return SMC_E_NOMEM;
+    HIP_TRY(c, hipMemcpyAsync(c->d_jobs, &J, sizeof(J), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, launch_sample_state(net->M <= 4 ? 4 : kBlocks, c->stream, c->d_jobs, T, count,
+                                   (int32_t *)c->d_rec, net->S));
+    HIP_TRY(c, hipMemcpyAsync(counts, c->d_rec, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return SMC_OK;
+}
+
+int smc_wilson_next_device(smc_ctx *c, const uint64_t *successes, const uint64_t *n, size_t count,
+                           double eps, double z, uint32_t flags, uint64_t *out)
+{
+    if (!c || (count && (!successes || !n || !out))) return fail(c, SMC_E_INVALID, "null argument");
+    if (!(eps > 0.0 && eps < 0.5) || !(z > 0.0)) return fail(c, SMC_E_INVALID, "need 0 < eps < 0.5, z > 0");
+    if (count == 0) return SMC_OK;
+    if (count > (1u << 30)) return fail(c, SMC_E_INVALID, "count too large");
+    for (size_t k = 0; k < count; ++k)
+        if (n[k] == 0 || successes[k] > n[k]) return fail(c, SMC_E_INVALID, "need 0 <= successes <= n, n > 0");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const size_t bytes = 3 * count * sizeof(uint64_t);
+    if (ensure(c, c->d_rec, c->cap_rec, bytes)) return SMC_E_NOMEM;
+    auto *d_y = (unsigned long long *)c->d_rec;
+    auto *d_n = d_y + count;
+    auto *d_o = d_n + count;
+    HIP_TRY(c, hipMemcpyAsync(d_y, successes, count * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d_n, n, count * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, launch_wilson_table(c->stream, d_y, d_n, (int)count, eps, z,
+                                   (flags & SMC_PAPER_ROUNDING) ? 1 : 0, d_o));
+    HIP_TRY(c, hipMemcpyAsync(out, d_o, count * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return SMC_OK;
+}
+
+// ---- Wilson formulas ---------------------------------------------------------
+double smc_z_value(double confidence)
+{
+    if (!(confidence > 0.0 && confidence < 1.0)) return NAN;
+    // Newton's method on Phi(z) = (1 + c) / 2 in extended precision.
+    const long double q = 0.5L + 0.5L * (long double)confidence;
+    long double z = std::sqrt(-2.0L * std::log(1.0L - q));   // rough start
+    const long double inv_sqrt2 = 0.70710678118654752440084436210484903928L;
+    const long double inv_sqrt2pi = 0.39894228040143267793994605993438186848L;
+    for (int it = 0; it < 100; ++it) {
+        const long double cdf = 0.5L * std::erfc(-z * inv_sqrt2);
+        const long double pdf = inv_sqrt2pi * std::exp(-0.5L * z * z);
+        const long double dz = (cdf - q) / pdf;
+        z -= dz;
+        if (std::fabs(dz) <= 1e-19L * std::fabs(z)) break;
+    }
+    return (double)z;
+}
+
+double smc_wilson_sample_value(double p, double eps, double z) { return wilson_value(p, eps, z); }
+
+uint64_t smc_wilson_sample(double p, double eps, double z)
+{
+    const double v = wilson_value(p, eps, z);
+    return v > 0.0 ? (uint64_t)std::ceil(v) : 0;
+}
+
+void smc_wilson_interval(uint64_t k, uint64_t n, double z, double *lo, double *hi)
+{
+    if (n == 0) {
+        if (lo) *lo = 0.0;
+        if (hi) *hi = 1.0;
+        return;
+    }
+    const double nd = (double)n;
+    const double p = (double)k / nd;
+    const double z2 = z * z;
+    const double center = p + z2 / (2.0 * nd);
+    const double half = z * std::sqrt(p * (1.0 - p) / nd + z2 / ((4.0 * nd) * nd));
+    const double den = 1.0 + z2 / nd;
+    const double l = (center - half) / den;
+    const double h = (center + half) / den;
+    if (lo) *lo = l < 0.0 ? 0.0 : l;
+    if (hi) *hi = h > 1.0 ? 1.0 : h;
+}
+
+}  // extern "C"

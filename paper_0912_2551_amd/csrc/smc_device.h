@@ -1,0 +1,135 @@
+// smc_device.h -- data layout shared by the host runtime and the HIP kernels.
+//
+// Everything here lives in device memory.  One Job describes one model: its
+// reaction network (Sec. 2.2), its compiled monitor program (Sec. 3.1-3.2),
+// its stopping rule (Sec. 3.3, eqs. 3-4, Fig. 2) and its accounting state.
+#pragma once
+#include <stdint.h>
+
+namespace smc {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kMaxBatches = 32;    // sample-size iterations per job
+constexpr int kShards = 16;        // counter replicas (spread atomics over L2 channels)
+constexpr int kMaxPreds = 16;
+constexpr int kMaxAtoms = 8;
+constexpr int kMaxNested = 2;      // nested-until atoms per formula
+constexpr int kMaxValOps = 96;     // arithmetic predicate programs
+constexpr int kMaxPropOps = 96;    // boolean programs over predicates
+constexpr int kMaxTopOps = 32;     // Kleene program over atoms
+constexpr int kValStack = 4;       // arithmetic stack depth on the device
+constexpr int kBlocks = 16;        // prefix-sum blocks for reaction selection
+
+enum CmpOp : int32_t { CMP_LT = 0, CMP_LE, CMP_GE, CMP_GT, CMP_EQ, CMP_NE };
+enum ValOp : int32_t { VO_VAR = 0, VO_CONST, VO_ADD, VO_SUB, VO_MUL, VO_DIV, VO_NEG, VO_SQRT };
+enum PropOp : int32_t { PO_PRED = 0, PO_TRUE, PO_FALSE, PO_NOT, PO_AND, PO_OR };
+enum TopOp : int32_t { TO_ATOM = 0, TO_NOT, TO_AND, TO_OR };
+enum AtomKind : int32_t { AK_PROP = 0, AK_UNTIL, AK_NEXT, AK_NESTED };
+enum Reason : int32_t { RS_STATE = 0, RS_TIME = 1, RS_ABSORB = 2, RS_CAP = 3, RS_TMAX = 4 };
+
+// A state predicate.  Linear form: sum_q w[q] * x[var[q]] + c  (op)  0 with
+// integer w, c (exact in int64).  General form: two arithmetic stack programs
+// evaluated in double in source order and compared.
+struct Pred {
+    int32_t linear;
+    int32_t op;
+    int32_t nterm;
+    int32_t var[4];
+    int64_t w[4];
+    int64_t c;
+    int32_t lhs_off, lhs_len, rhs_off, rhs_len;
+};
+
+// A temporal atom evaluated at position 0 of the path.
+//  AK_PROP   : boolean program p1 on the initial state.
+//  AK_UNTIL  : p1 U[lo,hi] p2, negated when neg = 1 (G I p = not(tt U I not p)).
+//  AK_NEXT   : X[lo,hi] p1.
+//  AK_NESTED : p1 U[0,hi] (p2 U[0,hi2] p3), registers (ok, latest start).
+struct Atom {
+    int32_t kind;
+    int32_t neg;
+    int32_t p1, p2, p3;   // boolean program ids (-1 = none)
+    int32_t slot;         // nested-until register slot
+    double lo, hi, hi2;
+};
+
+struct MonProg {
+    int32_t n_preds, n_atoms, n_top, n_props;
+    Pred preds[kMaxPreds];
+    int32_t vop[kMaxValOps];
+    int32_t vvar[kMaxValOps];
+    double vconst[kMaxValOps];
+    int32_t prop_off[3 * kMaxAtoms], prop_len[3 * kMaxAtoms];
+    int32_t pop[kMaxPropOps];
+    int32_t parg[kMaxPropOps];
+    Atom atoms[kMaxAtoms];
+    int32_t top_op[kMaxTopOps];
+    int32_t top_arg[kMaxTopOps];
+    double horizon;
+};
+
+// Reaction network tables (device memory, read-only in kernels).
+//   reac[j]  = (ra, rb): ra < 0 zero order; rb < 0 first order; ra == rb
+//              homodimer; otherwise two distinct reactants.
+//   chg[j]   = four packed entries ((species & 0xFFFF) << 16) | (delta & 0xFFFF),
+//              species 0xFFFF = unused.
+struct NetDev {
+    int32_t S, M;
+    const int32_t *x0;
+    const double *rate;
+    const int2 *reac;
+    const int4 *chg;
+};
+
+// Per-job accounting (device memory).  Batch b covers relative trajectory
+// indices [bound[b-1], bound[b]) with bound[-1] = 0; bound[b] = 0 means "not
+// known yet".  Counters are replicated over kShards slots.
+struct JobState {
+    unsigned long long next;                 // relative indices issued
+    unsigned long long limit;                // indices below this may be issued
+    unsigned long long bound[kMaxBatches];
+    unsigned long long yes[kMaxBatches][kShards];
+    unsigned long long no[kMaxBatches][kShards];
+    unsigned long long events[kMaxBatches][kShards];
+    unsigned long long trunc[kMaxBatches][kShards];
+    unsigned long long done[kMaxBatches];    // completions (iterative jobs only)
+    int32_t evaluated[kMaxBatches];
+    int32_t cur;                             // earliest batch not yet evaluated
+    int32_t final_flag;                      // 1 = stopping rule satisfied
+    int32_t n_batches;
+    int32_t overflow;                        // ran out of batch slots
+    unsigned long long n_final, yes_final, events_final, trunc_final;
+};
+
+struct Job {
+    NetDev net;
+    const MonProg *mon;
+    unsigned long long seed;
+    unsigned long long first;     // absolute index of relative index 0
+    unsigned long long capacity;  // relative indices that may ever be issued
+    unsigned long long n_first;   // end of the first batch
+    uint32_t model_id;
+    uint32_t max_events;          // 0 = none
+    double t_max;
+    int32_t iterative;            // 1 = Fig. 2 rule, 0 = fixed sample
+    int32_t literal;              // paper's rounding step without the stop at 0.5
+    double eps, z;
+    JobState *st;
+    uint32_t *rec_events;         // optional per-index outputs (relative index)
+    uint8_t *rec_vr;
+};
+
+// Compact per-job outcome copied back to the host.
+struct JobResult {
+    unsigned long long n, yes, events, trunc, issued;
+    int32_t batches, final_flag, overflow, pad;
+};
+
+// Launch-wide control block.
+struct Control {
+    int32_t open_jobs;            // iterative jobs not final yet
+    int32_t pad;
+    unsigned long long cancel_seen;
+};
+
+}  // namespace smc

@@ -1,0 +1,35 @@
+// smc_internal.h -- declarations shared by the host runtime translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "smc_device.h"
+
+namespace smc {
+
+struct ParseFailure : std::runtime_error {
+    using std::runtime_error::runtime_error;
+};
+struct Unsupported : std::runtime_error {
+    using std::runtime_error::runtime_error;
+};
+
+// formula.cpp
+void compile_formula(const std::string &text, const std::vector<std::string> &names, MonProg &out);
+
+// ssa_kernel.hip
+hipError_t launch_persistent(int nb_variant, int grid, int waves_per_block, size_t lds_bytes,
+                             hipStream_t stream, const Job *jobs, int n_jobs, int s_max,
+                             Control *ctl, const volatile int32_t *cancel, int spin_limit);
+hipError_t launch_sample_state(int nb_variant, hipStream_t stream, const Job *job, double T,
+                               unsigned long long count, int32_t *out, int s_max);
+hipError_t launch_init(hipStream_t stream, const Job *jobs, int n_jobs);
+hipError_t launch_finalize(hipStream_t stream, const Job *jobs, int n_jobs, JobResult *out);
+hipError_t launch_wilson_table(hipStream_t stream, const unsigned long long *yes,
+                               const unsigned long long *n, int count, double eps, double z,
+                               int literal, unsigned long long *out);
+
+}  // namespace smc

@@ -1,0 +1,971 @@
+// ssa_kernel.hip -- persistent on-the-fly SSA + BLTLc monitor kernels for gfx950.
+//
+// One trajectory per lane.  A wave works on one job (model) at a time; idle
+// lanes are refilled with new trajectory indices of that job as soon as their
+// trajectory is decided, so the wave stays full until the job runs out of
+// issuable indices.  Per event and lane:
+//   a_j and the running sum S_j in reaction order (Sec. 2.2, template step 1);
+//   one Philox4x32-10 block keyed by (trajectory, model), counter = event;
+//   tau = -log(u1) / a0 (eq. 2a); j = min{j : S_j > u2 a0} (eq. 2b);
+//   x += v_j, t += tau (step 4); monitor update (Sec. 3.2).
+// Species counts live in LDS (species-major, lane-minor: conflict-free);
+// reaction tables are read with wave-uniform (scalar) loads.  Time and
+// propensity sums are FP64, with no contraction (built with
+// -ffp-contract=off), so each lane reproduces the CPU reference bit for bit.
+//
+// Verdicts are reduced per wave (ballot/popcount) and added atomically to
+// per-(job, batch) counters.  Iterative jobs run the Wilson stopping rule
+// (eqs. 3-4, Fig. 2) on the device: the lane that completes a batch
+// evaluates it and either publishes the next batch bound or finalises the
+// job.  While a batch is pending, indices that every possible outcome of the
+// batch would still require are issued ahead (no speculative waste).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "smc_device.h"
+
+namespace smc {
+
+// ---------------------------------------------------------------------------
+// Numeric primitives (independent implementation of the numeric contract)
+// ---------------------------------------------------------------------------
+struct U4 {
+    uint32_t a, b, c, d;
+};
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplies, key bumped by the Weyl constants between rounds.
+__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t m0 = (uint64_t)c0 * 0xD2511F53ull;
+        const uint64_t m1 = (uint64_t)c2 * 0xCD9E8D57ull;
+        const uint32_t n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)m1;
+        c3 = (uint32_t)m0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// 53-bit uniforms: (0,1] for the waiting time, [0,1) for the channel.
+__device__ __forceinline__ double unif_oc(uint32_t hi, uint32_t lo)
+{
+    const uint64_t v = ((uint64_t)hi << 21) | (uint64_t)(lo >> 11);
+    return (double)(v + 1ull) * 0x1p-53;
+}
+__device__ __forceinline__ double unif_co(uint32_t hi, uint32_t lo)
+{
+    const uint64_t v = ((uint64_t)hi << 21) | (uint64_t)(lo >> 11);
+    return (double)v * 0x1p-53;
+}
+
+// Natural log of a positive normal double from IEEE operations only.
+// Reduce x = m 2^e with m in [sqrt(1/2), sqrt(2)); with f = m - 1,
+// s = f / (2 + f): ln m = f - (f^2/2 - s (f^2/2 + 2R)), R = sum_k s^2k/(2k+1).
+__device__ __forceinline__ double ctr_log(double x)
+{
+    const uint64_t bits = __double_as_longlong(x);
+    int e = (int)((bits >> 52) & 0x7FF) - 1023;
+    double m = __longlong_as_double((long long)((bits & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull));
+    if (m > 1.4142135623730951) {
+        m = m * 0.5;
+        e = e + 1;
+    }
+    const double f = m - 1.0;
+    const double s = f / (2.0 + f);
+    const double z = s * s;
+    double p = 1.0 / 21.0;
+    p = fma(z, p, 1.0 / 19.0);
+    p = fma(z, p, 1.0 / 17.0);
+    p = fma(z, p, 1.0 / 15.0);
+    p = fma(z, p, 1.0 / 13.0);
+    p = fma(z, p, 1.0 / 11.0);
+    p = fma(z, p, 1.0 / 9.0);
+    p = fma(z, p, 1.0 / 7.0);
+    p = fma(z, p, 1.0 / 5.0);
+    p = fma(z, p, 1.0 / 3.0);
+    const double R = z * p;
+    const double R2 = R + R;
+    const double h = (0.5 * f) * f;
+    const double ed = (double)e;
+    return ed * 6.93147180369123816490e-01 -
+           ((h - fma(s, h + R2, ed * 1.90821492927058770002e-10)) - f);
+}
+
+// Eq. 4 (before rounding up), in the contract's operation order.
+__device__ __forceinline__ double wilson_n(double p, double eps, double z)
+{
+    const double pq = p * (1.0 - p);
+    const double e2 = eps * eps;
+    const double d = p - 0.5;
+    const double rad = pq * pq + (4.0 * e2) * (d * d);
+    const double num = (pq - 2.0 * e2) + sqrt(rad);
+    return (z * z) * num / (2.0 * e2);
+}
+
+// Fig. 2 rounding of the estimate towards 0.5 (optionally stopping at 0.5).
+__device__ __forceinline__ double towards_half(double p, double eps, int literal)
+{
+    if (p <= 0.5) {
+        const double q = p + eps;
+        return literal ? q : fmin(q, 0.5);
+    }
+    const double q = p - eps;
+    return literal ? q : fmax(q, 0.5);
+}
+
+__device__ __forceinline__ unsigned long long next_sample(double p_hat, double eps, double z,
+                                                          int literal)
+{
+    return (unsigned long long)ceil(wilson_n(towards_half(p_hat, eps, literal), eps, z));
+}
+
+// ---------------------------------------------------------------------------
+// Wave helpers
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T ld_relaxed(T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T ld_acquire(T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_release(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+__device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ uint32_t read_lane_u32(uint32_t v, int l)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ unsigned long long read_lane_u64(unsigned long long v, int l)
+{
+    const uint32_t lo = read_lane_u32((uint32_t)v, l);
+    const uint32_t hi = read_lane_u32((uint32_t)(v >> 32), l);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int ffs64(uint64_t m) { return __ffsll((unsigned long long)m) - 1; }
+
+__device__ __forceinline__ int rank_in(uint64_t m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Per-wave view of a job: uniform values kept in scalar registers.
+// ---------------------------------------------------------------------------
+struct JobView {
+    const Job *job;
+    JobState *st;
+    const MonProg *mon;
+    NetDev net;
+    unsigned long long seed, first, capacity;
+    uint32_t model_id, max_events;
+    double t_max;
+    int iterative, literal;
+    double eps, z;
+    int nb, bs;   // prefix blocks and reactions per block
+
+    __device__ void load(const Job *jobs, int j)
+    {
+        job = jobs + j;
+        st = job->st;
+        mon = job->mon;
+        net = job->net;
+        seed = job->seed;
+        first = job->first;
+        capacity = job->capacity;
+        model_id = job->model_id;
+        max_events = job->max_events;
+        t_max = job->t_max;
+        iterative = job->iterative;
+        literal = job->literal;
+        eps = job->eps;
+        z = job->z;
+        nb = net.M < kBlocks ? net.M : kBlocks;
+        bs = (net.M + nb - 1) / nb;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Propensities (contract: one rounding per propensity, c * h(x)).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double propensity(int2 rr, double c, const int32_t *xs, int lane)
+{
+    if (rr.x < 0) return c;
+    const int32_t xa = xs[rr.x * kWave + lane];
+    if (rr.y < 0) return c * (double)xa;
+    if (rr.x == rr.y) return c * (((double)xa * (double)(xa - 1)) * 0.5);
+    const int32_t xb = xs[rr.y * kWave + lane];
+    return c * ((double)xa * (double)xb);
+}
+
+// ---------------------------------------------------------------------------
+// Monitor (compiled BLTLc program).  Atom status: 0 open, 1 true, 2 false.
+// ---------------------------------------------------------------------------
+struct MonState {
+    uint32_t status;   // 2 bits per atom
+    uint32_t ok;       // nested-until: left operand held on every earlier state
+    double ts[kMaxNested];   // nested-until: latest admissible inner start (< 0: none)
+};
+
+__device__ __forceinline__ double val_eval(const MonProg *mp, int off, int len, const int32_t *xs,
+                                           int lane)
+{
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int sp = 0;
+    for (int o = off; o < off + len; ++o) {
+        const int op = mp->vop[o];
+        double v;
+        if (op == VO_VAR || op == VO_CONST) {
+            v = (op == VO_VAR) ? (double)xs[mp->vvar[o] * kWave + lane] : mp->vconst[o];
+            if (sp == 0) s0 = v;
+            else if (sp == 1) s1 = v;
+            else if (sp == 2) s2 = v;
+            else s3 = v;
+            ++sp;
+            continue;
+        }
+        if (op == VO_NEG || op == VO_SQRT) {
+            const double a = sp == 1 ? s0 : sp == 2 ? s1 : sp == 3 ? s2 : s3;
+            v = (op == VO_NEG) ? -a : sqrt(a);
+            if (sp == 1) s0 = v;
+            else if (sp == 2) s1 = v;
+            else if (sp == 3) s2 = v;
+            else s3 = v;
+            continue;
+        }
+        const double b = sp == 2 ? s1 : sp == 3 ? s2 : s3;
+        const double a = sp == 2 ? s0 : sp == 3 ? s1 : s2;
+        if (op == VO_ADD) v = a + b;
+        else if (op == VO_SUB) v = a - b;
+        else if (op == VO_MUL) v = a * b;
+        else v = a / b;
+        --sp;
+        if (sp == 1) s0 = v;
+        else if (sp == 2) s1 = v;
+        else s2 = v;
+    }
+    return s0;
+}
+
+__device__ __forceinline__ bool cmp_d(double l, double r, int op)
+{
+    switch (op) {
+    case CMP_LT: return l < r;
+    case CMP_LE: return l <= r;
+    case CMP_GE: return l >= r;
+    case CMP_GT: return l > r;
+    case CMP_EQ: return l == r;
+    default: return l != r;
+    }
+}
+__device__ __forceinline__ bool cmp_i(long long v, int op)
+{
+    switch (op) {
+    case CMP_LT: return v < 0;
+    case CMP_LE: return v <= 0;
+    case CMP_GE: return v >= 0;
+    case CMP_GT: return v > 0;
+    case CMP_EQ: return v == 0;
+    default: return v != 0;
+    }
+}
+
+__device__ __forceinline__ uint32_t eval_preds(const MonProg *mp, const int32_t *xs, int lane)
+{
+    uint32_t pm = 0;
+    const int np = mp->n_preds;
+    for (int q = 0; q < np; ++q) {
+        const Pred &p = mp->preds[q];
+        bool r;
+        if (p.linear) {
+            long long v = p.c;
+            for (int k = 0; k < p.nterm; ++k) v += p.w[k] * (long long)xs[p.var[k] * kWave + lane];
+            r = cmp_i(v, p.op);
+        } else {
+            const double l = val_eval(mp, p.lhs_off, p.lhs_len, xs, lane);
+            const double rr = val_eval(mp, p.rhs_off, p.rhs_len, xs, lane);
+            r = cmp_d(l, rr, p.op);
+        }
+        pm |= (r ? 1u : 0u) << q;
+    }
+    return pm;
+}
+
+__device__ __forceinline__ bool prop_eval(const MonProg *mp, int id, uint32_t pm)
+{
+    const int off = mp->prop_off[id], len = mp->prop_len[id];
+    uint32_t st = 0;
+    for (int o = off; o < off + len; ++o) {
+        const int op = mp->pop[o];
+        if (op == PO_PRED) st = (st << 1) | ((pm >> mp->parg[o]) & 1u);
+        else if (op == PO_TRUE) st = (st << 1) | 1u;
+        else if (op == PO_FALSE) st = st << 1;
+        else if (op == PO_NOT) st ^= 1u;
+        else {
+            const uint32_t a = st & 1u, b = (st >> 1) & 1u;
+            st = ((st >> 2) << 1) | (op == PO_AND ? (a & b) : (a | b));
+        }
+    }
+    return (st & 1u) != 0;
+}
+
+__device__ __forceinline__ uint32_t put_status(uint32_t status, int a, uint32_t v)
+{
+    return (status & ~(3u << (2 * a))) | (v << (2 * a));
+}
+
+// Kleene value of the top-level program: 0 open, 1 true, 2 false.
+__device__ __forceinline__ uint32_t top_eval(const MonProg *mp, uint32_t status)
+{
+    const int n = mp->n_top;
+    if (n == 1) return status & 3u;
+    uint32_t tT = 0, tF = 0;
+    for (int o = 0; o < n; ++o) {
+        const int op = mp->top_op[o];
+        if (op == TO_ATOM) {
+            const uint32_t s = (status >> (2 * mp->top_arg[o])) & 3u;
+            tT = (tT << 1) | (s == 1u);
+            tF = (tF << 1) | (s == 2u);
+        } else if (op == TO_NOT) {
+            const uint32_t bt = tT & 1u, bf = tF & 1u;
+            tT = (tT & ~1u) | bf;
+            tF = (tF & ~1u) | bt;
+        } else {
+            const uint32_t t1 = tT & 1u, t2 = (tT >> 1) & 1u, f1 = tF & 1u, f2 = (tF >> 1) & 1u;
+            const uint32_t rt = op == TO_AND ? (t1 & t2) : (t1 | t2);
+            const uint32_t rf = op == TO_AND ? (f1 | f2) : (f1 & f2);
+            tT = ((tT >> 2) << 1) | rt;
+            tF = ((tF >> 2) << 1) | rf;
+        }
+    }
+    return (tT & 1u) ? 1u : ((tF & 1u) ? 2u : 0u);
+}
+
+// The state just entered (index k, entry time t) is inspected.
+__device__ __forceinline__ uint32_t mon_step(const MonProg *mp, MonState &ms, const int32_t *xs,
+                                             int lane, uint32_t k, double t)
+{
+    const uint32_t pm = eval_preds(mp, xs, lane);
+    const int na = mp->n_atoms;
+    for (int a = 0; a < na; ++a) {
+        if ((ms.status >> (2 * a)) & 3u) continue;
+        const Atom &A = mp->atoms[a];
+        uint32_t v = 0;
+        if (A.kind == AK_PROP) {
+            v = prop_eval(mp, A.p1, pm) ? 1u : 2u;
+        } else if (A.kind == AK_UNTIL) {
+            const bool in_window = (t >= A.lo) && (t <= A.hi);
+            if (in_window && prop_eval(mp, A.p2, pm)) v = 1u;
+            else if (!prop_eval(mp, A.p1, pm)) v = 2u;
+            if (v && A.neg) v = 3u - v;
+        } else if (A.kind == AK_NEXT) {
+            if (k == 1u) v = prop_eval(mp, A.p1, pm) ? 1u : 2u;
+        } else {   // nested until
+            const int sl = A.slot;
+            const uint32_t okb = (ms.ok >> a) & 1u;
+            double tsv = sl == 0 ? ms.ts[0] : ms.ts[1];
+            if (okb && t <= A.hi) tsv = t;                      // new admissible start
+            if (tsv >= 0.0 && prop_eval(mp, A.p3, pm)) v = 1u;
+            else {
+                if (!prop_eval(mp, A.p2, pm)) tsv = -1.0;        // inner left operand broken
+                const uint32_t ok2 = okb & (prop_eval(mp, A.p1, pm) ? 1u : 0u);
+                ms.ok = (ms.ok & ~(1u << a)) | (ok2 << a);
+                if (tsv < 0.0 && !ok2) v = 2u;
+            }
+            if (sl == 0) ms.ts[0] = tsv;
+            else ms.ts[1] = tsv;
+        }
+        if (v) ms.status = put_status(ms.status, a, v);
+    }
+    return top_eval(mp, ms.status);
+}
+
+// Time is about to advance to tn (absorbing: no further state).
+__device__ __forceinline__ uint32_t mon_advance(const MonProg *mp, MonState &ms, double tn,
+                                                bool absorbing)
+{
+    const int na = mp->n_atoms;
+    for (int a = 0; a < na; ++a) {
+        if ((ms.status >> (2 * a)) & 3u) continue;
+        const Atom &A = mp->atoms[a];
+        uint32_t v = 0;
+        if (A.kind == AK_UNTIL) {
+            if (absorbing || tn > A.hi) v = A.neg ? 1u : 2u;
+        } else if (A.kind == AK_NEXT) {
+            if (absorbing || !(tn >= A.lo && tn <= A.hi)) v = 2u;
+        } else if (A.kind == AK_NESTED) {
+            const int sl = A.slot;
+            double tsv = sl == 0 ? ms.ts[0] : ms.ts[1];
+            if (tsv >= 0.0 && (absorbing || tn - tsv > A.hi2)) tsv = -1.0;
+            const uint32_t okb = (ms.ok >> a) & 1u;
+            if (tsv < 0.0 && (!okb || absorbing || tn > A.hi)) v = 2u;
+            if (sl == 0) ms.ts[0] = tsv;
+            else ms.ts[1] = tsv;
+        }
+        if (v) ms.status = put_status(ms.status, a, v);
+    }
+    return top_eval(mp, ms.status);
+}
+
+__device__ __forceinline__ void mon_init(MonState &ms)
+{
+    ms.status = 0;
+    ms.ok = 0xFFFFFFFFu;
+    ms.ts[0] = -1.0;
+    ms.ts[1] = -1.0;
+}
+
+// ---------------------------------------------------------------------------
+// One SSA event for this lane.  Returns the next time (inf when absorbing)
+// and, unless absorbing, leaves the selected channel in *jsel.
+// ---------------------------------------------------------------------------
+template <int NB>
+__device__ __forceinline__ double ssa_draw(const JobView &V, const int32_t *xs, int lane,
+                                           unsigned long long abs_idx, uint32_t k, double t,
+                                           int *jsel)
+{
+    const int M = V.net.M;
+    const int nb = V.nb, bs = V.bs;
+    const int2 *reac = V.net.reac;
+    const double *rate = V.net.rate;
+    double P[NB];
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        P[q] = acc;
+        if (q < nb) {
+            const int j0 = q * bs;
+            const int j1 = (j0 + bs < M) ? j0 + bs : M;
+            for (int j = j0; j < j1; ++j) acc = acc + propensity(reac[j], rate[j], xs, lane);
+            P[q] = acc;
+        }
+    }
+    const double a0 = acc;
+    if (!(a0 > 0.0)) return INFINITY;
+    const U4 r = philox10(k, 0u, (uint32_t)V.seed, (uint32_t)(V.seed >> 32), (uint32_t)abs_idx,
+                          V.model_id);
+    const double u1 = unif_oc(r.a, r.b);
+    const double u2 = unif_co(r.c, r.d);
+    const double target = u2 * a0;
+    // first block whose running sum exceeds the target
+    int qsel = 0;
+    double base = 0.0;
+    bool found = false;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        if (q < nb) {
+            const bool hit = !found && (P[q] > target);
+            qsel = hit ? q : qsel;
+            base = hit ? (q == 0 ? 0.0 : P[q - 1]) : base;
+            found = found || hit;
+        }
+    }
+    if (bs == 1) {
+        *jsel = qsel;
+    } else {
+        // re-run the same running sum inside the block (identical operations)
+        const int j0 = qsel * bs;
+        const int j1 = (j0 + bs < M) ? j0 + bs : M;
+        double s = base;
+        int js = j1 - 1;
+        bool got = false;
+        for (int rr = 0; rr < bs; ++rr) {
+            const int j = j0 + rr;
+            if (!got && j < j1) {
+                s = s + propensity(reac[j], rate[j], xs, lane);
+                if (s > target) {
+                    js = j;
+                    got = true;
+                }
+            }
+            if (__ballot(!got) == 0) break;
+        }
+        *jsel = js;
+    }
+    const double tau = (-ctr_log(u1)) / a0;
+    return t + tau;
+}
+
+__device__ __forceinline__ void apply_change(int32_t *xs, int lane, int4 ch)
+{
+    const uint32_t e[4] = {(uint32_t)ch.x, (uint32_t)ch.y, (uint32_t)ch.z, (uint32_t)ch.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t s = e[q] >> 16;
+        if (s != 0xFFFFu) xs[s * kWave + lane] += (int32_t)(int16_t)(e[q] & 0xFFFFu);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stopping rule on the device.
+// ---------------------------------------------------------------------------
+__device__ unsigned long long sum_shards(unsigned long long (*arr)[kShards], int b)
+{
+    unsigned long long s = 0;
+    for (int q = 0; q < kShards; ++q) s += ld_relaxed(&arr[b][q]);
+    return s;
+}
+
+// Evaluate batch b (all of its trajectories are counted) and possibly the
+// batches after it.  Exactly one lane evaluates each batch.
+__device__ void evaluate_batches(const JobView &V, Control *ctl, int b)
+{
+    JobState *st = V.st;
+    for (;;) {
+        if (atomicCAS(&st->evaluated[b], 0, 1) != 0) return;
+        __threadfence();
+        unsigned long long Y = 0;
+        for (int q = 0; q <= b; ++q) Y += sum_shards(st->yes, q);
+        const unsigned long long Bb = ld_acquire(&st->bound[b]);
+        const double p_hat = (double)Y / (double)Bb;
+        const unsigned long long Np = next_sample(p_hat, V.eps, V.z, V.literal);
+        if (Np > Bb && b + 1 < kMaxBatches && Np <= V.capacity) {
+            st_release(&st->bound[b + 1], Np);
+            st_release(&st->cur, b + 1);
+            atomicMax(&st->limit, Np);
+            __threadfence();
+            const unsigned long long d = ld_acquire(&st->done[b + 1]);
+            if (d == Np - Bb) {
+                b = b + 1;
+                continue;
+            }
+            return;
+        }
+        unsigned long long E = 0, T = 0;
+        for (int q = 0; q <= b; ++q) {
+            E += sum_shards(st->events, q);
+            T += sum_shards(st->trunc, q);
+        }
+        st->n_final = Bb;
+        st->yes_final = Y;
+        st->events_final = E;
+        st->trunc_final = T;
+        st->n_batches = b + 1;
+        st->overflow = (Np > Bb) ? 1 : 0;
+        __threadfence();
+        st_release(&st->final_flag, 1);
+        atomicSub(&ctl->open_jobs, 1);
+        return;
+    }
+}
+
+// While batch c is pending, raise the issue limit to the smallest next bound
+// that any possible outcome of batch c would produce (minus one for safety).
+__device__ void speculate(const JobView &V, int c)
+{
+    JobState *st = V.st;
+    const unsigned long long Bc = ld_acquire(&st->bound[c]);
+    const unsigned long long Bp = c ? ld_acquire(&st->bound[c - 1]) : 0ull;
+    if (Bc == 0) return;
+    unsigned long long Yprev = 0;
+    for (int q = 0; q < c; ++q) Yprev += sum_shards(st->yes, q);
+    const unsigned long long ylo = sum_shards(st->yes, c);
+    const unsigned long long nlo = sum_shards(st->no, c);
+    const unsigned long long size = Bc - Bp;
+    if (ylo + nlo > size) return;
+    const double plo = (double)(Yprev + ylo) / (double)Bc;
+    const double phi = (double)(Yprev + size - nlo) / (double)Bc;
+    unsigned long long g = next_sample(plo, V.eps, V.z, V.literal);
+    const unsigned long long g2 = next_sample(phi, V.eps, V.z, V.literal);
+    g = g2 < g ? g2 : g;
+    if (V.literal && plo <= 0.5 && phi >= 0.5) {
+        const unsigned long long g3 = next_sample(0.5, V.eps, V.z, V.literal);
+        g = g3 < g ? g3 : g;
+    }
+    if (g > 1) g -= 1;
+    if (g > Bc) {
+        if (g > V.capacity) g = V.capacity;
+        atomicMax(&st->limit, g);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Job selection and index claims.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool claimable(const Job *jobs, int j)
+{
+    JobState *st = jobs[j].st;
+    return ld_relaxed(&st->next) < ld_relaxed(&st->limit) && ld_relaxed(&st->final_flag) == 0;
+}
+
+// Wave-cooperative scan for a job with issuable indices, starting at `start`.
+__device__ int pick_job(const Job *jobs, int n_jobs, int start)
+{
+    const int lane = lane_id();
+    for (int base = 0; base < n_jobs; base += kWave) {
+        const int q = base + lane;
+        int j = start + q;
+        if (j >= n_jobs) j -= n_jobs;
+        const bool ok = (q < n_jobs) && claimable(jobs, j);
+        const uint64_t m = __ballot(ok);
+        if (m) return __builtin_amdgcn_readlane(j, ffs64(m));
+    }
+    return -1;
+}
+
+// Claim up to n consecutive relative indices; returns the count, *base = first.
+__device__ int claim(JobState *st, int n, unsigned long long *base)
+{
+    unsigned long long cur = ld_relaxed(&st->next);
+    for (int tries = 0; tries < 256; ++tries) {
+        const unsigned long long lim = ld_relaxed(&st->limit);
+        if (cur >= lim) return 0;
+        const unsigned long long want = (lim - cur) < (unsigned long long)n ? (lim - cur) : (unsigned long long)n;
+        const unsigned long long prev = atomicCAS(&st->next, cur, cur + want);
+        if (prev == cur) {
+            *base = cur;
+            return (int)want;
+        }
+        cur = prev;
+    }
+    return 0;
+}
+
+struct KArgs {
+    const Job *jobs;
+    int n_jobs;
+    int s_max;
+    Control *ctl;
+    const volatile int32_t *cancel;   // host-visible stop word
+    int spin_limit;
+    int waves_per_block;
+};
+
+// ---------------------------------------------------------------------------
+// The persistent kernel.
+// ---------------------------------------------------------------------------
+template <int NB>
+__global__ __launch_bounds__(256) void ssa_persistent(KArgs A)
+{
+    extern __shared__ int32_t lds[];
+    const int lane = lane_id();
+    const int wid = (int)(threadIdx.x / kWave);
+    int32_t *xs = lds + (size_t)wid * (size_t)A.s_max * kWave;
+    const int gwave = (int)blockIdx.x * A.waves_per_block + wid;
+    const int shard = gwave & (kShards - 1);
+    const int n_waves = (int)gridDim.x * A.waves_per_block;
+    const int start = (int)(((long long)gwave * A.n_jobs) / n_waves);
+
+    int cur = -1;
+    JobView V;
+    bool active = false, fin = false;
+    unsigned long long ridx = 0;
+    uint32_t k = 0, verdict = 0, reason = 0;
+    double t = 0.0;
+    MonState ms;
+    mon_init(ms);
+    int spins = 0;
+
+    for (uint32_t it = 0;; ++it) {
+        if ((it & 255u) == 0u) {
+            int stop = 0;
+            if (lane == 0) stop = *A.cancel;
+            if (uniform_i(stop)) break;
+        }
+        if (__ballot(active) == 0ull) {
+            const int j = pick_job(A.jobs, A.n_jobs, start);
+            if (j < 0) {
+                if (ld_acquire(&A.ctl->open_jobs) <= 0) break;
+                __builtin_amdgcn_s_sleep(32);
+                if (++spins > A.spin_limit) break;
+                continue;
+            }
+            spins = 0;
+            if (j != cur) {
+                cur = j;
+                V.load(A.jobs, cur);
+            }
+        }
+        // -------- refill idle lanes with new trajectory indices --------
+        const uint64_t need = __ballot(!active);
+        if (need) {
+            const int leader = ffs64(need);
+            unsigned long long base = 0;
+            int got = 0;
+            if (lane == leader) got = claim(V.st, __popcll(need), &base);
+            got = __builtin_amdgcn_readlane(got, leader);
+            base = read_lane_u64(base, leader);
+            const int r = rank_in(need);
+            if (!active && r < got) {
+                ridx = base + (unsigned long long)r;
+                const int S = V.net.S;
+                for (int s = 0; s < S; ++s) xs[s * kWave + lane] = V.net.x0[s];
+                t = 0.0;
+                k = 0;
+                mon_init(ms);
+                const uint32_t v = mon_step(V.mon, ms, xs, lane, 0u, 0.0);
+                active = true;
+                if (v) {
+                    fin = true;
+                    verdict = (v == 1u);
+                    reason = RS_STATE;
+                }
+            }
+        }
+        if (__ballot(active) == 0ull) continue;
+
+        // -------- one event per running lane --------
+        if (active && !fin) {
+            if (V.max_events && k == V.max_events) {
+                fin = true;
+                verdict = 0;
+                reason = RS_CAP;
+            } else {
+                int j = 0;
+                const double tn = ssa_draw<NB>(V, xs, lane, V.first + ridx, k, t, &j);
+                const bool absorbing = isinf(tn);
+                const uint32_t v = mon_advance(V.mon, ms, tn, absorbing);
+                if (v) {
+                    fin = true;
+                    verdict = (v == 1u);
+                    reason = absorbing ? RS_ABSORB : RS_TIME;
+                } else if (tn > V.t_max) {
+                    fin = true;
+                    verdict = 0;
+                    reason = RS_TMAX;
+                } else {
+                    apply_change(xs, lane, V.net.chg[j]);
+                    t = tn;
+                    k = k + 1u;
+                    const uint32_t v2 = mon_step(V.mon, ms, xs, lane, k, t);
+                    if (v2) {
+                        fin = true;
+                        verdict = (v2 == 1u);
+                        reason = RS_STATE;
+                    }
+                }
+            }
+        }
+
+        // -------- accounting of decided trajectories --------
+        uint64_t fm = __ballot(fin);
+        if (fm) {
+            int b = 0;
+            if (fin) {
+                while (b < kMaxBatches - 1) {
+                    const unsigned long long bb = ld_acquire(&V.st->bound[b]);
+                    if (bb == 0ull || ridx < bb) break;
+                    ++b;
+                }
+                if (V.job->rec_events) V.job->rec_events[ridx] = k;
+                if (V.job->rec_vr) V.job->rec_vr[ridx] = (uint8_t)(verdict | (reason << 1));
+            }
+            while (fm) {
+                const int L = ffs64(fm);
+                const int b0 = __builtin_amdgcn_readlane(b, L);
+                const bool sel = fin && (b == b0);
+                const uint64_t sm = __ballot(sel);
+                const uint32_t ny = (uint32_t)__popcll(__ballot(sel && verdict));
+                const uint32_t nn = (uint32_t)__popcll(sm) - ny;
+                const uint32_t nt = (uint32_t)__popcll(__ballot(sel && reason == RS_CAP));
+                const unsigned long long ev = wave_sum_u64(sel ? (unsigned long long)k : 0ull);
+                if (lane == L) {
+                    JobState *st = V.st;
+                    if (ny) atomicAdd(&st->yes[b0][shard], (unsigned long long)ny);
+                    if (nn) atomicAdd(&st->no[b0][shard], (unsigned long long)nn);
+                    if (nt) atomicAdd(&st->trunc[b0][shard], (unsigned long long)nt);
+                    atomicAdd(&st->events[b0][shard], ev);
+                    if (V.iterative) {
+                        __threadfence();
+                        const unsigned long long d =
+                            atomicAdd(&st->done[b0], (unsigned long long)(ny + nn)) + ny + nn;
+                        __threadfence();
+                        const unsigned long long hi = ld_acquire(&st->bound[b0]);
+                        const unsigned long long lo = b0 ? ld_acquire(&st->bound[b0 - 1]) : 0ull;
+                        if (hi != 0ull && d == hi - lo) evaluate_batches(V, A.ctl, b0);
+                        else if (b0 == ld_acquire(&st->cur)) speculate(V, b0);
+                    }
+                }
+                fm &= ~sm;
+                if (sel) {
+                    fin = false;
+                    active = false;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// SSA probe: state at time T of trajectories first .. first+count-1.
+// ---------------------------------------------------------------------------
+template <int NB>
+__global__ __launch_bounds__(256) void ssa_sample_state(const Job *jobp, double T,
+                                                        unsigned long long count, int32_t *out,
+                                                        int s_max)
+{
+    extern __shared__ int32_t lds[];
+    const int lane = lane_id();
+    const int wid = (int)(threadIdx.x / kWave);
+    int32_t *xs = lds + (size_t)wid * (size_t)s_max * kWave;
+    JobView V;
+    V.load(jobp, 0);
+    const unsigned long long c = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = c < count;
+    const int S = V.net.S;
+    for (int s = 0; s < S; ++s) xs[s * kWave + lane] = V.net.x0[s];
+    double t = 0.0;
+    uint32_t k = 0;
+    bool run = live;
+    while (__ballot(run) != 0ull) {
+        if (run) {
+            int j = 0;
+            const double tn = ssa_draw<NB>(V, xs, lane, V.first + c, k, t, &j);
+            if (tn > T) {
+                run = false;
+            } else {
+                apply_change(xs, lane, V.net.chg[j]);
+                t = tn;
+                k = k + 1u;
+            }
+        }
+    }
+    if (live)
+        for (int s = 0; s < S; ++s) out[c * (unsigned long long)S + s] = xs[s * kWave + lane];
+}
+
+// Reset per-job accounting: batch 0 ends at n_first, which is also the first
+// issue limit (the rest of the state was cleared by the caller).
+__global__ void init_jobs(const Job *jobs, int n_jobs)
+{
+    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (j >= n_jobs) return;
+    JobState *st = jobs[j].st;
+    st->bound[0] = jobs[j].n_first;
+    st->limit = jobs[j].n_first;
+}
+
+// Sum the counter shards of every job into its final numbers (fixed-sample
+// jobs are finalised here; iterative jobs were finalised by the kernel) and
+// write the compact outcome.
+__global__ void finalize_jobs(const Job *jobs, int n_jobs, JobResult *out)
+{
+    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (j >= n_jobs) return;
+    JobState *st = jobs[j].st;
+    JobResult r;
+    if (jobs[j].iterative) {
+        r.n = st->n_final;
+        r.yes = st->yes_final;
+        r.events = st->events_final;
+        r.trunc = st->trunc_final;
+        r.batches = st->n_batches;
+        r.final_flag = st->final_flag;
+        r.overflow = st->overflow;
+    } else {
+        r.n = st->bound[0];
+        r.yes = sum_shards(st->yes, 0);
+        r.events = sum_shards(st->events, 0);
+        r.trunc = sum_shards(st->trunc, 0);
+        r.batches = 1;
+        r.final_flag = (st->next >= st->bound[0]) ? 1 : 0;
+        r.overflow = 0;
+    }
+    r.issued = st->next;
+    r.pad = 0;
+    out[j] = r;
+}
+
+// Device-side eq. 4 over a table of (successes, n): used to check that the
+// device and host stopping rules agree.
+__global__ void wilson_table(const unsigned long long *yes, const unsigned long long *n, int count,
+                             double eps, double z, int literal, unsigned long long *out)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= count) return;
+    out[i] = next_sample((double)yes[i] / (double)n[i], eps, z, literal);
+}
+
+}  // namespace smc
+
+// ---------------------------------------------------------------------------
+// Host-side launch wrappers (called from the runtime, C++ linkage).
+// ---------------------------------------------------------------------------
+namespace smc {
+
+hipError_t launch_persistent(int nb_variant, int grid, int waves_per_block, size_t lds_bytes,
+                             hipStream_t stream, const Job *jobs, int n_jobs, int s_max,
+                             Control *ctl, const volatile int32_t *cancel, int spin_limit)
+{
+    KArgs a;
+    a.jobs = jobs;
+    a.n_jobs = n_jobs;
+    a.s_max = s_max;
+    a.ctl = ctl;
+    a.cancel = cancel;
+    a.spin_limit = spin_limit;
+    a.waves_per_block = waves_per_block;
+    const dim3 block(kWave * waves_per_block);
+    if (nb_variant <= 4)
+        hipLaunchKernelGGL(ssa_persistent<4>, dim3(grid), block, lds_bytes, stream, a);
+    else
+        hipLaunchKernelGGL(ssa_persistent<kBlocks>, dim3(grid), block, lds_bytes, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_state(int nb_variant, hipStream_t stream, const Job *job, double T,
+                               unsigned long long count, int32_t *out, int s_max)
+{
+    const int threads = kWave;
+    const unsigned long long blocks = (count + threads - 1) / threads;
+    const size_t lds = (size_t)s_max * kWave * sizeof(int32_t);
+    if (nb_variant <= 4)
+        hipLaunchKernelGGL(ssa_sample_state<4>, dim3((unsigned)blocks), dim3(threads), lds, stream,
+                           job, T, count, out, s_max);
+    else
+        hipLaunchKernelGGL(ssa_sample_state<kBlocks>, dim3((unsigned)blocks), dim3(threads), lds,
+                           stream, job, T, count, out, s_max);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(hipStream_t stream, const Job *jobs, int n_jobs)
+{
+    hipLaunchKernelGGL(init_jobs, dim3((n_jobs + 63) / 64), dim3(64), 0, stream, jobs, n_jobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(hipStream_t stream, const Job *jobs, int n_jobs, JobResult *out)
+{
+    hipLaunchKernelGGL(finalize_jobs, dim3((n_jobs + 63) / 64), dim3(64), 0, stream, jobs, n_jobs,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_wilson_table(hipStream_t stream, const unsigned long long *yes,
+                               const unsigned long long *n, int count, double eps, double z,
+                               int literal, unsigned long long *out)
+{
+    hipLaunchKernelGGL(wilson_table, dim3((count + 255) / 256), dim3(256), 0, stream, yes, n, count,
+                       eps, z, literal, out);
+    return hipGetLastError();
+}
+
+}  // namespace smc
