@@ -213,7 +213,13 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
     int wpb = (int)std::min<size_t>(4, std::max<size_t>(1, 65536 / lds_wave));
     if (lds_wave > 65536) return fail(ctx, SMC_E_INVALID, "network too large for one wave's LDS");
     const int wpc = pick_waves_per_cu(ctx);
-    const int grid = std::max(1, (ctx->n_cu * wpc + wpb - 1) / wpb);
+    // No more waves than there are trajectories to run at once: idle waves
+    // only poll the job table.
+    unsigned long long lanes_needed = 0;
+    for (int k = 0; k < n; ++k) lanes_needed += P[k].capacity;
+    const unsigned long long waves_needed = (lanes_needed + kWave - 1) / kWave;
+    const unsigned long long waves = std::min<unsigned long long>((unsigned long long)ctx->n_cu * wpc, waves_needed);
+    const int grid = (int)std::max<unsigned long long>(1, (waves + wpb - 1) / wpb);
     const int nb_variant = m_max <= 4 ? 4 : kBlocks;
     res.assign(n, JobResult{});
     double total_ms = 0.0;

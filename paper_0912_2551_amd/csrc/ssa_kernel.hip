@@ -631,20 +631,39 @@ __device__ int pick_job(const Job *jobs, int n_jobs, int start)
     return -1;
 }
 
-// Claim up to n consecutive relative indices; returns the count, *base = first.
-__device__ int claim(JobState *st, int n, unsigned long long *base)
+// Claim a chunk of consecutive relative indices below the job's issue limit;
+// returns the count, *base = first.  The chunk shrinks as the remaining work
+// shrinks (guided self-scheduling) so that the last trajectories spread over
+// all waves; at least `need` indices are taken when available.
+//  - fixed-sample jobs: the limit never moves, so a fetch-add suffices (a
+//    claim past the end simply gets nothing);
+//  - iterative jobs: the limit rises while the job runs, so indices are
+//    claimed by compare-and-swap below the current limit, with back-off.
+__device__ int claim(JobState *st, bool iterative, int need, int n_waves, unsigned long long *base)
 {
     unsigned long long cur = ld_relaxed(&st->next);
-    for (int tries = 0; tries < 256; ++tries) {
-        const unsigned long long lim = ld_relaxed(&st->limit);
+    unsigned long long lim = ld_relaxed(&st->limit);
+    if (cur >= lim) return 0;
+    unsigned long long want = (lim - cur) / (4ull * (unsigned long long)n_waves);
+    if (want < (unsigned long long)need) want = (unsigned long long)need;
+    if (want > 256ull) want = 256ull;
+    if (!iterative) {
+        const unsigned long long b = atomicAdd(&st->next, want);
+        if (b >= lim) return 0;
+        *base = b;
+        return (int)((lim - b) < want ? (lim - b) : want);
+    }
+    for (int tries = 0; tries < 16; ++tries) {
         if (cur >= lim) return 0;
-        const unsigned long long want = (lim - cur) < (unsigned long long)n ? (lim - cur) : (unsigned long long)n;
-        const unsigned long long prev = atomicCAS(&st->next, cur, cur + want);
+        const unsigned long long w = (lim - cur) < want ? (lim - cur) : want;
+        const unsigned long long prev = atomicCAS(&st->next, cur, cur + w);
         if (prev == cur) {
             *base = cur;
-            return (int)want;
+            return (int)w;
         }
         cur = prev;
+        lim = ld_relaxed(&st->limit);
+        __builtin_amdgcn_s_sleep(4);
     }
     return 0;
 }
@@ -658,6 +677,17 @@ struct KArgs {
     int spin_limit;
     int waves_per_block;
 };
+
+// Add a wave's counts for batch b of its job to the sharded counters.
+__device__ __forceinline__ void add_counts(JobState *st, int b, int shard, unsigned long long ny,
+                                           unsigned long long nn, unsigned long long nt,
+                                           unsigned long long ev)
+{
+    if (ny) atomicAdd(&st->yes[b][shard], ny);
+    if (nn) atomicAdd(&st->no[b][shard], nn);
+    if (nt) atomicAdd(&st->trunc[b][shard], nt);
+    if (ev) atomicAdd(&st->events[b][shard], ev);
+}
 
 // ---------------------------------------------------------------------------
 // The persistent kernel.
@@ -683,6 +713,10 @@ __global__ __launch_bounds__(256) void ssa_persistent(KArgs A)
     MonState ms;
     mon_init(ms);
     int spins = 0;
+    // wave-local pool of claimed, not yet started indices [pool_next, pool_end)
+    unsigned long long pool_next = 0, pool_end = 0;
+    // fixed-sample jobs: per-lane counts, added to the job once per wave
+    unsigned long long my_yes = 0, my_no = 0, my_trunc = 0, my_events = 0;
 
     for (uint32_t it = 0;; ++it) {
         if ((it & 255u) == 0u) {
@@ -690,11 +724,19 @@ __global__ __launch_bounds__(256) void ssa_persistent(KArgs A)
             if (lane == 0) stop = *A.cancel;
             if (uniform_i(stop)) break;
         }
-        if (__ballot(active) == 0ull) {
+        if (__ballot(active) == 0ull && pool_next == pool_end) {
             const int j = pick_job(A.jobs, A.n_jobs, start);
+            if (j != cur && cur >= 0 && !V.iterative) {
+                // leaving a fixed-sample job: publish this wave's counts
+                const unsigned long long ny = wave_sum_u64(my_yes), nn = wave_sum_u64(my_no);
+                const unsigned long long nt = wave_sum_u64(my_trunc), ev = wave_sum_u64(my_events);
+                if (lane == 0) add_counts(V.st, 0, shard, ny, nn, nt, ev);
+                my_yes = my_no = my_trunc = my_events = 0;
+            }
             if (j < 0) {
-                if (ld_acquire(&A.ctl->open_jobs) <= 0) break;
-                __builtin_amdgcn_s_sleep(32);
+                cur = -1;
+                if (ld_relaxed(&A.ctl->open_jobs) <= 0) break;
+                __builtin_amdgcn_s_sleep(127);
                 if (++spins > A.spin_limit) break;
                 continue;
             }
@@ -707,15 +749,21 @@ __global__ __launch_bounds__(256) void ssa_persistent(KArgs A)
         // -------- refill idle lanes with new trajectory indices --------
         const uint64_t need = __ballot(!active);
         if (need) {
-            const int leader = ffs64(need);
-            unsigned long long base = 0;
-            int got = 0;
-            if (lane == leader) got = claim(V.st, __popcll(need), &base);
-            got = __builtin_amdgcn_readlane(got, leader);
-            base = read_lane_u64(base, leader);
+            const int n_need = __popcll(need);
+            if (pool_next == pool_end) {
+                unsigned long long base = 0;
+                int got = 0;
+                if (lane == 0) got = claim(V.st, V.iterative != 0, n_need, n_waves, &base);
+                got = __builtin_amdgcn_readfirstlane(got);
+                base = read_lane_u64(base, 0);
+                pool_next = base;
+                pool_end = base + (unsigned long long)got;
+            }
+            const unsigned long long avail = pool_end - pool_next;
+            const int give = (unsigned long long)n_need < avail ? n_need : (int)avail;
             const int r = rank_in(need);
-            if (!active && r < got) {
-                ridx = base + (unsigned long long)r;
+            if (!active && r < give) {
+                ridx = pool_next + (unsigned long long)r;
                 const int S = V.net.S;
                 for (int s = 0; s < S; ++s) xs[s * kWave + lane] = V.net.x0[s];
                 t = 0.0;
@@ -729,6 +777,7 @@ __global__ __launch_bounds__(256) void ssa_persistent(KArgs A)
                     reason = RS_STATE;
                 }
             }
+            pool_next += (unsigned long long)give;
         }
         if (__ballot(active) == 0ull) continue;
 
@@ -768,15 +817,28 @@ __global__ __launch_bounds__(256) void ssa_persistent(KArgs A)
         // -------- accounting of decided trajectories --------
         uint64_t fm = __ballot(fin);
         if (fm) {
+            if (fin) {
+                if (V.job->rec_events) V.job->rec_events[ridx] = k;
+                if (V.job->rec_vr) V.job->rec_vr[ridx] = (uint8_t)(verdict | (reason << 1));
+            }
+            if (!V.iterative) {
+                if (fin) {
+                    my_yes += verdict;
+                    my_no += 1u - verdict;
+                    my_trunc += (reason == RS_CAP) ? 1u : 0u;
+                    my_events += k;
+                    fin = false;
+                    active = false;
+                }
+                continue;
+            }
             int b = 0;
             if (fin) {
                 while (b < kMaxBatches - 1) {
-                    const unsigned long long bb = ld_acquire(&V.st->bound[b]);
+                    const unsigned long long bb = ld_relaxed(&V.st->bound[b]);
                     if (bb == 0ull || ridx < bb) break;
                     ++b;
                 }
-                if (V.job->rec_events) V.job->rec_events[ridx] = k;
-                if (V.job->rec_vr) V.job->rec_vr[ridx] = (uint8_t)(verdict | (reason << 1));
             }
             while (fm) {
                 const int L = ffs64(fm);
@@ -789,20 +851,15 @@ __global__ __launch_bounds__(256) void ssa_persistent(KArgs A)
                 const unsigned long long ev = wave_sum_u64(sel ? (unsigned long long)k : 0ull);
                 if (lane == L) {
                     JobState *st = V.st;
-                    if (ny) atomicAdd(&st->yes[b0][shard], (unsigned long long)ny);
-                    if (nn) atomicAdd(&st->no[b0][shard], (unsigned long long)nn);
-                    if (nt) atomicAdd(&st->trunc[b0][shard], (unsigned long long)nt);
-                    atomicAdd(&st->events[b0][shard], ev);
-                    if (V.iterative) {
-                        __threadfence();
-                        const unsigned long long d =
-                            atomicAdd(&st->done[b0], (unsigned long long)(ny + nn)) + ny + nn;
-                        __threadfence();
-                        const unsigned long long hi = ld_acquire(&st->bound[b0]);
-                        const unsigned long long lo = b0 ? ld_acquire(&st->bound[b0 - 1]) : 0ull;
-                        if (hi != 0ull && d == hi - lo) evaluate_batches(V, A.ctl, b0);
-                        else if (b0 == ld_acquire(&st->cur)) speculate(V, b0);
-                    }
+                    add_counts(st, b0, shard, ny, nn, nt, ev);
+                    __threadfence();
+                    const unsigned long long d =
+                        atomicAdd(&st->done[b0], (unsigned long long)(ny + nn)) + ny + nn;
+                    __threadfence();
+                    const unsigned long long hi = ld_acquire(&st->bound[b0]);
+                    const unsigned long long lo = b0 ? ld_acquire(&st->bound[b0 - 1]) : 0ull;
+                    if (hi != 0ull && d == hi - lo) evaluate_batches(V, A.ctl, b0);
+                    else if (b0 == ld_relaxed(&st->cur)) speculate(V, b0);
                 }
                 fm &= ~sm;
                 if (sel) {
@@ -811,6 +868,12 @@ __global__ __launch_bounds__(256) void ssa_persistent(KArgs A)
                 }
             }
         }
+    }
+    // publish the counts of a fixed-sample job this wave was still working on
+    if (cur >= 0 && !V.iterative) {
+        const unsigned long long ny = wave_sum_u64(my_yes), nn = wave_sum_u64(my_no);
+        const unsigned long long nt = wave_sum_u64(my_trunc), ev = wave_sum_u64(my_events);
+        if (lane == 0) add_counts(V.st, 0, shard, ny, nn, nt, ev);
     }
 }
 
