@@ -413,48 +413,75 @@ class Compiler {
 
     void compile(const Node *root)
     {
-        top(root);
+        const int top = top_expr(root);
+        const int n = p_.n_atoms;
+        for (uint32_t tm = 0; tm < (1u << n); ++tm)
+            for (uint32_t fm = 0; fm < (1u << n); ++fm) {
+                if (tm & fm) continue;
+                const int v = eval_top(top, tm, fm);
+                const uint32_t idx = tm | (fm << n);
+                if (v == 1) p_.topT[idx >> 6] |= 1ull << (idx & 63);
+                if (v == 2) p_.topF[idx >> 6] |= 1ull << (idx & 63);
+            }
         p_.horizon = horizon_of(root);
     }
 
   private:
-    void emit_top(int op, int arg)
+    // ---- top level: boolean combination of monitors ---------------------
+    struct TNode {
+        int kind;   // 0 atom, 1 not, 2 and, 3 or
+        int a, b, atom;
+    };
+
+    int push_top(int kind, int a, int b, int atom)
     {
-        if (p_.n_top >= kMaxTopOps) throw Unsupported("formula has too many boolean operators");
-        p_.top_op[p_.n_top] = op;
-        p_.top_arg[p_.n_top] = arg;
-        ++p_.n_top;
+        tops_.push_back({kind, a, b, atom});
+        return (int)tops_.size() - 1;
+    }
+
+    // Kleene value of the combination: 0 open, 1 true, 2 false.
+    int eval_top(int i, uint32_t tm, uint32_t fm) const
+    {
+        const TNode &t = tops_[i];
+        if (t.kind == 0) return ((tm >> t.atom) & 1u) ? 1 : (((fm >> t.atom) & 1u) ? 2 : 0);
+        if (t.kind == 1) {
+            const int v = eval_top(t.a, tm, fm);
+            return v == 0 ? 0 : 3 - v;
+        }
+        const int x = eval_top(t.a, tm, fm), y = eval_top(t.b, tm, fm);
+        if (t.kind == 2) {
+            if (x == 2 || y == 2) return 2;
+            return (x == 1 && y == 1) ? 1 : 0;
+        }
+        if (x == 1 || y == 1) return 1;
+        return (x == 2 && y == 2) ? 2 : 0;
     }
 
     int new_atom()
     {
-        if (p_.n_atoms >= kMaxAtoms) throw Unsupported("formula has more than 8 temporal operators");
+        if (p_.n_atoms >= kMaxAtoms) throw Unsupported("more than 4 temporal monitors in one formula");
         Atom &a = p_.atoms[p_.n_atoms];
         a.p1 = a.p2 = a.p3 = -1;
         a.slot = -1;
         return p_.n_atoms++;
     }
 
-    void top(const Node *n)
+    int top_expr(const Node *n)
     {
         if (is_state_formula(n)) {
             const int a = new_atom();
             p_.atoms[a].kind = AK_PROP;
             p_.atoms[a].p1 = prop(n, false);
-            emit_top(TO_ATOM, a);
-            return;
+            return push_top(0, -1, -1, a);
         }
         switch (n->kind) {
-        case Node::NOT:
-            top(n->a.get());
-            emit_top(TO_NOT, 0);
-            return;
+        case Node::NOT: return push_top(1, top_expr(n->a.get()), -1, -1);
         case Node::AND:
-        case Node::OR:
-            top(n->a.get());
-            top(n->b.get());
-            emit_top(n->kind == Node::AND ? TO_AND : TO_OR, 0);
-            return;
+        case Node::OR: {
+            const int x = top_expr(n->a.get());
+            const int y = top_expr(n->b.get());
+            return push_top(n->kind == Node::AND ? 2 : 3, x, y, -1);
+        }
         case Node::FIN:
         case Node::GLOB: {
             if (!is_state_formula(n->a.get()))
@@ -467,8 +494,7 @@ class Compiler {
             A.hi = n->hi;
             A.p1 = prop_true();
             A.p2 = prop(n->a.get(), n->kind == Node::GLOB);
-            emit_top(TO_ATOM, a);
-            return;
+            return push_top(0, -1, -1, a);
         }
         case Node::NEXT: {
             if (!is_state_formula(n->a.get()))
@@ -479,8 +505,7 @@ class Compiler {
             A.lo = n->lo;
             A.hi = n->hi;
             A.p1 = prop(n->a.get(), false);
-            emit_top(TO_ATOM, a);
-            return;
+            return push_top(0, -1, -1, a);
         }
         case Node::UNTIL: {
             const Node *l = n->a.get(), *r = n->b.get();
@@ -494,8 +519,7 @@ class Compiler {
                 A.hi = n->hi;
                 A.p1 = prop(l, false);
                 A.p2 = prop(r, false);
-                emit_top(TO_ATOM, a);
-                return;
+                return push_top(0, -1, -1, a);
             }
             // p U[0,a] (q U[0,b] r)  or  p U[0,a] F[0,b] r
             const bool inner_until = r->kind == Node::UNTIL && is_state_formula(r->a.get()) &&
@@ -522,60 +546,89 @@ class Compiler {
                 A.p2 = prop_true();
                 A.p3 = prop(r->a.get(), false);
             }
-            emit_top(TO_ATOM, a);
-            return;
+            return push_top(0, -1, -1, a);
         }
         default: throw Unsupported("formula outside the GPU monitor classes");
         }
     }
 
-    void emit_prop(int op, int arg)
+    // ---- state formulas: truth tables over contiguous predicates ----------
+    struct PNode {
+        int kind;   // 0 tt, 1 ff, 2 pred, 3 not, 4 and, 5 or
+        int a, b, local;
+    };
+
+    int build_prop(const Node *n, std::vector<PNode> &tree, int off)
     {
-        if (n_pops_ >= kMaxPropOps) throw Unsupported("state formulas too long");
-        p_.pop[n_pops_] = op;
-        p_.parg[n_pops_] = arg;
-        ++n_pops_;
+        PNode q{0, -1, -1, -1};
+        switch (n->kind) {
+        case Node::TT: q.kind = 0; break;
+        case Node::FF: q.kind = 1; break;
+        case Node::PRED:
+            q.kind = 2;
+            q.local = predicate(n) - off;
+            break;
+        case Node::NOT:
+            q.kind = 3;
+            q.a = build_prop(n->a.get(), tree, off);
+            break;
+        default:
+            q.kind = n->kind == Node::AND ? 4 : 5;
+            q.a = build_prop(n->a.get(), tree, off);
+            q.b = build_prop(n->b.get(), tree, off);
+            break;
+        }
+        tree.push_back(q);
+        return (int)tree.size() - 1;
     }
 
-    int finish_prop(int off)
+    static bool eval_prop(const std::vector<PNode> &tree, int i, uint32_t bits)
     {
-        if (p_.n_props >= 3 * kMaxAtoms) throw Unsupported("too many state formulas");
-        const int id = p_.n_props++;
-        p_.prop_off[id] = off;
-        p_.prop_len[id] = n_pops_ - off;
-        return id;
+        const PNode &q = tree[i];
+        switch (q.kind) {
+        case 0: return true;
+        case 1: return false;
+        case 2: return (bits >> q.local) & 1u;
+        case 3: return !eval_prop(tree, q.a, bits);
+        case 4: return eval_prop(tree, q.a, bits) && eval_prop(tree, q.b, bits);
+        default: return eval_prop(tree, q.a, bits) || eval_prop(tree, q.b, bits);
+        }
     }
 
-    int prop_true()
+    int finish_prop(int off, int cnt, uint32_t table)
     {
-        const int off = n_pops_;
-        emit_prop(PO_TRUE, 0);
-        return finish_prop(off);
+        if (p_.n_props >= kMaxProps) throw Unsupported("too many state formulas");
+        Prop &P = p_.props[p_.n_props];
+        P.off = off;
+        P.cnt = cnt;
+        P.table = table;
+        return p_.n_props++;
     }
+
+    int prop_true() { return finish_prop(0, 0, 1u); }
 
     int prop(const Node *n, bool negate)
     {
-        const int off = n_pops_;
-        prop_body(n);
-        if (negate) emit_prop(PO_NOT, 0);
-        return finish_prop(off);
+        const int off = p_.n_preds;
+        std::vector<PNode> tree;
+        const int root = build_prop(n, tree, off);
+        const int cnt = p_.n_preds - off;
+        if (cnt > kMaxPropPreds) throw Unsupported("a state formula uses more than 5 predicates");
+        uint32_t table = 0;
+        for (uint32_t bits = 0; bits < (1u << cnt); ++bits)
+            if (eval_prop(tree, root, bits) != negate) table |= 1u << bits;
+        return finish_prop(off, cnt, table);
     }
 
-    void prop_body(const Node *n)
+    // ---- predicates -------------------------------------------------------
+    static int mirror(int op)
     {
-        switch (n->kind) {
-        case Node::TT: emit_prop(PO_TRUE, 0); return;
-        case Node::FF: emit_prop(PO_FALSE, 0); return;
-        case Node::PRED: emit_prop(PO_PRED, predicate(n)); return;
-        case Node::NOT:
-            prop_body(n->a.get());
-            emit_prop(PO_NOT, 0);
-            return;
-        default:
-            prop_body(n->a.get());
-            prop_body(n->b.get());
-            emit_prop(n->kind == Node::AND ? PO_AND : PO_OR, 0);
-            return;
+        switch (op) {
+        case CMP_LT: return CMP_GT;
+        case CMP_LE: return CMP_GE;
+        case CMP_GE: return CMP_LE;
+        case CMP_GT: return CMP_LT;
+        default: return op;
         }
     }
 
@@ -585,33 +638,50 @@ class Compiler {
         const int id = p_.n_preds++;
         Pred &P = p_.preds[id];
         P.op = n->cmp;
+        const Expr *l = n->lhs.get(), *r = n->rhs.get();
+        auto int32_const = [](const Expr *e) {
+            return e->kind == Expr::CONST && std::floor(e->c) == e->c && std::fabs(e->c) <= 2147483647.0;
+        };
+        if (l->kind == Expr::VAR && int32_const(r)) {
+            P.kind = PK_VAR;
+            P.var = l->var;
+            P.c32 = (int32_t)r->c;
+            return id;
+        }
+        if (r->kind == Expr::VAR && int32_const(l)) {
+            P.kind = PK_VAR;
+            P.var = r->var;
+            P.c32 = (int32_t)l->c;
+            P.op = mirror(n->cmp);
+            return id;
+        }
         std::map<int, double> w;
         double c = 0.0;
-        const bool lin = integer_exact(n->lhs.get()) && integer_exact(n->rhs.get()) &&
-                         linear_form(n->lhs.get(), w, c, 1.0) && linear_form(n->rhs.get(), w, c, -1.0);
+        const bool lin = integer_exact(l) && integer_exact(r) && linear_form(l, w, c, 1.0) &&
+                         linear_form(r, w, c, -1.0);
         std::vector<std::pair<int, double>> terms;
         for (auto &kv : w)
             if (kv.second != 0.0) terms.push_back(kv);
         bool ok = lin && terms.size() <= 4 && is_small_int(c, 1125899906842624.0);
         for (auto &tm : terms) ok = ok && is_small_int(tm.second, 1048576.0);
         if (ok) {
-            P.linear = 1;
+            P.kind = PK_LINEAR;
             P.nterm = (int)terms.size();
             for (int k = 0; k < P.nterm; ++k) {
-                P.var[k] = terms[k].first;
+                P.vars[k] = terms[k].first;
                 P.w[k] = (int64_t)terms[k].second;
             }
             P.c = (int64_t)c;
             return id;
         }
-        P.linear = 0;
+        P.kind = PK_RPN;
         P.lhs_off = n_vops_;
         int depth = 0, maxd = 0;
-        val(n->lhs.get(), depth, maxd);
+        val(l, depth, maxd);
         P.lhs_len = n_vops_ - P.lhs_off;
         P.rhs_off = n_vops_;
         depth = 0;
-        val(n->rhs.get(), depth, maxd);
+        val(r, depth, maxd);
         P.rhs_len = n_vops_ - P.rhs_off;
         if (maxd > kValStack) throw Unsupported("arithmetic predicate too deep for the GPU");
         return id;
@@ -654,7 +724,7 @@ class Compiler {
     }
 
     MonProg &p_;
-    int n_pops_ = 0;
+    std::vector<TNode> tops_;
     int n_vops_ = 0;
 };
 

@@ -50,13 +50,13 @@ struct smc_net {
     int S = 0, M = 0;
     std::vector<int32_t> x0;
     std::vector<double> rate;
-    std::vector<int2> reac;
-    std::vector<int4> chg;
+    std::vector<int32_t> reac;    // [2M]
+    std::vector<uint32_t> chg;    // [4M]
     std::vector<std::string> names;
     int32_t *d_x0 = nullptr;
     double *d_rate = nullptr;
-    int2 *d_reac = nullptr;
-    int4 *d_chg = nullptr;
+    int32_t *d_reac = nullptr;
+    uint32_t *d_chg = nullptr;
 };
 
 struct smc_formula {
@@ -386,12 +386,12 @@ static int upload_net(smc_net *n)
     smc_ctx *c = n->ctx;
     HIP_TRY(c, hipMalloc((void **)&n->d_x0, n->S * sizeof(int32_t)));
     HIP_TRY(c, hipMalloc((void **)&n->d_rate, n->M * sizeof(double)));
-    HIP_TRY(c, hipMalloc((void **)&n->d_reac, n->M * sizeof(int2)));
-    HIP_TRY(c, hipMalloc((void **)&n->d_chg, n->M * sizeof(int4)));
+    HIP_TRY(c, hipMalloc((void **)&n->d_reac, 2 * n->M * sizeof(int32_t)));
+    HIP_TRY(c, hipMalloc((void **)&n->d_chg, 4 * n->M * sizeof(uint32_t)));
     HIP_TRY(c, hipMemcpy(n->d_x0, n->x0.data(), n->S * sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(n->d_rate, n->rate.data(), n->M * sizeof(double), hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(n->d_reac, n->reac.data(), n->M * sizeof(int2), hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(n->d_chg, n->chg.data(), n->M * sizeof(int4), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(n->d_reac, n->reac.data(), 2 * n->M * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(n->d_chg, n->chg.data(), 4 * n->M * sizeof(uint32_t), hipMemcpyHostToDevice));
     return SMC_OK;
 }
 
@@ -414,8 +414,8 @@ int smc_net_create(smc_ctx *c, const smc_net_desc *d, smc_net **out)
             delete n;
             return fail(c, SMC_E_INVALID, "negative initial count");
         }
-    n->reac.resize(M);
-    n->chg.resize(M);
+    n->reac.resize(2 * M);
+    n->chg.resize(4 * M);
     for (int j = 0; j < M; ++j) {
         if (!(n->rate[j] >= 0.0) || std::isinf(n->rate[j])) {
             delete n;
@@ -427,8 +427,9 @@ int smc_net_create(smc_ctx *c, const smc_net_desc *d, smc_net **out)
             return fail(c, SMC_E_INVALID, "reactant index out of range");
         }
         if (ra < 0 && rb >= 0) std::swap(ra, rb);
-        n->reac[j] = make_int2(ra, rb);
-        int packed[4];
+        n->reac[2 * j] = ra;
+        n->reac[2 * j + 1] = rb;
+        uint32_t packed[4];
         std::vector<std::pair<int, int>> net_change;
         for (int q = 0; q < 4; ++q) {
             const int s = d->change_idx[4 * j + q], v = d->change_val[4 * j + q];
@@ -436,7 +437,7 @@ int smc_net_create(smc_ctx *c, const smc_net_desc *d, smc_net **out)
                 delete n;
                 return fail(c, SMC_E_INVALID, "state change out of range");
             }
-            packed[q] = s < 0 ? (int)0xFFFF0000u : (int)(((uint32_t)s << 16) | ((uint32_t)v & 0xFFFFu));
+            packed[q] = s < 0 ? 0xFFFF0000u : (((uint32_t)s << 16) | ((uint32_t)v & 0xFFFFu));
             if (s >= 0) net_change.push_back({s, v});
         }
         // a reaction may not remove more molecules of a species than it consumes
@@ -450,7 +451,7 @@ int smc_net_create(smc_ctx *c, const smc_net_desc *d, smc_net **out)
                 return fail(c, SMC_E_INVALID, "reaction consumes more than its reactants");
             }
         }
-        n->chg[j] = make_int4(packed[0], packed[1], packed[2], packed[3]);
+        for (int q = 0; q < 4; ++q) n->chg[4 * j + q] = packed[q];
     }
     for (int s = 0; s < S; ++s)
         n->names.push_back(d->names && d->names[s] ? std::string(d->names[s]) : "X" + std::to_string(s));

@@ -11,74 +11,85 @@ namespace smc {
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kMaxBatches = 32;    // sample-size iterations per job
 constexpr int kShards = 16;        // counter replicas (spread atomics over L2 channels)
-constexpr int kMaxPreds = 16;
-constexpr int kMaxAtoms = 8;
-constexpr int kMaxNested = 2;      // nested-until atoms per formula
+constexpr int kMaxPreds = 16;      // state predicates per formula
+constexpr int kMaxAtoms = 4;       // temporal monitors per formula
+constexpr int kMaxProps = 12;      // state formulas (operands of the monitors)
+constexpr int kMaxPropPreds = 5;   // predicates per state formula (truth table of 32 bits)
+constexpr int kMaxNested = 2;      // nested-until monitors per formula
 constexpr int kMaxValOps = 96;     // arithmetic predicate programs
-constexpr int kMaxPropOps = 96;    // boolean programs over predicates
-constexpr int kMaxTopOps = 32;     // Kleene program over atoms
 constexpr int kValStack = 4;       // arithmetic stack depth on the device
 constexpr int kBlocks = 16;        // prefix-sum blocks for reaction selection
 
 enum CmpOp : int32_t { CMP_LT = 0, CMP_LE, CMP_GE, CMP_GT, CMP_EQ, CMP_NE };
 enum ValOp : int32_t { VO_VAR = 0, VO_CONST, VO_ADD, VO_SUB, VO_MUL, VO_DIV, VO_NEG, VO_SQRT };
-enum PropOp : int32_t { PO_PRED = 0, PO_TRUE, PO_FALSE, PO_NOT, PO_AND, PO_OR };
-enum TopOp : int32_t { TO_ATOM = 0, TO_NOT, TO_AND, TO_OR };
+enum PredKind : int32_t { PK_VAR = 0, PK_LINEAR = 1, PK_RPN = 2 };
 enum AtomKind : int32_t { AK_PROP = 0, AK_UNTIL, AK_NEXT, AK_NESTED };
 enum Reason : int32_t { RS_STATE = 0, RS_TIME = 1, RS_ABSORB = 2, RS_CAP = 3, RS_TMAX = 4 };
 
-// A state predicate.  Linear form: sum_q w[q] * x[var[q]] + c  (op)  0 with
-// integer w, c (exact in int64).  General form: two arithmetic stack programs
-// evaluated in double in source order and compared.
+// A state predicate over species counts x.
+//  PK_VAR    : x[var] (op) c32                         (int32 compare)
+//  PK_LINEAR : sum_q w[q] * x[vars[q]] + c  (op)  0    (integer, exact in int64)
+//  PK_RPN    : two arithmetic stack programs evaluated in double in source
+//              order, then compared
 struct Pred {
-    int32_t linear;
-    int32_t op;
+    int32_t kind, op;
+    int32_t var, c32;
     int32_t nterm;
-    int32_t var[4];
+    int32_t vars[4];
+    int32_t pad0;
     int64_t w[4];
     int64_t c;
     int32_t lhs_off, lhs_len, rhs_off, rhs_len;
 };
 
-// A temporal atom evaluated at position 0 of the path.
-//  AK_PROP   : boolean program p1 on the initial state.
+// A state formula: a boolean function of predicates off .. off+cnt-1, given
+// by its truth table (bit i = value when the predicate bits read i).
+struct Prop {
+    int32_t off, cnt;
+    uint32_t table;
+    int32_t pad;
+};
+
+// A temporal monitor evaluated at position 0 of the path.
+//  AK_PROP   : state formula p1 on the initial state.
 //  AK_UNTIL  : p1 U[lo,hi] p2, negated when neg = 1 (G I p = not(tt U I not p)).
 //  AK_NEXT   : X[lo,hi] p1.
 //  AK_NESTED : p1 U[0,hi] (p2 U[0,hi2] p3), registers (ok, latest start).
 struct Atom {
     int32_t kind;
     int32_t neg;
-    int32_t p1, p2, p3;   // boolean program ids (-1 = none)
+    int32_t p1, p2, p3;   // state-formula ids (-1 = none)
     int32_t slot;         // nested-until register slot
     double lo, hi, hi2;
 };
 
+// Compiled formula.  The top-level boolean combination of the monitors is a
+// table: with t (f) the mask of monitors known true (false), bit t | f << n of
+// topT (topF) says whether the formula is already true (false) in Kleene
+// logic.
 struct MonProg {
-    int32_t n_preds, n_atoms, n_top, n_props;
+    int32_t n_preds, n_atoms, n_props, pad;
+    uint64_t topT[4], topF[4];
+    Atom atoms[kMaxAtoms];
+    Prop props[kMaxProps];
     Pred preds[kMaxPreds];
     int32_t vop[kMaxValOps];
     int32_t vvar[kMaxValOps];
     double vconst[kMaxValOps];
-    int32_t prop_off[3 * kMaxAtoms], prop_len[3 * kMaxAtoms];
-    int32_t pop[kMaxPropOps];
-    int32_t parg[kMaxPropOps];
-    Atom atoms[kMaxAtoms];
-    int32_t top_op[kMaxTopOps];
-    int32_t top_arg[kMaxTopOps];
     double horizon;
 };
 
 // Reaction network tables (device memory, read-only in kernels).
-//   reac[j]  = (ra, rb): ra < 0 zero order; rb < 0 first order; ra == rb
-//              homodimer; otherwise two distinct reactants.
-//   chg[j]   = four packed entries ((species & 0xFFFF) << 16) | (delta & 0xFFFF),
+//   reac[2j], reac[2j+1] = (ra, rb): ra < 0 zero order; rb < 0 first order;
+//              ra == rb homodimer; otherwise two distinct reactants.
+//   chg[4j+q] = four packed entries ((species & 0xFFFF) << 16) | (delta & 0xFFFF),
 //              species 0xFFFF = unused.
 struct NetDev {
     int32_t S, M;
     const int32_t *x0;
     const double *rate;
-    const int2 *reac;
-    const int4 *chg;
+    const int32_t *reac;
+    const uint32_t *chg;
 };
 
 // Per-job accounting (device memory).  Batch b covers relative trajectory

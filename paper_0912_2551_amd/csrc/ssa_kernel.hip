@@ -178,13 +178,31 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 }
 
 // ---------------------------------------------------------------------------
+// Read-only tables are read through the constant address space: wave-uniform
+// reads then compile to scalar loads even though the kernel also writes
+// global memory (counters, records).
+// ---------------------------------------------------------------------------
+#define SMC_CONST __attribute__((address_space(4)))
+template <typename T>
+using cptr = const SMC_CONST T *;
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T *p)
+{
+    return (cptr<T>)p;
+}
+
+// ---------------------------------------------------------------------------
 // Per-wave view of a job: uniform values kept in scalar registers.
 // ---------------------------------------------------------------------------
 struct JobView {
     const Job *job;
     JobState *st;
-    const MonProg *mon;
-    NetDev net;
+    cptr<MonProg> mon;
+    cptr<int32_t> x0;
+    cptr<double> rate;
+    cptr<int32_t> reac;
+    cptr<uint32_t> chg;
+    int S, M;
     unsigned long long seed, first, capacity;
     uint32_t model_id, max_events;
     double t_max;
@@ -194,48 +212,59 @@ struct JobView {
 
     __device__ void load(const Job *jobs, int j)
     {
+        cptr<Job> J = as_const(jobs) + j;
         job = jobs + j;
-        st = job->st;
-        mon = job->mon;
-        net = job->net;
-        seed = job->seed;
-        first = job->first;
-        capacity = job->capacity;
-        model_id = job->model_id;
-        max_events = job->max_events;
-        t_max = job->t_max;
-        iterative = job->iterative;
-        literal = job->literal;
-        eps = job->eps;
-        z = job->z;
-        nb = net.M < kBlocks ? net.M : kBlocks;
-        bs = (net.M + nb - 1) / nb;
+        st = J->st;
+        mon = as_const(J->mon);
+        x0 = as_const(J->net.x0);
+        rate = as_const(J->net.rate);
+        reac = as_const(J->net.reac);
+        chg = as_const(J->net.chg);
+        S = J->net.S;
+        M = J->net.M;
+        seed = J->seed;
+        first = J->first;
+        capacity = J->capacity;
+        model_id = J->model_id;
+        max_events = J->max_events;
+        t_max = J->t_max;
+        iterative = J->iterative;
+        literal = J->literal;
+        eps = J->eps;
+        z = J->z;
+        nb = M < kBlocks ? M : kBlocks;
+        bs = (M + nb - 1) / nb;
     }
 };
 
 // ---------------------------------------------------------------------------
 // Propensities (contract: one rounding per propensity, c * h(x)).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double propensity(int2 rr, double c, const int32_t *xs, int lane)
+__device__ __forceinline__ double propensity(int ra, int rb, double c, const int32_t *xs, int lane)
 {
-    if (rr.x < 0) return c;
-    const int32_t xa = xs[rr.x * kWave + lane];
-    if (rr.y < 0) return c * (double)xa;
-    if (rr.x == rr.y) return c * (((double)xa * (double)(xa - 1)) * 0.5);
-    const int32_t xb = xs[rr.y * kWave + lane];
+    if (ra < 0) return c;
+    const int32_t xa = xs[ra * kWave + lane];
+    if (rb < 0) return c * (double)xa;
+    if (ra == rb) return c * (((double)xa * (double)(xa - 1)) * 0.5);
+    const int32_t xb = xs[rb * kWave + lane];
     return c * ((double)xa * (double)xb);
 }
 
-// ---------------------------------------------------------------------------
-// Monitor (compiled BLTLc program).  Atom status: 0 open, 1 true, 2 false.
-// ---------------------------------------------------------------------------
-struct MonState {
-    uint32_t status;   // 2 bits per atom
-    uint32_t ok;       // nested-until: left operand held on every earlier state
-    double ts[kMaxNested];   // nested-until: latest admissible inner start (< 0: none)
+struct Change {
+    uint32_t e0, e1, e2, e3;
 };
 
-__device__ __forceinline__ double val_eval(const MonProg *mp, int off, int len, const int32_t *xs,
+// ---------------------------------------------------------------------------
+// Monitor (compiled BLTLc program).  Per lane: masks of monitors known true
+// (tm) and false (fm); nested untils keep "left operand held so far" bits
+// (ok) and the latest admissible inner start time (ts, < 0: none).
+// ---------------------------------------------------------------------------
+struct MonState {
+    uint32_t tm, fm, ok;
+    double ts0, ts1;
+};
+
+__device__ __forceinline__ double val_eval(cptr<MonProg> mp, int off, int len, const int32_t *xs,
                                            int lane)
 {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
@@ -275,7 +304,8 @@ __device__ __forceinline__ double val_eval(const MonProg *mp, int off, int len, 
     return s0;
 }
 
-__device__ __forceinline__ bool cmp_d(double l, double r, int op)
+template <typename T>
+__device__ __forceinline__ bool compare(T l, T r, int op)
 {
     switch (op) {
     case CMP_LT: return l < r;
@@ -286,176 +316,159 @@ __device__ __forceinline__ bool cmp_d(double l, double r, int op)
     default: return l != r;
     }
 }
-__device__ __forceinline__ bool cmp_i(long long v, int op)
-{
-    switch (op) {
-    case CMP_LT: return v < 0;
-    case CMP_LE: return v <= 0;
-    case CMP_GE: return v >= 0;
-    case CMP_GT: return v > 0;
-    case CMP_EQ: return v == 0;
-    default: return v != 0;
-    }
-}
 
-__device__ __forceinline__ uint32_t eval_preds(const MonProg *mp, const int32_t *xs, int lane)
+// Bit q of the result = truth of predicate q in the state held in xs.
+__device__ __forceinline__ uint32_t eval_preds(cptr<MonProg> mp, const int32_t *xs, int lane)
 {
     uint32_t pm = 0;
     const int np = mp->n_preds;
     for (int q = 0; q < np; ++q) {
-        const Pred &p = mp->preds[q];
+        cptr<Pred> p = &mp->preds[q];
+        const int kind = p->kind;
         bool r;
-        if (p.linear) {
-            long long v = p.c;
-            for (int k = 0; k < p.nterm; ++k) v += p.w[k] * (long long)xs[p.var[k] * kWave + lane];
-            r = cmp_i(v, p.op);
+        if (kind == PK_VAR) {
+            r = compare<int32_t>(xs[p->var * kWave + lane], p->c32, p->op);
+        } else if (kind == PK_LINEAR) {
+            long long v = p->c;
+            const int nt = p->nterm;
+            for (int k = 0; k < nt; ++k) v += p->w[k] * (long long)xs[p->vars[k] * kWave + lane];
+            r = compare<long long>(v, 0ll, p->op);
         } else {
-            const double l = val_eval(mp, p.lhs_off, p.lhs_len, xs, lane);
-            const double rr = val_eval(mp, p.rhs_off, p.rhs_len, xs, lane);
-            r = cmp_d(l, rr, p.op);
+            const double l = val_eval(mp, p->lhs_off, p->lhs_len, xs, lane);
+            const double rr = val_eval(mp, p->rhs_off, p->rhs_len, xs, lane);
+            r = compare<double>(l, rr, p->op);
         }
         pm |= (r ? 1u : 0u) << q;
     }
     return pm;
 }
 
-__device__ __forceinline__ bool prop_eval(const MonProg *mp, int id, uint32_t pm)
+// A state formula: lookup in its truth table.
+__device__ __forceinline__ bool prop_val(cptr<MonProg> mp, int id, uint32_t pm)
 {
-    const int off = mp->prop_off[id], len = mp->prop_len[id];
-    uint32_t st = 0;
-    for (int o = off; o < off + len; ++o) {
-        const int op = mp->pop[o];
-        if (op == PO_PRED) st = (st << 1) | ((pm >> mp->parg[o]) & 1u);
-        else if (op == PO_TRUE) st = (st << 1) | 1u;
-        else if (op == PO_FALSE) st = st << 1;
-        else if (op == PO_NOT) st ^= 1u;
-        else {
-            const uint32_t a = st & 1u, b = (st >> 1) & 1u;
-            st = ((st >> 2) << 1) | (op == PO_AND ? (a & b) : (a | b));
-        }
-    }
-    return (st & 1u) != 0;
+    cptr<Prop> P = &mp->props[id];
+    const uint32_t idx = (pm >> P->off) & ((1u << P->cnt) - 1u);
+    return (P->table >> idx) & 1u;
 }
 
-__device__ __forceinline__ uint32_t put_status(uint32_t status, int a, uint32_t v)
+// Kleene value of the formula from the monitor masks: 0 open, 1 true, 2 false.
+__device__ __forceinline__ uint32_t top_value(cptr<MonProg> mp, const MonState &ms)
 {
-    return (status & ~(3u << (2 * a))) | (v << (2 * a));
+    const int n = mp->n_atoms;
+    const uint32_t idx = ms.tm | (ms.fm << n);
+    uint64_t wt, wf;
+    if (n <= 3) {
+        wt = mp->topT[0];
+        wf = mp->topF[0];
+    } else {
+        const uint32_t w = idx >> 6;
+        wt = w == 0 ? mp->topT[0] : w == 1 ? mp->topT[1] : w == 2 ? mp->topT[2] : mp->topT[3];
+        wf = w == 0 ? mp->topF[0] : w == 1 ? mp->topF[1] : w == 2 ? mp->topF[2] : mp->topF[3];
+    }
+    const uint32_t b = idx & 63u;
+    return ((wt >> b) & 1ull) ? 1u : (((wf >> b) & 1ull) ? 2u : 0u);
 }
 
-// Kleene value of the top-level program: 0 open, 1 true, 2 false.
-__device__ __forceinline__ uint32_t top_eval(const MonProg *mp, uint32_t status)
+__device__ __forceinline__ void mon_set(MonState &ms, int a, uint32_t v)
 {
-    const int n = mp->n_top;
-    if (n == 1) return status & 3u;
-    uint32_t tT = 0, tF = 0;
-    for (int o = 0; o < n; ++o) {
-        const int op = mp->top_op[o];
-        if (op == TO_ATOM) {
-            const uint32_t s = (status >> (2 * mp->top_arg[o])) & 3u;
-            tT = (tT << 1) | (s == 1u);
-            tF = (tF << 1) | (s == 2u);
-        } else if (op == TO_NOT) {
-            const uint32_t bt = tT & 1u, bf = tF & 1u;
-            tT = (tT & ~1u) | bf;
-            tF = (tF & ~1u) | bt;
-        } else {
-            const uint32_t t1 = tT & 1u, t2 = (tT >> 1) & 1u, f1 = tF & 1u, f2 = (tF >> 1) & 1u;
-            const uint32_t rt = op == TO_AND ? (t1 & t2) : (t1 | t2);
-            const uint32_t rf = op == TO_AND ? (f1 | f2) : (f1 & f2);
-            tT = ((tT >> 2) << 1) | rt;
-            tF = ((tF >> 2) << 1) | rf;
-        }
-    }
-    return (tT & 1u) ? 1u : ((tF & 1u) ? 2u : 0u);
+    ms.tm |= (v == 1u ? 1u : 0u) << a;
+    ms.fm |= (v == 2u ? 1u : 0u) << a;
 }
 
 // The state just entered (index k, entry time t) is inspected.
-__device__ __forceinline__ uint32_t mon_step(const MonProg *mp, MonState &ms, const int32_t *xs,
+__device__ __forceinline__ uint32_t mon_step(cptr<MonProg> mp, MonState &ms, const int32_t *xs,
                                              int lane, uint32_t k, double t)
 {
     const uint32_t pm = eval_preds(mp, xs, lane);
     const int na = mp->n_atoms;
-    for (int a = 0; a < na; ++a) {
-        if ((ms.status >> (2 * a)) & 3u) continue;
-        const Atom &A = mp->atoms[a];
+#pragma unroll
+    for (int a = 0; a < kMaxAtoms; ++a) {
+        if (a >= na) break;
+        if (((ms.tm | ms.fm) >> a) & 1u) continue;
+        cptr<Atom> A = &mp->atoms[a];
+        const int kind = A->kind;
         uint32_t v = 0;
-        if (A.kind == AK_PROP) {
-            v = prop_eval(mp, A.p1, pm) ? 1u : 2u;
-        } else if (A.kind == AK_UNTIL) {
-            const bool in_window = (t >= A.lo) && (t <= A.hi);
-            if (in_window && prop_eval(mp, A.p2, pm)) v = 1u;
-            else if (!prop_eval(mp, A.p1, pm)) v = 2u;
-            if (v && A.neg) v = 3u - v;
-        } else if (A.kind == AK_NEXT) {
-            if (k == 1u) v = prop_eval(mp, A.p1, pm) ? 1u : 2u;
+        if (kind == AK_PROP) {
+            v = prop_val(mp, A->p1, pm) ? 1u : 2u;
+        } else if (kind == AK_UNTIL) {
+            const bool in_window = (t >= A->lo) && (t <= A->hi);
+            if (in_window && prop_val(mp, A->p2, pm)) v = 1u;
+            else if (!prop_val(mp, A->p1, pm)) v = 2u;
+            if (v && A->neg) v = 3u - v;
+        } else if (kind == AK_NEXT) {
+            if (k == 1u) v = prop_val(mp, A->p1, pm) ? 1u : 2u;
         } else {   // nested until
-            const int sl = A.slot;
+            const bool s0 = A->slot == 0;
             const uint32_t okb = (ms.ok >> a) & 1u;
-            double tsv = sl == 0 ? ms.ts[0] : ms.ts[1];
-            if (okb && t <= A.hi) tsv = t;                      // new admissible start
-            if (tsv >= 0.0 && prop_eval(mp, A.p3, pm)) v = 1u;
+            double tsv = s0 ? ms.ts0 : ms.ts1;
+            if (okb && t <= A->hi) tsv = t;                      // new admissible start
+            if (tsv >= 0.0 && prop_val(mp, A->p3, pm)) v = 1u;
             else {
-                if (!prop_eval(mp, A.p2, pm)) tsv = -1.0;        // inner left operand broken
-                const uint32_t ok2 = okb & (prop_eval(mp, A.p1, pm) ? 1u : 0u);
+                if (!prop_val(mp, A->p2, pm)) tsv = -1.0;        // inner left operand broken
+                const uint32_t ok2 = okb & (prop_val(mp, A->p1, pm) ? 1u : 0u);
                 ms.ok = (ms.ok & ~(1u << a)) | (ok2 << a);
                 if (tsv < 0.0 && !ok2) v = 2u;
             }
-            if (sl == 0) ms.ts[0] = tsv;
-            else ms.ts[1] = tsv;
+            if (s0) ms.ts0 = tsv;
+            else ms.ts1 = tsv;
         }
-        if (v) ms.status = put_status(ms.status, a, v);
+        mon_set(ms, a, v);
     }
-    return top_eval(mp, ms.status);
+    return top_value(mp, ms);
 }
 
 // Time is about to advance to tn (absorbing: no further state).
-__device__ __forceinline__ uint32_t mon_advance(const MonProg *mp, MonState &ms, double tn,
+__device__ __forceinline__ uint32_t mon_advance(cptr<MonProg> mp, MonState &ms, double tn,
                                                 bool absorbing)
 {
     const int na = mp->n_atoms;
-    for (int a = 0; a < na; ++a) {
-        if ((ms.status >> (2 * a)) & 3u) continue;
-        const Atom &A = mp->atoms[a];
+#pragma unroll
+    for (int a = 0; a < kMaxAtoms; ++a) {
+        if (a >= na) break;
+        if (((ms.tm | ms.fm) >> a) & 1u) continue;
+        cptr<Atom> A = &mp->atoms[a];
+        const int kind = A->kind;
         uint32_t v = 0;
-        if (A.kind == AK_UNTIL) {
-            if (absorbing || tn > A.hi) v = A.neg ? 1u : 2u;
-        } else if (A.kind == AK_NEXT) {
-            if (absorbing || !(tn >= A.lo && tn <= A.hi)) v = 2u;
-        } else if (A.kind == AK_NESTED) {
-            const int sl = A.slot;
-            double tsv = sl == 0 ? ms.ts[0] : ms.ts[1];
-            if (tsv >= 0.0 && (absorbing || tn - tsv > A.hi2)) tsv = -1.0;
+        if (kind == AK_UNTIL) {
+            if (absorbing || tn > A->hi) v = A->neg ? 1u : 2u;
+        } else if (kind == AK_NEXT) {
+            if (absorbing || !(tn >= A->lo && tn <= A->hi)) v = 2u;
+        } else if (kind == AK_NESTED) {
+            const bool s0 = A->slot == 0;
+            double tsv = s0 ? ms.ts0 : ms.ts1;
+            if (tsv >= 0.0 && (absorbing || tn - tsv > A->hi2)) tsv = -1.0;
             const uint32_t okb = (ms.ok >> a) & 1u;
-            if (tsv < 0.0 && (!okb || absorbing || tn > A.hi)) v = 2u;
-            if (sl == 0) ms.ts[0] = tsv;
-            else ms.ts[1] = tsv;
+            if (tsv < 0.0 && (!okb || absorbing || tn > A->hi)) v = 2u;
+            if (s0) ms.ts0 = tsv;
+            else ms.ts1 = tsv;
         }
-        if (v) ms.status = put_status(ms.status, a, v);
+        mon_set(ms, a, v);
     }
-    return top_eval(mp, ms.status);
+    return top_value(mp, ms);
 }
 
 __device__ __forceinline__ void mon_init(MonState &ms)
 {
-    ms.status = 0;
+    ms.tm = 0;
+    ms.fm = 0;
     ms.ok = 0xFFFFFFFFu;
-    ms.ts[0] = -1.0;
-    ms.ts[1] = -1.0;
+    ms.ts0 = -1.0;
+    ms.ts1 = -1.0;
 }
 
 // ---------------------------------------------------------------------------
 // One SSA event for this lane.  Returns the next time (inf when absorbing)
-// and, unless absorbing, leaves the selected channel in *jsel.
+// and, unless absorbing, the state change of the selected channel.
 // ---------------------------------------------------------------------------
 template <int NB>
 __device__ __forceinline__ double ssa_draw(const JobView &V, const int32_t *xs, int lane,
                                            unsigned long long abs_idx, uint32_t k, double t,
-                                           int *jsel)
+                                           Change *change)
 {
-    const int M = V.net.M;
+    const int M = V.M;
     const int nb = V.nb, bs = V.bs;
-    const int2 *reac = V.net.reac;
-    const double *rate = V.net.rate;
+    cptr<int32_t> reac = V.reac;
+    cptr<double> rate = V.rate;
     double P[NB];
     double acc = 0.0;
 #pragma unroll
@@ -464,7 +477,8 @@ __device__ __forceinline__ double ssa_draw(const JobView &V, const int32_t *xs, 
         if (q < nb) {
             const int j0 = q * bs;
             const int j1 = (j0 + bs < M) ? j0 + bs : M;
-            for (int j = j0; j < j1; ++j) acc = acc + propensity(reac[j], rate[j], xs, lane);
+            for (int j = j0; j < j1; ++j)
+                acc = acc + propensity(reac[2 * j], reac[2 * j + 1], rate[j], xs, lane);
             P[q] = acc;
         }
     }
@@ -488,35 +502,50 @@ __device__ __forceinline__ double ssa_draw(const JobView &V, const int32_t *xs, 
             found = found || hit;
         }
     }
-    if (bs == 1) {
-        *jsel = qsel;
-    } else {
+    int jsel = qsel;
+    if (bs > 1) {
         // re-run the same running sum inside the block (identical operations)
         const int j0 = qsel * bs;
         const int j1 = (j0 + bs < M) ? j0 + bs : M;
         double s = base;
-        int js = j1 - 1;
+        jsel = j1 - 1;
         bool got = false;
         for (int rr = 0; rr < bs; ++rr) {
             const int j = j0 + rr;
             if (!got && j < j1) {
-                s = s + propensity(reac[j], rate[j], xs, lane);
+                s = s + propensity(reac[2 * j], reac[2 * j + 1], rate[j], xs, lane);
                 if (s > target) {
-                    js = j;
+                    jsel = j;
                     got = true;
                 }
             }
             if (__ballot(!got) == 0) break;
         }
-        *jsel = js;
+    }
+    cptr<uint32_t> chg = V.chg;
+    if (NB <= 4) {
+        // at most four channels: pick the change among wave-uniform entries
+        Change ch{chg[0], chg[1], chg[2], chg[3]};
+#pragma unroll
+        for (int q = 1; q < NB; ++q) {
+            if (q < M && jsel == q) {
+                ch.e0 = chg[4 * q];
+                ch.e1 = chg[4 * q + 1];
+                ch.e2 = chg[4 * q + 2];
+                ch.e3 = chg[4 * q + 3];
+            }
+        }
+        *change = ch;
+    } else {
+        *change = Change{chg[4 * jsel], chg[4 * jsel + 1], chg[4 * jsel + 2], chg[4 * jsel + 3]};
     }
     const double tau = (-ctr_log(u1)) / a0;
     return t + tau;
 }
 
-__device__ __forceinline__ void apply_change(int32_t *xs, int lane, int4 ch)
+__device__ __forceinline__ void apply_change(int32_t *xs, int lane, Change ch)
 {
-    const uint32_t e[4] = {(uint32_t)ch.x, (uint32_t)ch.y, (uint32_t)ch.z, (uint32_t)ch.w};
+    const uint32_t e[4] = {ch.e0, ch.e1, ch.e2, ch.e3};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const uint32_t s = e[q] >> 16;
@@ -530,6 +559,7 @@ __device__ __forceinline__ void apply_change(int32_t *xs, int lane, int4 ch)
 __device__ unsigned long long sum_shards(unsigned long long (*arr)[kShards], int b)
 {
     unsigned long long s = 0;
+#pragma unroll 1
     for (int q = 0; q < kShards; ++q) s += ld_relaxed(&arr[b][q]);
     return s;
 }
@@ -716,7 +746,8 @@ __global__ __launch_bounds__(256) void ssa_persistent(KArgs A)
     // wave-local pool of claimed, not yet started indices [pool_next, pool_end)
     unsigned long long pool_next = 0, pool_end = 0;
     // fixed-sample jobs: per-lane counts, added to the job once per wave
-    unsigned long long my_yes = 0, my_no = 0, my_trunc = 0, my_events = 0;
+    uint32_t my_yes = 0, my_no = 0, my_trunc = 0;
+    unsigned long long my_events = 0;
 
     for (uint32_t it = 0;; ++it) {
         if ((it & 255u) == 0u) {
@@ -747,6 +778,7 @@ __global__ __launch_bounds__(256) void ssa_persistent(KArgs A)
             }
         }
         // -------- refill idle lanes with new trajectory indices --------
+        bool entered = false;   // this lane entered a state in this iteration
         const uint64_t need = __ballot(!active);
         if (need) {
             const int n_need = __popcll(need);
@@ -764,32 +796,27 @@ __global__ __launch_bounds__(256) void ssa_persistent(KArgs A)
             const int r = rank_in(need);
             if (!active && r < give) {
                 ridx = pool_next + (unsigned long long)r;
-                const int S = V.net.S;
-                for (int s = 0; s < S; ++s) xs[s * kWave + lane] = V.net.x0[s];
+                const int S = V.S;
+                for (int s = 0; s < S; ++s) xs[s * kWave + lane] = V.x0[s];
                 t = 0.0;
                 k = 0;
                 mon_init(ms);
-                const uint32_t v = mon_step(V.mon, ms, xs, lane, 0u, 0.0);
                 active = true;
-                if (v) {
-                    fin = true;
-                    verdict = (v == 1u);
-                    reason = RS_STATE;
-                }
+                entered = true;
             }
             pool_next += (unsigned long long)give;
         }
         if (__ballot(active) == 0ull) continue;
 
         // -------- one event per running lane --------
-        if (active && !fin) {
+        if (active && !entered) {
             if (V.max_events && k == V.max_events) {
                 fin = true;
                 verdict = 0;
                 reason = RS_CAP;
             } else {
-                int j = 0;
-                const double tn = ssa_draw<NB>(V, xs, lane, V.first + ridx, k, t, &j);
+                Change ch;
+                const double tn = ssa_draw<NB>(V, xs, lane, V.first + ridx, k, t, &ch);
                 const bool absorbing = isinf(tn);
                 const uint32_t v = mon_advance(V.mon, ms, tn, absorbing);
                 if (v) {
@@ -801,16 +828,20 @@ __global__ __launch_bounds__(256) void ssa_persistent(KArgs A)
                     verdict = 0;
                     reason = RS_TMAX;
                 } else {
-                    apply_change(xs, lane, V.net.chg[j]);
+                    apply_change(xs, lane, ch);
                     t = tn;
                     k = k + 1u;
-                    const uint32_t v2 = mon_step(V.mon, ms, xs, lane, k, t);
-                    if (v2) {
-                        fin = true;
-                        verdict = (v2 == 1u);
-                        reason = RS_STATE;
-                    }
+                    entered = true;
                 }
+            }
+        }
+        // -------- inspect the state just entered (new or after an event) --------
+        if (entered) {
+            const uint32_t v = mon_step(V.mon, ms, xs, lane, k, t);
+            if (v) {
+                fin = true;
+                verdict = (v == 1u);
+                reason = RS_STATE;
             }
         }
 
@@ -893,19 +924,19 @@ __global__ __launch_bounds__(256) void ssa_sample_state(const Job *jobp, double 
     V.load(jobp, 0);
     const unsigned long long c = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = c < count;
-    const int S = V.net.S;
-    for (int s = 0; s < S; ++s) xs[s * kWave + lane] = V.net.x0[s];
+    const int S = V.S;
+    for (int s = 0; s < S; ++s) xs[s * kWave + lane] = V.x0[s];
     double t = 0.0;
     uint32_t k = 0;
     bool run = live;
     while (__ballot(run) != 0ull) {
         if (run) {
-            int j = 0;
-            const double tn = ssa_draw<NB>(V, xs, lane, V.first + c, k, t, &j);
+            Change ch;
+            const double tn = ssa_draw<NB>(V, xs, lane, V.first + c, k, t, &ch);
             if (tn > T) {
                 run = false;
             } else {
-                apply_change(xs, lane, V.net.chg[j]);
+                apply_change(xs, lane, ch);
                 t = tn;
                 k = k + 1u;
             }
