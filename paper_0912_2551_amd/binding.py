@@ -15,7 +15,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsmc.so")
+# SMC_LIBRARY may name another build of the same library (tuning experiments).
+LIB_PATH = os.environ.get("SMC_LIBRARY") or os.path.join(_HERE, "libsmc.so")
 
 SMC_OK = 0
 SMC_E_INVALID = -1

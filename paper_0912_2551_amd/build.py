@@ -29,12 +29,13 @@ def _run(cmd, verbose):
     subprocess.check_call(cmd)
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 4, out: str | None = None, defines=()) -> str:
     hipcc = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
     clang = os.path.join(ROCM, "bin", "amdclang++")
     if not os.path.exists(clang):
         clang = os.path.join(ROCM, "llvm", "bin", "clang++")
-    inc = ["-I", INCLUDE, "-I", CSRC]
+    inc = ["-I", INCLUDE, "-I", CSRC] + [f"-D{d}" for d in defines]
+    lib_path = out or LIB
     tmp = tempfile.mkdtemp(prefix="smc_build_")
     try:
         procs, objs = [], []
@@ -61,12 +62,12 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
                 failed.append(" ".join(cmd))
         if failed:
             raise RuntimeError("compilation failed:\n" + "\n".join(failed))
-        out_tmp = LIB + ".tmp%d" % os.getpid()
+        out_tmp = lib_path + ".tmp%d" % os.getpid()
         _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", out_tmp], verbose)
-        os.replace(out_tmp, LIB)
+        os.replace(out_tmp, lib_path)
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
-    return LIB
+    return lib_path
 
 
 if __name__ == "__main__":

@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cctype>
+#include <climits>
+#include <cstdint>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -424,6 +426,8 @@ class Compiler {
                 if (v == 2) p_.topF[idx >> 6] |= 1ull << (idx & 63);
             }
         p_.horizon = horizon_of(root);
+        p_.all_var = 1;
+        for (int q = 0; q < p_.n_preds; ++q) p_.all_var &= p_.preds[q].kind == PK_VAR;
     }
 
   private:
@@ -642,17 +646,22 @@ class Compiler {
         auto int32_const = [](const Expr *e) {
             return e->kind == Expr::CONST && std::floor(e->c) == e->c && std::fabs(e->c) <= 2147483647.0;
         };
-        if (l->kind == Expr::VAR && int32_const(r)) {
+        if ((l->kind == Expr::VAR && int32_const(r)) || (r->kind == Expr::VAR && int32_const(l))) {
+            const bool left = l->kind == Expr::VAR;
             P.kind = PK_VAR;
-            P.var = l->var;
-            P.c32 = (int32_t)r->c;
-            return id;
-        }
-        if (r->kind == Expr::VAR && int32_const(l)) {
-            P.kind = PK_VAR;
-            P.var = r->var;
-            P.c32 = (int32_t)l->c;
-            P.op = mirror(n->cmp);
+            P.var = left ? l->var : r->var;
+            P.c32 = (int32_t)(left ? r->c : l->c);
+            P.op = left ? n->cmp : mirror(n->cmp);
+            // x op c as a range test lo <= x <= hi, possibly negated
+            const int32_t c = P.c32, mn = INT32_MIN, mx = INT32_MAX;
+            switch (P.op) {
+            case CMP_GE: P.lo32 = c; P.hi32 = mx; P.neg = 0; break;
+            case CMP_LT: P.lo32 = c; P.hi32 = mx; P.neg = 1; break;
+            case CMP_LE: P.lo32 = mn; P.hi32 = c; P.neg = 0; break;
+            case CMP_GT: P.lo32 = mn; P.hi32 = c; P.neg = 1; break;
+            case CMP_EQ: P.lo32 = c; P.hi32 = c; P.neg = 0; break;
+            default: P.lo32 = c; P.hi32 = c; P.neg = 1; break;
+            }
             return id;
         }
         std::map<int, double> w;

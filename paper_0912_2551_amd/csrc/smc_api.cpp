@@ -220,7 +220,7 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
     const unsigned long long waves_needed = (lanes_needed + kWave - 1) / kWave;
     const unsigned long long waves = std::min<unsigned long long>((unsigned long long)ctx->n_cu * wpc, waves_needed);
     const int grid = (int)std::max<unsigned long long>(1, (waves + wpb - 1) / wpb);
-    const int nb_variant = m_max <= 4 ? 4 : kBlocks;
+    const int variant = m_max <= 4 ? 0 : 1;
     res.assign(n, JobResult{});
     double total_ms = 0.0;
     const auto t_start = std::chrono::steady_clock::now();
@@ -235,7 +235,7 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
         c.open_jobs = open;
         HIP_TRY(ctx, hipMemcpyAsync(ctx->d_ctl, &c, sizeof(c), hipMemcpyHostToDevice, s));
         HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
-        HIP_TRY(ctx, launch_persistent(nb_variant, grid, wpb, lds_wave * wpb, s, ctx->d_jobs, n, s_max,
+        HIP_TRY(ctx, launch_persistent(variant, grid, wpb, lds_wave * wpb, s, ctx->d_jobs, n, s_max,
                                        ctx->d_ctl, ctx->cancel_dev, 1 << 18));
         HIP_TRY(ctx, launch_finalize(s, ctx->d_jobs, n, ctx->d_results));
         HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
@@ -621,7 +621,7 @@ int smc_sample_state(smc_ctx *c, const smc_net *net, const smc_params *p, double
     const size_t bytes = count * (size_t)net->S * sizeof(int32_t);
     if (ensure(c, c->d_rec, c->cap_rec, bytes)) return SMC_E_NOMEM;
     HIP_TRY(c, hipMemcpyAsync(c->d_jobs, &J, sizeof(J), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, launch_sample_state(net->M <= 4 ? 4 : kBlocks, c->stream, c->d_jobs, T, count,
+    HIP_TRY(c, launch_sample_state(net->M <= 4 ? 0 : 1, c->stream, c->d_jobs, T, count,
                                    (int32_t *)c->d_rec, net->S));
     HIP_TRY(c, hipMemcpyAsync(counts, c->d_rec, bytes, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));

@@ -34,6 +34,7 @@ enum Reason : int32_t { RS_STATE = 0, RS_TIME = 1, RS_ABSORB = 2, RS_CAP = 3, RS
 struct Pred {
     int32_t kind, op;
     int32_t var, c32;
+    int32_t lo32, hi32, neg;   // PK_VAR as a range test: (lo32 <= x[var] <= hi32) != neg
     int32_t nterm;
     int32_t vars[4];
     int32_t pad0;
@@ -68,7 +69,8 @@ struct Atom {
 // topT (topF) says whether the formula is already true (false) in Kleene
 // logic.
 struct MonProg {
-    int32_t n_preds, n_atoms, n_props, pad;
+    int32_t n_preds, n_atoms, n_props;
+    int32_t all_var;   // every predicate is PK_VAR
     uint64_t topT[4], topF[4];
     Atom atoms[kMaxAtoms];
     Prop props[kMaxProps];

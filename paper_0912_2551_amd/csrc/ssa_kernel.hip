@@ -238,15 +238,40 @@ struct JobView {
 };
 
 // ---------------------------------------------------------------------------
+// Species counts of one lane's trajectory: species-major / lane-minor in the
+// wave's LDS slice (consecutive lanes hit consecutive banks).
+// ---------------------------------------------------------------------------
+struct LdsCounts {
+    int32_t *xs;
+    int lane;
+    __device__ __forceinline__ int32_t get(int s) const { return xs[s * kWave + lane]; }
+    __device__ __forceinline__ void init(cptr<int32_t> x0, int S)
+    {
+        for (int s = 0; s < S; ++s) xs[s * kWave + lane] = x0[s];
+    }
+    // four packed (species, delta) entries
+    __device__ __forceinline__ void apply(uint32_t e0, uint32_t e1, uint32_t e2, uint32_t e3)
+    {
+        const uint32_t e[4] = {e0, e1, e2, e3};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t sp = e[q] >> 16;
+            if (sp != 0xFFFFu) xs[sp * kWave + lane] += (int32_t)(int16_t)(e[q] & 0xFFFFu);
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Propensities (contract: one rounding per propensity, c * h(x)).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double propensity(int ra, int rb, double c, const int32_t *xs, int lane)
+template <class C>
+__device__ __forceinline__ double propensity(int ra, int rb, double c, const C &X)
 {
     if (ra < 0) return c;
-    const int32_t xa = xs[ra * kWave + lane];
+    const int32_t xa = X.get(ra);
     if (rb < 0) return c * (double)xa;
     if (ra == rb) return c * (((double)xa * (double)(xa - 1)) * 0.5);
-    const int32_t xb = xs[rb * kWave + lane];
+    const int32_t xb = X.get(rb);
     return c * ((double)xa * (double)xb);
 }
 
@@ -264,8 +289,8 @@ struct MonState {
     double ts0, ts1;
 };
 
-__device__ __forceinline__ double val_eval(cptr<MonProg> mp, int off, int len, const int32_t *xs,
-                                           int lane)
+template <class C>
+__device__ __noinline__ double val_eval(cptr<MonProg> mp, int off, int len, const C &X)
 {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int sp = 0;
@@ -273,7 +298,7 @@ __device__ __forceinline__ double val_eval(cptr<MonProg> mp, int off, int len, c
         const int op = mp->vop[o];
         double v;
         if (op == VO_VAR || op == VO_CONST) {
-            v = (op == VO_VAR) ? (double)xs[mp->vvar[o] * kWave + lane] : mp->vconst[o];
+            v = (op == VO_VAR) ? (double)X.get(mp->vvar[o]) : mp->vconst[o];
             if (sp == 0) s0 = v;
             else if (sp == 1) s1 = v;
             else if (sp == 2) s2 = v;
@@ -317,25 +342,43 @@ __device__ __forceinline__ bool compare(T l, T r, int op)
     }
 }
 
-// Bit q of the result = truth of predicate q in the state held in xs.
-__device__ __forceinline__ uint32_t eval_preds(cptr<MonProg> mp, const int32_t *xs, int lane)
+// lo <= x <= hi as one unsigned compare, then negated when asked
+__device__ __forceinline__ bool range_test(int32_t x, cptr<Pred> p)
+{
+    const uint32_t lo = (uint32_t)p->lo32;
+    const bool in = ((uint32_t)x - lo) <= ((uint32_t)p->hi32 - lo);
+    return in != (p->neg != 0);
+}
+
+// Bit q of the result = truth of predicate q in the current state.
+template <class C>
+__device__ __forceinline__ uint32_t eval_preds(cptr<MonProg> mp, const C &X)
 {
     uint32_t pm = 0;
     const int np = mp->n_preds;
+    if (mp->all_var) {
+#pragma unroll
+        for (int q = 0; q < kMaxPreds; ++q) {
+            if (q >= np) break;
+            cptr<Pred> p = &mp->preds[q];
+            pm |= (range_test(X.get(p->var), p) ? 1u : 0u) << q;
+        }
+        return pm;
+    }
     for (int q = 0; q < np; ++q) {
         cptr<Pred> p = &mp->preds[q];
         const int kind = p->kind;
         bool r;
         if (kind == PK_VAR) {
-            r = compare<int32_t>(xs[p->var * kWave + lane], p->c32, p->op);
+            r = range_test(X.get(p->var), p);
         } else if (kind == PK_LINEAR) {
             long long v = p->c;
             const int nt = p->nterm;
-            for (int k = 0; k < nt; ++k) v += p->w[k] * (long long)xs[p->vars[k] * kWave + lane];
+            for (int k = 0; k < nt; ++k) v += p->w[k] * (long long)X.get(p->vars[k]);
             r = compare<long long>(v, 0ll, p->op);
         } else {
-            const double l = val_eval(mp, p->lhs_off, p->lhs_len, xs, lane);
-            const double rr = val_eval(mp, p->rhs_off, p->rhs_len, xs, lane);
+            const double l = val_eval(mp, p->lhs_off, p->lhs_len, X);
+            const double rr = val_eval(mp, p->rhs_off, p->rhs_len, X);
             r = compare<double>(l, rr, p->op);
         }
         pm |= (r ? 1u : 0u) << q;
@@ -376,10 +419,11 @@ __device__ __forceinline__ void mon_set(MonState &ms, int a, uint32_t v)
 }
 
 // The state just entered (index k, entry time t) is inspected.
-__device__ __forceinline__ uint32_t mon_step(cptr<MonProg> mp, MonState &ms, const int32_t *xs,
-                                             int lane, uint32_t k, double t)
+template <class C>
+__device__ __forceinline__ uint32_t mon_step(cptr<MonProg> mp, MonState &ms, const C &X, uint32_t k,
+                                             double t)
 {
-    const uint32_t pm = eval_preds(mp, xs, lane);
+    const uint32_t pm = eval_preds(mp, X);
     const int na = mp->n_atoms;
 #pragma unroll
     for (int a = 0; a < kMaxAtoms; ++a) {
@@ -460,10 +504,9 @@ __device__ __forceinline__ void mon_init(MonState &ms)
 // One SSA event for this lane.  Returns the next time (inf when absorbing)
 // and, unless absorbing, the state change of the selected channel.
 // ---------------------------------------------------------------------------
-template <int NB>
-__device__ __forceinline__ double ssa_draw(const JobView &V, const int32_t *xs, int lane,
-                                           unsigned long long abs_idx, uint32_t k, double t,
-                                           Change *change)
+template <int NB, class C>
+__device__ __forceinline__ double ssa_draw(const JobView &V, const C &X, unsigned long long abs_idx,
+                                           uint32_t k, double t, Change *change)
 {
     const int M = V.M;
     const int nb = V.nb, bs = V.bs;
@@ -471,15 +514,24 @@ __device__ __forceinline__ double ssa_draw(const JobView &V, const int32_t *xs, 
     cptr<double> rate = V.rate;
     double P[NB];
     double acc = 0.0;
+    if (NB <= 4) {
+        // at most four channels, one per block
 #pragma unroll
-    for (int q = 0; q < NB; ++q) {
-        P[q] = acc;
-        if (q < nb) {
-            const int j0 = q * bs;
-            const int j1 = (j0 + bs < M) ? j0 + bs : M;
-            for (int j = j0; j < j1; ++j)
-                acc = acc + propensity(reac[2 * j], reac[2 * j + 1], rate[j], xs, lane);
+        for (int j = 0; j < NB; ++j) {
+            if (j < M) acc = acc + propensity(reac[2 * j], reac[2 * j + 1], rate[j], X);
+            P[j] = acc;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
             P[q] = acc;
+            if (q < nb) {
+                const int j0 = q * bs;
+                const int j1 = (j0 + bs < M) ? j0 + bs : M;
+                for (int j = j0; j < j1; ++j)
+                    acc = acc + propensity(reac[2 * j], reac[2 * j + 1], rate[j], X);
+                P[q] = acc;
+            }
         }
     }
     const double a0 = acc;
@@ -503,7 +555,7 @@ __device__ __forceinline__ double ssa_draw(const JobView &V, const int32_t *xs, 
         }
     }
     int jsel = qsel;
-    if (bs > 1) {
+    if (NB > 4 && bs > 1) {
         // re-run the same running sum inside the block (identical operations)
         const int j0 = qsel * bs;
         const int j1 = (j0 + bs < M) ? j0 + bs : M;
@@ -513,7 +565,7 @@ __device__ __forceinline__ double ssa_draw(const JobView &V, const int32_t *xs, 
         for (int rr = 0; rr < bs; ++rr) {
             const int j = j0 + rr;
             if (!got && j < j1) {
-                s = s + propensity(reac[2 * j], reac[2 * j + 1], rate[j], xs, lane);
+                s = s + propensity(reac[2 * j], reac[2 * j + 1], rate[j], X);
                 if (s > target) {
                     jsel = j;
                     got = true;
@@ -522,35 +574,26 @@ __device__ __forceinline__ double ssa_draw(const JobView &V, const int32_t *xs, 
             if (__ballot(!got) == 0) break;
         }
     }
-    cptr<uint32_t> chg = V.chg;
     if (NB <= 4) {
         // at most four channels: pick the change among wave-uniform entries
-        Change ch{chg[0], chg[1], chg[2], chg[3]};
+        cptr<uint32_t> tab = V.chg;
+        Change ch{tab[0], tab[1], tab[2], tab[3]};
 #pragma unroll
         for (int q = 1; q < NB; ++q) {
             if (q < M && jsel == q) {
-                ch.e0 = chg[4 * q];
-                ch.e1 = chg[4 * q + 1];
-                ch.e2 = chg[4 * q + 2];
-                ch.e3 = chg[4 * q + 3];
+                ch.e0 = tab[4 * q];
+                ch.e1 = tab[4 * q + 1];
+                ch.e2 = tab[4 * q + 2];
+                ch.e3 = tab[4 * q + 3];
             }
         }
         *change = ch;
     } else {
+        cptr<uint32_t> chg = V.chg;
         *change = Change{chg[4 * jsel], chg[4 * jsel + 1], chg[4 * jsel + 2], chg[4 * jsel + 3]};
     }
     const double tau = (-ctr_log(u1)) / a0;
     return t + tau;
-}
-
-__device__ __forceinline__ void apply_change(int32_t *xs, int lane, Change ch)
-{
-    const uint32_t e[4] = {ch.e0, ch.e1, ch.e2, ch.e3};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const uint32_t s = e[q] >> 16;
-        if (s != 0xFFFFu) xs[s * kWave + lane] += (int32_t)(int16_t)(e[q] & 0xFFFFu);
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -722,13 +765,19 @@ __device__ __forceinline__ void add_counts(JobState *st, int b, int shard, unsig
 // ---------------------------------------------------------------------------
 // The persistent kernel.
 // ---------------------------------------------------------------------------
-template <int NB>
-__global__ __launch_bounds__(256) void ssa_persistent(KArgs A)
+#ifndef SMC_MIN_WAVES_PER_EU
+#define SMC_MIN_WAVES_PER_EU 1
+#endif
+
+template <int NB, class C>
+__global__ __launch_bounds__(256, SMC_MIN_WAVES_PER_EU) void ssa_persistent(KArgs A)
 {
     extern __shared__ int32_t lds[];
     const int lane = lane_id();
     const int wid = (int)(threadIdx.x / kWave);
-    int32_t *xs = lds + (size_t)wid * (size_t)A.s_max * kWave;
+    C X;
+    X.xs = lds + (size_t)wid * (size_t)A.s_max * kWave;
+    X.lane = lane;
     const int gwave = (int)blockIdx.x * A.waves_per_block + wid;
     const int shard = gwave & (kShards - 1);
     const int n_waves = (int)gridDim.x * A.waves_per_block;
@@ -796,8 +845,7 @@ __global__ __launch_bounds__(256) void ssa_persistent(KArgs A)
             const int r = rank_in(need);
             if (!active && r < give) {
                 ridx = pool_next + (unsigned long long)r;
-                const int S = V.S;
-                for (int s = 0; s < S; ++s) xs[s * kWave + lane] = V.x0[s];
+                X.init(V.x0, V.S);
                 t = 0.0;
                 k = 0;
                 mon_init(ms);
@@ -816,7 +864,7 @@ __global__ __launch_bounds__(256) void ssa_persistent(KArgs A)
                 reason = RS_CAP;
             } else {
                 Change ch;
-                const double tn = ssa_draw<NB>(V, xs, lane, V.first + ridx, k, t, &ch);
+                const double tn = ssa_draw<NB>(V, X, V.first + ridx, k, t, &ch);
                 const bool absorbing = isinf(tn);
                 const uint32_t v = mon_advance(V.mon, ms, tn, absorbing);
                 if (v) {
@@ -828,7 +876,7 @@ __global__ __launch_bounds__(256) void ssa_persistent(KArgs A)
                     verdict = 0;
                     reason = RS_TMAX;
                 } else {
-                    apply_change(xs, lane, ch);
+                    X.apply(ch.e0, ch.e1, ch.e2, ch.e3);
                     t = tn;
                     k = k + 1u;
                     entered = true;
@@ -837,7 +885,7 @@ __global__ __launch_bounds__(256) void ssa_persistent(KArgs A)
         }
         // -------- inspect the state just entered (new or after an event) --------
         if (entered) {
-            const uint32_t v = mon_step(V.mon, ms, xs, lane, k, t);
+            const uint32_t v = mon_step(V.mon, ms, X, k, t);
             if (v) {
                 fin = true;
                 verdict = (v == 1u);
@@ -911,7 +959,7 @@ __global__ __launch_bounds__(256) void ssa_persistent(KArgs A)
 // ---------------------------------------------------------------------------
 // SSA probe: state at time T of trajectories first .. first+count-1.
 // ---------------------------------------------------------------------------
-template <int NB>
+template <int NB, class C>
 __global__ __launch_bounds__(256) void ssa_sample_state(const Job *jobp, double T,
                                                         unsigned long long count, int32_t *out,
                                                         int s_max)
@@ -919,31 +967,33 @@ __global__ __launch_bounds__(256) void ssa_sample_state(const Job *jobp, double 
     extern __shared__ int32_t lds[];
     const int lane = lane_id();
     const int wid = (int)(threadIdx.x / kWave);
-    int32_t *xs = lds + (size_t)wid * (size_t)s_max * kWave;
+    C X;
+    X.xs = lds + (size_t)wid * (size_t)s_max * kWave;
+    X.lane = lane;
     JobView V;
     V.load(jobp, 0);
     const unsigned long long c = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = c < count;
     const int S = V.S;
-    for (int s = 0; s < S; ++s) xs[s * kWave + lane] = V.x0[s];
+    X.init(V.x0, S);
     double t = 0.0;
     uint32_t k = 0;
     bool run = live;
     while (__ballot(run) != 0ull) {
         if (run) {
             Change ch;
-            const double tn = ssa_draw<NB>(V, xs, lane, V.first + c, k, t, &ch);
+            const double tn = ssa_draw<NB>(V, X, V.first + c, k, t, &ch);
             if (tn > T) {
                 run = false;
             } else {
-                apply_change(xs, lane, ch);
+                X.apply(ch.e0, ch.e1, ch.e2, ch.e3);
                 t = tn;
                 k = k + 1u;
             }
         }
     }
     if (live)
-        for (int s = 0; s < S; ++s) out[c * (unsigned long long)S + s] = xs[s * kWave + lane];
+        for (int s = 0; s < S; ++s) out[c * (unsigned long long)S + s] = X.get(s);
 }
 
 // Reset per-job accounting: batch 0 ends at n_first, which is also the first
@@ -1005,7 +1055,8 @@ __global__ void wilson_table(const unsigned long long *yes, const unsigned long 
 // ---------------------------------------------------------------------------
 namespace smc {
 
-hipError_t launch_persistent(int nb_variant, int grid, int waves_per_block, size_t lds_bytes,
+// variant: 0 = at most 4 reaction channels, 1 = any network
+hipError_t launch_persistent(int variant, int grid, int waves_per_block, size_t lds_bytes,
                              hipStream_t stream, const Job *jobs, int n_jobs, int s_max,
                              Control *ctl, const volatile int32_t *cancel, int spin_limit)
 {
@@ -1018,25 +1069,25 @@ hipError_t launch_persistent(int nb_variant, int grid, int waves_per_block, size
     a.spin_limit = spin_limit;
     a.waves_per_block = waves_per_block;
     const dim3 block(kWave * waves_per_block);
-    if (nb_variant <= 4)
-        hipLaunchKernelGGL(ssa_persistent<4>, dim3(grid), block, lds_bytes, stream, a);
+    if (variant == 0)
+        hipLaunchKernelGGL((ssa_persistent<4, LdsCounts>), dim3(grid), block, lds_bytes, stream, a);
     else
-        hipLaunchKernelGGL(ssa_persistent<kBlocks>, dim3(grid), block, lds_bytes, stream, a);
+        hipLaunchKernelGGL((ssa_persistent<kBlocks, LdsCounts>), dim3(grid), block, lds_bytes, stream, a);
     return hipGetLastError();
 }
 
-hipError_t launch_sample_state(int nb_variant, hipStream_t stream, const Job *job, double T,
+hipError_t launch_sample_state(int variant, hipStream_t stream, const Job *job, double T,
                                unsigned long long count, int32_t *out, int s_max)
 {
     const int threads = kWave;
     const unsigned long long blocks = (count + threads - 1) / threads;
     const size_t lds = (size_t)s_max * kWave * sizeof(int32_t);
-    if (nb_variant <= 4)
-        hipLaunchKernelGGL(ssa_sample_state<4>, dim3((unsigned)blocks), dim3(threads), lds, stream,
-                           job, T, count, out, s_max);
-    else
-        hipLaunchKernelGGL(ssa_sample_state<kBlocks>, dim3((unsigned)blocks), dim3(threads), lds,
+    if (variant == 0)
+        hipLaunchKernelGGL((ssa_sample_state<4, LdsCounts>), dim3((unsigned)blocks), dim3(threads), lds,
                            stream, job, T, count, out, s_max);
+    else
+        hipLaunchKernelGGL((ssa_sample_state<kBlocks, LdsCounts>), dim3((unsigned)blocks), dim3(threads),
+                           lds, stream, job, T, count, out, s_max);
     return hipGetLastError();
 }
 
