@@ -10,7 +10,11 @@ trajectories per second, the roofline fraction of the dominant kernel (VALU
 issue slots, from HIP-event kernel time), the CPU oracle timed on the host,
 and the iterative-Wilson immigration-death run (95%, +-0.01).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+The surrogate section answers 10^6 Michaelis-Menten rate points (both the
+workload formula and F[0,60](P>=575)) with surrogate + fallback and reports
+the time against plain batched SMC at 95% +-0.01.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-surrogate]
        python bench.py --copy-calibration   (HBM counter calibration copy)
 """
 import argparse
@@ -54,6 +58,72 @@ def cpu_baseline(net, text, sample):
                       f"{dt:.2f} s, {sample / dt:.0f} trajectories/s"}
 
 
+def surrogate_vs_plain(ctx, B, W, text, n_train=512, n_query=10**6, n_sub=4096, eps=0.01, margin=0.05,
+                       steps=2000):
+    """Answer n_query rate points either with plain batched SMC or with the
+    surrogate (plain SMC on n_train sweep points, training, one fused query
+    launch) plus SMC fallback on the points the gate rejects.  Plain SMC is
+    timed on the first n_sub query points (a uniform subsample, the points are
+    i.i.d.) and scaled to n_query; the fallback is timed the same way, as one
+    batch of the subsample's rejected points, scaled likewise."""
+    import torch
+    import numpy as np
+    keep = []
+
+    def jobs_for(rates, seed):
+        jobs = []
+        for k, rr in enumerate(rates):
+            nh = ctx.network(W.michaelis_menten(*rr))
+            fh = ctx.formula(nh, text)
+            keep.append((nh, fh))
+            jobs.append((nh, fh, B.params(confidence=0.95, half_width=eps, seed=seed, model_id=k)))
+        return jobs
+
+    train = W.mm_sweep(n_train, seed=4)
+    jt = jobs_for(train, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ctx.estimate_batch(jt)
+    t_train_smc = time.perf_counter() - t0
+    x = np.log10(train).astype(np.float32)
+    y = np.array([r["p_hat"] for r in res], dtype=np.float32)
+    w = np.array([r["n"] for r in res], dtype=np.float32)
+    t0 = time.perf_counter()
+    sg = B.Surrogate(ctx, seed=4)
+    losses = sg.train(x, y, w, steps=steps, lr=2e-3)
+    t_fit = time.perf_counter() - t0
+    q = W.surrogate_queries(n_query, seed=6)
+    sg.query(q[:4096], margin=margin)
+    t0 = time.perf_counter()
+    p, use = sg.query(q, margin=margin)
+    t_query = time.perf_counter() - t0
+    js = jobs_for(10.0 ** q[:n_sub].astype(np.float64), 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = ctx.estimate_batch(js)
+    t_sub = time.perf_counter() - t0
+    u = use[:n_sub]
+    jf = [j for j, ui in zip(js, u) if not ui]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if jf:
+        ctx.estimate_batch(jf)
+    t_fallback_sub = time.perf_counter() - t0
+    plain_total = t_sub * n_query / n_sub
+    fallback_total = t_fallback_sub * n_query / n_sub
+    sur_total = t_train_smc + t_fit + t_query + fallback_total
+    err = np.array([max(r["lo"] - pi, pi - r["hi"], 0.0) for r, pi, ui in zip(plain, p[:n_sub], u) if ui])
+    return {"formula": text, "queries": n_query, "train_points": n_train, "subsample": n_sub,
+            "plain_seconds_scaled": plain_total, "surrogate_plus_fallback_seconds": sur_total,
+            "speedup": plain_total / sur_total, "surrogate_share": float(use.mean()),
+            "train_smc_seconds": t_train_smc, "fit_seconds": t_fit, "fit_steps": steps,
+            "final_loss": float(losses[-1]), "query_seconds": t_query,
+            "query_points_per_s": n_query / t_query, "fallback_seconds_scaled": fallback_total,
+            "error_vs_wilson": {"answered": int(err.size), "inside_interval": float(np.mean(err == 0)) if err.size else None,
+                                "within_margin": float(np.mean(err <= margin)) if err.size else None,
+                                "max_outside": float(err.max()) if err.size else None}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +131,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-c1", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=N_TRAJ)
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true")
@@ -147,6 +218,9 @@ def main():
                              "n": r1["n"], "batches": r1["batches"], "p_hat": r1["p_hat"],
                              "interval": [r1["lo"], r1["hi"]], "seconds": w1,
                              "verified_trajectories_per_s": r1["n"] / w1, "events_per_s": r1["events"] / w1}
+    if not args.no_surrogate:
+        line["surrogate_vs_plain"] = [surrogate_vs_plain(ctx, B, W, t)
+                                      for t in (W.C2_FORMULA, W.MM_COMPANION_FORMULA)]
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(net, W.C2_FORMULA, args.cpu_sample)
     print(json.dumps(line), flush=True)

@@ -202,6 +202,54 @@ void smc_wilson_interval(uint64_t k, uint64_t n, double z, double *lo, double *h
 int smc_wilson_next_device(smc_ctx *ctx, const uint64_t *successes, const uint64_t *n, size_t count,
                            double eps, double z, uint32_t flags, uint64_t *out);
 
+/* ---- surrogate: learned p(rate constants) (MLP 3-256-256-1) -------------
+ * A small network maps log10 rate constants (3 per point) to the estimated
+ * satisfaction probability.  It is trained on estimates produced by
+ * smc_estimate_batch over a parameter sweep, and answers a query only where it
+ * is confident: inside the 3-D convex hull of the training points and at
+ * least `margin` away from the query threshold; elsewhere the caller runs
+ * plain SMC (the fallback that also measures the surrogate's error).
+ * Arithmetic: BF16 weights and activations, FP32 accumulation on the GPU's
+ * matrix cores (MFMA), FP32 master weights trained with Adam on the GPU.
+ * Parameter vector (FP32): W1[256][3], b1[256], W2[256][256] (output-major),
+ * b2[256], W3[256], b3, then mu[3], sigma[3] (input standardisation);
+ * smc_surrogate_param_count() values in all. */
+typedef struct smc_surrogate smc_surrogate;
+typedef struct {
+    uint32_t steps;   /* full-batch Adam steps                              */
+    float lr;         /* learning rate (> 0)                                */
+    float beta1;      /* Adam moments (0: 0.9 / 0.999); eps (0: 1e-8)       */
+    float beta2;
+    float adam_eps;
+} smc_train_opts;
+/* Seeded Glorot-uniform weights, zero biases, identity standardisation. */
+int smc_surrogate_create(smc_ctx *ctx, uint64_t seed, smc_surrogate **out);
+size_t smc_surrogate_param_count(void);
+int smc_surrogate_set_params(smc_surrogate *s, const float *params, size_t count);
+int smc_surrogate_get_params(const smc_surrogate *s, float *params, size_t count);
+/* One forward and backward pass over n points: x[n][3] log10 rates, y[n]
+ * target probabilities, w[n] weights (NULL: 1).  loss = sum_i w_i BCE(p_i,
+ * y_i) / sum_i w_i; grads (optional) receives d loss / d params for the
+ * first param_count - 6 values. */
+int smc_surrogate_gradients(smc_surrogate *s, const float *x, const float *y, const float *w, size_t n,
+                            float *loss, float *grads);
+/* Set the standardisation and the training hull from x, then run
+ * opts->steps Adam steps on the loss above; loss_out[steps] optional. */
+int smc_surrogate_train(smc_surrogate *s, const float *x, const float *y, const float *w, size_t n,
+                        const smc_train_opts *opts, float *loss_out);
+/* p_out[k] = network output at x[k]; use_surrogate[k] (optional) = 1 when
+ * x[k] lies in the training hull and |p_out[k] - threshold| >= margin. */
+int smc_surrogate_query(smc_surrogate *s, const float *x, size_t n, float threshold, float margin,
+                        float *p_out, uint8_t *use_surrogate);
+/* Facets of the training hull as planes (nx, ny, nz, d), inside: n.x <= d.
+ * Writes up to cap planes; returns the number of facets. */
+int smc_surrogate_hull(const smc_surrogate *s, float *planes, size_t cap);
+void smc_surrogate_destroy(smc_surrogate *s);
+/* The same hull construction without a context (host only): planes of the
+ * convex hull of pts[n][3]; returns the number of facets (0 if the points
+ * span less than three dimensions), writing up to cap planes. */
+int smc_convex_hull(const float *pts, size_t n, float *planes, size_t cap);
+
 #ifdef __cplusplus
 }
 #endif

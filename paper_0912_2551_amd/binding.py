@@ -36,7 +36,10 @@ EXPORTS = [
     "smc_net_set_rates", "smc_net_destroy", "smc_formula_compile", "smc_formula_horizon",
     "smc_formula_destroy", "smc_estimate", "smc_estimate_batch", "smc_trajectories",
     "smc_sample_state", "smc_z_value", "smc_wilson_sample_value", "smc_wilson_sample",
-    "smc_wilson_interval", "smc_wilson_next_device",
+    "smc_wilson_interval", "smc_wilson_next_device", "smc_surrogate_create",
+    "smc_surrogate_param_count", "smc_surrogate_set_params", "smc_surrogate_get_params",
+    "smc_surrogate_gradients", "smc_surrogate_train", "smc_surrogate_query", "smc_surrogate_hull",
+    "smc_surrogate_destroy", "smc_convex_hull",
 ]
 
 
@@ -74,6 +77,11 @@ class Result(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_uint32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float)]
 
 
 class JobDesc(ctypes.Structure):
@@ -121,6 +129,23 @@ def lib():
             "smc_wilson_next_device": (i32, [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
                                              ctypes.c_size_t, dbl, dbl, ctypes.c_uint32,
                                              ctypes.POINTER(ctypes.c_uint64)]),
+            "smc_surrogate_create": (i32, [vp, u64, ctypes.POINTER(vp)]),
+            "smc_surrogate_param_count": (ctypes.c_size_t, []),
+            "smc_surrogate_set_params": (i32, [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
+            "smc_surrogate_get_params": (i32, [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
+            "smc_surrogate_gradients": (i32, [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                              ctypes.POINTER(ctypes.c_float), ctypes.c_size_t,
+                                              ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+            "smc_surrogate_train": (i32, [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                          ctypes.POINTER(ctypes.c_float), ctypes.c_size_t,
+                                          ctypes.POINTER(TrainOpts), ctypes.POINTER(ctypes.c_float)]),
+            "smc_surrogate_query": (i32, [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t, ctypes.c_float,
+                                          ctypes.c_float, ctypes.POINTER(ctypes.c_float),
+                                          ctypes.POINTER(ctypes.c_uint8)]),
+            "smc_surrogate_hull": (i32, [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
+            "smc_surrogate_destroy": (None, [vp]),
+            "smc_convex_hull": (i32, [ctypes.POINTER(ctypes.c_float), ctypes.c_size_t,
+                                      ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -303,3 +328,81 @@ def wilson_interval(k: int, n: int, z: float):
     lo, hi = ctypes.c_double(), ctypes.c_double()
     lib().smc_wilson_interval(k, n, z, ctypes.byref(lo), ctypes.byref(hi))
     return lo.value, hi.value
+
+
+def convex_hull(points) -> np.ndarray:
+    """Facet planes (nx, ny, nz, d) of the convex hull of points [n, 3]."""
+    pts = np.ascontiguousarray(points, dtype=np.float32)
+    n = pts.shape[0]
+    nf = lib().smc_convex_hull(_ptr(pts, ctypes.c_float), n, None, 0)
+    out = np.zeros((max(nf, 0), 4), dtype=np.float32)
+    if nf > 0:
+        lib().smc_convex_hull(_ptr(pts, ctypes.c_float), n, _ptr(out, ctypes.c_float), nf)
+    return out
+
+
+class Surrogate:
+    """MLP surrogate p(log10 rates) trained and evaluated by the library."""
+
+    def __init__(self, ctx: Context, seed: int = 0):
+        self.ctx = ctx
+        out = ctypes.c_void_p()
+        ctx._check(lib().smc_surrogate_create(ctx.h, seed, ctypes.byref(out)))
+        self.h = out
+        self.n_params = int(lib().smc_surrogate_param_count())
+
+    def get_params(self) -> np.ndarray:
+        p = np.zeros(self.n_params, dtype=np.float32)
+        self.ctx._check(lib().smc_surrogate_get_params(self.h, _ptr(p, ctypes.c_float), self.n_params))
+        return p
+
+    def set_params(self, p):
+        q = np.ascontiguousarray(p, dtype=np.float32)
+        self.ctx._check(lib().smc_surrogate_set_params(self.h, _ptr(q, ctypes.c_float), q.size))
+
+    def gradients(self, x, y, w=None):
+        xx = np.ascontiguousarray(x, dtype=np.float32)
+        yy = np.ascontiguousarray(y, dtype=np.float32)
+        ww = None if w is None else np.ascontiguousarray(w, dtype=np.float32)
+        loss = ctypes.c_float()
+        g = np.zeros(self.n_params - 6, dtype=np.float32)
+        self.ctx._check(lib().smc_surrogate_gradients(
+            self.h, _ptr(xx, ctypes.c_float), _ptr(yy, ctypes.c_float),
+            None if ww is None else _ptr(ww, ctypes.c_float), xx.shape[0], ctypes.byref(loss),
+            _ptr(g, ctypes.c_float)))
+        return loss.value, g
+
+    def train(self, x, y, w=None, steps=2000, lr=1e-3):
+        xx = np.ascontiguousarray(x, dtype=np.float32)
+        yy = np.ascontiguousarray(y, dtype=np.float32)
+        ww = None if w is None else np.ascontiguousarray(w, dtype=np.float32)
+        losses = np.zeros(steps, dtype=np.float32)
+        opts = TrainOpts(steps, lr, 0.0, 0.0, 0.0)
+        self.ctx._check(lib().smc_surrogate_train(
+            self.h, _ptr(xx, ctypes.c_float), _ptr(yy, ctypes.c_float),
+            None if ww is None else _ptr(ww, ctypes.c_float), xx.shape[0], ctypes.byref(opts),
+            _ptr(losses, ctypes.c_float)))
+        return losses
+
+    def query(self, x, threshold=0.5, margin=0.05):
+        xx = np.ascontiguousarray(x, dtype=np.float32)
+        n = xx.shape[0]
+        p = np.zeros(n, dtype=np.float32)
+        use = np.zeros(n, dtype=np.uint8)
+        self.ctx._check(lib().smc_surrogate_query(self.h, _ptr(xx, ctypes.c_float), n, threshold, margin,
+                                                  _ptr(p, ctypes.c_float), _ptr(use, ctypes.c_uint8)))
+        return p, use.astype(bool)
+
+    def hull(self) -> np.ndarray:
+        nf = lib().smc_surrogate_hull(self.h, None, 0)
+        out = np.zeros((max(nf, 0), 4), dtype=np.float32)
+        if nf > 0:
+            lib().smc_surrogate_hull(self.h, _ptr(out, ctypes.c_float), nf)
+        return out
+
+    def __del__(self):
+        try:
+            if self.h and self.ctx.h:
+                lib().smc_surrogate_destroy(self.h)
+        except Exception:
+            pass

@@ -19,8 +19,8 @@ LIB = os.path.join(HERE, "libsmc.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = os.environ.get("SMC_OFFLOAD_ARCH", "gfx950")
 
-DEVICE_SOURCES = ["ssa_kernel.hip"]
-HOST_SOURCES = ["smc_api.cpp", "formula.cpp"]
+DEVICE_SOURCES = ["ssa_kernel.hip", "surrogate.hip"]
+HOST_SOURCES = ["smc_api.cpp", "formula.cpp", "surrogate_api.cpp", "hull.cpp"]
 
 
 def _run(cmd, verbose):

@@ -301,6 +301,13 @@ void fill_result(const JobResult &r, double z, smc_result *out)
 
 }  // namespace
 
+// Accessors used by the surrogate's translation unit.
+namespace smc {
+int set_ctx_error(smc_ctx *ctx, int code, const std::string &msg) { return fail(ctx, code, msg); }
+hipStream_t ctx_stream(smc_ctx *ctx) { return ctx->stream; }
+int ctx_device(smc_ctx *ctx) { return ctx->device; }
+}  // namespace smc
+
 // ===========================================================================
 // C ABI
 // ===========================================================================

@@ -1,0 +1,366 @@
+// surrogate.hip -- MLP surrogate p(rates) on gfx950: BF16 operands, FP32
+// accumulation on MFMA (v_mfma_f32_32x32x16_bf16), trained on the GPU.
+//
+// Network: 3 -> 256 -> 256 -> 1, ReLU hidden units, sigmoid output, inputs
+// standardised log10 rate constants.  Numeric contract:
+//   - matrix operands are BF16 (round to nearest even from FP32): the
+//     standardised inputs xb, the weights W1b, W2b, W3b, the activations h1b,
+//     h2b and the layer-2 error d2b;
+//   - every product-sum accumulates in FP32; biases, losses, gradients and
+//     the Adam state are FP32; FP32 master weights are rounded to BF16 after
+//     every update;
+//   - batch sums run in index order (no atomics), so results are repeatable.
+// Layer 2 (K = 256) and its two backward products run on MFMA; layers 1
+// (K = 3) and 3 (N = 1) are vector work.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace smc {
+
+constexpr int kH = 256;   // hidden width
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// FP32 -> BF16 bits, round to nearest, ties to even (finite inputs).
+__device__ __forceinline__ uint16_t to_bf16(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    const uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(r >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// ---------------------------------------------------------------------------
+// C(m, n) = sum_k A(m, k) B(k, n) for BF16 A, B given by strides, FP32 C
+// (row-major, ldc), optionally added to C.  M, N multiples of 32, K of 16;
+// one wave per 32 x 32 tile of C.  Lane l holds row/column l % 32 and the
+// k-slice 8 (l / 32) .. 8 (l / 32) + 7 of each 16-wide step for both
+// operands; the 16 results of lane l are rows 8 (r / 4) + 4 (l / 32) + r % 4
+// of column l % 32.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void gemm_bf16(const uint16_t *A, long sam, long sak,
+                                                 const uint16_t *B, long sbk, long sbn, float *C,
+                                                 long ldc, int M, int N, int K, int accumulate)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const int wave = (int)(blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
+    const int tiles_n = N / 32;
+    const int tm = wave / tiles_n, tn = wave % tiles_n;
+    if (tm >= M / 32) return;
+    const int rc = lane & 31, half = lane >> 5;
+    const long arow = (long)(tm * 32 + rc) * sam;
+    const long bcol = (long)(tn * 32 + rc) * sbn;
+    floatx16 acc = {};
+    for (int kb = 0; kb < K; kb += 16) {
+        bf16x8 a, b;
+        const int k0 = kb + 8 * half;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            a[e] = __builtin_bit_cast(__bf16, A[arow + (long)(k0 + e) * sak]);
+            b[e] = __builtin_bit_cast(__bf16, B[(long)(k0 + e) * sbk + bcol]);
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const long row = tm * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+        float *c = &C[row * ldc + tn * 32 + rc];
+        *c = accumulate ? *c + acc[r] : acc[r];
+    }
+}
+
+// xb = bf16((x - mu) / sigma); pre1 = b1 + xb . W1b; h1b = bf16(relu(pre1)).
+// One thread per (row, unit).
+__global__ void layer1_forward(const float *x, int n, const float *mu, const float *sigma,
+                               const uint16_t *W1b, const float *b1, uint16_t *xb, float *pre1,
+                               uint16_t *h1b)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long row = t / kH;
+    const int j = (int)(t % kH);
+    if (row >= n) return;
+    float acc = b1[j];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const uint16_t xk = to_bf16((x[row * 3 + k] - mu[k]) / sigma[k]);
+        if (j == 0) xb[row * 3 + k] = xk;
+        acc = fmaf(from_bf16(xk), from_bf16(W1b[j * 3 + k]), acc);
+    }
+    pre1[row * kH + j] = acc;
+    h1b[row * kH + j] = to_bf16(acc > 0.0f ? acc : 0.0f);
+}
+
+// pre2 += b2 (pre2 holds the product); h2b = bf16(relu(pre2)).
+__global__ void layer2_epilogue(float *pre2, int n, const float *b2, uint16_t *h2b)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)n * kH) return;
+    const float v = pre2[t] + b2[t % kH];
+    pre2[t] = v;
+    h2b[t] = to_bf16(v > 0.0f ? v : 0.0f);
+}
+
+// Per row: z = b3 + sum_j h2b W3b (j in order), p = sigmoid(z), weighted
+// binary cross-entropy against the soft target y, dz = w (p - y) / sum w.
+__global__ void layer3_forward_loss(const uint16_t *h2b, int n, const uint16_t *W3b, const float *b3,
+                                    const float *y, const float *w, float inv_wsum, float *p_out,
+                                    float *loss_row, float *dz)
+{
+    const int row = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (row >= n) return;
+    float z = b3[0];
+    for (int j = 0; j < kH; ++j) z = fmaf(from_bf16(h2b[(long)row * kH + j]), from_bf16(W3b[j]), z);
+    const float p = 1.0f / (1.0f + expf(-z));
+    if (p_out) p_out[row] = p;
+    if (y) {
+        const float yy = y[row], ww = w[row];
+        // log(1 + e^-|z|) + max(z, 0) - z y  (stable form of the cross-entropy)
+        const float l = fmaxf(z, 0.0f) - z * yy + log1pf(expf(-fabsf(z)));
+        loss_row[row] = ww * l * inv_wsum;
+        dz[row] = ww * (p - yy) * inv_wsum;
+    }
+}
+
+// Column sums over rows in order: dW3[j] = sum_b dz_b h2b[b][j], db3 = sum dz;
+// d2 = dz W3b relu'(pre2), d2b = bf16(d2).
+__global__ void layer3_backward(const uint16_t *h2b, const float *pre2, int n, const uint16_t *W3b,
+                                const float *dz, float *dW3, float *db3, float *d2, uint16_t *d2b)
+{
+    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (j >= kH) return;
+    const float w3 = from_bf16(W3b[j]);
+    float s = 0.0f, sz = 0.0f;
+    for (int b = 0; b < n; ++b) {
+        const long t = (long)b * kH + j;
+        const float g = dz[b];
+        s = fmaf(g, from_bf16(h2b[t]), s);
+        sz += g;
+        const float d = pre2[t] > 0.0f ? g * w3 : 0.0f;
+        d2[t] = d;
+        d2b[t] = to_bf16(d);
+    }
+    dW3[j] = s;
+    if (j == 0) db3[0] = sz;
+}
+
+// db2[j] = sum_b d2[b][j].
+__global__ void column_sum(const float *a, int n, float *out)
+{
+    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (j >= kH) return;
+    float s = 0.0f;
+    for (int b = 0; b < n; ++b) s += a[(long)b * kH + j];
+    out[j] = s;
+}
+
+// d1 = dh1 relu'(pre1); dW1[j][k] = sum_b d1 xb[b][k]; db1[j] = sum_b d1.
+__global__ void layer1_backward(const float *dh1, const float *pre1, const uint16_t *xb, int n,
+                                float *dW1, float *db1)
+{
+    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (j >= kH) return;
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, sb = 0.0f;
+    for (int b = 0; b < n; ++b) {
+        const long t = (long)b * kH + j;
+        const float d = pre1[t] > 0.0f ? dh1[t] : 0.0f;
+        s0 = fmaf(d, from_bf16(xb[b * 3 + 0]), s0);
+        s1 = fmaf(d, from_bf16(xb[b * 3 + 1]), s1);
+        s2 = fmaf(d, from_bf16(xb[b * 3 + 2]), s2);
+        sb += d;
+    }
+    dW1[j * 3 + 0] = s0;
+    dW1[j * 3 + 1] = s1;
+    dW1[j * 3 + 2] = s2;
+    db1[j] = sb;
+}
+
+// Adam on FP32 masters; BF16 copies of the weight matrices refreshed.
+__global__ void adam_update(float *w, const float *g, float *m, float *v, uint16_t *wb, long count,
+                            float lr, float beta1, float beta2, float eps, float bc1, float bc2)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
+    const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    w[i] = wi;
+    if (wb) wb[i] = to_bf16(wi);
+}
+
+__global__ void round_bf16(const float *w, uint16_t *wb, long count)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) wb[i] = to_bf16(w[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Inference + gate: 32 points per block of 256 threads.  Layer 1 into LDS as
+// BF16, layer 2 on MFMA (wave w owns output columns 64 w .. 64 w + 63), layer
+// 3 products staged in LDS and summed per point in column order.  A point
+// uses the surrogate when it lies in the training hull (n.x <= d for every
+// facet, in log10-rate space) and |p - threshold| >= margin.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void mlp_query(const float *x, long n, const float *mu,
+                                                 const float *sigma, const uint16_t *W1b,
+                                                 const float *b1, const uint16_t *W2b,
+                                                 const float *b2, const uint16_t *W3b,
+                                                 const float *b3, const float *planes, int n_planes,
+                                                 float hull_tol, float threshold, float margin,
+                                                 float *p_out, uint8_t *use)
+{
+    __shared__ uint16_t h1s[32 * kH];
+    __shared__ float prod[32 * kH];
+    __shared__ float xs[32 * 3];
+    const int tid = (int)threadIdx.x;
+    const long base = (long)blockIdx.x * 32;
+    if (tid < 96) {
+        const long row = base + tid / 3;
+        xs[tid] = row < n ? x[row * 3 + tid % 3] : 0.0f;
+    }
+    __syncthreads();
+    {
+        const int j = tid;
+        float w0 = from_bf16(W1b[j * 3]), w1 = from_bf16(W1b[j * 3 + 1]), w2 = from_bf16(W1b[j * 3 + 2]);
+        const float bj = b1[j];
+        for (int r = 0; r < 32; ++r) {
+            float acc = bj;
+            acc = fmaf(from_bf16(to_bf16((xs[r * 3 + 0] - mu[0]) / sigma[0])), w0, acc);
+            acc = fmaf(from_bf16(to_bf16((xs[r * 3 + 1] - mu[1]) / sigma[1])), w1, acc);
+            acc = fmaf(from_bf16(to_bf16((xs[r * 3 + 2] - mu[2]) / sigma[2])), w2, acc);
+            h1s[r * kH + j] = to_bf16(acc > 0.0f ? acc : 0.0f);
+        }
+    }
+    __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6;
+    const int rc = lane & 31, half = lane >> 5;
+#pragma unroll
+    for (int tile = 0; tile < 2; ++tile) {
+        const int col = wave * 64 + tile * 32 + rc;   // output unit of this lane
+        floatx16 acc = {};
+        for (int kb = 0; kb < kH; kb += 16) {
+            bf16x8 a, b;
+            const int k0 = kb + 8 * half;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                a[e] = __builtin_bit_cast(__bf16, h1s[rc * kH + k0 + e]);
+                b[e] = __builtin_bit_cast(__bf16, W2b[(long)col * kH + k0 + e]);
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+        const float b2c = b2[col];
+        const float w3 = from_bf16(W3b[col]);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = 8 * (r / 4) + 4 * half + (r % 4);
+            const float v = acc[r] + b2c;
+            prod[row * kH + col] = from_bf16(to_bf16(v > 0.0f ? v : 0.0f)) * w3;
+        }
+    }
+    __syncthreads();
+    if (tid < 32) {
+        const long row = base + tid;
+        float z = b3[0];
+        for (int j = 0; j < kH; ++j) z += prod[tid * kH + j];
+        const float p = 1.0f / (1.0f + expf(-z));
+        if (row < n) {
+            p_out[row] = p;
+            if (use) {
+                bool inside = n_planes > 0;
+                for (int f = 0; f < n_planes && inside; ++f) {
+                    const float *pl = planes + 4 * f;
+                    const float v = pl[0] * xs[tid * 3] + pl[1] * xs[tid * 3 + 1] + pl[2] * xs[tid * 3 + 2];
+                    inside = v <= pl[3] + hull_tol;
+                }
+                use[row] = (inside && fabsf(p - threshold) >= margin) ? 1 : 0;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch helpers.
+// ---------------------------------------------------------------------------
+static unsigned blocks_for(long n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+hipError_t sg_gemm(hipStream_t s, const uint16_t *A, long sam, long sak, const uint16_t *B, long sbk,
+                   long sbn, float *C, long ldc, int M, int N, int K, int accumulate)
+{
+    const long waves = (long)(M / 32) * (N / 32);
+    hipLaunchKernelGGL(gemm_bf16, dim3(blocks_for(waves, 4)), dim3(256), 0, s, A, sam, sak, B, sbk, sbn,
+                       C, ldc, M, N, K, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t sg_layer1_forward(hipStream_t s, const float *x, int n, const float *mu, const float *sigma,
+                             const uint16_t *W1b, const float *b1, uint16_t *xb, float *pre1, uint16_t *h1b)
+{
+    hipLaunchKernelGGL(layer1_forward, dim3(blocks_for((long)n * kH, 256)), dim3(256), 0, s, x, n, mu,
+                       sigma, W1b, b1, xb, pre1, h1b);
+    return hipGetLastError();
+}
+
+hipError_t sg_layer2_epilogue(hipStream_t s, float *pre2, int n, const float *b2, uint16_t *h2b)
+{
+    hipLaunchKernelGGL(layer2_epilogue, dim3(blocks_for((long)n * kH, 256)), dim3(256), 0, s, pre2, n, b2, h2b);
+    return hipGetLastError();
+}
+
+hipError_t sg_layer3_forward_loss(hipStream_t s, const uint16_t *h2b, int n, const uint16_t *W3b,
+                                  const float *b3, const float *y, const float *w, float inv_wsum,
+                                  float *p_out, float *loss_row, float *dz)
+{
+    hipLaunchKernelGGL(layer3_forward_loss, dim3(blocks_for(n, 256)), dim3(256), 0, s, h2b, n, W3b, b3, y, w,
+                       inv_wsum, p_out, loss_row, dz);
+    return hipGetLastError();
+}
+
+hipError_t sg_layer3_backward(hipStream_t s, const uint16_t *h2b, const float *pre2, int n,
+                              const uint16_t *W3b, const float *dz, float *dW3, float *db3, float *d2,
+                              uint16_t *d2b)
+{
+    hipLaunchKernelGGL(layer3_backward, dim3(1), dim3(kH), 0, s, h2b, pre2, n, W3b, dz, dW3, db3, d2, d2b);
+    return hipGetLastError();
+}
+
+hipError_t sg_column_sum(hipStream_t s, const float *a, int n, float *out)
+{
+    hipLaunchKernelGGL(column_sum, dim3(1), dim3(kH), 0, s, a, n, out);
+    return hipGetLastError();
+}
+
+hipError_t sg_layer1_backward(hipStream_t s, const float *dh1, const float *pre1, const uint16_t *xb, int n,
+                              float *dW1, float *db1)
+{
+    hipLaunchKernelGGL(layer1_backward, dim3(1), dim3(kH), 0, s, dh1, pre1, xb, n, dW1, db1);
+    return hipGetLastError();
+}
+
+hipError_t sg_adam(hipStream_t s, float *w, const float *g, float *m, float *v, uint16_t *wb, long count,
+                   float lr, float beta1, float beta2, float eps, float bc1, float bc2)
+{
+    hipLaunchKernelGGL(adam_update, dim3(blocks_for(count, 256)), dim3(256), 0, s, w, g, m, v, wb, count, lr,
+                       beta1, beta2, eps, bc1, bc2);
+    return hipGetLastError();
+}
+
+hipError_t sg_round(hipStream_t s, const float *w, uint16_t *wb, long count)
+{
+    hipLaunchKernelGGL(round_bf16, dim3(blocks_for(count, 256)), dim3(256), 0, s, w, wb, count);
+    return hipGetLastError();
+}
+
+hipError_t sg_query(hipStream_t s, const float *x, long n, const float *mu, const float *sigma,
+                    const uint16_t *W1b, const float *b1, const uint16_t *W2b, const float *b2,
+                    const uint16_t *W3b, const float *b3, const float *planes, int n_planes, float hull_tol,
+                    float threshold, float margin, float *p_out, uint8_t *use)
+{
+    hipLaunchKernelGGL(mlp_query, dim3(blocks_for(n, 32)), dim3(256), 0, s, x, n, mu, sigma, W1b, b1, W2b, b2,
+                       W3b, b3, planes, n_planes, hull_tol, threshold, margin, p_out, use);
+    return hipGetLastError();
+}
+
+}  // namespace smc

@@ -1,0 +1,139 @@
+"""GPU surrogate (BF16 MFMA MLP) against the FP64 oracle, and its gain.
+
+Tolerances: the GPU accumulates in FP32 where the oracle uses FP64 (relative
+error ~ K * 2^-24 for K <= 512 terms), and an FP32 activation lying within a
+few FP32 ulps of a bfloat16 rounding boundary can round to the neighbouring
+bfloat16 value (one element off by 2^-8 relative).  Losses therefore agree to
+1e-5 relative and each gradient block to 1e-3 in relative Euclidean norm.
+For the forward pass one such flip of a layer-2 unit k moves the logit by
+|W3_k h2_k| 2^-8; with trained weights (|W3_k h2_k| up to ~0.1) that is up to
+~4e-4 in the logit and ~1e-4 in p, so a trained network is held to 1e-3 at
+the worst point and 1e-4 at all but 1 % of the points.
+"""
+import numpy as np
+import pytest
+from scipy.spatial import Delaunay
+
+from oracle import mlp
+from paper_0912_2551_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+BLOCKS = [("W1", 0, 768), ("b1", 768, 1024), ("W2", 1024, 1024 + 65536), ("b2", 66560, 66816),
+          ("W3", 66816, 67072), ("b3", 67072, 67073)]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_0912_2551_amd import binding as B
+    c = B.Context(0)
+    c.set_watchdog(120)
+    yield c
+    c.close()
+
+
+def _sample(rng, n):
+    x = (np.log10(np.asarray(W.MM_RATES))[None, :] + rng.uniform(-1, 1, size=(n, 3))).astype(np.float32)
+    y = rng.uniform(0, 1, size=n).astype(np.float32)
+    w = rng.integers(100, 10000, size=n).astype(np.float32)
+    return x, y, w
+
+
+@pytest.mark.parametrize("n", [512, 77])
+def test_gradients_match_oracle(ctx, n):
+    from paper_0912_2551_amd import binding as B
+    rng = np.random.default_rng(n)
+    x, y, w = _sample(rng, n)
+    params = mlp.init_params(11, mu=tuple(np.log10(W.MM_RATES)), sigma=(0.57, 0.57, 0.57))
+    s = B.Surrogate(ctx)
+    s.set_params(params.astype(np.float32))
+    loss, g = s.gradients(x, y, w)
+    oloss, og = mlp.loss_and_grads(params, x.astype(np.float64), y.astype(np.float64), w.astype(np.float64))
+    assert abs(loss - oloss) <= 1e-5 * abs(oloss)
+    for name, a, b in BLOCKS:
+        ref = og[a:b]
+        err = np.linalg.norm(g[a:b] - ref) / max(np.linalg.norm(ref), 1e-30)
+        assert err <= 1e-3, (name, err)
+
+
+def test_query_matches_oracle_forward(ctx):
+    from paper_0912_2551_amd import binding as B
+    rng = np.random.default_rng(5)
+    params = mlp.init_params(12, mu=tuple(np.log10(W.MM_RATES)), sigma=(0.57, 0.57, 0.57))
+    s = B.Surrogate(ctx)
+    s.set_params(params.astype(np.float32))
+    x = W.surrogate_queries(5000, seed=5)
+    p, use = s.query(x)
+    ref = mlp.forward(params, x.astype(np.float64))["p"]
+    assert np.max(np.abs(p - ref)) <= 1e-4
+    assert not use.any()            # no training hull yet: never confident
+
+
+def test_training_fits_and_gate(ctx):
+    from paper_0912_2551_amd import binding as B
+    rng = np.random.default_rng(9)
+    x = (np.log10(np.asarray(W.MM_RATES))[None, :] + rng.uniform(-1, 1, size=(512, 3))).astype(np.float32)
+    c = x - np.log10(np.asarray(W.MM_RATES))
+    y = (1.0 / (1.0 + np.exp(-(3 * c[:, 2] - 1.5 * c[:, 0])))).astype(np.float32)
+    w = np.full(512, 1000.0, dtype=np.float32)
+    s = B.Surrogate(ctx, seed=3)
+    losses = s.train(x, y, w, steps=600, lr=2e-3)
+    ent = float(np.mean(-(y * np.log(y) + (1 - y) * np.log(1 - y))))
+    assert losses[-1] < losses[0]
+    assert losses[-1] - ent < 0.1 * (losses[0] - ent)      # most of the excess loss is gone
+    params = s.get_params().astype(np.float64)
+    q = W.surrogate_queries(20000, seed=10)
+    p, use = s.query(q)
+    ref = mlp.forward(params, q.astype(np.float64))["p"]
+    dp = np.abs(p - ref)
+    assert dp.max() <= 1e-3
+    assert np.mean(dp > 1e-4) <= 0.01
+    inside = Delaunay(x.astype(np.float64)).find_simplex(q.astype(np.float64)) >= 0
+    expect = inside & (np.abs(ref - 0.5) >= 0.05)
+    borderline = np.abs(np.abs(ref - 0.5) - 0.05) <= dp + 1e-6
+    hull = s.hull().astype(np.float64)
+    margin_in = np.min(hull[:, 3][None, :] - q.astype(np.float64) @ hull[:, :3].T, axis=1)
+    borderline |= np.abs(margin_in) < 1e-5
+    assert np.array_equal(use[~borderline], expect[~borderline])
+    assert 0.2 < use.mean() < 0.95
+
+
+def test_surrogate_gain_over_plain_smc(ctx):
+    """Rate sweep of the Michaelis-Menten model under the companion formula
+    (p runs from ~0 to ~1 across the box): the surrogate answers a large share
+    of the queries, its answers lie within the plain-SMC Wilson interval
+    widened by the gate margin, and the SMC work left over is a fraction of
+    what plain SMC spends on the same queries."""
+    from paper_0912_2551_amd import binding as B
+    eps, n_train, n_query, margin = 0.03, 384, 512, 0.05
+    text = W.MM_COMPANION_FORMULA
+    keep = []
+
+    def run(rate_sets, seed):
+        jobs = []
+        for k, rr in enumerate(rate_sets):
+            nh = ctx.network(W.michaelis_menten(*rr))
+            fh = ctx.formula(nh, text)
+            keep.append((nh, fh))
+            jobs.append((nh, fh, B.params(half_width=eps, seed=seed, model_id=k)))
+        return ctx.estimate_batch(jobs)
+
+    train = W.mm_sweep(n_train, seed=21)
+    res = run(train, 1)
+    x = np.log10(train).astype(np.float32)
+    y = np.array([r["p_hat"] for r in res], dtype=np.float32)
+    w = np.array([r["n"] for r in res], dtype=np.float32)
+    s = B.Surrogate(ctx, seed=4)
+    losses = s.train(x, y, w, steps=2000, lr=2e-3)
+    assert losses[-1] < losses[0]
+    q = W.surrogate_queries(n_query, seed=22)
+    p, use = s.query(q, threshold=0.5, margin=margin)
+    plain = run(10.0 ** q.astype(np.float64), 2)
+    plain_events = sum(r["events"] for r in plain)
+    fallback_events = sum(r["events"] for r, u in zip(plain, use) if not u)
+    err = np.array([max(r["lo"] - pi, pi - r["hi"], 0.0) for r, pi, u in zip(plain, p, use) if u])
+    print(f"use={use.mean():.3f} within={np.mean(err == 0):.3f} within+margin={np.mean(err <= margin):.3f} "
+          f"max_err={err.max():.3f} work={fallback_events / plain_events:.3f}")
+    assert use.mean() > 0.3
+    assert np.mean(err <= margin) >= 0.95
+    assert fallback_events < 0.8 * plain_events
