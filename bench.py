@@ -29,10 +29,32 @@ sys.path.insert(0, ROOT)
 
 # VALU issue slots per SSA event of this workload (per lane), counted from the
 # direct method's required arithmetic; see the work model in the design notes.
-WORK_SLOTS_PER_EVENT_C2 = 244
-WORK_SLOTS_PER_EVENT_C1 = 212
+WORK_SLOTS_PER_EVENT_C2 = 220
+WORK_SLOTS_PER_EVENT_C1 = 198
 PEAK_VALU_SLOTS = 256 * 64 * 2.4e9    # CUs x lanes x clock: 3.93e13 lane-slots/s
 N_TRAJ = 10**6
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ssa_persistent_mm_c2_hbm_counters.txt")
+KERNEL_SOURCES = ["paper_0912_2551_amd/csrc/ssa_kernel.hip", "paper_0912_2551_amd/csrc/smc_device.h"]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE scaled by the copy calibration), or None when the kernel
+    sources have changed since the counters were taken."""
+    import hashlib
+    try:
+        fields = dict(l.split(": ", 1) for l in open(TRAFFIC_PROFILE).read().splitlines() if ": " in l)
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if fields.get("kernel_sources_sha256", "").strip() != h.hexdigest():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def copy_calibration():
@@ -197,7 +219,8 @@ def main():
         "verified_trajectories_per_s": trajectories / wall,
         "p_hat": r["p_hat"], "interval_95": [r["lo"], r["hi"]],
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_SLOTS / 1e12,
-                     "unit": "Tslot/s", "frac": achieved / PEAK_VALU_SLOTS, "traffic": None,
+                     "unit": "Tslot/s", "frac": achieved / PEAK_VALU_SLOTS, "traffic": measured_traffic(),
+                     "traffic_unit": "bytes per launch",
                      "kernel": "ssa_persistent", "kernel_ms": 1e3 * kernel_s,
                      "work_slots_per_event": WORK_SLOTS_PER_EVENT_C2},
     }
