@@ -36,7 +36,8 @@ N_TRAJ = 10**6
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ssa_persistent_mm_c2_hbm_counters.txt")
-KERNEL_SOURCES = ["paper_0912_2551_amd/csrc/ssa_kernel.hip", "paper_0912_2551_amd/csrc/smc_device.h"]
+KERNEL_SOURCES = ["paper_0912_2551_amd/csrc/ssa_core.h", "paper_0912_2551_amd/csrc/ssa_kernel.hip",
+                  "paper_0912_2551_amd/csrc/smc_device.h", "paper_0912_2551_amd/csrc/spec.cpp"]
 
 
 def measured_traffic():
@@ -156,6 +157,9 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=N_TRAJ)
     ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--occupancy", type=int, default=0, help="waves per SIMD budget of specialised kernels")
+    ap.add_argument("--kernel", choices=["auto", "generic"], default="auto",
+                    help="auto: kernel specialised to the network structure when supported")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -176,6 +180,10 @@ def main():
     ctx = B.Context(0, stream=stream)
     if args.waves_per_cu:
         ctx.set_waves_per_cu(args.waves_per_cu)
+    if args.occupancy:
+        ctx.set_kernel_occupancy(args.occupancy)
+    if args.kernel == "generic":
+        ctx.set_specialization(B.SPECIALIZE_OFF)
     net = W.michaelis_menten()
     nh = ctx.network(net)
     fh = ctx.formula(nh, W.C2_FORMULA)
@@ -197,6 +205,8 @@ def main():
     wall = time.perf_counter() - t0
     value = events / wall
     kernel_s = dev / args.steps
+    kernel_name = ("smc_spec_kernel (specialised to the network and formula)"
+                   if ctx.last_kernel() == B.KERNEL_SPECIALIZED else "ssa_persistent (generic)")
     ev_per_launch = events / args.steps
     achieved = WORK_SLOTS_PER_EVENT_C2 * ev_per_launch / kernel_s
     line = {
@@ -221,7 +231,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_SLOTS / 1e12,
                      "unit": "Tslot/s", "frac": achieved / PEAK_VALU_SLOTS, "traffic": measured_traffic(),
                      "traffic_unit": "bytes per launch",
-                     "kernel": "ssa_persistent", "kernel_ms": 1e3 * kernel_s,
+                     "kernel": kernel_name, "kernel_ms": 1e3 * kernel_s,
                      "work_slots_per_event": WORK_SLOTS_PER_EVENT_C2},
     }
     if not args.no_c1:

@@ -79,6 +79,34 @@ int smc_set_watchdog(smc_ctx *ctx, double seconds);
 /* Launch shape of the SSA kernel: waves per compute unit (1..32, 0 = tuned
  * default).  Results do not depend on it. */
 int smc_set_waves_per_cu(smc_ctx *ctx, int waves_per_cu);
+/* Kernel specialisation.  For a launch whose jobs all share one network
+ * structure (reactants and state changes, S <= 16 species, M <= 8 channels)
+ * and one formula without arithmetic (RPN) predicates, the library can
+ * compile, at run time, a kernel with that structure as constants (species
+ * counts in registers, table indices as immediates) and cache it per device
+ * and structure for the life of the process.  Rate constants, initial counts
+ * and seeds stay inputs, so one kernel serves a whole rate sweep.  Results are
+ * identical to the generic kernel's.  Modes: SMC_SPECIALIZE_AUTO (default:
+ * specialise when supported; if run-time compilation fails, warn once on
+ * stderr and use the generic kernel), SMC_SPECIALIZE_OFF (generic kernel
+ * only), SMC_SPECIALIZE_REQUIRED (fail with SMC_E_UNSUPPORTED or SMC_E_HIP
+ * instead of using the generic kernel).  Errors: SMC_E_INVALID. */
+#define SMC_SPECIALIZE_AUTO 0
+#define SMC_SPECIALIZE_OFF 1
+#define SMC_SPECIALIZE_REQUIRED 2
+int smc_set_specialization(smc_ctx *ctx, int mode);
+/* Which SSA kernel the last estimation call on ctx launched: -1 none yet,
+ * SMC_KERNEL_GENERIC_SMALL (table-driven, <= 4 channels), SMC_KERNEL_GENERIC
+ * (table-driven, blocked prefix), SMC_KERNEL_SPECIALIZED. */
+#define SMC_KERNEL_GENERIC_SMALL 0
+#define SMC_KERNEL_GENERIC 1
+#define SMC_KERNEL_SPECIALIZED 2
+int smc_last_kernel(const smc_ctx *ctx);
+/* Register budget of specialised kernels: compile them so that
+ * `waves_per_simd` waves fit on one SIMD (1..8; registers beyond the budget
+ * go to scratch memory), or 0 for the compiler's own choice (default).
+ * Results do not depend on it.  Errors: SMC_E_INVALID. */
+int smc_set_kernel_occupancy(smc_ctx *ctx, int waves_per_simd);
 /* Ask a running call on ctx (from another thread) to stop: it returns
  * SMC_E_CANCELLED. */
 void smc_cancel(smc_ctx *ctx);

@@ -30,9 +30,13 @@ SMC_CONSERVATIVE_START = 1
 SMC_PAPER_ROUNDING = 2
 REASON_STATE, REASON_TIME, REASON_ABSORB, REASON_CAP, REASON_TMAX = range(5)
 
+SPECIALIZE_AUTO, SPECIALIZE_OFF, SPECIALIZE_REQUIRED = 0, 1, 2
+KERNEL_GENERIC_SMALL, KERNEL_GENERIC, KERNEL_SPECIALIZED = 0, 1, 2
+
 EXPORTS = [
     "smc_ctx_create", "smc_ctx_destroy", "smc_last_error", "smc_set_watchdog",
-    "smc_set_waves_per_cu", "smc_cancel", "smc_device_cus", "smc_net_create",
+    "smc_set_waves_per_cu", "smc_set_specialization", "smc_last_kernel",
+    "smc_set_kernel_occupancy", "smc_cancel", "smc_device_cus", "smc_net_create",
     "smc_net_set_rates", "smc_net_destroy", "smc_formula_compile", "smc_formula_horizon",
     "smc_formula_destroy", "smc_estimate", "smc_estimate_batch", "smc_trajectories",
     "smc_sample_state", "smc_z_value", "smc_wilson_sample_value", "smc_wilson_sample",
@@ -108,6 +112,9 @@ def lib():
             "smc_last_error": (ctypes.c_char_p, [vp]),
             "smc_set_watchdog": (i32, [vp, dbl]),
             "smc_set_waves_per_cu": (i32, [vp, i32]),
+            "smc_set_specialization": (i32, [vp, i32]),
+            "smc_last_kernel": (i32, [vp]),
+            "smc_set_kernel_occupancy": (i32, [vp, i32]),
             "smc_cancel": (None, [vp]),
             "smc_device_cus": (i32, [vp]),
             "smc_net_create": (i32, [vp, ctypes.POINTER(NetDesc), ctypes.POINTER(vp)]),
@@ -207,6 +214,18 @@ class Context:
 
     def set_waves_per_cu(self, w: int):
         self._check(lib().smc_set_waves_per_cu(self.h, int(w)))
+
+    def set_specialization(self, mode: int):
+        """SPECIALIZE_AUTO, SPECIALIZE_OFF or SPECIALIZE_REQUIRED."""
+        self._check(lib().smc_set_specialization(self.h, int(mode)))
+
+    def set_kernel_occupancy(self, waves_per_simd: int):
+        """Register budget of specialised kernels (0 = compiler default)."""
+        self._check(lib().smc_set_kernel_occupancy(self.h, int(waves_per_simd)))
+
+    def last_kernel(self) -> int:
+        """KERNEL_GENERIC_SMALL, KERNEL_GENERIC or KERNEL_SPECIALIZED (-1: none yet)."""
+        return int(lib().smc_last_kernel(self.h))
 
     def cus(self) -> int:
         return lib().smc_device_cus(self.h)

@@ -20,7 +20,21 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = os.environ.get("SMC_OFFLOAD_ARCH", "gfx950")
 
 DEVICE_SOURCES = ["ssa_kernel.hip", "surrogate.hip"]
-HOST_SOURCES = ["smc_api.cpp", "formula.cpp", "surrogate_api.cpp", "hull.cpp"]
+HOST_SOURCES = ["smc_api.cpp", "formula.cpp", "surrogate_api.cpp", "hull.cpp", "spec.cpp"]
+# device headers the runtime compiler needs for specialised kernels
+EMBEDDED = [("kEmbeddedDeviceHeader", "smc_device.h"), ("kEmbeddedCoreHeader", "ssa_core.h")]
+
+
+def _embedded_source(path, csrc=CSRC):
+    """C++ file defining the device headers as strings (raw literals)."""
+    out = ["namespace smc {"]
+    for sym, name in EMBEDDED:
+        text = open(os.path.join(csrc, name)).read()
+        assert ")SMCSRC\"" not in text
+        out.append(f'extern const char {sym}[] = R"SMCSRC({text})SMCSRC";')
+    out.append("}")
+    with open(path, "w") as f:
+        f.write("\n".join(out) + "\n")
 
 
 def _run(cmd, verbose):
@@ -29,12 +43,14 @@ def _run(cmd, verbose):
     subprocess.check_call(cmd)
 
 
-def build(verbose: bool = False, jobs: int = 4, out: str | None = None, defines=()) -> str:
+def build(verbose: bool = False, jobs: int = 4, out: str | None = None, defines=(), csrc: str = CSRC) -> str:
+    """Compile and link the library (default: in-tree).  `csrc` selects another
+    source directory with the same file names (e.g. a modified copy)."""
     hipcc = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
     clang = os.path.join(ROCM, "bin", "amdclang++")
     if not os.path.exists(clang):
         clang = os.path.join(ROCM, "llvm", "bin", "clang++")
-    inc = ["-I", INCLUDE, "-I", CSRC] + [f"-D{d}" for d in defines]
+    inc = ["-I", INCLUDE, "-I", csrc] + [f"-D{d}" for d in defines]
     lib_path = out or LIB
     tmp = tempfile.mkdtemp(prefix="smc_build_")
     try:
@@ -43,14 +59,16 @@ def build(verbose: bool = False, jobs: int = 4, out: str | None = None, defines=
             obj = os.path.join(tmp, src + ".o")
             cmd = [hipcc, "-c", "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
                    "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                   "-Wno-unused-command-line-argument", *inc, os.path.join(CSRC, src), "-o", obj]
+                   "-Wno-unused-command-line-argument", *inc, os.path.join(csrc, src), "-o", obj]
             procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
             objs.append(obj)
-        for src in HOST_SOURCES:
-            obj = os.path.join(tmp, src + ".o")
+        emb = os.path.join(tmp, "embedded_headers.cpp")
+        _embedded_source(emb, csrc)
+        for src in HOST_SOURCES + [emb]:
+            obj = os.path.join(tmp, os.path.basename(src) + ".o")
             cmd = [clang, "-c", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off",
                    "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROCM, "include"), *inc,
-                   os.path.join(CSRC, src), "-o", obj]
+                   os.path.join(csrc, src), "-o", obj]
             procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
             objs.append(obj)
         failed = []
@@ -63,7 +81,8 @@ def build(verbose: bool = False, jobs: int = 4, out: str | None = None, defines=
         if failed:
             raise RuntimeError("compilation failed:\n" + "\n".join(failed))
         out_tmp = lib_path + ".tmp%d" % os.getpid()
-        _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", out_tmp], verbose)
+        _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-L", os.path.join(ROCM, "lib"),
+              "-lhiprtc", "-o", out_tmp], verbose)
         os.replace(out_tmp, lib_path)
     finally:
         shutil.rmtree(tmp, ignore_errors=True)

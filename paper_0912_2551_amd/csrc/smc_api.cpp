@@ -10,6 +10,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <thread>
@@ -28,6 +29,10 @@ struct smc_ctx {
     std::string err;
     int n_cu = 256;
     int waves_per_cu = 0;
+    int spec_mode = SMC_SPECIALIZE_AUTO;
+    int spec_waves_per_simd = 0;
+    int last_kernel = -1;
+    bool spec_warned = false;
     double watchdog = 300.0;
     int32_t *cancel_host = nullptr;   // pinned, read by kernels
     int32_t *cancel_dev = nullptr;
@@ -117,6 +122,8 @@ double resolve_z(const smc_params &p) { return p.z > 0.0 ? p.z : smc_z_value(p.c
 
 struct Prepared {
     Job job;
+    const smc_net *net = nullptr;
+    const smc_formula *f = nullptr;
     int S = 0, M = 0;
     uint64_t capacity = 0;
     double z = 0.0;
@@ -172,10 +179,49 @@ int prepare(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_pa
     J.literal = (p->flags & SMC_PAPER_ROUNDING) ? 1 : 0;
     J.eps = p->half_width;
     J.z = z;
+    out.net = net;
+    out.f = f;
     out.S = net->S;
     out.M = net->M;
     out.capacity = capacity;
     out.z = z;
+    return SMC_OK;
+}
+
+// The specialised kernel for a launch, if every job shares one network
+// structure and formula that the specialisation supports (else nullptr).
+int pick_spec_kernel(smc_ctx *ctx, const std::vector<Prepared> &P, hipFunction_t *fn)
+{
+    *fn = nullptr;
+    if (ctx->spec_mode == SMC_SPECIALIZE_OFF || P.empty()) return SMC_OK;
+    const smc_net *n0 = P[0].net;
+    const smc_formula *f0 = P[0].f;
+    bool ok = n0 && f0 && spec_supported(n0->S, n0->M, f0->prog);
+    std::string src;
+    if (ok) src = spec_source(n0->S, n0->M, n0->reac.data(), n0->chg.data(), f0->prog, ctx->spec_waves_per_simd);
+    const smc_net *ln = n0;
+    const smc_formula *lf = f0;
+    for (size_t k = 1; ok && k < P.size(); ++k) {
+        if (P[k].net == ln && P[k].f == lf) continue;
+        ln = P[k].net;
+        lf = P[k].f;
+        ok = ln && lf && ln->S == n0->S && ln->M == n0->M &&
+             spec_source(ln->S, ln->M, ln->reac.data(), ln->chg.data(), lf->prog, ctx->spec_waves_per_simd) == src;
+    }
+    if (!ok) {
+        if (ctx->spec_mode == SMC_SPECIALIZE_REQUIRED)
+            return fail(ctx, SMC_E_UNSUPPORTED, "jobs do not share one structure the specialised kernels support");
+        return SMC_OK;
+    }
+    std::string err;
+    if (spec_kernel(ctx->device, src, fn, err) != 0) {
+        *fn = nullptr;
+        if (ctx->spec_mode == SMC_SPECIALIZE_REQUIRED) return fail(ctx, SMC_E_HIP, err);
+        if (!ctx->spec_warned) {
+            std::fprintf(stderr, "libsmc: using the generic kernel: %s\n", err.c_str());
+            ctx->spec_warned = true;
+        }
+    }
     return SMC_OK;
 }
 
@@ -221,6 +267,9 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
     const unsigned long long waves = std::min<unsigned long long>((unsigned long long)ctx->n_cu * wpc, waves_needed);
     const int grid = (int)std::max<unsigned long long>(1, (waves + wpb - 1) / wpb);
     const int variant = m_max <= 4 ? 0 : 1;
+    hipFunction_t spec_fn = nullptr;
+    if (const int rc = pick_spec_kernel(ctx, P, &spec_fn)) return rc;
+    ctx->last_kernel = spec_fn ? SMC_KERNEL_SPECIALIZED : (variant == 0 ? SMC_KERNEL_GENERIC_SMALL : SMC_KERNEL_GENERIC);
     res.assign(n, JobResult{});
     double total_ms = 0.0;
     const auto t_start = std::chrono::steady_clock::now();
@@ -235,8 +284,12 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
         c.open_jobs = open;
         HIP_TRY(ctx, hipMemcpyAsync(ctx->d_ctl, &c, sizeof(c), hipMemcpyHostToDevice, s));
         HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
-        HIP_TRY(ctx, launch_persistent(variant, grid, wpb, lds_wave * wpb, s, ctx->d_jobs, n, s_max,
-                                       ctx->d_ctl, ctx->cancel_dev, 1 << 18));
+        if (spec_fn)
+            HIP_TRY(ctx, launch_module(spec_fn, grid, wpb, s, ctx->d_jobs, n, s_max, ctx->d_ctl,
+                                       ctx->cancel_dev, 1 << 18));
+        else
+            HIP_TRY(ctx, launch_persistent(variant, grid, wpb, lds_wave * wpb, s, ctx->d_jobs, n, s_max,
+                                           ctx->d_ctl, ctx->cancel_dev, 1 << 18));
         HIP_TRY(ctx, launch_finalize(s, ctx->d_jobs, n, ctx->d_results));
         HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
         // wait under the watchdog
@@ -369,6 +422,26 @@ int smc_set_watchdog(smc_ctx *c, double seconds)
 {
     if (!c) return SMC_E_INVALID;
     c->watchdog = seconds;
+    return SMC_OK;
+}
+
+int smc_set_specialization(smc_ctx *c, int mode)
+{
+    if (!c) return SMC_E_INVALID;
+    if (mode != SMC_SPECIALIZE_AUTO && mode != SMC_SPECIALIZE_OFF && mode != SMC_SPECIALIZE_REQUIRED)
+        return fail(c, SMC_E_INVALID, "unknown specialization mode");
+    c->spec_mode = mode;
+    return SMC_OK;
+}
+
+int smc_last_kernel(const smc_ctx *c) { return c ? c->last_kernel : -1; }
+
+int smc_set_kernel_occupancy(smc_ctx *c, int waves_per_simd)
+{
+    if (!c) return SMC_E_INVALID;
+    if (waves_per_simd < 0 || waves_per_simd > 8)
+        return fail(c, SMC_E_INVALID, "waves per SIMD must lie in 0..8");
+    c->spec_waves_per_simd = waves_per_simd;
     return SMC_OK;
 }
 

@@ -4,7 +4,19 @@
 // reaction network (Sec. 2.2), its compiled monitor program (Sec. 3.1-3.2),
 // its stopping rule (Sec. 3.3, eqs. 3-4, Fig. 2) and its accounting state.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <stdint.h>
+#else
+// the runtime compiler has no C library headers; it defines the fixed-width
+// integer types in its own namespace
+using __hip_internal::int16_t;
+using __hip_internal::int32_t;
+using __hip_internal::int64_t;
+using __hip_internal::uint16_t;
+using __hip_internal::uint32_t;
+using __hip_internal::uint64_t;
+using __hip_internal::uint8_t;
+#endif
 
 namespace smc {
 
@@ -19,6 +31,8 @@ constexpr int kMaxNested = 2;      // nested-until monitors per formula
 constexpr int kMaxValOps = 96;     // arithmetic predicate programs
 constexpr int kValStack = 4;       // arithmetic stack depth on the device
 constexpr int kBlocks = 16;        // prefix-sum blocks for reaction selection
+constexpr int kSpecMaxS = 16;      // specialised kernels: species counts in registers
+constexpr int kSpecMaxM = 8;       // specialised kernels: channels
 
 enum CmpOp : int32_t { CMP_LT = 0, CMP_LE, CMP_GE, CMP_GT, CMP_EQ, CMP_NE };
 enum ValOp : int32_t { VO_VAR = 0, VO_CONST, VO_ADD, VO_SUB, VO_MUL, VO_DIV, VO_NEG, VO_SQRT };

@@ -26,10 +26,21 @@ hipError_t launch_persistent(int nb_variant, int grid, int waves_per_block, size
                              Control *ctl, const volatile int32_t *cancel, int spin_limit);
 hipError_t launch_sample_state(int nb_variant, hipStream_t stream, const Job *job, double T,
                                unsigned long long count, int32_t *out, int s_max);
+// a specialised persistent kernel (spec.cpp) with the generic kernel's arguments
+hipError_t launch_module(hipFunction_t fn, int grid, int waves_per_block, hipStream_t stream,
+                         const Job *jobs, int n_jobs, int s_max, Control *ctl,
+                         const volatile int32_t *cancel, int spin_limit);
 hipError_t launch_init(hipStream_t stream, const Job *jobs, int n_jobs);
 hipError_t launch_finalize(hipStream_t stream, const Job *jobs, int n_jobs, JobResult *out);
 hipError_t launch_wilson_table(hipStream_t stream, const unsigned long long *yes,
                                const unsigned long long *n, int count, double eps, double z,
                                int literal, unsigned long long *out);
+
+// spec.cpp
+bool spec_supported(int S, int M, const MonProg &mp);
+// waves_per_simd > 0: register budget for that many waves per SIMD
+std::string spec_source(int S, int M, const int32_t *reac, const uint32_t *chg, const MonProg &mp,
+                        int waves_per_simd);
+int spec_kernel(int device, const std::string &src, hipFunction_t *fn, std::string &err);
 
 }  // namespace smc

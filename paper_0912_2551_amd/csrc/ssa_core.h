@@ -1,0 +1,1145 @@
+// ssa_core.h -- device code of the on-the-fly SSA + BLTLc monitor path for
+// gfx950, shared by the generic kernels (ssa_kernel.hip, built ahead of time)
+// and by kernels specialised to one network structure and formula (compiled
+// at run time by the library, which passes this header to the runtime
+// compiler).
+//
+// One trajectory per lane.  A wave works on one job (model) at a time; idle
+// lanes are refilled with new trajectory indices of that job as soon as their
+// trajectory is decided, so the wave stays full until the job runs out of
+// issuable indices.  Per event and lane:
+//   a_j and the running sum S_j in reaction order (Sec. 2.2, template step 1);
+//   one Philox4x32-10 block keyed by (trajectory, model), counter = event;
+//   tau = -log(u1) / a0 (eq. 2a); j = min{j : S_j > u2 a0} (eq. 2b);
+//   x += v_j, t += tau (step 4); monitor update (Sec. 3.2).
+// Time and propensity sums are FP64, with no contraction (built with
+// -ffp-contract=off), so each lane reproduces the CPU reference bit for bit.
+//
+// Verdicts are reduced per wave (ballot/popcount) and added atomically to
+// per-(job, batch) counters.  Iterative jobs run the Wilson stopping rule
+// (eqs. 3-4, Fig. 2) on the device: the lane that completes a batch
+// evaluates it and either publishes the next batch bound or finalises the
+// job.  While a batch is pending, indices that every possible outcome of the
+// batch would still require are issued ahead (no speculative waste).
+#pragma once
+#ifndef __HIPCC_RTC__
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#endif
+
+#include "smc_device.h"
+
+namespace smc {
+
+// ---------------------------------------------------------------------------
+// Numeric primitives (independent implementation of the numeric contract)
+// ---------------------------------------------------------------------------
+struct U4 {
+    uint32_t a, b, c, d;
+};
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplies, key bumped by the Weyl constants between rounds.
+__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t m0 = (uint64_t)c0 * 0xD2511F53ull;
+        const uint64_t m1 = (uint64_t)c2 * 0xCD9E8D57ull;
+        const uint32_t n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)m1;
+        c3 = (uint32_t)m0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// 53-bit uniforms: (0,1] for the waiting time, [0,1) for the channel.
+__device__ __forceinline__ double unif_oc(uint32_t hi, uint32_t lo)
+{
+    const uint64_t v = ((uint64_t)hi << 21) | (uint64_t)(lo >> 11);
+    return (double)(v + 1ull) * 0x1p-53;
+}
+__device__ __forceinline__ double unif_co(uint32_t hi, uint32_t lo)
+{
+    const uint64_t v = ((uint64_t)hi << 21) | (uint64_t)(lo >> 11);
+    return (double)v * 0x1p-53;
+}
+
+// Natural log of a positive normal double from IEEE operations only.
+// Reduce x = m 2^e with m in [sqrt(1/2), sqrt(2)); with f = m - 1,
+// s = f / (2 + f): ln m = f - (f^2/2 - s (f^2/2 + 2R)), R = sum_k s^2k/(2k+1).
+__device__ __forceinline__ double ctr_log(double x)
+{
+    const uint64_t bits = __double_as_longlong(x);
+    int e = (int)((bits >> 52) & 0x7FF) - 1023;
+    double m = __longlong_as_double((long long)((bits & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull));
+    if (m > 1.4142135623730951) {
+        m = m * 0.5;
+        e = e + 1;
+    }
+    const double f = m - 1.0;
+    const double s = f / (2.0 + f);
+    const double z = s * s;
+    double p = 1.0 / 21.0;
+    p = fma(z, p, 1.0 / 19.0);
+    p = fma(z, p, 1.0 / 17.0);
+    p = fma(z, p, 1.0 / 15.0);
+    p = fma(z, p, 1.0 / 13.0);
+    p = fma(z, p, 1.0 / 11.0);
+    p = fma(z, p, 1.0 / 9.0);
+    p = fma(z, p, 1.0 / 7.0);
+    p = fma(z, p, 1.0 / 5.0);
+    p = fma(z, p, 1.0 / 3.0);
+    const double R = z * p;
+    const double R2 = R + R;
+    const double h = (0.5 * f) * f;
+    const double ed = (double)e;
+    return ed * 6.93147180369123816490e-01 -
+           ((h - fma(s, h + R2, ed * 1.90821492927058770002e-10)) - f);
+}
+
+// Eq. 4 (before rounding up), in the contract's operation order.
+__device__ __forceinline__ double wilson_n(double p, double eps, double z)
+{
+    const double pq = p * (1.0 - p);
+    const double e2 = eps * eps;
+    const double d = p - 0.5;
+    const double rad = pq * pq + (4.0 * e2) * (d * d);
+    const double num = (pq - 2.0 * e2) + sqrt(rad);
+    return (z * z) * num / (2.0 * e2);
+}
+
+// Fig. 2 rounding of the estimate towards 0.5 (optionally stopping at 0.5).
+__device__ __forceinline__ double towards_half(double p, double eps, int literal)
+{
+    if (p <= 0.5) {
+        const double q = p + eps;
+        return literal ? q : fmin(q, 0.5);
+    }
+    const double q = p - eps;
+    return literal ? q : fmax(q, 0.5);
+}
+
+__device__ __forceinline__ unsigned long long next_sample(double p_hat, double eps, double z,
+                                                          int literal)
+{
+    return (unsigned long long)ceil(wilson_n(towards_half(p_hat, eps, literal), eps, z));
+}
+
+// ---------------------------------------------------------------------------
+// Wave helpers
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T ld_relaxed(T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T ld_acquire(T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_release(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+__device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ uint32_t read_lane_u32(uint32_t v, int l)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ unsigned long long read_lane_u64(unsigned long long v, int l)
+{
+    const uint32_t lo = read_lane_u32((uint32_t)v, l);
+    const uint32_t hi = read_lane_u32((uint32_t)(v >> 32), l);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int ffs64(uint64_t m) { return __ffsll((unsigned long long)m) - 1; }
+
+__device__ __forceinline__ int rank_in(uint64_t m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Read-only tables are read through the constant address space: wave-uniform
+// reads then compile to scalar loads even though the kernel also writes
+// global memory (counters, records).
+// ---------------------------------------------------------------------------
+#define SMC_CONST __attribute__((address_space(4)))
+template <typename T>
+using cptr = const SMC_CONST T *;
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T *p)
+{
+    return (cptr<T>)p;
+}
+
+// ---------------------------------------------------------------------------
+// Per-wave view of a job: uniform values kept in scalar registers.
+// ---------------------------------------------------------------------------
+struct JobView {
+    const Job *job;
+    JobState *st;
+    cptr<MonProg> mon;
+    cptr<int32_t> x0;
+    cptr<double> rate;
+    cptr<int32_t> reac;
+    cptr<uint32_t> chg;
+    int S, M;
+    unsigned long long seed, first, capacity;
+    uint32_t model_id, max_events;
+    double t_max;
+    int iterative, literal;
+    double eps, z;
+    int nb, bs;   // prefix blocks and reactions per block
+    uint32_t *rec_events;   // optional per-index outputs
+    uint8_t *rec_vr;
+
+    __device__ void load(const Job *jobs, int j)
+    {
+        cptr<Job> J = as_const(jobs) + j;
+        job = jobs + j;
+        st = J->st;
+        mon = as_const(J->mon);
+        x0 = as_const(J->net.x0);
+        rate = as_const(J->net.rate);
+        reac = as_const(J->net.reac);
+        chg = as_const(J->net.chg);
+        S = J->net.S;
+        M = J->net.M;
+        seed = J->seed;
+        first = J->first;
+        capacity = J->capacity;
+        model_id = J->model_id;
+        max_events = J->max_events;
+        t_max = J->t_max;
+        iterative = J->iterative;
+        literal = J->literal;
+        eps = J->eps;
+        z = J->z;
+        nb = M < kBlocks ? M : kBlocks;
+        bs = (M + nb - 1) / nb;
+        rec_events = J->rec_events;
+        rec_vr = J->rec_vr;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Species counts of one lane's trajectory: species-major / lane-minor in the
+// wave's LDS slice (consecutive lanes hit consecutive banks).
+// ---------------------------------------------------------------------------
+struct LdsCounts {
+    int32_t *xs;
+    int lane;
+    __device__ __forceinline__ int32_t get(int s) const { return xs[s * kWave + lane]; }
+    __device__ __forceinline__ void init(cptr<int32_t> x0, int S)
+    {
+        for (int s = 0; s < S; ++s) xs[s * kWave + lane] = x0[s];
+    }
+    // four packed (species, delta) entries
+    __device__ __forceinline__ void apply(uint32_t e0, uint32_t e1, uint32_t e2, uint32_t e3)
+    {
+        const uint32_t e[4] = {e0, e1, e2, e3};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t sp = e[q] >> 16;
+            if (sp != 0xFFFFu) xs[sp * kWave + lane] += (int32_t)(int16_t)(e[q] & 0xFFFFu);
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Propensities (contract: one rounding per propensity, c * h(x)).
+// ---------------------------------------------------------------------------
+template <class C>
+__device__ __forceinline__ double propensity(int ra, int rb, double c, const C &X)
+{
+    if (ra < 0) return c;
+    const int32_t xa = X.get(ra);
+    if (rb < 0) return c * (double)xa;
+    if (ra == rb) return c * (((double)xa * (double)(xa - 1)) * 0.5);
+    const int32_t xb = X.get(rb);
+    return c * ((double)xa * (double)xb);
+}
+
+struct Change {
+    uint32_t e0, e1, e2, e3;
+};
+
+// ---------------------------------------------------------------------------
+// Monitor (compiled BLTLc program).  Per lane: masks of monitors known true
+// (tm) and false (fm); nested untils keep "left operand held so far" bits
+// (ok) and the latest admissible inner start time (ts, < 0: none).
+// ---------------------------------------------------------------------------
+struct MonState {
+    uint32_t tm, fm, ok;
+    double ts0, ts1;
+};
+
+// Monitor programs come either from device memory (generic kernels) or from
+// a compile-time constant (kernels specialised to one formula).
+template <class MP>
+struct MonAccess {
+    static constexpr bool kMemory = false;
+};
+template <>
+struct MonAccess<cptr<MonProg>> {
+    static constexpr bool kMemory = true;
+};
+
+template <class C>
+__device__ __noinline__ double val_eval(cptr<MonProg> mp, int off, int len, const C &X)
+{
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int sp = 0;
+    for (int o = off; o < off + len; ++o) {
+        const int op = mp->vop[o];
+        double v;
+        if (op == VO_VAR || op == VO_CONST) {
+            v = (op == VO_VAR) ? (double)X.get(mp->vvar[o]) : mp->vconst[o];
+            if (sp == 0) s0 = v;
+            else if (sp == 1) s1 = v;
+            else if (sp == 2) s2 = v;
+            else s3 = v;
+            ++sp;
+            continue;
+        }
+        if (op == VO_NEG || op == VO_SQRT) {
+            const double a = sp == 1 ? s0 : sp == 2 ? s1 : sp == 3 ? s2 : s3;
+            v = (op == VO_NEG) ? -a : sqrt(a);
+            if (sp == 1) s0 = v;
+            else if (sp == 2) s1 = v;
+            else if (sp == 3) s2 = v;
+            else s3 = v;
+            continue;
+        }
+        const double b = sp == 2 ? s1 : sp == 3 ? s2 : s3;
+        const double a = sp == 2 ? s0 : sp == 3 ? s1 : s2;
+        if (op == VO_ADD) v = a + b;
+        else if (op == VO_SUB) v = a - b;
+        else if (op == VO_MUL) v = a * b;
+        else v = a / b;
+        --sp;
+        if (sp == 1) s0 = v;
+        else if (sp == 2) s1 = v;
+        else s2 = v;
+    }
+    return s0;
+}
+
+template <typename T>
+__device__ __forceinline__ bool compare(T l, T r, int op)
+{
+    switch (op) {
+    case CMP_LT: return l < r;
+    case CMP_LE: return l <= r;
+    case CMP_GE: return l >= r;
+    case CMP_GT: return l > r;
+    case CMP_EQ: return l == r;
+    default: return l != r;
+    }
+}
+
+// lo <= x <= hi as one unsigned compare, then negated when asked
+template <class PP>
+__device__ __forceinline__ bool range_test(int32_t x, PP p)
+{
+    const uint32_t lo = (uint32_t)p->lo32;
+    const bool in = ((uint32_t)x - lo) <= ((uint32_t)p->hi32 - lo);
+    return in != (p->neg != 0);
+}
+
+// Bit q of the result = truth of predicate q in the current state.
+template <class MP, class C>
+__device__ __forceinline__ uint32_t eval_preds(MP mp, const C &X)
+{
+    uint32_t pm = 0;
+    const int np = mp->n_preds;
+    if (mp->all_var) {
+#pragma unroll
+        for (int q = 0; q < kMaxPreds; ++q) {
+            if (q >= np) break;
+            const auto p = &mp->preds[q];
+            pm |= (range_test(X.get(p->var), p) ? 1u : 0u) << q;
+        }
+        return pm;
+    }
+    for (int q = 0; q < np; ++q) {
+        const auto p = &mp->preds[q];
+        const int kind = p->kind;
+        bool r;
+        if (kind == PK_VAR) {
+            r = range_test(X.get(p->var), p);
+        } else if (kind == PK_LINEAR) {
+            long long v = p->c;
+            const int nt = p->nterm;
+            for (int k = 0; k < nt; ++k) v += p->w[k] * (long long)X.get(p->vars[k]);
+            r = compare<long long>(v, 0ll, p->op);
+        } else if constexpr (MonAccess<MP>::kMemory) {
+            const double l = val_eval(mp, p->lhs_off, p->lhs_len, X);
+            const double rr = val_eval(mp, p->rhs_off, p->rhs_len, X);
+            r = compare<double>(l, rr, p->op);
+        } else {
+            r = false;   // arithmetic predicates are never compiled into constant programs
+        }
+        pm |= (r ? 1u : 0u) << q;
+    }
+    return pm;
+}
+
+// A state formula: lookup in its truth table.
+template <class MP>
+__device__ __forceinline__ bool prop_val(MP mp, int id, uint32_t pm)
+{
+    const auto P = &mp->props[id];
+    const uint32_t idx = (pm >> P->off) & ((1u << P->cnt) - 1u);
+    return (P->table >> idx) & 1u;
+}
+
+// Kleene value of the formula from the monitor masks: 0 open, 1 true, 2 false.
+template <class MP>
+__device__ __forceinline__ uint32_t top_value(MP mp, const MonState &ms)
+{
+    const int n = mp->n_atoms;
+    const uint32_t idx = ms.tm | (ms.fm << n);
+    uint64_t wt, wf;
+    if (n <= 3) {
+        wt = mp->topT[0];
+        wf = mp->topF[0];
+    } else {
+        const uint32_t w = idx >> 6;
+        wt = w == 0 ? mp->topT[0] : w == 1 ? mp->topT[1] : w == 2 ? mp->topT[2] : mp->topT[3];
+        wf = w == 0 ? mp->topF[0] : w == 1 ? mp->topF[1] : w == 2 ? mp->topF[2] : mp->topF[3];
+    }
+    const uint32_t b = idx & 63u;
+    return ((wt >> b) & 1ull) ? 1u : (((wf >> b) & 1ull) ? 2u : 0u);
+}
+
+__device__ __forceinline__ void mon_set(MonState &ms, int a, uint32_t v)
+{
+    ms.tm |= (v == 1u ? 1u : 0u) << a;
+    ms.fm |= (v == 2u ? 1u : 0u) << a;
+}
+
+// The monitor updates below are written as selects: a monitor that is already
+// decided (or a lane with nothing to inspect) keeps its registers, without a
+// lane-divergent branch.
+
+// The state just entered (index k, entry time t) is inspected.
+template <class MP, class C>
+__device__ __forceinline__ uint32_t mon_step(MP mp, MonState &ms, const C &X, uint32_t k, double t)
+{
+    const uint32_t pm = eval_preds(mp, X);
+    const int na = mp->n_atoms;
+#pragma unroll
+    for (int a = 0; a < kMaxAtoms; ++a) {
+        if (a >= na) break;
+        const bool open = !(((ms.tm | ms.fm) >> a) & 1u);
+        const auto A = &mp->atoms[a];
+        const int kind = A->kind;
+        uint32_t v = 0;
+        if (kind == AK_PROP) {
+            v = prop_val(mp, A->p1, pm) ? 1u : 2u;
+        } else if (kind == AK_UNTIL) {
+            const bool in_window = (t >= A->lo) && (t <= A->hi);
+            const bool hit = in_window && prop_val(mp, A->p2, pm);
+            const bool broken = !prop_val(mp, A->p1, pm);
+            v = hit ? 1u : (broken ? 2u : 0u);
+            if (A->neg) v = v ? 3u - v : 0u;
+        } else if (kind == AK_NEXT) {
+            v = (k == 1u) ? (prop_val(mp, A->p1, pm) ? 1u : 2u) : 0u;
+        } else {   // nested until
+            const bool s0 = A->slot == 0;
+            const uint32_t okb = (ms.ok >> a) & 1u;
+            double tsv = s0 ? ms.ts0 : ms.ts1;
+            tsv = (okb && t <= A->hi) ? t : tsv;                   // new admissible start
+            const bool hit = tsv >= 0.0 && prop_val(mp, A->p3, pm);
+            tsv = (!hit && !prop_val(mp, A->p2, pm)) ? -1.0 : tsv; // inner left operand broken
+            const uint32_t ok2 = okb & (prop_val(mp, A->p1, pm) ? 1u : 0u);
+            v = hit ? 1u : ((tsv < 0.0 && !ok2) ? 2u : 0u);
+            if (open && !hit) ms.ok = (ms.ok & ~(1u << a)) | (ok2 << a);
+            if (s0) ms.ts0 = open ? tsv : ms.ts0;
+            else ms.ts1 = open ? tsv : ms.ts1;
+        }
+        mon_set(ms, a, open ? v : 0u);
+    }
+    return top_value(mp, ms);
+}
+
+// Time is about to advance to tn (absorbing: no further state).
+template <class MP>
+__device__ __forceinline__ uint32_t mon_advance(MP mp, MonState &ms, double tn, bool absorbing)
+{
+    const int na = mp->n_atoms;
+#pragma unroll
+    for (int a = 0; a < kMaxAtoms; ++a) {
+        if (a >= na) break;
+        const bool open = !(((ms.tm | ms.fm) >> a) & 1u);
+        const auto A = &mp->atoms[a];
+        const int kind = A->kind;
+        uint32_t v = 0;
+        if (kind == AK_UNTIL) {
+            v = (absorbing || tn > A->hi) ? (A->neg ? 1u : 2u) : 0u;
+        } else if (kind == AK_NEXT) {
+            v = (absorbing || !(tn >= A->lo && tn <= A->hi)) ? 2u : 0u;
+        } else if (kind == AK_NESTED) {
+            const bool s0 = A->slot == 0;
+            double tsv = s0 ? ms.ts0 : ms.ts1;
+            tsv = (tsv >= 0.0 && (absorbing || tn - tsv > A->hi2)) ? -1.0 : tsv;
+            const uint32_t okb = (ms.ok >> a) & 1u;
+            v = (tsv < 0.0 && (!okb || absorbing || tn > A->hi)) ? 2u : 0u;
+            if (s0) ms.ts0 = open ? tsv : ms.ts0;
+            else ms.ts1 = open ? tsv : ms.ts1;
+        }
+        mon_set(ms, a, open ? v : 0u);
+    }
+    return top_value(mp, ms);
+}
+
+// ms = on ? src : ms, field by field (kept in registers)
+__device__ __forceinline__ void ms_select(MonState &ms, const MonState &src, bool on)
+{
+    ms.tm = on ? src.tm : ms.tm;
+    ms.fm = on ? src.fm : ms.fm;
+    ms.ok = on ? src.ok : ms.ok;
+    ms.ts0 = on ? src.ts0 : ms.ts0;
+    ms.ts1 = on ? src.ts1 : ms.ts1;
+}
+
+__device__ __forceinline__ void mon_init(MonState &ms)
+{
+    ms.tm = 0;
+    ms.fm = 0;
+    ms.ok = 0xFFFFFFFFu;
+    ms.ts0 = -1.0;
+    ms.ts1 = -1.0;
+}
+
+// ---------------------------------------------------------------------------
+// The random numbers of event k of a trajectory: one Philox4x32-10 block
+// keyed by (trajectory, model), counter (k, 0, seed); nl = -ln(u1) with u1 in
+// (0,1], and u2 in [0,1).  They depend on nothing but (trajectory, k), so the
+// persistent loop draws those of a lane's next event while the current event
+// is still being computed (the two dependency chains overlap).
+// ---------------------------------------------------------------------------
+struct Draw {
+    double nl, u2;
+};
+
+__device__ __forceinline__ Draw event_uniforms(const JobView &V, unsigned long long abs_idx, uint32_t k)
+{
+    const U4 r = philox10(k, 0u, (uint32_t)V.seed, (uint32_t)(V.seed >> 32), (uint32_t)abs_idx,
+                          V.model_id);
+    Draw d;
+    d.nl = -ctr_log(unif_oc(r.a, r.b));
+    d.u2 = unif_co(r.c, r.d);
+    return d;
+}
+
+// ---------------------------------------------------------------------------
+// One SSA event for this lane.  Returns the next time (inf when absorbing)
+// and, unless absorbing, the state change of the selected channel.
+// ---------------------------------------------------------------------------
+template <int NB, class C>
+__device__ __forceinline__ double ssa_draw(const JobView &V, const C &X, const Draw &d, double t,
+                                           Change *change)
+{
+    const int M = V.M;
+    const int nb = V.nb, bs = V.bs;
+    cptr<int32_t> reac = V.reac;
+    cptr<double> rate = V.rate;
+    double P[NB];
+    double acc = 0.0;
+    if (NB <= 4) {
+        // at most four channels, one per block
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            if (j < M) acc = acc + propensity(reac[2 * j], reac[2 * j + 1], rate[j], X);
+            P[j] = acc;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            P[q] = acc;
+            if (q < nb) {
+                const int j0 = q * bs;
+                const int j1 = (j0 + bs < M) ? j0 + bs : M;
+                for (int j = j0; j < j1; ++j)
+                    acc = acc + propensity(reac[2 * j], reac[2 * j + 1], rate[j], X);
+                P[q] = acc;
+            }
+        }
+    }
+    const double a0 = acc;
+    if (!(a0 > 0.0)) return __builtin_inf();
+    const double target = d.u2 * a0;
+    // first block whose running sum exceeds the target
+    int qsel = 0;
+    double base = 0.0;
+    bool found = false;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        if (q < nb) {
+            const bool hit = !found && (P[q] > target);
+            qsel = hit ? q : qsel;
+            base = hit ? (q == 0 ? 0.0 : P[q - 1]) : base;
+            found = found || hit;
+        }
+    }
+    int jsel = qsel;
+    if (NB > 4 && bs > 1) {
+        // re-run the same running sum inside the block (identical operations)
+        const int j0 = qsel * bs;
+        const int j1 = (j0 + bs < M) ? j0 + bs : M;
+        double s = base;
+        jsel = j1 - 1;
+        bool got = false;
+        for (int rr = 0; rr < bs; ++rr) {
+            const int j = j0 + rr;
+            if (!got && j < j1) {
+                s = s + propensity(reac[2 * j], reac[2 * j + 1], rate[j], X);
+                if (s > target) {
+                    jsel = j;
+                    got = true;
+                }
+            }
+            if (__ballot(!got) == 0) break;
+        }
+    }
+    if (NB <= 4) {
+        // at most four channels: pick the change among wave-uniform entries
+        cptr<uint32_t> tab = V.chg;
+        Change ch{tab[0], tab[1], tab[2], tab[3]};
+#pragma unroll
+        for (int q = 1; q < NB; ++q) {
+            if (q < M && jsel == q) {
+                ch.e0 = tab[4 * q];
+                ch.e1 = tab[4 * q + 1];
+                ch.e2 = tab[4 * q + 2];
+                ch.e3 = tab[4 * q + 3];
+            }
+        }
+        *change = ch;
+    } else {
+        cptr<uint32_t> chg = V.chg;
+        *change = Change{chg[4 * jsel], chg[4 * jsel + 1], chg[4 * jsel + 2], chg[4 * jsel + 3]};
+    }
+    const double tau = d.nl / a0;
+    return t + tau;
+}
+
+// ---------------------------------------------------------------------------
+// Access policies of the persistent loop.
+//
+// DynPolicy: the generic kernels.  Network and monitor tables are read from
+// device memory through the job's pointers; counts live in LDS.
+//
+// StaticPolicy<Spec>: kernels specialised to one network structure and one
+// formula (compiled at run time).  Spec supplies, as compile-time constants,
+//   static constexpr int S, M;               species and channels
+//   static constexpr NetTab<M> net;          reactants and packed changes
+//   static constexpr MonProg mon;            compiled formula (no RPN predicates)
+// Rate constants and initial counts still come from the job in device
+// memory, so one specialised kernel serves every rate set of a sweep.  Counts
+// live in registers; every table index is an immediate.  The arithmetic is
+// the same sequence of operations as the generic path.
+// ---------------------------------------------------------------------------
+template <int NB>
+struct DynPolicy {
+    using Counts = LdsCounts;
+    using Sel = Change;
+    __device__ static __forceinline__ Counts counts(int32_t *lds, int wid, int s_max, int lane)
+    {
+        Counts X;
+        X.xs = lds + (size_t)wid * (size_t)s_max * kWave;
+        X.lane = lane;
+        return X;
+    }
+    __device__ static __forceinline__ void init(Counts &X, const JobView &V) { X.init(V.x0, V.S); }
+    __device__ static __forceinline__ double draw(const JobView &V, const Counts &X, const Draw &d,
+                                                  double t, Sel *s)
+    {
+        return ssa_draw<NB>(V, X, d, t, s);
+    }
+    __device__ static __forceinline__ void apply_if(Counts &X, const Sel &c, bool on)
+    {
+        if (on) X.apply(c.e0, c.e1, c.e2, c.e3);
+    }
+    __device__ static __forceinline__ uint32_t step(const JobView &V, MonState &ms, const Counts &X,
+                                                    uint32_t k, double t)
+    {
+        return mon_step(V.mon, ms, X, k, t);
+    }
+    __device__ static __forceinline__ uint32_t advance(const JobView &V, MonState &ms, double tn,
+                                                       bool absorbing)
+    {
+        return mon_advance(V.mon, ms, tn, absorbing);
+    }
+};
+
+template <int M>
+struct NetTab {
+    int32_t reac[2 * M];
+    uint32_t chg[4 * M];
+};
+
+template <int S>
+struct RegCounts {
+    int32_t x[S];
+    __device__ __forceinline__ int32_t get(int s) const { return x[s]; }
+};
+
+template <class Spec>
+struct StaticPolicy {
+    static constexpr int S = Spec::S;
+    static constexpr int M = Spec::M;
+    using Counts = RegCounts<S>;
+    using Sel = int;
+    __device__ static __forceinline__ Counts counts(int32_t *, int, int, int) { return Counts{}; }
+    __device__ static __forceinline__ void init(Counts &X, const JobView &V)
+    {
+#pragma unroll
+        for (int s = 0; s < S; ++s) X.x[s] = V.x0[s];
+    }
+    __device__ static __forceinline__ double draw(const JobView &V, const Counts &X, const Draw &d,
+                                                  double t, Sel *jsel)
+    {
+        constexpr NetTab<M> T = Spec::net;
+        cptr<double> rate = V.rate;
+        double P[M];
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            acc = acc + propensity(T.reac[2 * j], T.reac[2 * j + 1], rate[j], X);
+            P[j] = acc;
+        }
+        const double a0 = acc;
+        if (!(a0 > 0.0)) return __builtin_inf();
+        const double target = d.u2 * a0;
+        // u2 < 1 makes target < a0 = P[M-1], so some channel always qualifies
+        int js = M - 1;
+#pragma unroll
+        for (int j = M - 2; j >= 0; --j) js = (P[j] > target) ? j : js;
+        *jsel = js;
+        const double tau = d.nl / a0;
+        return t + tau;
+    }
+    __device__ static __forceinline__ void apply_if(Counts &X, Sel js, bool on)
+    {
+        constexpr NetTab<M> T = Spec::net;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const bool hit = on && js == j;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t e = T.chg[4 * j + q];
+                const uint32_t sp = e >> 16;
+                if (sp != 0xFFFFu) X.x[sp] += hit ? (int32_t)(int16_t)(e & 0xFFFFu) : 0;
+            }
+        }
+    }
+    __device__ static __forceinline__ uint32_t step(const JobView &, MonState &ms, const Counts &X,
+                                                    uint32_t k, double t)
+    {
+        constexpr MonProg mp = Spec::mon;
+        return mon_step(&mp, ms, X, k, t);
+    }
+    __device__ static __forceinline__ uint32_t advance(const JobView &, MonState &ms, double tn,
+                                                       bool absorbing)
+    {
+        constexpr MonProg mp = Spec::mon;
+        return mon_advance(&mp, ms, tn, absorbing);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Stopping rule on the device.
+// ---------------------------------------------------------------------------
+__device__ unsigned long long sum_shards(unsigned long long (*arr)[kShards], int b)
+{
+    unsigned long long s = 0;
+#pragma unroll 1
+    for (int q = 0; q < kShards; ++q) s += ld_relaxed(&arr[b][q]);
+    return s;
+}
+
+// Evaluate batch b (all of its trajectories are counted) and possibly the
+// batches after it.  Exactly one lane evaluates each batch.
+__device__ void evaluate_batches(const JobView &V, Control *ctl, int b)
+{
+    JobState *st = V.st;
+    for (;;) {
+        if (atomicCAS(&st->evaluated[b], 0, 1) != 0) return;
+        __threadfence();
+        unsigned long long Y = 0;
+        for (int q = 0; q <= b; ++q) Y += sum_shards(st->yes, q);
+        const unsigned long long Bb = ld_acquire(&st->bound[b]);
+        const double p_hat = (double)Y / (double)Bb;
+        const unsigned long long Np = next_sample(p_hat, V.eps, V.z, V.literal);
+        if (Np > Bb && b + 1 < kMaxBatches && Np <= V.capacity) {
+            st_release(&st->bound[b + 1], Np);
+            st_release(&st->cur, b + 1);
+            atomicMax(&st->limit, Np);
+            __threadfence();
+            const unsigned long long d = ld_acquire(&st->done[b + 1]);
+            if (d == Np - Bb) {
+                b = b + 1;
+                continue;
+            }
+            return;
+        }
+        unsigned long long E = 0, T = 0;
+        for (int q = 0; q <= b; ++q) {
+            E += sum_shards(st->events, q);
+            T += sum_shards(st->trunc, q);
+        }
+        st->n_final = Bb;
+        st->yes_final = Y;
+        st->events_final = E;
+        st->trunc_final = T;
+        st->n_batches = b + 1;
+        st->overflow = (Np > Bb) ? 1 : 0;
+        __threadfence();
+        st_release(&st->final_flag, 1);
+        atomicSub(&ctl->open_jobs, 1);
+        return;
+    }
+}
+
+// While batch c is pending, raise the issue limit to the smallest next bound
+// that any possible outcome of batch c would produce (minus one for safety).
+__device__ void speculate(const JobView &V, int c)
+{
+    JobState *st = V.st;
+    const unsigned long long Bc = ld_acquire(&st->bound[c]);
+    const unsigned long long Bp = c ? ld_acquire(&st->bound[c - 1]) : 0ull;
+    if (Bc == 0) return;
+    unsigned long long Yprev = 0;
+    for (int q = 0; q < c; ++q) Yprev += sum_shards(st->yes, q);
+    const unsigned long long ylo = sum_shards(st->yes, c);
+    const unsigned long long nlo = sum_shards(st->no, c);
+    const unsigned long long size = Bc - Bp;
+    if (ylo + nlo > size) return;
+    const double plo = (double)(Yprev + ylo) / (double)Bc;
+    const double phi = (double)(Yprev + size - nlo) / (double)Bc;
+    unsigned long long g = next_sample(plo, V.eps, V.z, V.literal);
+    const unsigned long long g2 = next_sample(phi, V.eps, V.z, V.literal);
+    g = g2 < g ? g2 : g;
+    if (V.literal && plo <= 0.5 && phi >= 0.5) {
+        const unsigned long long g3 = next_sample(0.5, V.eps, V.z, V.literal);
+        g = g3 < g ? g3 : g;
+    }
+    if (g > 1) g -= 1;
+    if (g > Bc) {
+        if (g > V.capacity) g = V.capacity;
+        atomicMax(&st->limit, g);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Job selection and index claims.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool claimable(const Job *jobs, int j)
+{
+    JobState *st = jobs[j].st;
+    return ld_relaxed(&st->next) < ld_relaxed(&st->limit) && ld_relaxed(&st->final_flag) == 0;
+}
+
+// Wave-cooperative scan for a job with issuable indices, starting at `start`.
+__device__ int pick_job(const Job *jobs, int n_jobs, int start)
+{
+    const int lane = lane_id();
+    for (int base = 0; base < n_jobs; base += kWave) {
+        const int q = base + lane;
+        int j = start + q;
+        if (j >= n_jobs) j -= n_jobs;
+        const bool ok = (q < n_jobs) && claimable(jobs, j);
+        const uint64_t m = __ballot(ok);
+        if (m) return __builtin_amdgcn_readlane(j, ffs64(m));
+    }
+    return -1;
+}
+
+// Claim a chunk of consecutive relative indices below the job's issue limit;
+// returns the count, *base = first.  The chunk shrinks as the remaining work
+// shrinks (guided self-scheduling) so that the last trajectories spread over
+// the waves, but never below one index per lane of the wave (nor below
+// `need`) while that many remain: each claim is an atomic on one counter
+// shared by every wave of the job.
+//  - fixed-sample jobs: the limit never moves, so a fetch-add suffices (a
+//    claim past the end simply gets nothing);
+//  - iterative jobs: the limit rises while the job runs, so indices are
+//    claimed by compare-and-swap below the current limit, with back-off.
+__device__ int claim(JobState *st, bool iterative, int need, int n_waves, unsigned long long *base)
+{
+    unsigned long long cur = ld_relaxed(&st->next);
+    unsigned long long lim = ld_relaxed(&st->limit);
+    if (cur >= lim) return 0;
+    unsigned long long want = (lim - cur) / (4ull * (unsigned long long)n_waves);
+    if (want < (unsigned long long)need) want = (unsigned long long)need;
+    // At least a wave's worth: claims of a few indices at a time (when lanes
+    // finish one by one) turn the issue counter into a contended hot spot.
+    if (want < (unsigned long long)kWave) want = kWave;
+    if (want > 256ull) want = 256ull;
+    if (!iterative) {
+        const unsigned long long b = atomicAdd(&st->next, want);
+        if (b >= lim) return 0;
+        *base = b;
+        return (int)((lim - b) < want ? (lim - b) : want);
+    }
+    for (int tries = 0; tries < 16; ++tries) {
+        if (cur >= lim) return 0;
+        const unsigned long long w = (lim - cur) < want ? (lim - cur) : want;
+        const unsigned long long prev = atomicCAS(&st->next, cur, cur + w);
+        if (prev == cur) {
+            *base = cur;
+            return (int)w;
+        }
+        cur = prev;
+        lim = ld_relaxed(&st->limit);
+        __builtin_amdgcn_s_sleep(4);
+    }
+    return 0;
+}
+
+struct KArgs {
+    const Job *jobs;
+    int n_jobs;
+    int s_max;
+    Control *ctl;
+    const volatile int32_t *cancel;   // host-visible stop word
+    int spin_limit;
+    int waves_per_block;
+};
+
+// Add a wave's counts for batch b of its job to the sharded counters.
+__device__ __forceinline__ void add_counts(JobState *st, int b, int shard, unsigned long long ny,
+                                           unsigned long long nn, unsigned long long nt,
+                                           unsigned long long ev)
+{
+    if (ny) atomicAdd(&st->yes[b][shard], ny);
+    if (nn) atomicAdd(&st->no[b][shard], nn);
+    if (nt) atomicAdd(&st->trunc[b][shard], nt);
+    if (ev) atomicAdd(&st->events[b][shard], ev);
+}
+
+// ---------------------------------------------------------------------------
+// The persistent kernel.
+// ---------------------------------------------------------------------------
+template <class Pol>
+__device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
+{
+    const int lane = lane_id();
+    const int wid = (int)(threadIdx.x / kWave);
+    typename Pol::Counts X = Pol::counts(lds, wid, A.s_max, lane);
+    const int gwave = (int)blockIdx.x * A.waves_per_block + wid;
+    const int shard = gwave & (kShards - 1);
+    const int n_waves = (int)gridDim.x * A.waves_per_block;
+    const int start = (int)(((long long)gwave * A.n_jobs) / n_waves);
+
+    int cur = -1;
+    JobView V;
+    bool active = false, fin = false;
+    unsigned long long ridx = 0;
+    uint32_t k = 0, verdict = 0, reason = 0;
+    double t = 0.0;
+    MonState ms;
+    mon_init(ms);
+    Draw dr{0.0, 0.0};   // random numbers of the lane's next event (index k)
+    int spins = 0;
+    // wave-local pool of claimed, not yet started indices [pool_next, pool_end)
+    unsigned long long pool_next = 0, pool_end = 0;
+    // fixed-sample jobs: per-lane counts, added to the job once per wave
+    uint32_t my_yes = 0, my_no = 0, my_trunc = 0;
+    unsigned long long my_events = 0;
+
+    for (uint32_t it = 0;; ++it) {
+        if ((it & 255u) == 0u) {
+            int stop = 0;
+            if (lane == 0) stop = *A.cancel;
+            if (uniform_i(stop)) break;
+        }
+        if (__ballot(active) == 0ull && pool_next == pool_end) {
+            const int j = pick_job(A.jobs, A.n_jobs, start);
+            if (j != cur && cur >= 0 && !V.iterative) {
+                // leaving a fixed-sample job: publish this wave's counts
+                const unsigned long long ny = wave_sum_u64(my_yes), nn = wave_sum_u64(my_no);
+                const unsigned long long nt = wave_sum_u64(my_trunc), ev = wave_sum_u64(my_events);
+                if (lane == 0) add_counts(V.st, 0, shard, ny, nn, nt, ev);
+                my_yes = my_no = my_trunc = my_events = 0;
+            }
+            if (j < 0) {
+                cur = -1;
+                if (ld_relaxed(&A.ctl->open_jobs) <= 0) break;
+                __builtin_amdgcn_s_sleep(127);
+                if (++spins > A.spin_limit) break;
+                continue;
+            }
+            spins = 0;
+            if (j != cur) {
+                cur = j;
+                V.load(A.jobs, cur);
+            }
+        }
+        // -------- refill idle lanes with new trajectory indices --------
+        bool entered = false;   // this lane entered a state in this iteration
+        const uint64_t need = __ballot(!active);
+        if (need) {
+            const int n_need = __popcll(need);
+            if (pool_next == pool_end) {
+                unsigned long long base = 0;
+                int got = 0;
+                if (lane == 0) got = claim(V.st, V.iterative != 0, n_need, n_waves, &base);
+                got = __builtin_amdgcn_readfirstlane(got);
+                base = read_lane_u64(base, 0);
+                pool_next = base;
+                pool_end = base + (unsigned long long)got;
+            }
+            const unsigned long long avail = pool_end - pool_next;
+            const int give = (unsigned long long)n_need < avail ? n_need : (int)avail;
+            const int r = rank_in(need);
+            if (!active && r < give) {
+                ridx = pool_next + (unsigned long long)r;
+                Pol::init(X, V);
+                t = 0.0;
+                k = 0;
+                mon_init(ms);
+                active = true;
+                entered = true;
+            }
+            pool_next += (unsigned long long)give;
+        }
+        if (__ballot(active) == 0ull) continue;
+
+        // The event and the inspection of the state it enters run as straight-
+        // line code on every lane, and each lane keeps only the results that
+        // apply to it (selects, no divergent branches): masked-off lanes would
+        // occupy the same issue slots anyway, and a single basic block lets the
+        // compiler interleave the independent dependency chains below.
+        //
+        // Random numbers this lane needs next: those of event k + 1, or of
+        // event 0 of a trajectory it has just started.  Nothing below feeds
+        // them, so their computation overlaps the event.
+        const Draw nxt = event_uniforms(V, V.first + ridx, entered ? 0u : k + 1u);
+
+        // -------- one event per running lane --------
+        const bool ev_lane = active && !entered;
+        const bool capped = V.max_events != 0u && k == V.max_events;
+        typename Pol::Sel ch;
+        const double tn = Pol::draw(V, X, dr, t, &ch);
+        const bool absorbing = __builtin_isinf(tn);
+        MonState ms_adv = ms;
+        const uint32_t va = Pol::advance(V, ms_adv, tn, absorbing);
+        const bool stepping = ev_lane && !capped;
+        const bool dec_time = stepping && va != 0u;
+        const bool dec_tmax = stepping && va == 0u && tn > V.t_max;
+        const bool applied = stepping && va == 0u && !(tn > V.t_max);
+        ms_select(ms, ms_adv, stepping);
+        Pol::apply_if(X, ch, applied);
+        t = applied ? tn : t;
+        k = applied ? k + 1u : k;
+        entered = entered || applied;
+        fin = fin || (ev_lane && capped) || dec_time || dec_tmax;
+        verdict = dec_time ? (va == 1u ? 1u : 0u) : ((ev_lane && capped) || dec_tmax ? 0u : verdict);
+        reason = (ev_lane && capped) ? (uint32_t)RS_CAP
+                 : dec_time           ? (uint32_t)(absorbing ? RS_ABSORB : RS_TIME)
+                 : dec_tmax           ? (uint32_t)RS_TMAX
+                                      : reason;
+
+        // -------- inspect the state just entered (new or after an event) --------
+        MonState ms_st = ms;
+        const uint32_t vs = Pol::step(V, ms_st, X, k, t);
+        ms_select(ms, ms_st, entered);
+        dr.nl = entered ? nxt.nl : dr.nl;   // field by field: a select of whole
+        dr.u2 = entered ? nxt.u2 : dr.u2;   // structs would go through memory
+        const bool dec_state = entered && vs != 0u;
+        fin = fin || dec_state;
+        verdict = dec_state ? (vs == 1u ? 1u : 0u) : verdict;
+        reason = dec_state ? (uint32_t)RS_STATE : reason;
+
+        // -------- accounting of decided trajectories --------
+        uint64_t fm = __ballot(fin);
+        if (fm) {
+            if (fin) {
+                if (V.rec_events) V.rec_events[ridx] = k;
+                if (V.rec_vr) V.rec_vr[ridx] = (uint8_t)(verdict | (reason << 1));
+            }
+            if (!V.iterative) {
+                if (fin) {
+                    my_yes += verdict;
+                    my_no += 1u - verdict;
+                    my_trunc += (reason == RS_CAP) ? 1u : 0u;
+                    my_events += k;
+                    fin = false;
+                    active = false;
+                }
+                continue;
+            }
+            int b = 0;
+            if (fin) {
+                while (b < kMaxBatches - 1) {
+                    const unsigned long long bb = ld_relaxed(&V.st->bound[b]);
+                    if (bb == 0ull || ridx < bb) break;
+                    ++b;
+                }
+            }
+            while (fm) {
+                const int L = ffs64(fm);
+                const int b0 = __builtin_amdgcn_readlane(b, L);
+                const bool sel = fin && (b == b0);
+                const uint64_t sm = __ballot(sel);
+                const uint32_t ny = (uint32_t)__popcll(__ballot(sel && verdict));
+                const uint32_t nn = (uint32_t)__popcll(sm) - ny;
+                const uint32_t nt = (uint32_t)__popcll(__ballot(sel && reason == RS_CAP));
+                const unsigned long long ev = wave_sum_u64(sel ? (unsigned long long)k : 0ull);
+                if (lane == L) {
+                    JobState *st = V.st;
+                    add_counts(st, b0, shard, ny, nn, nt, ev);
+                    __threadfence();
+                    const unsigned long long d =
+                        atomicAdd(&st->done[b0], (unsigned long long)(ny + nn)) + ny + nn;
+                    __threadfence();
+                    const unsigned long long hi = ld_acquire(&st->bound[b0]);
+                    const unsigned long long lo = b0 ? ld_acquire(&st->bound[b0 - 1]) : 0ull;
+                    if (hi != 0ull && d == hi - lo) evaluate_batches(V, A.ctl, b0);
+                    else if (b0 == ld_relaxed(&st->cur)) speculate(V, b0);
+                }
+                fm &= ~sm;
+                if (sel) {
+                    fin = false;
+                    active = false;
+                }
+            }
+        }
+    }
+    // publish the counts of a fixed-sample job this wave was still working on
+    if (cur >= 0 && !V.iterative) {
+        const unsigned long long ny = wave_sum_u64(my_yes), nn = wave_sum_u64(my_no);
+        const unsigned long long nt = wave_sum_u64(my_trunc), ev = wave_sum_u64(my_events);
+        if (lane == 0) add_counts(V.st, 0, shard, ny, nn, nt, ev);
+    }
+}
+
+}  // namespace smc

@@ -56,20 +56,38 @@ TRAJ_CASES = [
 ]
 
 
+# formulas with arithmetic (RPN) predicates always run on the generic kernel
+GENERIC_ONLY = {"arith"}
+
+
+@pytest.mark.parametrize("mode", ["generic", "specialized"])
 @pytest.mark.parametrize("name,make,text,kw,count", TRAJ_CASES, ids=[c[0] for c in TRAJ_CASES])
-def test_trajectory_parity(ctx, name, make, text, kw, count):
+def test_trajectory_parity(ctx, name, make, text, kw, count, mode):
     B = _B()
     net = make()
     n = ctx.network(net)
     f = ctx.formula(n, text)
-    for first, seed in ((0, 1), (123457, 99)):
-        p = B.params(seed=seed, model_id=3, **kw)
-        ev, vd, rs = ctx.trajectories(n, f, p, first, count)
-        oev, ovd, ors = oracle.trajectories(net, oracle.parse(text, net), first, count, seed=seed,
-                                            model_id=3, **kw)
-        assert np.array_equal(rs, ors), (name, np.nonzero(rs != ors)[0][:5])
-        assert np.array_equal(vd, ovd), (name, np.nonzero(vd != ovd)[0][:5])
-        assert np.array_equal(ev, oev), (name, np.nonzero(ev != oev)[0][:5])
+    if mode == "generic":
+        ctx.set_specialization(B.SPECIALIZE_OFF)
+    elif name in GENERIC_ONLY:
+        pytest.skip("arithmetic predicates are not specialised")
+    else:
+        ctx.set_specialization(B.SPECIALIZE_REQUIRED)
+    try:
+        for first, seed in ((0, 1), (123457, 99)):
+            p = B.params(seed=seed, model_id=3, **kw)
+            print(f"case {name} mode {mode} first {first} seed {seed}", flush=True)
+            ev, vd, rs = ctx.trajectories(n, f, p, first, count)
+            expect = B.KERNEL_SPECIALIZED if mode == "specialized" else (
+                B.KERNEL_GENERIC_SMALL if net.M <= 4 else B.KERNEL_GENERIC)
+            assert ctx.last_kernel() == expect
+            oev, ovd, ors = oracle.trajectories(net, oracle.parse(text, net), first, count, seed=seed,
+                                                model_id=3, **kw)
+            assert np.array_equal(rs, ors), (name, np.nonzero(rs != ors)[0][:5])
+            assert np.array_equal(vd, ovd), (name, np.nonzero(vd != ovd)[0][:5])
+            assert np.array_equal(ev, oev), (name, np.nonzero(ev != oev)[0][:5])
+    finally:
+        ctx.set_specialization(B.SPECIALIZE_AUTO)
 
 
 def test_c3_random_network_parity(ctx):
@@ -225,3 +243,37 @@ def test_errors_and_edges(ctx):
     r = ctx.estimate(n, f2, B.params(fixed_n=1))
     o = oracle.estimate(net, W.C1_FORMULA, fixed_n=1)
     assert (r["n"], r["successes"], r["events"]) == (o["n"], o["successes"], o["events"])
+
+
+def test_specialized_kernel_selection_and_estimates(ctx):
+    """One specialised kernel serves a rate sweep over one structure (a batch of
+    Michaelis-Menten rate sets); mixed structures use the generic kernel; the
+    estimates are identical either way."""
+    B = _B()
+    rates = W.mm_sweep(48, seed=11)
+    keep, jobs = [], []
+    for k, rr in enumerate(rates):
+        nh = ctx.network(W.michaelis_menten(*rr))
+        fh = ctx.formula(nh, W.MM_COMPANION_FORMULA)
+        keep.append((nh, fh))
+        jobs.append((nh, fh, B.params(half_width=0.05, seed=3, model_id=k)))
+    out = {}
+    for mode in (B.SPECIALIZE_OFF, B.SPECIALIZE_AUTO):
+        ctx.set_specialization(mode)
+        out[mode] = ctx.estimate_batch(jobs)
+        assert ctx.last_kernel() == (B.KERNEL_SPECIALIZED if mode == B.SPECIALIZE_AUTO else B.KERNEL_GENERIC_SMALL)
+    keys = ("n", "successes", "events", "batches", "p_hat", "lo", "hi")
+    assert [tuple(r[k] for k in keys) for r in out[B.SPECIALIZE_OFF]] == \
+           [tuple(r[k] for k in keys) for r in out[B.SPECIALIZE_AUTO]]
+    # a different structure in the same launch: generic kernel
+    c1 = ctx.network(W.immigration_death())
+    f1 = ctx.formula(c1, W.C1_FORMULA)
+    mixed = jobs[:4] + [(c1, f1, B.params(half_width=0.05, seed=3, model_id=99))]
+    r_mixed = ctx.estimate_batch(mixed)
+    assert ctx.last_kernel() == B.KERNEL_GENERIC_SMALL
+    assert [tuple(r[k] for k in keys) for r in r_mixed[:4]] == \
+           [tuple(r[k] for k in keys) for r in out[B.SPECIALIZE_AUTO][:4]]
+    ctx.set_specialization(B.SPECIALIZE_REQUIRED)
+    with pytest.raises(B.SmcError):
+        ctx.estimate_batch(mixed)
+    ctx.set_specialization(B.SPECIALIZE_AUTO)
