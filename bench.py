@@ -35,7 +35,7 @@ PEAK_VALU_SLOTS = 256 * 64 * 2.4e9    # CUs x lanes x clock: 3.93e13 lane-slots/
 N_TRAJ = 10**6
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ssa_persistent_mm_c2_hbm_counters.txt")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ssa_spec_kernel_mm_c2_hbm_counters.txt")
 KERNEL_SOURCES = ["paper_0912_2551_amd/csrc/ssa_core.h", "paper_0912_2551_amd/csrc/ssa_kernel.hip",
                   "paper_0912_2551_amd/csrc/smc_device.h", "paper_0912_2551_amd/csrc/spec.cpp"]
 
