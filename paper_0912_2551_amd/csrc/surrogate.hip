@@ -9,7 +9,7 @@
 //   - every product-sum accumulates in FP32; biases, losses, gradients and
 //     the Adam state are FP32; FP32 master weights are rounded to BF16 after
 //     every update;
-//   - batch sums run in index order (no atomics), so results are repeatable.
+//   - batch sums run in a fixed order (no atomics), so results are repeatable.
 // Layer 2 (K = 256) and its two backward products run on MFMA; layers 1
 // (K = 3) and 3 (N = 1) are vector work.
 #include <hip/hip_runtime.h>
@@ -122,46 +122,61 @@ __global__ void layer3_forward_loss(const uint16_t *h2b, int n, const uint16_t *
     }
 }
 
-// Column sums over rows in order: dW3[j] = sum_b dz_b h2b[b][j], db3 = sum dz;
-// d2 = dz W3b relu'(pre2), d2b = bf16(d2).
-__global__ void layer3_backward(const uint16_t *h2b, const float *pre2, int n, const uint16_t *W3b,
-                                const float *dz, float *dW3, float *db3, float *d2, uint16_t *d2b)
+// Batch reductions (column sums over the n rows of a [n][256] activation):
+// a block of 64 columns x 16 row slices; thread (c, q) accumulates rows q,
+// q + 16, q + 32, ... of column c in order (a wave reads 64 consecutive
+// columns of one row), then the 16 slice sums are added in slice order, so
+// the result does not depend on scheduling.
+constexpr int kColBlock = 64;
+constexpr int kSlices = 16;
+
+// dW3[j] = sum_b dz_b h2b[b][j], db3 = sum_b dz_b; d2 = dz W3b relu'(pre2)
+// stored as d2b = bf16(d2) (the operand of both layer-2 backward products);
+// db2[j] = sum_b d2[b][j] (FP32, before rounding).
+__global__ __launch_bounds__(kColBlock * kSlices) void layer3_backward(
+    const uint16_t *h2b, const float *pre2, int n, const uint16_t *W3b, const float *dz, float *dW3,
+    float *db3, float *db2, uint16_t *d2b)
 {
-    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (j >= kH) return;
+    __shared__ float red[3][kSlices][kColBlock];
+    const int c = (int)(threadIdx.x % kColBlock), q = (int)(threadIdx.x / kColBlock);
+    const int j = (int)blockIdx.x * kColBlock + c;
     const float w3 = from_bf16(W3b[j]);
-    float s = 0.0f, sz = 0.0f;
-    for (int b = 0; b < n; ++b) {
+    float sw = 0.0f, sd = 0.0f, sz = 0.0f;
+    for (int b = q; b < n; b += kSlices) {
         const long t = (long)b * kH + j;
         const float g = dz[b];
-        s = fmaf(g, from_bf16(h2b[t]), s);
+        sw = fmaf(g, from_bf16(h2b[t]), sw);
         sz += g;
         const float d = pre2[t] > 0.0f ? g * w3 : 0.0f;
-        d2[t] = d;
+        sd += d;
         d2b[t] = to_bf16(d);
     }
-    dW3[j] = s;
-    if (j == 0) db3[0] = sz;
-}
-
-// db2[j] = sum_b d2[b][j].
-__global__ void column_sum(const float *a, int n, float *out)
-{
-    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (j >= kH) return;
-    float s = 0.0f;
-    for (int b = 0; b < n; ++b) s += a[(long)b * kH + j];
-    out[j] = s;
+    red[0][q][c] = sw;
+    red[1][q][c] = sd;
+    red[2][q][c] = sz;
+    __syncthreads();
+    if (q == 0) {
+        float a = 0.0f, bb = 0.0f, z = 0.0f;
+        for (int r = 0; r < kSlices; ++r) {
+            a += red[0][r][c];
+            bb += red[1][r][c];
+            z += red[2][r][c];
+        }
+        dW3[j] = a;
+        db2[j] = bb;
+        if (j == 0) db3[0] = z;
+    }
 }
 
 // d1 = dh1 relu'(pre1); dW1[j][k] = sum_b d1 xb[b][k]; db1[j] = sum_b d1.
-__global__ void layer1_backward(const float *dh1, const float *pre1, const uint16_t *xb, int n,
-                                float *dW1, float *db1)
+__global__ __launch_bounds__(kColBlock * kSlices) void layer1_backward(
+    const float *dh1, const float *pre1, const uint16_t *xb, int n, float *dW1, float *db1)
 {
-    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (j >= kH) return;
+    __shared__ float red[4][kSlices][kColBlock];
+    const int c = (int)(threadIdx.x % kColBlock), q = (int)(threadIdx.x / kColBlock);
+    const int j = (int)blockIdx.x * kColBlock + c;
     float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, sb = 0.0f;
-    for (int b = 0; b < n; ++b) {
+    for (int b = q; b < n; b += kSlices) {
         const long t = (long)b * kH + j;
         const float d = pre1[t] > 0.0f ? dh1[t] : 0.0f;
         s0 = fmaf(d, from_bf16(xb[b * 3 + 0]), s0);
@@ -169,10 +184,41 @@ __global__ void layer1_backward(const float *dh1, const float *pre1, const uint1
         s2 = fmaf(d, from_bf16(xb[b * 3 + 2]), s2);
         sb += d;
     }
-    dW1[j * 3 + 0] = s0;
-    dW1[j * 3 + 1] = s1;
-    dW1[j * 3 + 2] = s2;
-    db1[j] = sb;
+    red[0][q][c] = s0;
+    red[1][q][c] = s1;
+    red[2][q][c] = s2;
+    red[3][q][c] = sb;
+    __syncthreads();
+    if (q == 0) {
+        float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, ab = 0.0f;
+        for (int r = 0; r < kSlices; ++r) {
+            a0 += red[0][r][c];
+            a1 += red[1][r][c];
+            a2 += red[2][r][c];
+            ab += red[3][r][c];
+        }
+        dW1[j * 3 + 0] = a0;
+        dW1[j * 3 + 1] = a1;
+        dW1[j * 3 + 2] = a2;
+        db1[j] = ab;
+    }
+}
+
+// out[0] = sum of the n per-row losses: thread t sums rows t, t + 256, ...
+// in order (FP64), then the 256 partial sums are added in thread order.
+__global__ __launch_bounds__(256) void loss_sum(const float *loss_row, int n, float *out)
+{
+    __shared__ double part[256];
+    const int t = (int)threadIdx.x;
+    double acc = 0.0;
+    for (int b = t; b < n; b += 256) acc += (double)loss_row[b];
+    part[t] = acc;
+    __syncthreads();
+    if (t == 0) {
+        double s = 0.0;
+        for (int r = 0; r < 256; ++r) s += part[r];
+        out[0] = (float)s;
+    }
 }
 
 // Adam on FP32 masters; BF16 copies of the weight matrices refreshed.
@@ -319,23 +365,25 @@ hipError_t sg_layer3_forward_loss(hipStream_t s, const uint16_t *h2b, int n, con
 }
 
 hipError_t sg_layer3_backward(hipStream_t s, const uint16_t *h2b, const float *pre2, int n,
-                              const uint16_t *W3b, const float *dz, float *dW3, float *db3, float *d2,
+                              const uint16_t *W3b, const float *dz, float *dW3, float *db3, float *db2,
                               uint16_t *d2b)
 {
-    hipLaunchKernelGGL(layer3_backward, dim3(1), dim3(kH), 0, s, h2b, pre2, n, W3b, dz, dW3, db3, d2, d2b);
-    return hipGetLastError();
-}
-
-hipError_t sg_column_sum(hipStream_t s, const float *a, int n, float *out)
-{
-    hipLaunchKernelGGL(column_sum, dim3(1), dim3(kH), 0, s, a, n, out);
+    hipLaunchKernelGGL(layer3_backward, dim3(kH / kColBlock), dim3(kColBlock * kSlices), 0, s, h2b, pre2, n,
+                       W3b, dz, dW3, db3, db2, d2b);
     return hipGetLastError();
 }
 
 hipError_t sg_layer1_backward(hipStream_t s, const float *dh1, const float *pre1, const uint16_t *xb, int n,
                               float *dW1, float *db1)
 {
-    hipLaunchKernelGGL(layer1_backward, dim3(1), dim3(kH), 0, s, dh1, pre1, xb, n, dW1, db1);
+    hipLaunchKernelGGL(layer1_backward, dim3(kH / kColBlock), dim3(kColBlock * kSlices), 0, s, dh1, pre1, xb,
+                       n, dW1, db1);
+    return hipGetLastError();
+}
+
+hipError_t sg_loss_sum(hipStream_t s, const float *loss_row, int n, float *out)
+{
+    hipLaunchKernelGGL(loss_sum, dim3(1), dim3(256), 0, s, loss_row, n, out);
     return hipGetLastError();
 }
 

@@ -26,11 +26,11 @@ hipError_t sg_layer3_forward_loss(hipStream_t s, const uint16_t *h2b, int n, con
                                   const float *b3, const float *y, const float *w, float inv_wsum,
                                   float *p_out, float *loss_row, float *dz);
 hipError_t sg_layer3_backward(hipStream_t s, const uint16_t *h2b, const float *pre2, int n,
-                              const uint16_t *W3b, const float *dz, float *dW3, float *db3, float *d2,
+                              const uint16_t *W3b, const float *dz, float *dW3, float *db3, float *db2,
                               uint16_t *d2b);
-hipError_t sg_column_sum(hipStream_t s, const float *a, int n, float *out);
 hipError_t sg_layer1_backward(hipStream_t s, const float *dh1, const float *pre1, const uint16_t *xb, int n,
                               float *dW1, float *db1);
+hipError_t sg_loss_sum(hipStream_t s, const float *loss_row, int n, float *out);
 hipError_t sg_adam(hipStream_t s, float *w, const float *g, float *m, float *v, uint16_t *wb, long count,
                    float lr, float beta1, float beta2, float eps, float bc1, float bc2);
 hipError_t sg_round(hipStream_t s, const float *w, uint16_t *wb, long count);
@@ -61,7 +61,7 @@ struct smc_surrogate {
     long step = 0;
     // activations for a training batch of up to cap rows
     int cap = 0;
-    float *x = nullptr, *y = nullptr, *wt = nullptr, *pre1 = nullptr, *pre2 = nullptr, *d2 = nullptr,
+    float *x = nullptr, *y = nullptr, *wt = nullptr, *pre1 = nullptr, *pre2 = nullptr,
           *dh1 = nullptr, *p = nullptr, *loss_row = nullptr, *dz = nullptr;
     uint16_t *xb = nullptr, *h1b = nullptr, *h2b = nullptr, *d2b = nullptr;
     // query buffers
@@ -119,7 +119,6 @@ int ensure_batch(smc_surrogate *s, int n)
     SG_TRY(s, dalloc(s->xb, (size_t)c * 3));
     SG_TRY(s, dalloc(s->pre1, (size_t)c * H));
     SG_TRY(s, dalloc(s->pre2, (size_t)c * H));
-    SG_TRY(s, dalloc(s->d2, (size_t)c * H));
     SG_TRY(s, dalloc(s->dh1, (size_t)c * H));
     SG_TRY(s, dalloc(s->h1b, (size_t)c * H));
     SG_TRY(s, dalloc(s->h2b, (size_t)c * H));
@@ -165,11 +164,10 @@ int forward_backward(smc_surrogate *s, int n, float inv_wsum)
     SG_TRY(s, sg_layer2_epilogue(st, s->pre2, n, w + OFF_B2, s->h2b));
     SG_TRY(s, sg_layer3_forward_loss(st, s->h2b, n, wb + OFF_W3, w + OFF_B3, s->y, s->wt, inv_wsum, s->p,
                                      s->loss_row, s->dz));
-    SG_TRY(s, sg_layer3_backward(st, s->h2b, s->pre2, n, wb + OFF_W3, s->dz, g + OFF_W3, g + OFF_B3, s->d2,
-                                 s->d2b));
+    SG_TRY(s, sg_layer3_backward(st, s->h2b, s->pre2, n, wb + OFF_W3, s->dz, g + OFF_W3, g + OFF_B3,
+                                 g + OFF_B2, s->d2b));
     // dW2[j][i] = sum_b d2b[b][j] h1b[b][i]
     SG_TRY(s, sg_gemm(st, s->d2b, 1, H, s->h1b, H, 1, g + OFF_W2, H, H, H, n, 0));
-    SG_TRY(s, sg_column_sum(st, s->d2, n, g + OFF_B2));
     // dh1[b][i] = sum_j d2b[b][j] W2b[j][i]
     SG_TRY(s, sg_gemm(st, s->d2b, H, 1, wb + OFF_W2, H, 1, s->dh1, H, n, H, H, 0));
     SG_TRY(s, sg_layer1_backward(st, s->dh1, s->pre1, s->xb, n, g + OFF_W1, g + OFF_B1));
@@ -308,18 +306,25 @@ int smc_surrogate_train(smc_surrogate *s, const float *x, const float *y, const 
     const float b1 = opts->beta1 > 0.0f ? opts->beta1 : 0.9f;
     const float b2 = opts->beta2 > 0.0f ? opts->beta2 : 0.999f;
     const float eps = opts->adam_eps > 0.0f ? opts->adam_eps : 1e-8f;
+    // per-step losses are summed on the device and copied back once
+    float *hist = nullptr;
+    if (loss_out) SG_TRY(s, hipMalloc((void **)&hist, (size_t)opts->steps * sizeof(float)));
+    struct Free {
+        float *p;
+        ~Free() { if (p) (void)hipFree(p); }
+    } free_hist{hist};
     for (uint32_t it = 0; it < opts->steps; ++it) {
         rc = forward_backward(s, np, inv);
         if (rc != SMC_OK) return rc;
-        if (loss_out) {
-            rc = sum_loss(s, np, &loss_out[it]);
-            if (rc != SMC_OK) return rc;
-        }
+        if (hist) SG_TRY(s, sg_loss_sum(s->stream, s->loss_row, np, hist + it));
         s->step += 1;
         const float bc1 = 1.0f - std::pow(b1, (float)s->step);
         const float bc2 = 1.0f - std::pow(b2, (float)s->step);
         SG_TRY(s, sg_adam(s->stream, s->w, s->g, s->m, s->v, s->wb, N_PARAMS, opts->lr, b1, b2, eps, bc1, bc2));
     }
+    if (hist)
+        SG_TRY(s, hipMemcpyAsync(loss_out, hist, (size_t)opts->steps * sizeof(float), hipMemcpyDeviceToHost,
+                                 s->stream));
     SG_TRY(s, hipStreamSynchronize(s->stream));
     return SMC_OK;
 }
@@ -374,7 +379,7 @@ void smc_surrogate_destroy(smc_surrogate *s)
 {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
-    for (float *p : {s->w, s->g, s->m, s->v, s->norm, s->planes, s->x, s->y, s->wt, s->pre1, s->pre2, s->d2,
+    for (float *p : {s->w, s->g, s->m, s->v, s->norm, s->planes, s->x, s->y, s->wt, s->pre1, s->pre2,
                      s->dh1, s->p, s->loss_row, s->dz, s->qx, s->qp})
         if (p) (void)hipFree(p);
     for (uint16_t *p : {s->wb, s->xb, s->h1b, s->h2b, s->d2b})
