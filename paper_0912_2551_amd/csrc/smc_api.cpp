@@ -159,6 +159,8 @@ int prepare(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_pa
     }
     if (first + capacity > (1ull << 32))
         return fail(ctx, SMC_E_INVALID, "trajectory indices must stay below 2^32");
+    if (iterative && capacity >= kMaxBatchSize)
+        return fail(ctx, SMC_E_INVALID, "iterative sample sizes must stay below 2^30 (half_width too small)");
     Job &J = out.job;
     std::memset(&J, 0, sizeof(J));
     J.net.S = net->S;
@@ -190,7 +192,7 @@ int prepare(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_pa
 
 // The specialised kernel for a launch, if every job shares one network
 // structure and formula that the specialisation supports (else nullptr).
-int pick_spec_kernel(smc_ctx *ctx, const std::vector<Prepared> &P, hipFunction_t *fn)
+int pick_spec_kernel(smc_ctx *ctx, const std::vector<Prepared> &P, bool iterative, hipFunction_t *fn)
 {
     *fn = nullptr;
     if (ctx->spec_mode == SMC_SPECIALIZE_OFF || P.empty()) return SMC_OK;
@@ -198,7 +200,7 @@ int pick_spec_kernel(smc_ctx *ctx, const std::vector<Prepared> &P, hipFunction_t
     const smc_formula *f0 = P[0].f;
     bool ok = n0 && f0 && spec_supported(n0->S, n0->M, f0->prog);
     std::string src;
-    if (ok) src = spec_source(n0->S, n0->M, n0->reac.data(), n0->chg.data(), f0->prog, ctx->spec_waves_per_simd);
+    if (ok) src = spec_source(n0->S, n0->M, n0->reac.data(), n0->chg.data(), f0->prog, ctx->spec_waves_per_simd, iterative);
     const smc_net *ln = n0;
     const smc_formula *lf = f0;
     for (size_t k = 1; ok && k < P.size(); ++k) {
@@ -206,7 +208,7 @@ int pick_spec_kernel(smc_ctx *ctx, const std::vector<Prepared> &P, hipFunction_t
         ln = P[k].net;
         lf = P[k].f;
         ok = ln && lf && ln->S == n0->S && ln->M == n0->M &&
-             spec_source(ln->S, ln->M, ln->reac.data(), ln->chg.data(), lf->prog, ctx->spec_waves_per_simd) == src;
+             spec_source(ln->S, ln->M, ln->reac.data(), ln->chg.data(), lf->prog, ctx->spec_waves_per_simd, iterative) == src;
     }
     if (!ok) {
         if (ctx->spec_mode == SMC_SPECIALIZE_REQUIRED)
@@ -268,7 +270,7 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
     const int grid = (int)std::max<unsigned long long>(1, (waves + wpb - 1) / wpb);
     const int variant = m_max <= 4 ? 0 : 1;
     hipFunction_t spec_fn = nullptr;
-    if (const int rc = pick_spec_kernel(ctx, P, &spec_fn)) return rc;
+    if (const int rc = pick_spec_kernel(ctx, P, n_iter > 0, &spec_fn)) return rc;
     ctx->last_kernel = spec_fn ? SMC_KERNEL_SPECIALIZED : (variant == 0 ? SMC_KERNEL_GENERIC_SMALL : SMC_KERNEL_GENERIC);
     res.assign(n, JobResult{});
     double total_ms = 0.0;
@@ -288,7 +290,7 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
             HIP_TRY(ctx, launch_module(spec_fn, grid, wpb, s, ctx->d_jobs, n, s_max, ctx->d_ctl,
                                        ctx->cancel_dev, 1 << 18));
         else
-            HIP_TRY(ctx, launch_persistent(variant, grid, wpb, lds_wave * wpb, s, ctx->d_jobs, n, s_max,
+            HIP_TRY(ctx, launch_persistent(variant, n_iter > 0, grid, wpb, lds_wave * wpb, s, ctx->d_jobs, n, s_max,
                                            ctx->d_ctl, ctx->cancel_dev, 1 << 18));
         HIP_TRY(ctx, launch_finalize(s, ctx->d_jobs, n, ctx->d_results));
         HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
@@ -349,7 +351,9 @@ void fill_result(const JobResult &r, double z, smc_result *out)
         out->lo = 0.0;
         out->hi = 1.0;
     }
-    out->status = r.overflow ? SMC_E_INVALID : SMC_OK;
+    // overflow 1: Fig. 2 needed more batches (or trajectories) than allowed;
+    // 2: a published bound fell below the look-ahead (an internal error)
+    out->status = r.overflow == 1 ? SMC_E_INVALID : r.overflow ? SMC_E_HIP : SMC_OK;
 }
 
 }  // namespace
@@ -633,7 +637,8 @@ int smc_estimate_batch(smc_ctx *c, const smc_job *jobs, size_t n_jobs, smc_resul
         out[k].device_seconds = secs;
         if (out[k].status != SMC_OK && first_err == SMC_OK) {
             first_err = out[k].status;
-            c->err = "stopping rule ran out of batch slots";
+            c->err = res[k].overflow == 1 ? "stopping rule ran out of batch slots"
+                                          : "stopping rule: a batch bound fell below the issued look-ahead";
         }
     }
     return first_err;

@@ -110,22 +110,32 @@ struct NetDev {
 
 // Per-job accounting (device memory).  Batch b covers relative trajectory
 // indices [bound[b-1], bound[b]) with bound[-1] = 0; bound[b] = 0 means "not
-// known yet".  Counters are replicated over kShards slots.
+// known yet".  Counters are replicated over kShards slots (spread atomics).
+//
+// Iterative jobs (Fig. 2) keep one counter word per batch, cnt[b] =
+// (TRUE verdicts << 32) + low word, where completions add to the low word
+// and the publication of bound[b] adds kDoneFlag - (bound[b] - bound[b-1]):
+// the batch is complete exactly when the low word equals kDoneFlag, and the
+// one atomic that makes it so (a completion or the publication) tells its
+// wave to evaluate the batch.  Batch sizes stay below 2^30, so the low word
+// never carries into the high one.
+constexpr unsigned long long kDoneFlag = 1ull << 31;
+constexpr unsigned long long kMaxBatchSize = 1ull << 30;
+
 struct JobState {
     unsigned long long next;                 // relative indices issued
     unsigned long long limit;                // indices below this may be issued
     unsigned long long bound[kMaxBatches];
-    unsigned long long yes[kMaxBatches][kShards];
-    unsigned long long no[kMaxBatches][kShards];
+    unsigned long long yes[kMaxBatches][kShards];    // fixed-sample jobs
+    unsigned long long no[kMaxBatches][kShards];     // fixed-sample jobs
     unsigned long long events[kMaxBatches][kShards];
     unsigned long long trunc[kMaxBatches][kShards];
-    unsigned long long done[kMaxBatches];    // completions (iterative jobs only)
-    int32_t evaluated[kMaxBatches];
+    unsigned long long cnt[kMaxBatches];             // iterative jobs, see above
     int32_t cur;                             // earliest batch not yet evaluated
     int32_t final_flag;                      // 1 = stopping rule satisfied
     int32_t n_batches;
     int32_t overflow;                        // ran out of batch slots
-    unsigned long long n_final, yes_final, events_final, trunc_final;
+    unsigned long long n_final, yes_final;
 };
 
 struct Job {

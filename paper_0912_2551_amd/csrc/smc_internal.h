@@ -21,7 +21,7 @@ struct Unsupported : std::runtime_error {
 void compile_formula(const std::string &text, const std::vector<std::string> &names, MonProg &out);
 
 // ssa_kernel.hip
-hipError_t launch_persistent(int nb_variant, int grid, int waves_per_block, size_t lds_bytes,
+hipError_t launch_persistent(int nb_variant, bool iterative, int grid, int waves_per_block, size_t lds_bytes,
                              hipStream_t stream, const Job *jobs, int n_jobs, int s_max,
                              Control *ctl, const volatile int32_t *cancel, int spin_limit);
 hipError_t launch_sample_state(int nb_variant, hipStream_t stream, const Job *job, double T,
@@ -40,7 +40,7 @@ hipError_t launch_wilson_table(hipStream_t stream, const unsigned long long *yes
 bool spec_supported(int S, int M, const MonProg &mp);
 // waves_per_simd > 0: register budget for that many waves per SIMD
 std::string spec_source(int S, int M, const int32_t *reac, const uint32_t *chg, const MonProg &mp,
-                        int waves_per_simd);
+                        int waves_per_simd, bool iterative);
 int spec_kernel(int device, const std::string &src, hipFunction_t *fn, std::string &err);
 
 }  // namespace smc

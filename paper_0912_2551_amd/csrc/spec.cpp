@@ -85,7 +85,7 @@ bool spec_supported(int S, int M, const MonProg &mp)
 }
 
 std::string spec_source(int S, int M, const int32_t *reac, const uint32_t *chg, const MonProg &mp,
-                        int waves_per_simd)
+                        int waves_per_simd, bool iterative)
 {
     std::string s;
     s.reserve(8192);
@@ -155,7 +155,8 @@ std::string spec_source(int S, int M, const int32_t *reac, const uint32_t *chg, 
     if (waves_per_simd > 0)
         attr += " __attribute__((amdgpu_waves_per_eu(" + std::to_string(waves_per_simd) + ", 8)))";
     s += "extern \"C\" __global__ " + attr + " void smc_spec_kernel(smc::KArgs A)\n{\n"
-         "    smc::persistent_body<smc::StaticPolicy<smc::gen::Spec>>(A, nullptr);\n}\n";
+         "    smc::persistent_body<smc::StaticPolicy<smc::gen::Spec>, " +
+         std::string(iterative ? "true" : "false") + ">(A, nullptr);\n}\n";
     return s;
 }
 

@@ -141,17 +141,6 @@ __device__ __forceinline__ T ld_relaxed(T *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-template <typename T>
-__device__ __forceinline__ T ld_acquire(T *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T>
-__device__ __forceinline__ void st_release(T *p, T v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
 __device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -785,63 +774,120 @@ __device__ unsigned long long sum_shards(unsigned long long (*arr)[kShards], int
     return s;
 }
 
-// Evaluate batch b (all of its trajectories are counted) and possibly the
-// batches after it.  Exactly one lane evaluates each batch.
-__device__ void evaluate_batches(const JobView &V, Control *ctl, int b)
+// A 64-bit value every lane holds identically, as a wave-uniform value.
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) { return read_lane_u64(v, 0); }
+
+// Wait until this wave's earlier memory operations have been performed.  The
+// stopping-rule state is only ever accessed with device-scope atomic
+// operations (read-modify-writes, and loads and stores at agent scope), which
+// the hardware performs coherently for the whole device; so making one
+// atomic visible before the next needs no cache write-back or invalidation
+// (which is what a device-scope fence does, for the whole L2), only this.
+__device__ __forceinline__ void wait_performed() { __builtin_amdgcn_s_waitcnt(0); }
+
+__device__ __forceinline__ void st_relaxed(unsigned long long *p, unsigned long long v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed_i32(int32_t *p, int32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum of the TRUE verdicts of batches 0 .. b-1 (all complete, so their
+// counter words no longer change), read by the whole wave in one round trip.
+__device__ __forceinline__ unsigned long long yes_before(JobState *st, int b)
+{
+    const int lane = lane_id();
+    unsigned long long v = 0;
+    if (lane < b) v = ld_relaxed(&st->cnt[lane]) >> 32;
+    return wave_sum_u64(v);
+}
+
+// Batch b is complete (its counter word is cw): apply Fig. 2.  Either the
+// next bound is published (and, if that batch is complete already, it is
+// evaluated in turn), or the job is finalised.  The whole wave runs this;
+// exactly one wave evaluates each batch.
+__device__ void evaluate_batches(const JobView &V, Control *ctl, int b, unsigned long long cw)
 {
     JobState *st = V.st;
+    const int lane = lane_id();
     for (;;) {
-        if (atomicCAS(&st->evaluated[b], 0, 1) != 0) return;
-        __threadfence();
-        unsigned long long Y = 0;
-        for (int q = 0; q <= b; ++q) Y += sum_shards(st->yes, q);
-        const unsigned long long Bb = ld_acquire(&st->bound[b]);
+        const unsigned long long Y = yes_before(st, b) + (cw >> 32);
+        const unsigned long long Bb = uniform_u64(ld_relaxed(&st->bound[b]));
         const double p_hat = (double)Y / (double)Bb;
-        const unsigned long long Np = next_sample(p_hat, V.eps, V.z, V.literal);
+        const unsigned long long Np = uniform_u64(next_sample(p_hat, V.eps, V.z, V.literal));
+        // Indices up to the look-ahead limit may already be running as part
+        // of the next batch; the look-ahead is a lower bound of Np (the
+        // smallest Fig. 2 bound over the possible outcomes), so a smaller Np
+        // would mean a miscounted batch: the job then stops with an error
+        // instead.
+        const unsigned long long lim_now = uniform_u64(ld_relaxed(&st->limit));
+        if (Np > Bb && Np < lim_now) {
+            if (lane == 0) {
+                st->n_final = Bb;
+                st->yes_final = Y;
+                st->n_batches = b + 1;
+                st->overflow = 2;
+                st_relaxed_i32(&st->final_flag, 1);
+                atomicSub(&ctl->open_jobs, 1);
+            }
+            return;
+        }
         if (Np > Bb && b + 1 < kMaxBatches && Np <= V.capacity) {
-            st_release(&st->bound[b + 1], Np);
-            st_release(&st->cur, b + 1);
-            atomicMax(&st->limit, Np);
-            __threadfence();
-            const unsigned long long d = ld_acquire(&st->done[b + 1]);
-            if (d == Np - Bb) {
+            unsigned long long old = 0;
+            const unsigned long long flag = kDoneFlag - (Np - Bb);
+            if (lane == 0) {
+                // the bound is in place before any index of the new batch can
+                // be claimed, and before the batch can be seen complete
+                st_relaxed(&st->bound[b + 1], Np);
+                st_relaxed_i32(&st->cur, b + 1);
+                wait_performed();
+                atomicMax(&st->limit, Np);
+                old = atomicAdd(&st->cnt[b + 1], flag);
+            }
+            const unsigned long long now = read_lane_u64(old, 0) + flag;
+            if ((now & 0xFFFFFFFFull) == kDoneFlag) {
                 b = b + 1;
+                cw = now;
                 continue;
             }
             return;
         }
-        unsigned long long E = 0, T = 0;
-        for (int q = 0; q <= b; ++q) {
-            E += sum_shards(st->events, q);
-            T += sum_shards(st->trunc, q);
+        if (lane == 0) {
+            st->n_final = Bb;
+            st->yes_final = Y;
+            st->n_batches = b + 1;
+            st->overflow = (Np > Bb) ? 1 : 0;
+            st_relaxed_i32(&st->final_flag, 1);
+            atomicSub(&ctl->open_jobs, 1);
         }
-        st->n_final = Bb;
-        st->yes_final = Y;
-        st->events_final = E;
-        st->trunc_final = T;
-        st->n_batches = b + 1;
-        st->overflow = (Np > Bb) ? 1 : 0;
-        __threadfence();
-        st_release(&st->final_flag, 1);
-        atomicSub(&ctl->open_jobs, 1);
         return;
     }
 }
 
-// While batch c is pending, raise the issue limit to the smallest next bound
-// that any possible outcome of batch c would produce (minus one for safety).
-__device__ void speculate(const JobView &V, int c)
+// While batch c is pending (counter word cw, as last seen), raise the issue
+// limit to the smallest next bound that any possible outcome of batch c
+// would produce: the bound grows as the estimate moves towards 0.5, so the
+// smallest is at one of the two extreme outcomes (all remaining FALSE, or all
+// TRUE), computed with the very operations the evaluation will use.  Counts
+// seen here can only lag, which widens the range of outcomes and lowers the
+// bound.  The whole wave runs this.
+__device__ void speculate(const JobView &V, int c, unsigned long long cw)
 {
     JobState *st = V.st;
-    const unsigned long long Bc = ld_acquire(&st->bound[c]);
-    const unsigned long long Bp = c ? ld_acquire(&st->bound[c - 1]) : 0ull;
+    const unsigned long long Bc = uniform_u64(ld_relaxed(&st->bound[c]));
+    const unsigned long long Bp = c ? uniform_u64(ld_relaxed(&st->bound[c - 1])) : 0ull;
     if (Bc == 0) return;
-    unsigned long long Yprev = 0;
-    for (int q = 0; q < c; ++q) Yprev += sum_shards(st->yes, q);
-    const unsigned long long ylo = sum_shards(st->yes, c);
-    const unsigned long long nlo = sum_shards(st->no, c);
     const unsigned long long size = Bc - Bp;
-    if (ylo + nlo > size) return;
+    const unsigned long long low = cw & 0xFFFFFFFFull;
+    // the low word holds the completions, plus kDoneFlag - size once the
+    // bound is published (it is: Bc is known)
+    const unsigned long long done = low + size >= kDoneFlag ? low + size - kDoneFlag : low;
+    const unsigned long long ylo = cw >> 32;
+    if (done > size || ylo > done) return;
+    const unsigned long long nlo = done - ylo;
+    const unsigned long long Yprev = yes_before(st, c);
     const double plo = (double)(Yprev + ylo) / (double)Bc;
     const double phi = (double)(Yprev + size - nlo) / (double)Bc;
     unsigned long long g = next_sample(plo, V.eps, V.z, V.literal);
@@ -851,10 +897,10 @@ __device__ void speculate(const JobView &V, int c)
         const unsigned long long g3 = next_sample(0.5, V.eps, V.z, V.literal);
         g = g3 < g ? g3 : g;
     }
-    if (g > 1) g -= 1;
+    g = uniform_u64(g);
     if (g > Bc) {
         if (g > V.capacity) g = V.capacity;
-        atomicMax(&st->limit, g);
+        if (lane_id() == 0) atomicMax(&st->limit, g);
     }
 }
 
@@ -867,15 +913,31 @@ __device__ __forceinline__ bool claimable(const Job *jobs, int j)
     return ld_relaxed(&st->next) < ld_relaxed(&st->limit) && ld_relaxed(&st->final_flag) == 0;
 }
 
-// Wave-cooperative scan for a job with issuable indices, starting at `start`.
-__device__ int pick_job(const Job *jobs, int n_jobs, int start)
+// Wave-cooperative scan for a job with issuable indices, starting at the
+// wave's home job `start` (waves are spread evenly over the jobs, `wph` per
+// job).  A job whose issuable range is small is left to the waves whose home
+// is near it: a job at distance q (in scan order) is taken only if
+// q * wph <= (room / 32 + wph) * (1 + idle), where room = limit - next and
+// idle counts this wave's consecutive fruitless scans.  Without this, every
+// idle wave of a launch converges on the one job whose limit has just risen
+// (by a single index, say) and their claims serialise on its counter; the
+// idle term lets distant waves in when the nearby ones stay busy.
+__device__ int pick_job(const Job *jobs, int n_jobs, int start, int wph, int idle)
 {
     const int lane = lane_id();
+    const unsigned long long w = (unsigned long long)wph;
+    const unsigned long long age = 1ull + (unsigned long long)(idle < 4096 ? idle : 4096);
     for (int base = 0; base < n_jobs; base += kWave) {
         const int q = base + lane;
         int j = start + q;
         if (j >= n_jobs) j -= n_jobs;
-        const bool ok = (q < n_jobs) && claimable(jobs, j);
+        bool ok = false;
+        if (q < n_jobs) {
+            JobState *st = jobs[j].st;
+            const unsigned long long nx = ld_relaxed(&st->next), lm = ld_relaxed(&st->limit);
+            if (nx < lm && ld_relaxed(&st->final_flag) == 0)
+                ok = (unsigned long long)q * w <= ((lm - nx) / 32ull + w) * age;
+        }
         const uint64_t m = __ballot(ok);
         if (m) return __builtin_amdgcn_readlane(j, ffs64(m));
     }
@@ -948,7 +1010,10 @@ __device__ __forceinline__ void add_counts(JobState *st, int b, int shard, unsig
 // ---------------------------------------------------------------------------
 // The persistent kernel.
 // ---------------------------------------------------------------------------
-template <class Pol>
+// kIter: the launch may hold iterative (Fig. 2) jobs.  Launches of fixed-size
+// jobs only are compiled without the stopping-rule machinery, which would
+// otherwise cost registers (occupancy) in the event loop.
+template <class Pol, bool kIter>
 __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
 {
     const int lane = lane_id();
@@ -958,6 +1023,7 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
     const int shard = gwave & (kShards - 1);
     const int n_waves = (int)gridDim.x * A.waves_per_block;
     const int start = (int)(((long long)gwave * A.n_jobs) / n_waves);
+    const int wph = n_waves > A.n_jobs ? n_waves / A.n_jobs : 1;   // waves per home job
 
     int cur = -1;
     JobView V;
@@ -982,7 +1048,7 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
             if (uniform_i(stop)) break;
         }
         if (__ballot(active) == 0ull && pool_next == pool_end) {
-            const int j = pick_job(A.jobs, A.n_jobs, start);
+            const int j = pick_job(A.jobs, A.n_jobs, start, wph, spins);
             if (j != cur && cur >= 0 && !V.iterative) {
                 // leaving a fixed-sample job: publish this wave's counts
                 const unsigned long long ny = wave_sum_u64(my_yes), nn = wave_sum_u64(my_no);
@@ -993,8 +1059,13 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
             if (j < 0) {
                 cur = -1;
                 if (ld_relaxed(&A.ctl->open_jobs) <= 0) break;
-                __builtin_amdgcn_s_sleep(127);
-                if (++spins > A.spin_limit) break;
+                // Idle waves back off longer after each fruitless scan of the
+                // job table (its counters are read with coherent loads that
+                // compete with the working waves' atomics).
+                ++spins;
+                const int naps = spins < 16 ? spins : 16;
+                for (int z = 0; z < naps; ++z) __builtin_amdgcn_s_sleep(127);
+                if (spins > A.spin_limit) break;
                 continue;
             }
             spins = 0;
@@ -1086,7 +1157,7 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
                 if (V.rec_events) V.rec_events[ridx] = k;
                 if (V.rec_vr) V.rec_vr[ridx] = (uint8_t)(verdict | (reason << 1));
             }
-            if (!V.iterative) {
+            if (!kIter || !V.iterative) {
                 if (fin) {
                     my_yes += verdict;
                     my_no += 1u - verdict;
@@ -1097,12 +1168,17 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
                 }
                 continue;
             }
+            // batch of each finishing lane: the number of published bounds at
+            // or below its index (the bounds are read once, one per lane)
             int b = 0;
-            if (fin) {
-                while (b < kMaxBatches - 1) {
-                    const unsigned long long bb = ld_relaxed(&V.st->bound[b]);
-                    if (bb == 0ull || ridx < bb) break;
-                    ++b;
+            {
+                const unsigned long long bq = lane < kMaxBatches ? ld_relaxed(&V.st->bound[lane]) : 0ull;
+                if (fin) {
+                    for (int q = 0; q < kMaxBatches - 1; ++q) {
+                        const unsigned long long bb = read_lane_u64(bq, q);
+                        if (bb == 0ull || ridx < bb) break;
+                        ++b;
+                    }
                 }
             }
             while (fm) {
@@ -1114,17 +1190,22 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
                 const uint32_t nn = (uint32_t)__popcll(sm) - ny;
                 const uint32_t nt = (uint32_t)__popcll(__ballot(sel && reason == RS_CAP));
                 const unsigned long long ev = wave_sum_u64(sel ? (unsigned long long)k : 0ull);
+                JobState *st = V.st;
+                const unsigned long long delta = ((unsigned long long)ny << 32) | (unsigned long long)(ny + nn);
+                unsigned long long old = 0;
                 if (lane == L) {
-                    JobState *st = V.st;
-                    add_counts(st, b0, shard, ny, nn, nt, ev);
-                    __threadfence();
-                    const unsigned long long d =
-                        atomicAdd(&st->done[b0], (unsigned long long)(ny + nn)) + ny + nn;
-                    __threadfence();
-                    const unsigned long long hi = ld_acquire(&st->bound[b0]);
-                    const unsigned long long lo = b0 ? ld_acquire(&st->bound[b0 - 1]) : 0ull;
-                    if (hi != 0ull && d == hi - lo) evaluate_batches(V, A.ctl, b0);
-                    else if (b0 == ld_relaxed(&st->cur)) speculate(V, b0);
+                    add_counts(st, b0, shard, 0, 0, nt, ev);
+                    old = atomicAdd(&st->cnt[b0], delta);
+                }
+                old = read_lane_u64(old, L);
+                const unsigned long long now = old + delta;
+                if ((now & 0xFFFFFFFFull) == kDoneFlag) {
+                    evaluate_batches(V, A.ctl, b0, now);
+                } else if (b0 == uniform_i(ld_relaxed(&st->cur))) {
+                    // the look-ahead only moves with the counts: refresh it on
+                    // a batch's first completions and every 64 after that
+                    if ((old & 0xFFFFFFFFull) == 0ull || ((old >> 6) & 0x3FFFFFFull) != ((now >> 6) & 0x3FFFFFFull))
+                        speculate(V, b0, now);
                 }
                 fm &= ~sm;
                 if (sel) {

@@ -9,11 +9,11 @@ namespace smc {
 #endif
 
 // Persistent SSA + monitor kernel reading its tables from device memory.
-template <int NB>
+template <int NB, bool kIter>
 __global__ __launch_bounds__(256, SMC_MIN_WAVES_PER_EU) void ssa_persistent(KArgs A)
 {
     extern __shared__ int32_t lds[];
-    persistent_body<DynPolicy<NB>>(A, lds);
+    persistent_body<DynPolicy<NB>, kIter>(A, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -56,15 +56,29 @@ __global__ __launch_bounds__(256) void ssa_sample_state(const Job *jobp, double 
         for (int s = 0; s < S; ++s) out[c * (unsigned long long)S + s] = X.get(s);
 }
 
-// Reset per-job accounting: batch 0 ends at n_first, which is also the first
-// issue limit (the rest of the state was cleared by the caller).
+// Reset per-job accounting: batch 0 ends at n_first (the rest of the state
+// was cleared by the caller).  The first issue limit also covers what every
+// outcome of batch 0 would require: whatever the first estimate, the next
+// bound is at least the Fig. 2 bound at the estimate's extremes (p = 0 or 1),
+// so indices below it are issued at once instead of after the first
+// completions.
 __global__ void init_jobs(const Job *jobs, int n_jobs)
 {
     const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (j >= n_jobs) return;
-    JobState *st = jobs[j].st;
-    st->bound[0] = jobs[j].n_first;
-    st->limit = jobs[j].n_first;
+    const Job &J = jobs[j];
+    JobState *st = J.st;
+    st->bound[0] = J.n_first;
+    st->cnt[0] = kDoneFlag - J.n_first;   // batch 0's bound is published
+    unsigned long long lim = J.n_first;
+    if (J.iterative) {
+        unsigned long long g = next_sample(0.0, J.eps, J.z, J.literal);
+        const unsigned long long g1 = next_sample(1.0, J.eps, J.z, J.literal);
+        g = g1 < g ? g1 : g;
+        if (g > J.capacity) g = J.capacity;
+        if (g > lim) lim = g;
+    }
+    st->limit = lim;
 }
 
 // Sum the counter shards of every job into its final numbers (fixed-sample
@@ -79,8 +93,12 @@ __global__ void finalize_jobs(const Job *jobs, int n_jobs, JobResult *out)
     if (jobs[j].iterative) {
         r.n = st->n_final;
         r.yes = st->yes_final;
-        r.events = st->events_final;
-        r.trunc = st->trunc_final;
+        r.events = 0;
+        r.trunc = 0;
+        for (int b = 0; b < st->n_batches; ++b) {   // trajectories past n_final are excluded
+            r.events += sum_shards(st->events, b);
+            r.trunc += sum_shards(st->trunc, b);
+        }
         r.batches = st->n_batches;
         r.final_flag = st->final_flag;
         r.overflow = st->overflow;
@@ -115,8 +133,9 @@ __global__ void wilson_table(const unsigned long long *yes, const unsigned long 
 // ---------------------------------------------------------------------------
 namespace smc {
 
-// variant: 0 = at most 4 reaction channels, 1 = any network
-hipError_t launch_persistent(int variant, int grid, int waves_per_block, size_t lds_bytes,
+// variant: 0 = at most 4 reaction channels, 1 = any network; iterative:
+// the launch holds jobs with the Fig. 2 stopping rule
+hipError_t launch_persistent(int variant, bool iterative, int grid, int waves_per_block, size_t lds_bytes,
                              hipStream_t stream, const Job *jobs, int n_jobs, int s_max,
                              Control *ctl, const volatile int32_t *cancel, int spin_limit)
 {
@@ -129,10 +148,14 @@ hipError_t launch_persistent(int variant, int grid, int waves_per_block, size_t 
     a.spin_limit = spin_limit;
     a.waves_per_block = waves_per_block;
     const dim3 block(kWave * waves_per_block);
-    if (variant == 0)
-        hipLaunchKernelGGL((ssa_persistent<4>), dim3(grid), block, lds_bytes, stream, a);
+    if (variant == 0 && iterative)
+        hipLaunchKernelGGL((ssa_persistent<4, true>), dim3(grid), block, lds_bytes, stream, a);
+    else if (variant == 0)
+        hipLaunchKernelGGL((ssa_persistent<4, false>), dim3(grid), block, lds_bytes, stream, a);
+    else if (iterative)
+        hipLaunchKernelGGL((ssa_persistent<kBlocks, true>), dim3(grid), block, lds_bytes, stream, a);
     else
-        hipLaunchKernelGGL((ssa_persistent<kBlocks>), dim3(grid), block, lds_bytes, stream, a);
+        hipLaunchKernelGGL((ssa_persistent<kBlocks, false>), dim3(grid), block, lds_bytes, stream, a);
     return hipGetLastError();
 }
 
