@@ -71,6 +71,9 @@ struct smc_formula {
     double horizon = 0.0;
 };
 
+// Channels held by the device tables (see upload_net).
+static int padded_channels(int M) { return (M + kSubBlock - 1) / kSubBlock * kSubBlock; }
+
 namespace {
 
 thread_local std::string g_create_error;
@@ -165,6 +168,7 @@ int prepare(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_pa
     std::memset(&J, 0, sizeof(J));
     J.net.S = net->S;
     J.net.M = net->M;
+    J.net.Mp = padded_channels(net->M);
     J.net.x0 = net->d_x0;
     J.net.rate = net->d_rate;
     J.net.reac = net->d_reac;
@@ -465,17 +469,27 @@ void smc_cancel(smc_ctx *c)
 int smc_device_cus(const smc_ctx *c) { return c ? c->n_cu : 0; }
 
 // ---- networks ----------------------------------------------------------------
+// Device tables hold Mp = M rounded up to kSubBlock channels; the extra ones
+// have rate 0, no reactants and no state change, so they add exactly 0 to
+// every running sum and are never selected.
 static int upload_net(smc_net *n)
 {
     smc_ctx *c = n->ctx;
+    const int Mp = padded_channels(n->M);
+    std::vector<double> rate(Mp, 0.0);
+    std::vector<int32_t> reac(2 * Mp, -1);
+    std::vector<uint32_t> chg(4 * Mp, 0xFFFF0000u);
+    std::copy(n->rate.begin(), n->rate.end(), rate.begin());
+    std::copy(n->reac.begin(), n->reac.end(), reac.begin());
+    std::copy(n->chg.begin(), n->chg.end(), chg.begin());
     HIP_TRY(c, hipMalloc((void **)&n->d_x0, n->S * sizeof(int32_t)));
-    HIP_TRY(c, hipMalloc((void **)&n->d_rate, n->M * sizeof(double)));
-    HIP_TRY(c, hipMalloc((void **)&n->d_reac, 2 * n->M * sizeof(int32_t)));
-    HIP_TRY(c, hipMalloc((void **)&n->d_chg, 4 * n->M * sizeof(uint32_t)));
+    HIP_TRY(c, hipMalloc((void **)&n->d_rate, Mp * sizeof(double)));
+    HIP_TRY(c, hipMalloc((void **)&n->d_reac, 2 * Mp * sizeof(int32_t)));
+    HIP_TRY(c, hipMalloc((void **)&n->d_chg, 4 * Mp * sizeof(uint32_t)));
     HIP_TRY(c, hipMemcpy(n->d_x0, n->x0.data(), n->S * sizeof(int32_t), hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(n->d_rate, n->rate.data(), n->M * sizeof(double), hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(n->d_reac, n->reac.data(), 2 * n->M * sizeof(int32_t), hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(n->d_chg, n->chg.data(), 4 * n->M * sizeof(uint32_t), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(n->d_rate, rate.data(), Mp * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(n->d_reac, reac.data(), 2 * Mp * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(n->d_chg, chg.data(), 4 * Mp * sizeof(uint32_t), hipMemcpyHostToDevice));
     return SMC_OK;
 }
 
@@ -695,6 +709,7 @@ int smc_sample_state(smc_ctx *c, const smc_net *net, const smc_params *p, double
     std::memset(&J, 0, sizeof(J));
     J.net.S = net->S;
     J.net.M = net->M;
+    J.net.Mp = padded_channels(net->M);
     J.net.x0 = net->d_x0;
     J.net.rate = net->d_rate;
     J.net.reac = net->d_reac;

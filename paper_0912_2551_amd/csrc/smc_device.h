@@ -31,6 +31,7 @@ constexpr int kMaxNested = 2;      // nested-until monitors per formula
 constexpr int kMaxValOps = 96;     // arithmetic predicate programs
 constexpr int kValStack = 4;       // arithmetic stack depth on the device
 constexpr int kBlocks = 16;        // prefix-sum blocks for reaction selection
+constexpr int kSubBlock = 8;       // channels per unrolled step of the blocked prefix
 constexpr int kSpecMaxS = 16;      // specialised kernels: species counts in registers
 constexpr int kSpecMaxM = 8;       // specialised kernels: channels
 
@@ -102,6 +103,9 @@ struct MonProg {
 //              species 0xFFFF = unused.
 struct NetDev {
     int32_t S, M;
+    int32_t Mp;   // M rounded up to kSubBlock: the tables hold Mp channels, the
+                  // extra ones with rate 0, no reactants and no state change
+    int32_t pad_;
     const int32_t *x0;
     const double *rate;
     const int32_t *reac;

@@ -185,6 +185,17 @@ __device__ __forceinline__ cptr<T> as_const(const T *p)
     return (cptr<T>)p;
 }
 
+// A pointer every lane holds identically, as a wave-uniform (scalar) value, so
+// that reads at uniform indices through it become scalar loads.
+template <typename T>
+__device__ __forceinline__ cptr<T> uniform_ptr(cptr<T> p)
+{
+    const unsigned long long v = (unsigned long long)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (cptr<T>)(((unsigned long long)hi << 32) | lo);
+}
+
 // ---------------------------------------------------------------------------
 // Per-wave view of a job: uniform values kept in scalar registers.
 // ---------------------------------------------------------------------------
@@ -196,7 +207,7 @@ struct JobView {
     cptr<double> rate;
     cptr<int32_t> reac;
     cptr<uint32_t> chg;
-    int S, M;
+    int S, M, Mp;
     unsigned long long seed, first, capacity;
     uint32_t model_id, max_events;
     double t_max;
@@ -208,6 +219,7 @@ struct JobView {
 
     __device__ void load(const Job *jobs, int j)
     {
+        j = __builtin_amdgcn_readfirstlane(j);   // the same job on every lane: scalar loads
         cptr<Job> J = as_const(jobs) + j;
         job = jobs + j;
         st = J->st;
@@ -218,6 +230,7 @@ struct JobView {
         chg = as_const(J->net.chg);
         S = J->net.S;
         M = J->net.M;
+        Mp = J->net.Mp;
         seed = J->seed;
         first = J->first;
         capacity = J->capacity;
@@ -228,8 +241,11 @@ struct JobView {
         literal = J->literal;
         eps = J->eps;
         z = J->z;
-        nb = M < kBlocks ? M : kBlocks;
-        bs = (M + nb - 1) / nb;
+        // blocked prefix (networks of more than four channels): at most
+        // kBlocks blocks, each a whole number of kSubBlock-channel steps
+        const int nsub = Mp / kSubBlock;
+        nb = nsub < kBlocks ? nsub : kBlocks;
+        bs = (nsub + nb - 1) / nb * kSubBlock;
         rec_events = J->rec_events;
         rec_vr = J->rec_vr;
     }
@@ -271,6 +287,20 @@ __device__ __forceinline__ double propensity(int ra, int rb, double c, const C &
     if (ra == rb) return c * (((double)xa * (double)(xa - 1)) * 0.5);
     const int32_t xb = X.get(rb);
     return c * ((double)xa * (double)xb);
+}
+
+// The same propensity from counts already read (xa = x[ra], xb = x[rb]),
+// without branches: the combinatorial factor h is selected, then c * h.  Each
+// case performs the same operations as above (c * 1 = c exactly), so the
+// result is identical; the generic kernels use this form because the kinds
+// differ from channel to channel.
+__device__ __forceinline__ double propensity_x(int ra, int rb, double c, int32_t xa, int32_t xb)
+{
+    const double da = (double)xa, db = (double)xb;
+    const double hetero = da * db;
+    const double homo = (da * (double)(xa - 1)) * 0.5;
+    const double h = ra < 0 ? 1.0 : (rb < 0 ? da : (ra == rb ? homo : hetero));
+    return c * h;
 }
 
 struct Change {
@@ -551,14 +581,16 @@ __device__ __forceinline__ Draw event_uniforms(const JobView &V, unsigned long l
 // One SSA event for this lane.  Returns the next time (inf when absorbing)
 // and, unless absorbing, the state change of the selected channel.
 // ---------------------------------------------------------------------------
+// live: this lane steps its trajectory with the result (other lanes compute
+// along and discard it).
 template <int NB, class C>
 __device__ __forceinline__ double ssa_draw(const JobView &V, const C &X, const Draw &d, double t,
-                                           Change *change)
+                                           Change *change, bool live)
 {
-    const int M = V.M;
-    const int nb = V.nb, bs = V.bs;
-    cptr<int32_t> reac = V.reac;
-    cptr<double> rate = V.rate;
+    const int M = __builtin_amdgcn_readfirstlane(V.M);
+    const int nb = __builtin_amdgcn_readfirstlane(V.nb), bs = __builtin_amdgcn_readfirstlane(V.bs);
+    cptr<int32_t> reac = uniform_ptr(V.reac);
+    cptr<double> rate = uniform_ptr(V.rate);
     double P[NB];
     double acc = 0.0;
     if (NB <= 4) {
@@ -569,14 +601,42 @@ __device__ __forceinline__ double ssa_draw(const JobView &V, const C &X, const D
             P[j] = acc;
         }
     } else {
+        // Blocks of whole kSubBlock-channel steps, each step unrolled so that
+        // its table and count reads are issued together.  The tables are
+        // padded with zero-rate channels to a multiple of kSubBlock: those add
+        // exactly 0 to the running sum and are never selected.
+        const int Mp = __builtin_amdgcn_readfirstlane(V.Mp);
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             P[q] = acc;
             if (q < nb) {
                 const int j0 = q * bs;
-                const int j1 = (j0 + bs < M) ? j0 + bs : M;
-                for (int j = j0; j < j1; ++j)
-                    acc = acc + propensity(reac[2 * j], reac[2 * j + 1], rate[j], X);
+                const int j1 = (j0 + bs < Mp) ? j0 + bs : Mp;
+                for (int jj = j0; jj < j1; jj += kSubBlock) {
+                    // Three phases per step: the table entries (scalar loads),
+                    // then the counts they name (LDS), then the arithmetic.
+                    // Kept apart, each phase waits once: scalar loads can
+                    // return out of order, so mixed with LDS reads on the
+                    // same wait counter they would force a wait per read.
+                    const int jb = __builtin_amdgcn_readfirstlane(jj);
+                    int ra[kSubBlock], rb[kSubBlock];
+                    double cr[kSubBlock];
+#pragma unroll
+                    for (int r = 0; r < kSubBlock; ++r) {
+                        ra[r] = reac[2 * (jb + r)];
+                        rb[r] = reac[2 * (jb + r) + 1];
+                        cr[r] = rate[jb + r];
+                    }
+                    int32_t xa[kSubBlock], xb[kSubBlock];
+#pragma unroll
+                    for (int r = 0; r < kSubBlock; ++r) {
+                        xa[r] = X.get(ra[r] < 0 ? 0 : ra[r]);   // species 0 stands in (unused)
+                        xb[r] = X.get(rb[r] < 0 ? 0 : rb[r]);
+                    }
+#pragma unroll
+                    for (int r = 0; r < kSubBlock; ++r)
+                        acc = acc + propensity_x(ra[r], rb[r], cr[r], xa[r], xb[r]);
+                }
                 P[q] = acc;
             }
         }
@@ -584,13 +644,15 @@ __device__ __forceinline__ double ssa_draw(const JobView &V, const C &X, const D
     const double a0 = acc;
     if (!(a0 > 0.0)) return __builtin_inf();
     const double target = d.u2 * a0;
-    // first block whose running sum exceeds the target
+    // first block whose running sum exceeds the target (with at most four
+    // channels, each channel is a block)
+    const int nblk = NB <= 4 ? M : nb;
     int qsel = 0;
     double base = 0.0;
     bool found = false;
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-        if (q < nb) {
+        if (q < nblk) {
             const bool hit = !found && (P[q] > target);
             qsel = hit ? q : qsel;
             base = hit ? (q == 0 ? 0.0 : P[q - 1]) : base;
@@ -598,28 +660,45 @@ __device__ __forceinline__ double ssa_draw(const JobView &V, const C &X, const D
         }
     }
     int jsel = qsel;
-    if (NB > 4 && bs > 1) {
-        // re-run the same running sum inside the block (identical operations)
+    if (NB > 4) {
+        // Re-run the same running sum inside the selected block (identical
+        // operations).  The block differs between lanes, so its table entries
+        // are per-lane loads: each step reads its 16 entries first, so that
+        // the loads overlap instead of waiting one by one.
+        const int Mp = __builtin_amdgcn_readfirstlane(V.Mp);
         const int j0 = qsel * bs;
-        const int j1 = (j0 + bs < M) ? j0 + bs : M;
+        const int j1 = (j0 + bs < Mp) ? j0 + bs : Mp;
         double s = base;
         jsel = j1 - 1;
-        bool got = false;
-        for (int rr = 0; rr < bs; ++rr) {
-            const int j = j0 + rr;
-            if (!got && j < j1) {
-                s = s + propensity(reac[2 * j], reac[2 * j + 1], rate[j], X);
-                if (s > target) {
-                    jsel = j;
-                    got = true;
-                }
+        bool got = !live;
+        for (int jj = j0; jj < j1; jj += kSubBlock) {
+            int ra[kSubBlock], rb[kSubBlock];
+            double cr[kSubBlock];
+#pragma unroll
+            for (int r = 0; r < kSubBlock; ++r) {
+                ra[r] = reac[2 * (jj + r)];
+                rb[r] = reac[2 * (jj + r) + 1];
+                cr[r] = rate[jj + r];
+            }
+            int32_t xa[kSubBlock], xb[kSubBlock];
+#pragma unroll
+            for (int r = 0; r < kSubBlock; ++r) {
+                xa[r] = X.get(ra[r] < 0 ? 0 : ra[r]);
+                xb[r] = X.get(rb[r] < 0 ? 0 : rb[r]);
+            }
+#pragma unroll
+            for (int r = 0; r < kSubBlock; ++r) {
+                s = s + propensity_x(ra[r], rb[r], cr[r], xa[r], xb[r]);
+                const bool hit = !got && s > target;
+                jsel = hit ? jj + r : jsel;
+                got = got || hit;
             }
             if (__ballot(!got) == 0) break;
         }
     }
     if (NB <= 4) {
         // at most four channels: pick the change among wave-uniform entries
-        cptr<uint32_t> tab = V.chg;
+        cptr<uint32_t> tab = uniform_ptr(V.chg);
         Change ch{tab[0], tab[1], tab[2], tab[3]};
 #pragma unroll
         for (int q = 1; q < NB; ++q) {
@@ -666,11 +745,14 @@ struct DynPolicy {
         X.lane = lane;
         return X;
     }
-    __device__ static __forceinline__ void init(Counts &X, const JobView &V) { X.init(V.x0, V.S); }
-    __device__ static __forceinline__ double draw(const JobView &V, const Counts &X, const Draw &d,
-                                                  double t, Sel *s)
+    __device__ static __forceinline__ void init(Counts &X, const JobView &V)
     {
-        return ssa_draw<NB>(V, X, d, t, s);
+        X.init(uniform_ptr(V.x0), __builtin_amdgcn_readfirstlane(V.S));
+    }
+    __device__ static __forceinline__ double draw(const JobView &V, const Counts &X, const Draw &d,
+                                                  double t, Sel *s, bool live)
+    {
+        return ssa_draw<NB>(V, X, d, t, s, live);
     }
     __device__ static __forceinline__ void apply_if(Counts &X, const Sel &c, bool on)
     {
@@ -679,12 +761,12 @@ struct DynPolicy {
     __device__ static __forceinline__ uint32_t step(const JobView &V, MonState &ms, const Counts &X,
                                                     uint32_t k, double t)
     {
-        return mon_step(V.mon, ms, X, k, t);
+        return mon_step(uniform_ptr(V.mon), ms, X, k, t);
     }
     __device__ static __forceinline__ uint32_t advance(const JobView &V, MonState &ms, double tn,
                                                        bool absorbing)
     {
-        return mon_advance(V.mon, ms, tn, absorbing);
+        return mon_advance(uniform_ptr(V.mon), ms, tn, absorbing);
     }
 };
 
@@ -713,7 +795,7 @@ struct StaticPolicy {
         for (int s = 0; s < S; ++s) X.x[s] = V.x0[s];
     }
     __device__ static __forceinline__ double draw(const JobView &V, const Counts &X, const Draw &d,
-                                                  double t, Sel *jsel)
+                                                  double t, Sel *jsel, bool)
     {
         constexpr NetTab<M> T = Spec::net;
         cptr<double> rate = V.rate;
@@ -1119,7 +1201,7 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
         const bool ev_lane = active && !entered;
         const bool capped = V.max_events != 0u && k == V.max_events;
         typename Pol::Sel ch;
-        const double tn = Pol::draw(V, X, dr, t, &ch);
+        const double tn = Pol::draw(V, X, dr, t, &ch, ev_lane);
         const bool absorbing = __builtin_isinf(tn);
         MonState ms_adv = ms;
         const uint32_t va = Pol::advance(V, ms_adv, tn, absorbing);

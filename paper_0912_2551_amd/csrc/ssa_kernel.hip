@@ -42,7 +42,7 @@ __global__ __launch_bounds__(256) void ssa_sample_state(const Job *jobp, double 
     while (__ballot(run) != 0ull) {
         if (run) {
             Change ch;
-            const double tn = ssa_draw<NB>(V, X, event_uniforms(V, V.first + c, k), t, &ch);
+            const double tn = ssa_draw<NB>(V, X, event_uniforms(V, V.first + c, k), t, &ch, true);
             if (tn > T) {
                 run = false;
             } else {
