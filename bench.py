@@ -81,6 +81,58 @@ def cpu_baseline(net, text, sample):
                       f"{dt:.2f} s, {sample / dt:.0f} trajectories/s"}
 
 
+def random_network_run(ctx, B, W, n=100_000):
+    """Seeded random network (64 species, 256 channels), nested bounded-until
+    formula, 10^5 trajectories with the 10^5-event cap, fixed sample."""
+    import torch
+    net = W.c3_network()
+    nh = ctx.network(net)
+    fh = ctx.formula(nh, W.c3_formula(net))
+    p = B.params(fixed_n=n, seed=1, confidence=0.95, max_events=W.C3_CAP)
+    ctx.estimate(nh, fh, B.params(fixed_n=256, seed=2, max_events=W.C3_CAP))   # kernel choice, warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.estimate(nh, fh, p)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return {"workload": "random network S=64 M=256 (seed 1), nested until, 10^5 trajectories, cap 10^5",
+            "seconds": wall, "device_seconds": r["device_seconds"], "events": r["events"],
+            "events_per_s": r["events"] / wall, "verified_trajectories_per_s": r["n"] / wall,
+            "truncated": r["truncated"], "p_hat": r["p_hat"], "interval_95": [r["lo"], r["hi"]]}
+
+
+def batched_sweep_run(ctx, B, W):
+    """512 Michaelis-Menten rate sets (each rate within +-1 decade) under the
+    workload formula plus 64 random networks (8..128 species, 4 channels per
+    species) under nested-until formulas, every model with its own 95% +-0.01
+    Wilson rule, in one persistent launch."""
+    import torch
+    keep, jobs = [], []
+    for k, rr in enumerate(W.mm_sweep(512, seed=4)):
+        a = ctx.network(W.michaelis_menten(*rr))
+        b = ctx.formula(a, W.C2_FORMULA)
+        keep.append((a, b))
+        jobs.append((a, b, B.params(confidence=0.95, half_width=0.01, seed=1, model_id=k)))
+    for k, (rn, rt) in enumerate(W.c4_networks(64, seed=5)):
+        a = ctx.network(rn)
+        b = ctx.formula(a, rt)
+        keep.append((a, b))
+        jobs.append((a, b, B.params(confidence=0.95, half_width=0.01, seed=1, model_id=512 + k,
+                                    max_events=W.C3_CAP)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ctx.estimate_batch(jobs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev = sum(r["events"] for r in res)
+    n = sum(r["n"] for r in res)
+    return {"workload": "512 Michaelis-Menten rate sets + 64 random networks (S 8..128, M = 4S), "
+                        "95% Wilson +-0.01 each, one launch",
+            "models": len(jobs), "seconds": wall, "device_seconds": res[0]["device_seconds"],
+            "verified_trajectories": n, "verified_trajectories_per_s": n / wall, "events": ev,
+            "events_per_s": ev / wall, "max_batches": max(r["batches"] for r in res)}
+
+
 def surrogate_vs_plain(ctx, B, W, text, n_train=512, n_query=10**6, n_sub=4096, eps=0.01, margin=0.05,
                        steps=2000):
     """Answer n_query rate points either with plain batched SMC or with the
@@ -155,6 +207,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-c1", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the random-network and batched-sweep runs")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=N_TRAJ)
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--occupancy", type=int, default=0, help="waves per SIMD budget of specialised kernels")
@@ -188,6 +242,11 @@ def main():
     nh = ctx.network(net)
     fh = ctx.formula(nh, W.C2_FORMULA)
     p = B.params(fixed_n=N_TRAJ, seed=1, confidence=0.95)
+    tune = None
+    if not args.no_autotune and not args.waves_per_cu and not args.occupancy and args.kernel == "auto":
+        # launch configuration chosen by the library's autotuner (pilot runs,
+        # before the timed region; estimates do not depend on it)
+        tune = ctx.autotune(nh, fh, p, pilot_n=N_TRAJ)
 
     for _ in range(args.warmup):
         ctx.estimate(nh, fh, p)
@@ -227,6 +286,7 @@ def main():
                    "trajectories_per_step": N_TRAJ, "events_per_step": ev_per_launch,
                    "parallelism": "1 GPU, one trajectory per lane"},
         "verified_trajectories_per_s": trajectories / wall,
+        "autotune": tune,
         "p_hat": r["p_hat"], "interval_95": [r["lo"], r["hi"]],
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_SLOTS / 1e12,
                      "unit": "Tslot/s", "frac": achieved / PEAK_VALU_SLOTS, "traffic": measured_traffic(),
@@ -251,6 +311,9 @@ def main():
                              "n": r1["n"], "batches": r1["batches"], "p_hat": r1["p_hat"],
                              "interval": [r1["lo"], r1["hi"]], "seconds": w1,
                              "verified_trajectories_per_s": r1["n"] / w1, "events_per_s": r1["events"] / w1}
+    if not args.no_large:
+        line["c3_random_network"] = random_network_run(ctx, B, W)
+        line["c4_batched_sweep"] = batched_sweep_run(ctx, B, W)
     if not args.no_surrogate:
         line["surrogate_vs_plain"] = [surrogate_vs_plain(ctx, B, W, t)
                                       for t in (W.C2_FORMULA, W.MM_COMPANION_FORMULA)]

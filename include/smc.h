@@ -107,6 +107,7 @@ int smc_last_kernel(const smc_ctx *ctx);
  * go to scratch memory), or 0 for the compiler's own choice (default).
  * Results do not depend on it.  Errors: SMC_E_INVALID. */
 int smc_set_kernel_occupancy(smc_ctx *ctx, int waves_per_simd);
+
 /* Ask a running call on ctx (from another thread) to stop: it returns
  * SMC_E_CANCELLED. */
 void smc_cancel(smc_ctx *ctx);
@@ -211,6 +212,32 @@ int smc_trajectories(smc_ctx *ctx, const smc_net *net, const smc_formula *f, con
  * counts[k*S + s] (no formula involved). */
 int smc_sample_state(smc_ctx *ctx, const smc_net *net, const smc_params *p, double T,
                      uint64_t first, uint64_t count, int32_t *counts);
+
+/* Autotuning of the launch configuration (batching of many models into one
+ * launch and its shape).  Runs short fixed-size pilot estimates of one model
+ * (pilot_n trajectories, 1..2^26, with a seed derived from p->seed, so the
+ * estimate's own trajectories are not consumed) for each candidate
+ * configuration: generic or specialised kernel, the specialised kernel's
+ * register budget (compiler default, 5, 6 or 8 waves per SIMD) and waves per
+ * compute unit (4, 8, 16, 24, 32).  The fastest, in SSA events per second of
+ * device time, is recorded on the context for the model's structure (network
+ * tables and formula; rates, initial state and parameters do not enter): later
+ * launches of fixed-size jobs that all share that structure use it in place
+ * of the context's settings (smc_set_specialization, smc_set_kernel_occupancy,
+ * smc_set_waves_per_cu), which are otherwise left unchanged.  A second call
+ * for the same structure returns the recorded choice without pilots.
+ * Estimates do not depend on the configuration.  Errors: SMC_E_INVALID, and
+ * those of smc_estimate. */
+typedef struct {
+    int32_t waves_per_cu;         /* chosen launch shape                         */
+    int32_t waves_per_simd;       /* chosen register budget (0: compiler's)      */
+    int32_t specialization;       /* SMC_SPECIALIZE_AUTO or SMC_SPECIALIZE_OFF    */
+    int32_t candidates;           /* configurations timed                        */
+    double events_per_s;          /* pilot rate of the choice                    */
+    double default_events_per_s;  /* pilot rate of the default configuration     */
+} smc_tune_result;
+int smc_autotune(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_params *p,
+                 uint64_t pilot_n, smc_tune_result *out);
 
 /* ---- Wilson formulas (host, no context) -------------------------------- */
 /* z_{1-alpha/2} for confidence 1 - alpha. */

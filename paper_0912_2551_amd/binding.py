@@ -36,7 +36,7 @@ KERNEL_GENERIC_SMALL, KERNEL_GENERIC, KERNEL_SPECIALIZED = 0, 1, 2
 EXPORTS = [
     "smc_ctx_create", "smc_ctx_destroy", "smc_last_error", "smc_set_watchdog",
     "smc_set_waves_per_cu", "smc_set_specialization", "smc_last_kernel",
-    "smc_set_kernel_occupancy", "smc_cancel", "smc_device_cus", "smc_net_create",
+    "smc_set_kernel_occupancy", "smc_autotune", "smc_cancel", "smc_device_cus", "smc_net_create",
     "smc_net_set_rates", "smc_net_destroy", "smc_formula_compile", "smc_formula_horizon",
     "smc_formula_destroy", "smc_estimate", "smc_estimate_batch", "smc_trajectories",
     "smc_sample_state", "smc_z_value", "smc_wilson_sample_value", "smc_wilson_sample",
@@ -45,6 +45,12 @@ EXPORTS = [
     "smc_surrogate_gradients", "smc_surrogate_train", "smc_surrogate_query", "smc_surrogate_hull",
     "smc_surrogate_destroy", "smc_convex_hull",
 ]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("waves_per_cu", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
+                ("specialization", ctypes.c_int32), ("candidates", ctypes.c_int32),
+                ("events_per_s", ctypes.c_double), ("default_events_per_s", ctypes.c_double)]
 
 
 class LibraryMissing(RuntimeError):
@@ -115,6 +121,7 @@ def lib():
             "smc_set_specialization": (i32, [vp, i32]),
             "smc_last_kernel": (i32, [vp]),
             "smc_set_kernel_occupancy": (i32, [vp, i32]),
+            "smc_autotune": (i32, [vp, vp, vp, ctypes.POINTER(Params), ctypes.c_uint64, ctypes.POINTER(TuneResult)]),
             "smc_cancel": (None, [vp]),
             "smc_device_cus": (i32, [vp]),
             "smc_net_create": (i32, [vp, ctypes.POINTER(NetDesc), ctypes.POINTER(vp)]),
@@ -222,6 +229,12 @@ class Context:
     def set_kernel_occupancy(self, waves_per_simd: int):
         """Register budget of specialised kernels (0 = compiler default)."""
         self._check(lib().smc_set_kernel_occupancy(self.h, int(waves_per_simd)))
+
+    def autotune(self, network, formula, p, pilot_n=1 << 16) -> dict:
+        """Pick and apply the fastest launch configuration for this model's structure."""
+        r = TuneResult()
+        self._check(lib().smc_autotune(self.h, network.h, formula.h, ctypes.byref(p), int(pilot_n), ctypes.byref(r)))
+        return {k: getattr(r, k) for k, _ in TuneResult._fields_}
 
     def last_kernel(self) -> int:
         """KERNEL_GENERIC_SMALL, KERNEL_GENERIC or KERNEL_SPECIALIZED (-1: none yet)."""

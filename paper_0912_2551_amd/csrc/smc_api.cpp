@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <thread>
 #include <vector>
@@ -31,6 +32,9 @@ struct smc_ctx {
     int waves_per_cu = 0;
     int spec_mode = SMC_SPECIALIZE_AUTO;
     int spec_waves_per_simd = 0;
+    // autotuned configurations per model structure (see smc_autotune)
+    std::map<std::string, smc_tune_result> tuned;
+    bool tuning = false;
     int last_kernel = -1;
     bool spec_warned = false;
     double watchdog = 300.0;
@@ -194,6 +198,17 @@ int prepare(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_pa
     return SMC_OK;
 }
 
+// The structure of a model: network tables and compiled formula (rates,
+// initial state, seeds and stopping parameters do not enter).
+std::string structure_key(const smc_net *net, const smc_formula *f)
+{
+    std::string key = spec_source(net->S, net->M, net->reac.data(), net->chg.data(), f->prog, 0, false);
+    key.append((const char *)f->prog.vop, sizeof f->prog.vop);
+    key.append((const char *)f->prog.vvar, sizeof f->prog.vvar);
+    key.append((const char *)f->prog.vconst, sizeof f->prog.vconst);
+    return key;
+}
+
 // The specialised kernel for a launch, if every job shares one network
 // structure and formula that the specialisation supports (else nullptr).
 int pick_spec_kernel(smc_ctx *ctx, const std::vector<Prepared> &P, bool iterative, hipFunction_t *fn)
@@ -261,6 +276,31 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
     *ctx->cancel_host = 0;
     ctx->cancel_req.store(0);
 
+    // A configuration tuned for this structure (fixed-size pilots) applies to
+    // launches of fixed-size jobs that all share it; the context's own
+    // settings are restored before returning.
+    struct Restore {
+        smc_ctx *c;
+        int wpc, occ, mode;
+        ~Restore()
+        {
+            c->waves_per_cu = wpc;
+            c->spec_waves_per_simd = occ;
+            c->spec_mode = mode;
+        }
+    } restore{ctx, ctx->waves_per_cu, ctx->spec_waves_per_simd, ctx->spec_mode};
+    if (!ctx->tuned.empty() && !ctx->tuning && n_iter == 0 && P[0].net && P[0].f) {
+        const std::string key = structure_key(P[0].net, P[0].f);
+        auto it = ctx->tuned.find(key);
+        bool same = it != ctx->tuned.end();
+        for (int k = 1; same && k < n; ++k)
+            same = (P[k].net == P[0].net && P[k].f == P[0].f) || structure_key(P[k].net, P[k].f) == key;
+        if (same) {
+            ctx->waves_per_cu = it->second.waves_per_cu;
+            ctx->spec_waves_per_simd = it->second.waves_per_simd;
+            ctx->spec_mode = it->second.specialization;
+        }
+    }
     const size_t lds_wave = (size_t)s_max * kWave * sizeof(int32_t);
     int wpb = (int)std::min<size_t>(4, std::max<size_t>(1, 65536 / lds_wave));
     if (lds_wave > 65536) return fail(ctx, SMC_E_INVALID, "network too large for one wave's LDS");
@@ -443,6 +483,80 @@ int smc_set_specialization(smc_ctx *c, int mode)
 }
 
 int smc_last_kernel(const smc_ctx *c) { return c ? c->last_kernel : -1; }
+
+int smc_autotune(smc_ctx *c, const smc_net *net, const smc_formula *f, const smc_params *p, uint64_t pilot_n,
+                 smc_tune_result *out)
+{
+    if (!c || !net || !f || !p || !out) return fail(c, SMC_E_INVALID, "null argument");
+    if (pilot_n == 0 || pilot_n > (1ull << 26)) return fail(c, SMC_E_INVALID, "pilot_n must lie in 1..2^26");
+    const std::string key = structure_key(net, f);
+    auto it = c->tuned.find(key);
+    if (it != c->tuned.end()) {
+        *out = it->second;
+        return SMC_OK;
+    }
+    const int save_wpc = c->waves_per_cu, save_occ = c->spec_waves_per_simd, save_mode = c->spec_mode;
+    struct Tuning {
+        smc_ctx *c;
+        Tuning(smc_ctx *x) : c(x) { c->tuning = true; }
+        ~Tuning() { c->tuning = false; }
+    } tuning_scope(c);
+    smc_params q = *p;
+    q.fixed_n = pilot_n;
+    q.seed = p->seed ^ 0x9E3779B97F4A7C15ull;   // pilot trajectories are not the estimate's
+    if (q.confidence <= 0.0 || q.confidence >= 1.0) q.confidence = 0.95;
+    struct Cand {
+        int mode, occ;
+    };
+    std::vector<Cand> cands = {{SMC_SPECIALIZE_OFF, 0}};
+    if (spec_supported(net->S, net->M, f->prog))
+        for (int occ : {0, 5, 6, 8}) cands.push_back({SMC_SPECIALIZE_REQUIRED, occ});
+    const int wpcs[] = {4, 8, 16, 24, 32};
+    smc_tune_result best{};
+    best.events_per_s = -1.0;
+    int tried = 0;
+    double default_rate = 0.0;
+    int rc = SMC_OK;
+    for (const Cand &cd : cands) {
+        for (int w : wpcs) {
+            c->spec_mode = cd.mode;
+            c->spec_waves_per_simd = cd.occ;
+            c->waves_per_cu = w;
+            smc_result r;
+            double rate = 0.0;
+            // first run compiles (specialised kernels) and warms up; the second is timed
+            for (int rep = 0; rep < 2 && rc == SMC_OK; ++rep) {
+                rc = smc_estimate(c, net, f, &q, &r);
+                if (rc == SMC_OK && r.device_seconds > 0.0) rate = (double)r.events / r.device_seconds;
+            }
+            if (rc != SMC_OK) break;
+            ++tried;
+            if (cd.mode == SMC_SPECIALIZE_REQUIRED && cd.occ == 0 && w == 16) default_rate = rate;
+            if (cd.mode == SMC_SPECIALIZE_OFF && w == 16 && cands.size() == 1) default_rate = rate;
+            if (rate > best.events_per_s) {
+                best.events_per_s = rate;
+                best.waves_per_cu = w;
+                best.waves_per_simd = cd.occ;
+                best.specialization = cd.mode == SMC_SPECIALIZE_OFF ? SMC_SPECIALIZE_OFF : SMC_SPECIALIZE_AUTO;
+            }
+        }
+        if (rc != SMC_OK) break;
+    }
+    if (rc != SMC_OK) {
+        c->waves_per_cu = save_wpc;
+        c->spec_waves_per_simd = save_occ;
+        c->spec_mode = save_mode;
+        return rc;
+    }
+    best.candidates = tried;
+    best.default_events_per_s = default_rate;
+    c->waves_per_cu = save_wpc;
+    c->spec_waves_per_simd = save_occ;
+    c->spec_mode = save_mode;
+    c->tuned[key] = best;
+    *out = best;
+    return SMC_OK;
+}
 
 int smc_set_kernel_occupancy(smc_ctx *c, int waves_per_simd)
 {

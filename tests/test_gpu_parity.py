@@ -277,3 +277,33 @@ def test_specialized_kernel_selection_and_estimates(ctx):
     with pytest.raises(B.SmcError):
         ctx.estimate_batch(mixed)
     ctx.set_specialization(B.SPECIALIZE_AUTO)
+
+
+def test_autotune_keeps_results(ctx):
+    """The autotuner only changes the launch configuration: estimates before
+    and after tuning are identical, and a second call reuses the cached
+    choice."""
+    B = _B()
+    net = W.michaelis_menten()
+    n = ctx.network(net)
+    f = ctx.formula(n, W.C2_FORMULA)
+    p = B.params(fixed_n=50000, seed=3)
+    before = ctx.estimate(n, f, p)
+    t = ctx.autotune(n, f, p, pilot_n=1 << 14)
+    assert t["candidates"] >= 5 and t["events_per_s"] > 0
+    assert t["waves_per_cu"] in (4, 8, 16, 24, 32)
+    after = ctx.estimate(n, f, p)
+    keys = ("n", "successes", "events", "p_hat", "lo", "hi")
+    assert tuple(before[k] for k in keys) == tuple(after[k] for k in keys)
+    t2 = ctx.autotune(n, f, p, pilot_n=1 << 14)
+    assert t2 == t
+    # iterative estimate under the tuned configuration matches the oracle
+    c1 = W.immigration_death()
+    n1 = ctx.network(c1)
+    f1 = ctx.formula(n1, W.C1_FORMULA)
+    r = ctx.estimate(n1, f1, B.params(confidence=0.95, half_width=0.01, seed=1))
+    o = oracle.estimate(c1, W.C1_FORMULA, confidence=0.95, eps=0.01, seed=1)
+    assert (r["n"], r["successes"], r["events"]) == (o["n"], o["successes"], o["events"])
+    ctx.set_waves_per_cu(0)
+    ctx.set_kernel_occupancy(0)
+    ctx.set_specialization(B.SPECIALIZE_AUTO)
