@@ -307,3 +307,64 @@ def test_autotune_keeps_results(ctx):
     ctx.set_waves_per_cu(0)
     ctx.set_kernel_occupancy(0)
     ctx.set_specialization(B.SPECIALIZE_AUTO)
+
+
+def test_mixed_batch_matches_oracle(ctx):
+    """A launch of models of different structure and size (Michaelis-Menten
+    rate sets and small random networks), each with its own Fig. 2 rule:
+    every job's n, successes, events and truncations equal the oracle's
+    iterative estimate on the same streams."""
+    B = _B()
+    models = []
+    for k, rr in enumerate(W.mm_sweep(6, seed=31)):
+        models.append((W.michaelis_menten(*rr), W.MM_COMPANION_FORMULA, 0))
+    for q in range(3):
+        rn = W.random_network(8 + 4 * q, 4 * (8 + 4 * q), seed=77 + q)
+        models.append((rn, W.nested_until_formula(rn, W.C3_DELTA, W.c3_species(rn)), 3000))
+    keep, jobs = [], []
+    for k, (net, text, cap) in enumerate(models):
+        nh = ctx.network(net)
+        fh = ctx.formula(nh, text)
+        keep.append((nh, fh))
+        jobs.append((nh, fh, B.params(confidence=0.95, half_width=0.05, seed=5, model_id=k, max_events=cap)))
+    res = ctx.estimate_batch(jobs)
+    assert ctx.last_kernel() == B.KERNEL_GENERIC
+    for k, ((net, text, cap), r) in enumerate(zip(models, res)):
+        o = oracle.estimate(net, text, confidence=0.95, eps=0.05, seed=5, model_id=k, max_events=cap)
+        got = (r["n"], r["successes"], r["events"], r["truncated"], r["batches"])
+        want = (o["n"], o["successes"], o["events"], o["truncated"], len(o["bounds"]))
+        assert got == want, (k, got, want)
+        assert (r["lo"], r["hi"]) == (o["lo"], o["hi"])
+
+
+def test_watchdog_and_cancel_stop_cleanly(ctx):
+    """A tiny watchdog stops a long launch with SMC_E_TIMEOUT (the kernel sees
+    the host's stop word and exits), a cancel from another thread gives
+    SMC_E_CANCELLED, and the context stays usable afterwards."""
+    import threading
+    B = _B()
+    net = W.c3_network()
+    nh = ctx.network(net)
+    fh = ctx.formula(nh, W.c3_formula(net))
+    long_run = B.params(fixed_n=32768, seed=1, max_events=W.C3_CAP)
+    ctx.set_watchdog(0.05)
+    try:
+        with pytest.raises(B.SmcError) as e:
+            ctx.estimate(nh, fh, long_run)
+        assert e.value.code == -7            # SMC_E_TIMEOUT
+    finally:
+        ctx.set_watchdog(120)
+    timer = threading.Timer(0.1, ctx.cancel)
+    timer.start()
+    try:
+        with pytest.raises(B.SmcError) as e:
+            ctx.estimate(nh, fh, long_run)
+        assert e.value.code == -6            # SMC_E_CANCELLED
+    finally:
+        timer.cancel()
+    small = W.immigration_death()
+    n1 = ctx.network(small)
+    f1 = ctx.formula(n1, W.C1_FORMULA)
+    r = ctx.estimate(n1, f1, B.params(fixed_n=4096, seed=1))
+    o = oracle.estimate(small, W.C1_FORMULA, fixed_n=4096, seed=1)
+    assert (r["n"], r["successes"], r["events"]) == (o["n"], o["successes"], o["events"])
