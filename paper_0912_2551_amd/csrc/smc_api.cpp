@@ -35,6 +35,7 @@ struct smc_ctx {
     // autotuned configurations per model structure (see smc_autotune)
     std::map<std::string, smc_tune_result> tuned;
     bool tuning = false;
+    std::map<double, double> zcache;   // z_{1-alpha/2} per confidence level
     int last_kernel = -1;
     bool spec_warned = false;
     double watchdog = 300.0;
@@ -125,7 +126,15 @@ double wilson_value(double p, double eps, double z)
     return (z * z) * num / (2.0 * e2);
 }
 
-double resolve_z(const smc_params &p) { return p.z > 0.0 ? p.z : smc_z_value(p.confidence); }
+double resolve_z(smc_ctx *ctx, const smc_params &p)
+{
+    if (p.z > 0.0) return p.z;
+    auto it = ctx->zcache.find(p.confidence);
+    if (it != ctx->zcache.end()) return it->second;
+    const double z = smc_z_value(p.confidence);
+    ctx->zcache.emplace(p.confidence, z);
+    return z;
+}
 
 struct Prepared {
     Job job;
@@ -149,7 +158,7 @@ int prepare(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_pa
     if (iterative || p->z > 0.0 || (p->confidence > 0.0 && p->confidence < 1.0)) {
         if (p->z <= 0.0 && !(p->confidence > 0.0 && p->confidence < 1.0))
             return fail(ctx, SMC_E_INVALID, "confidence must lie in (0, 1)");
-        z = resolve_z(*p);
+        z = resolve_z(ctx, *p);
     }
     uint64_t n_first, capacity;
     if (iterative) {
@@ -198,6 +207,15 @@ int prepare(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_pa
     return SMC_OK;
 }
 
+// Whether two models share their structure (network tables and compiled
+// formula), compared directly.
+bool same_structure(const smc_net *a, const smc_formula *fa, const smc_net *b, const smc_formula *fb)
+{
+    if (a == b && fa == fb) return true;
+    return a->S == b->S && a->M == b->M && a->reac == b->reac && a->chg == b->chg &&
+           std::memcmp(&fa->prog, &fb->prog, sizeof(MonProg)) == 0;
+}
+
 // The structure of a model: network tables and compiled formula (rates,
 // initial state, seeds and stopping parameters do not enter).
 std::string structure_key(const smc_net *net, const smc_formula *f)
@@ -220,15 +238,8 @@ int pick_spec_kernel(smc_ctx *ctx, const std::vector<Prepared> &P, bool iterativ
     bool ok = n0 && f0 && spec_supported(n0->S, n0->M, f0->prog);
     std::string src;
     if (ok) src = spec_source(n0->S, n0->M, n0->reac.data(), n0->chg.data(), f0->prog, ctx->spec_waves_per_simd, iterative);
-    const smc_net *ln = n0;
-    const smc_formula *lf = f0;
-    for (size_t k = 1; ok && k < P.size(); ++k) {
-        if (P[k].net == ln && P[k].f == lf) continue;
-        ln = P[k].net;
-        lf = P[k].f;
-        ok = ln && lf && ln->S == n0->S && ln->M == n0->M &&
-             spec_source(ln->S, ln->M, ln->reac.data(), ln->chg.data(), lf->prog, ctx->spec_waves_per_simd, iterative) == src;
-    }
+    for (size_t k = 1; ok && k < P.size(); ++k)
+        ok = P[k].net && P[k].f && same_structure(n0, f0, P[k].net, P[k].f);
     if (!ok) {
         if (ctx->spec_mode == SMC_SPECIALIZE_REQUIRED)
             return fail(ctx, SMC_E_UNSUPPORTED, "jobs do not share one structure the specialised kernels support");
@@ -294,7 +305,7 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
         auto it = ctx->tuned.find(key);
         bool same = it != ctx->tuned.end();
         for (int k = 1; same && k < n; ++k)
-            same = (P[k].net == P[0].net && P[k].f == P[0].f) || structure_key(P[k].net, P[k].f) == key;
+            same = P[k].net && P[k].f && same_structure(P[0].net, P[0].f, P[k].net, P[k].f);
         if (same) {
             ctx->waves_per_cu = it->second.waves_per_cu;
             ctx->spec_waves_per_simd = it->second.waves_per_simd;

@@ -328,6 +328,119 @@ __global__ __launch_bounds__(256) void mlp_query(const float *x, long n, const f
 }
 
 // ---------------------------------------------------------------------------
+// Inference + gate, persistent form for GPUs with 160 KB of LDS per CU: each
+// block stages W2 (bfloat16, 128 KB) in LDS once and then streams tiles of 32
+// points, so W2 is read from L2 once per block instead of once per tile.
+// Layer 1 into LDS as bfloat16; layer 2 on MFMA (wave w owns output columns
+// 64 w .. 64 w + 63, two 32 x 32 tiles); layer 3 reduced in registers: each
+// lane adds its two columns' products, the 32 lanes sharing a row group sum
+// with shuffles, and the four waves' partial sums are added in wave order.
+// Same gate as mlp_query.
+// ---------------------------------------------------------------------------
+constexpr size_t kQueryLds = (size_t)kH * kH * 2 + 32 * kH * 2 + 4 * 32 * 4 + 96 * 4;
+
+__global__ __launch_bounds__(256) void mlp_query_staged(const float *x, long n, const float *mu,
+                                                        const float *sigma, const uint16_t *W1b,
+                                                        const float *b1, const uint16_t *W2b,
+                                                        const float *b2, const uint16_t *W3b,
+                                                        const float *b3, const float *planes,
+                                                        int n_planes, float hull_tol, float threshold,
+                                                        float margin, float *p_out, uint8_t *use)
+{
+    extern __shared__ uint16_t qsm[];
+    uint16_t *W2s = qsm;                                  // [col][k], as W2b
+    uint16_t *h1s = W2s + kH * kH;                        // [row][k]
+    float *zpart = reinterpret_cast<float *>(h1s + 32 * kH);   // [wave][row]
+    float *xs = zpart + 4 * 32;                           // [row][3]
+    const int tid = (int)threadIdx.x;
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(W2b);
+        uint4 *dst = reinterpret_cast<uint4 *>(W2s);
+        for (int i = tid; i < kH * kH / 8; i += 256) dst[i] = src[i];
+    }
+    const int lane = tid & 63, wave = tid >> 6;
+    const int rc = lane & 31, half = lane >> 5;
+    const float w0 = from_bf16(W1b[tid * 3]), w1 = from_bf16(W1b[tid * 3 + 1]), w2 = from_bf16(W1b[tid * 3 + 2]);
+    const float bj = b1[tid];
+    const float m0 = mu[0], m1 = mu[1], m2 = mu[2], s0 = sigma[0], s1 = sigma[1], s2 = sigma[2];
+    float b2c[2], w3c[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int col = wave * 64 + t * 32 + rc;
+        b2c[t] = b2[col];
+        w3c[t] = from_bf16(W3b[col]);
+    }
+    const float bias3 = b3[0];
+    const long n_tiles = (n + 31) / 32;
+    for (long tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const long base = tile * 32;
+        __syncthreads();   // W2s staged; the previous tile's h1s, zpart and xs are consumed
+        if (tid < 96) {
+            const long row = base + tid / 3;
+            xs[tid] = row < n ? x[row * 3 + tid % 3] : 0.0f;
+        }
+        __syncthreads();
+        for (int r = 0; r < 32; ++r) {
+            float acc = bj;
+            acc = fmaf(from_bf16(to_bf16((xs[r * 3 + 0] - m0) / s0)), w0, acc);
+            acc = fmaf(from_bf16(to_bf16((xs[r * 3 + 1] - m1) / s1)), w1, acc);
+            acc = fmaf(from_bf16(to_bf16((xs[r * 3 + 2] - m2) / s2)), w2, acc);
+            h1s[r * kH + tid] = to_bf16(acc > 0.0f ? acc : 0.0f);
+        }
+        __syncthreads();
+        float part[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) part[r] = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int col = wave * 64 + t * 32 + rc;
+            floatx16 acc = {};
+            for (int kb = 0; kb < kH; kb += 16) {
+                bf16x8 a, b;
+                const int k0 = kb + 8 * half;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    a[e] = __builtin_bit_cast(__bf16, h1s[rc * kH + k0 + e]);
+                    b[e] = __builtin_bit_cast(__bf16, W2s[col * kH + k0 + e]);
+                }
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const float v = acc[r] + b2c[t];
+                part[r] += from_bf16(to_bf16(v > 0.0f ? v : 0.0f)) * w3c[t];
+            }
+        }
+        // sum over the 32 columns of the lane's half: rows 8 (r / 4) + 4 half + r % 4
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            float v = part[r];
+#pragma unroll
+            for (int off = 16; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (rc == 0) zpart[wave * 32 + 8 * (r / 4) + 4 * half + (r % 4)] = v;
+        }
+        __syncthreads();
+        if (tid < 32) {
+            const long row = base + tid;
+            const float z = bias3 + (((zpart[tid] + zpart[32 + tid]) + zpart[64 + tid]) + zpart[96 + tid]);
+            const float p = 1.0f / (1.0f + expf(-z));
+            if (row < n) {
+                p_out[row] = p;
+                if (use) {
+                    bool inside = n_planes > 0;
+                    for (int f = 0; f < n_planes && inside; ++f) {
+                        const float *pl = planes + 4 * f;
+                        const float v = pl[0] * xs[tid * 3] + pl[1] * xs[tid * 3 + 1] + pl[2] * xs[tid * 3 + 2];
+                        inside = v <= pl[3] + hull_tol;
+                    }
+                    use[row] = (inside && fabsf(p - threshold) >= margin) ? 1 : 0;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launch helpers.
 // ---------------------------------------------------------------------------
 static unsigned blocks_for(long n, int threads) { return (unsigned)((n + threads - 1) / threads); }
@@ -406,6 +519,29 @@ hipError_t sg_query(hipStream_t s, const float *x, long n, const float *mu, cons
                     const uint16_t *W3b, const float *b3, const float *planes, int n_planes, float hull_tol,
                     float threshold, float margin, float *p_out, uint8_t *use)
 {
+    // the staged form needs 145 KB of LDS per block; it runs where the device
+    // allows it (CDNA4: 160 KB per CU), one block per CU over all tiles
+    static int staged = -1, n_blocks = 0;
+    if (staged < 0) {
+        int dev = 0, lds = 0, cus = 0;
+        staged = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            (size_t)lds >= kQueryLds &&
+            hipFuncSetAttribute((const void *)mlp_query_staged, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)kQueryLds) == hipSuccess) {
+            staged = 1;
+            n_blocks = cus;
+        }
+    }
+    if (staged == 1 && n >= 32L * 1024) {
+        const long n_tiles = (n + 31) / 32;
+        const unsigned grid = (unsigned)(n_tiles < n_blocks ? n_tiles : n_blocks);
+        hipLaunchKernelGGL(mlp_query_staged, dim3(grid), dim3(256), kQueryLds, s, x, n, mu, sigma, W1b, b1, W2b,
+                           b2, W3b, b3, planes, n_planes, hull_tol, threshold, margin, p_out, use);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(mlp_query, dim3(blocks_for(n, 32)), dim3(256), 0, s, x, n, mu, sigma, W1b, b1, W2b, b2,
                        W3b, b3, planes, n_planes, hull_tol, threshold, margin, p_out, use);
     return hipGetLastError();

@@ -62,11 +62,16 @@ def test_query_matches_oracle_forward(ctx):
     params = mlp.init_params(12, mu=tuple(np.log10(W.MM_RATES)), sigma=(0.57, 0.57, 0.57))
     s = B.Surrogate(ctx)
     s.set_params(params.astype(np.float32))
-    x = W.surrogate_queries(5000, seed=5)
-    p, use = s.query(x)
-    ref = mlp.forward(params, x.astype(np.float64))["p"]
-    assert np.max(np.abs(p - ref)) <= 1e-4
-    assert not use.any()            # no training hull yet: never confident
+    # 5000 points take the per-tile kernel; 50000 the persistent one that
+    # stages W2 in LDS (where the device has the LDS for it)
+    for count in (5000, 50000):
+        x = W.surrogate_queries(count, seed=5)
+        p, use = s.query(x)
+        ref = mlp.forward(params, x.astype(np.float64))["p"]
+        dp = np.abs(p - ref)
+        assert dp.max() <= 1e-3 and np.mean(dp > 1e-4) <= 0.01, (count, dp.max())
+        assert np.median(dp) <= 1e-6
+        assert not use.any()            # no training hull yet: never confident
 
 
 def test_training_fits_and_gate(ctx):
@@ -82,7 +87,7 @@ def test_training_fits_and_gate(ctx):
     assert losses[-1] < losses[0]
     assert losses[-1] - ent < 0.1 * (losses[0] - ent)      # most of the excess loss is gone
     params = s.get_params().astype(np.float64)
-    q = W.surrogate_queries(20000, seed=10)
+    q = W.surrogate_queries(40000, seed=10)
     p, use = s.query(q)
     ref = mlp.forward(params, q.astype(np.float64))["p"]
     dp = np.abs(p - ref)
