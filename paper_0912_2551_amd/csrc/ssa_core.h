@@ -39,6 +39,13 @@ struct U4 {
     uint32_t a, b, c, d;
 };
 
+// a ^ b ^ c in one instruction (gfx950's three-input bit operation; 0x96 is
+// the truth table of odd parity).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 32x32->64 multiplies, key bumped by the Weyl constants between rounds.
 __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
@@ -48,8 +55,8 @@ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
     for (int r = 0; r < 10; ++r) {
         const uint64_t m0 = (uint64_t)c0 * 0xD2511F53ull;
         const uint64_t m1 = (uint64_t)c2 * 0xCD9E8D57ull;
-        const uint32_t n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(m1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(m0 >> 32), c3, k1);
         c1 = (uint32_t)m1;
         c3 = (uint32_t)m0;
         c0 = n0;
@@ -61,15 +68,30 @@ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
 }
 
 // 53-bit uniforms: (0,1] for the waiting time, [0,1) for the channel.
+// v = hi 2^21 + (lo >> 11) is formed as vh 2^32 + vl from two 32-bit words;
+// every step below is exact (all values are integers < 2^53, or such integers
+// times a power of two), so the results equal (v + 1) 2^-53 and v 2^-53.
 __device__ __forceinline__ double unif_oc(uint32_t hi, uint32_t lo)
 {
-    const uint64_t v = ((uint64_t)hi << 21) | (uint64_t)(lo >> 11);
-    return (double)(v + 1ull) * 0x1p-53;
+    const double vh = (double)(hi >> 11);
+    const double vl = (double)((hi << 21) | (lo >> 11));
+    return fma(fma(vh, 0x1p32, vl), 0x1p-53, 0x1p-53);
 }
 __device__ __forceinline__ double unif_co(uint32_t hi, uint32_t lo)
 {
-    const uint64_t v = ((uint64_t)hi << 21) | (uint64_t)(lo >> 11);
-    return (double)v * 0x1p-53;
+    const double vh = (double)(hi >> 11);
+    const double vl = (double)((hi << 21) | (lo >> 11));
+    return fma(vh, 0x1p-21, vl * 0x1p-53);
+}
+
+// fma(a, b, c) for a constant c, read from scalar registers.  Left to
+// itself the compiler keeps loop-invariant FP64 constants in vector registers
+// and copies one before each accumulate-in-place multiply-add.
+__device__ __forceinline__ double fma_sconst(double a, double b, double c)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
 }
 
 // Natural log of a positive normal double from IEEE operations only.
@@ -88,15 +110,15 @@ __device__ __forceinline__ double ctr_log(double x)
     const double s = f / (2.0 + f);
     const double z = s * s;
     double p = 1.0 / 21.0;
-    p = fma(z, p, 1.0 / 19.0);
-    p = fma(z, p, 1.0 / 17.0);
-    p = fma(z, p, 1.0 / 15.0);
-    p = fma(z, p, 1.0 / 13.0);
-    p = fma(z, p, 1.0 / 11.0);
-    p = fma(z, p, 1.0 / 9.0);
-    p = fma(z, p, 1.0 / 7.0);
-    p = fma(z, p, 1.0 / 5.0);
-    p = fma(z, p, 1.0 / 3.0);
+    p = fma_sconst(z, p, 1.0 / 19.0);
+    p = fma_sconst(z, p, 1.0 / 17.0);
+    p = fma_sconst(z, p, 1.0 / 15.0);
+    p = fma_sconst(z, p, 1.0 / 13.0);
+    p = fma_sconst(z, p, 1.0 / 11.0);
+    p = fma_sconst(z, p, 1.0 / 9.0);
+    p = fma_sconst(z, p, 1.0 / 7.0);
+    p = fma_sconst(z, p, 1.0 / 5.0);
+    p = fma_sconst(z, p, 1.0 / 3.0);
     const double R = z * p;
     const double R2 = R + R;
     const double h = (0.5 * f) * f;
