@@ -169,8 +169,7 @@ struct JobResult {
 // Launch-wide control block.
 struct Control {
     int32_t open_jobs;            // iterative jobs not final yet
-    int32_t pad;
-    unsigned long long cancel_seen;
+    int32_t stop;                 // a wave has seen the host's stop word
 };
 
 }  // namespace smc

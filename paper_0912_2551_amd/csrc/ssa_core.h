@@ -829,15 +829,16 @@ struct StaticPolicy {
             P[j] = acc;
         }
         const double a0 = acc;
-        if (!(a0 > 0.0)) return __builtin_inf();
         const double target = d.u2 * a0;
         // u2 < 1 makes target < a0 = P[M-1], so some channel always qualifies
         int js = M - 1;
 #pragma unroll
         for (int j = M - 2; j >= 0; --j) js = (P[j] > target) ? j : js;
         *jsel = js;
+        // computed on every lane and discarded where a0 = 0 (absorbing): a
+        // select keeps the event in one basic block
         const double tau = d.nl / a0;
-        return t + tau;
+        return a0 > 0.0 ? t + tau : __builtin_inf();
     }
     __device__ static __forceinline__ void apply_if(Counts &X, Sel js, bool on)
     {
@@ -1146,9 +1147,21 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
     unsigned long long my_events = 0;
 
     for (uint32_t it = 0;; ++it) {
-        if ((it & 255u) == 0u) {
+        // Stop requests, checked once per 4096 iterations.  The host's stop
+        // word lives in host memory, and reads of it cross the bus and queue
+        // behind one another (thousands of waves reading it together stall for
+        // hundreds of microseconds).  So at each check only the waves of one
+        // counter shard (one in kShards), in turn, read it, and pass a request
+        // on through a word in device memory that every wave reads.
+        if ((it & 4095u) == 4095u) {
             int stop = 0;
-            if (lane == 0) stop = *A.cancel;
+            if (lane == 0) {
+                stop = ld_relaxed(&A.ctl->stop);
+                if (!stop && (((it >> 12) + (uint32_t)shard) & (kShards - 1)) == 0u) {
+                    stop = *A.cancel;
+                    if (stop) st_relaxed_i32(&A.ctl->stop, 1);
+                }
+            }
             if (uniform_i(stop)) break;
         }
         if (__ballot(active) == 0ull && pool_next == pool_end) {
@@ -1236,12 +1249,14 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
         t = applied ? tn : t;
         k = applied ? k + 1u : k;
         entered = entered || applied;
-        fin = fin || (ev_lane && capped) || dec_time || dec_tmax;
-        verdict = dec_time ? (va == 1u ? 1u : 0u) : ((ev_lane && capped) || dec_tmax ? 0u : verdict);
-        reason = (ev_lane && capped) ? (uint32_t)RS_CAP
-                 : dec_time           ? (uint32_t)(absorbing ? RS_ABSORB : RS_TIME)
-                 : dec_tmax           ? (uint32_t)RS_TMAX
-                                      : reason;
+        // capped, dec_time and dec_tmax exclude each other
+        const bool dec_cap = ev_lane && capped;
+        fin = fin || dec_cap || dec_time || dec_tmax;
+        verdict = dec_time ? (va == 1u ? 1u : 0u) : (dec_cap || dec_tmax ? 0u : verdict);
+        const uint32_t r_time = absorbing ? (uint32_t)RS_ABSORB : (uint32_t)RS_TIME;
+        reason = dec_tmax ? (uint32_t)RS_TMAX : reason;
+        reason = dec_time ? r_time : reason;
+        reason = dec_cap ? (uint32_t)RS_CAP : reason;
 
         // -------- inspect the state just entered (new or after an event) --------
         MonState ms_st = ms;
