@@ -13,8 +13,10 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "smc.h"
@@ -33,7 +35,10 @@ struct smc_ctx {
     int spec_mode = SMC_SPECIALIZE_AUTO;
     int spec_waves_per_simd = 0;
     // autotuned configurations per model structure (see smc_autotune)
-    std::map<std::string, smc_tune_result> tuned;
+    std::map<std::pair<uint64_t, uint64_t>, smc_tune_result> tuned;
+    // specialised kernels per (network structure, formula structure,
+    // iterative, occupancy hint): spares regenerating the kernel source
+    std::map<std::tuple<uint64_t, uint64_t, int, int>, hipFunction_t> spec_fns;
     bool tuning = false;
     std::map<double, double> zcache;   // z_{1-alpha/2} per confidence level
     int last_kernel = -1;
@@ -53,10 +58,18 @@ struct smc_ctx {
     Control *d_ctl = nullptr;
     char *d_rec = nullptr;
     size_t cap_rec = 0;
+    // pinned staging for the per-launch copies (asynchronous DMA instead of
+    // the staged copies of pageable memory)
+    Job *h_jobs = nullptr;
+    size_t cap_h_jobs = 0;
+    JobResult *h_results = nullptr;
+    size_t cap_h_results = 0;
+    Control *h_ctl = nullptr;
 };
 
 struct smc_net {
     smc_ctx *ctx = nullptr;
+    uint64_t sid = 0;             // structure id: equal ids, equal (S, M, reac, chg)
     int S = 0, M = 0;
     std::vector<int32_t> x0;
     std::vector<double> rate;
@@ -71,6 +84,7 @@ struct smc_net {
 
 struct smc_formula {
     smc_ctx *ctx = nullptr;
+    uint64_t sid = 0;             // structure id: equal ids, equal compiled programs
     MonProg prog;
     MonProg *d_prog = nullptr;
     double horizon = 0.0;
@@ -106,13 +120,40 @@ template <typename T>
 int ensure(smc_ctx *ctx, T *&ptr, size_t &cap, size_t n)
 {
     if (n <= cap) return SMC_OK;
+    const size_t want = std::max(n, cap * 2);
     if (ptr) (void)hipFree(ptr);
     ptr = nullptr;
     cap = 0;
-    const size_t want = std::max(n, cap * 2);
     HIP_TRY(ctx, hipMalloc((void **)&ptr, want * sizeof(T)));
     cap = want;
     return SMC_OK;
+}
+
+template <typename T>
+int ensure_pinned(smc_ctx *ctx, T *&ptr, size_t &cap, size_t n)
+{
+    if (n <= cap) return SMC_OK;
+    const size_t want = std::max(n, cap * 2);
+    if (ptr) (void)hipHostFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+    HIP_TRY(ctx, hipHostMalloc((void **)&ptr, want * sizeof(T), hipHostMallocDefault));
+    cap = want;
+    return SMC_OK;
+}
+
+// Process-wide ids of distinct structures (byte strings): equal ids, equal
+// structures.  The table only grows, by one entry per distinct structure.
+uint64_t intern_structure(const std::string &bytes)
+{
+    static std::mutex mu;
+    static auto *tab = new std::map<std::string, uint64_t>();
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = tab->find(bytes);
+    if (it != tab->end()) return it->second;
+    const uint64_t id = tab->size() + 1;
+    tab->emplace(bytes, id);
+    return id;
 }
 
 // Eq. 4 before rounding, in the contract's operation order.
@@ -211,20 +252,14 @@ int prepare(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_pa
 // formula), compared directly.
 bool same_structure(const smc_net *a, const smc_formula *fa, const smc_net *b, const smc_formula *fb)
 {
-    if (a == b && fa == fb) return true;
-    return a->S == b->S && a->M == b->M && a->reac == b->reac && a->chg == b->chg &&
-           std::memcmp(&fa->prog, &fb->prog, sizeof(MonProg)) == 0;
+    return a->sid == b->sid && fa->sid == fb->sid;
 }
 
 // The structure of a model: network tables and compiled formula (rates,
 // initial state, seeds and stopping parameters do not enter).
-std::string structure_key(const smc_net *net, const smc_formula *f)
+std::pair<uint64_t, uint64_t> structure_key(const smc_net *net, const smc_formula *f)
 {
-    std::string key = spec_source(net->S, net->M, net->reac.data(), net->chg.data(), f->prog, 0, false);
-    key.append((const char *)f->prog.vop, sizeof f->prog.vop);
-    key.append((const char *)f->prog.vvar, sizeof f->prog.vvar);
-    key.append((const char *)f->prog.vconst, sizeof f->prog.vconst);
-    return key;
+    return {net->sid, f->sid};
 }
 
 // The specialised kernel for a launch, if every job shares one network
@@ -236,8 +271,6 @@ int pick_spec_kernel(smc_ctx *ctx, const std::vector<Prepared> &P, bool iterativ
     const smc_net *n0 = P[0].net;
     const smc_formula *f0 = P[0].f;
     bool ok = n0 && f0 && spec_supported(n0->S, n0->M, f0->prog);
-    std::string src;
-    if (ok) src = spec_source(n0->S, n0->M, n0->reac.data(), n0->chg.data(), f0->prog, ctx->spec_waves_per_simd, iterative);
     for (size_t k = 1; ok && k < P.size(); ++k)
         ok = P[k].net && P[k].f && same_structure(n0, f0, P[k].net, P[k].f);
     if (!ok) {
@@ -245,8 +278,18 @@ int pick_spec_kernel(smc_ctx *ctx, const std::vector<Prepared> &P, bool iterativ
             return fail(ctx, SMC_E_UNSUPPORTED, "jobs do not share one structure the specialised kernels support");
         return SMC_OK;
     }
+    const auto key = std::make_tuple(n0->sid, f0->sid, iterative ? 1 : 0, ctx->spec_waves_per_simd);
+    const auto hit = ctx->spec_fns.find(key);
+    if (hit != ctx->spec_fns.end()) {
+        *fn = hit->second;
+        return SMC_OK;
+    }
+    const std::string src =
+        spec_source(n0->S, n0->M, n0->reac.data(), n0->chg.data(), f0->prog, ctx->spec_waves_per_simd, iterative);
     std::string err;
-    if (spec_kernel(ctx->device, src, fn, err) != 0) {
+    if (spec_kernel(ctx->device, src, fn, err) == 0) {
+        ctx->spec_fns.emplace(key, *fn);
+    } else {
         *fn = nullptr;
         if (ctx->spec_mode == SMC_SPECIALIZE_REQUIRED) return fail(ctx, SMC_E_HIP, err);
         if (!ctx->spec_warned) {
@@ -271,8 +314,10 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
     if (ensure(ctx, ctx->d_jobs, ctx->cap_jobs, (size_t)n)) return SMC_E_NOMEM;
     if (ensure(ctx, ctx->d_states, ctx->cap_states, (size_t)n)) return SMC_E_NOMEM;
     if (ensure(ctx, ctx->d_results, ctx->cap_results, (size_t)n)) return SMC_E_NOMEM;
+    if (ensure_pinned(ctx, ctx->h_jobs, ctx->cap_h_jobs, (size_t)n)) return SMC_E_NOMEM;
+    if (ensure_pinned(ctx, ctx->h_results, ctx->cap_h_results, (size_t)n)) return SMC_E_NOMEM;
     int s_max = 1, m_max = 1, n_iter = 0;
-    std::vector<Job> jobs(n);
+    Job *jobs = ctx->h_jobs;   // the previous call's copies have completed
     for (int k = 0; k < n; ++k) {
         jobs[k] = P[k].job;
         jobs[k].st = ctx->d_states + k;
@@ -281,7 +326,7 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
         n_iter += jobs[k].iterative;
     }
     hipStream_t s = ctx->stream;
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_jobs, jobs.data(), n * sizeof(Job), hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_jobs, jobs, n * sizeof(Job), hipMemcpyHostToDevice, s));
     HIP_TRY(ctx, hipMemsetAsync(ctx->d_states, 0, n * sizeof(JobState), s));
     HIP_TRY(ctx, launch_init(s, ctx->d_jobs, n));
     *ctx->cancel_host = 0;
@@ -301,8 +346,7 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
         }
     } restore{ctx, ctx->waves_per_cu, ctx->spec_waves_per_simd, ctx->spec_mode};
     if (!ctx->tuned.empty() && !ctx->tuning && n_iter == 0 && P[0].net && P[0].f) {
-        const std::string key = structure_key(P[0].net, P[0].f);
-        auto it = ctx->tuned.find(key);
+        auto it = ctx->tuned.find(structure_key(P[0].net, P[0].f));
         bool same = it != ctx->tuned.end();
         for (int k = 1; same && k < n; ++k)
             same = P[k].net && P[k].f && same_structure(P[0].net, P[0].f, P[k].net, P[k].f);
@@ -333,13 +377,14 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
     unsigned long long last_progress = ~0ull;
     int stalls = 0;
     for (int launch = 0; launch < 1000; ++launch) {
-        Control c{};
         int open = 0;
         if (launch == 0) open = n_iter;
         else
             for (int k = 0; k < n; ++k) open += (jobs[k].iterative && !res[k].final_flag);
-        c.open_jobs = open;
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->d_ctl, &c, sizeof(c), hipMemcpyHostToDevice, s));
+        // the previous launch (and its copies) completed before this point
+        *ctx->h_ctl = Control{};
+        ctx->h_ctl->open_jobs = open;
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->d_ctl, ctx->h_ctl, sizeof(Control), hipMemcpyHostToDevice, s));
         HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
         if (spec_fn)
             HIP_TRY(ctx, launch_module(spec_fn, grid, wpb, s, ctx->d_jobs, n, s_max, ctx->d_ctl,
@@ -362,8 +407,9 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
         float ms = 0.0f;
         HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
         total_ms += ms;
-        HIP_TRY(ctx, hipMemcpyAsync(res.data(), ctx->d_results, n * sizeof(JobResult), hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->h_results, ctx->d_results, n * sizeof(JobResult), hipMemcpyDeviceToHost, s));
         HIP_TRY(ctx, hipStreamSynchronize(s));
+        std::memcpy(res.data(), ctx->h_results, n * sizeof(JobResult));
         if (*ctx->cancel_host) {
             *seconds = total_ms * 1e-3;
             return ctx->cancel_req.load() ? fail(ctx, SMC_E_CANCELLED, "cancelled")
@@ -449,6 +495,7 @@ int smc_ctx_create(int hip_device, void *hip_stream, smc_ctx **out)
     if ((e = hipHostMalloc((void **)&c->cancel_host, sizeof(int32_t), hipHostMallocMapped)) != hipSuccess ||
         (e = hipHostGetDevicePointer((void **)&c->cancel_dev, c->cancel_host, 0)) != hipSuccess ||
         (e = hipMalloc((void **)&c->d_ctl, sizeof(Control))) != hipSuccess ||
+        (e = hipHostMalloc((void **)&c->h_ctl, sizeof(Control), hipHostMallocDefault)) != hipSuccess ||
         (e = hipEventCreate(&c->ev0)) != hipSuccess || (e = hipEventCreate(&c->ev1)) != hipSuccess) {
         smc_ctx_destroy(c);
         return fail(nullptr, SMC_E_HIP, hipGetErrorString(e));
@@ -469,6 +516,9 @@ void smc_ctx_destroy(smc_ctx *c)
     if (c->d_rec) (void)hipFree(c->d_rec);
     if (c->d_ctl) (void)hipFree(c->d_ctl);
     if (c->cancel_host) (void)hipHostFree(c->cancel_host);
+    if (c->h_jobs) (void)hipHostFree(c->h_jobs);
+    if (c->h_results) (void)hipHostFree(c->h_results);
+    if (c->h_ctl) (void)hipHostFree(c->h_ctl);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -500,7 +550,7 @@ int smc_autotune(smc_ctx *c, const smc_net *net, const smc_formula *f, const smc
 {
     if (!c || !net || !f || !p || !out) return fail(c, SMC_E_INVALID, "null argument");
     if (pilot_n == 0 || pilot_n > (1ull << 26)) return fail(c, SMC_E_INVALID, "pilot_n must lie in 1..2^26");
-    const std::string key = structure_key(net, f);
+    const auto key = structure_key(net, f);
     auto it = c->tuned.find(key);
     if (it != c->tuned.end()) {
         *out = it->second;
@@ -678,6 +728,14 @@ int smc_net_create(smc_ctx *c, const smc_net_desc *d, smc_net **out)
     }
     for (int s = 0; s < S; ++s)
         n->names.push_back(d->names && d->names[s] ? std::string(d->names[s]) : "X" + std::to_string(s));
+    {
+        std::string b = "N";
+        b.append((const char *)&n->S, sizeof n->S);
+        b.append((const char *)&n->M, sizeof n->M);
+        b.append((const char *)n->reac.data(), n->reac.size() * sizeof(int32_t));
+        b.append((const char *)n->chg.data(), n->chg.size() * sizeof(uint32_t));
+        n->sid = intern_structure(b);
+    }
     const int rc = upload_net(n);
     if (rc != SMC_OK) {
         smc_net_destroy(n);
@@ -728,6 +786,7 @@ int smc_formula_compile(smc_ctx *c, const smc_net *net, const char *text, smc_fo
         return fail(c, SMC_E_INVALID, e.what());
     }
     f->horizon = f->prog.horizon;
+    f->sid = intern_structure(std::string("F") + std::string((const char *)&f->prog, sizeof(MonProg)));
     hipError_t e = hipMalloc((void **)&f->d_prog, sizeof(MonProg));
     if (e == hipSuccess) e = hipMemcpy(f->d_prog, &f->prog, sizeof(MonProg), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
