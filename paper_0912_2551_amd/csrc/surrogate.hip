@@ -250,6 +250,24 @@ __global__ void round_bf16(const float *w, uint16_t *wb, long count)
 // uses the surrogate when it lies in the training hull (n.x <= d for every
 // facet, in log10-rate space) and |p - threshold| >= margin.
 // ---------------------------------------------------------------------------
+// Hull test of a tile's 32 points, spread over the block's 256 threads: thread
+// t tests point t % 32 against facets t / 32, t / 32 + 8, ...  A point found
+// outside any facet (n.x > d + tol) has its flag cleared; the flags start at 1.
+__device__ __forceinline__ void hull_test(const float *xs, const float *planes, int n_planes, float hull_tol,
+                                          int *inside_s)
+{
+    const int tid = (int)threadIdx.x;
+    const int r = tid & 31;
+    const float a0 = xs[r * 3], a1 = xs[r * 3 + 1], a2 = xs[r * 3 + 2];
+    bool ok = true;
+    for (int f = tid >> 5; f < n_planes && ok; f += 8) {
+        const float *pl = planes + 4 * f;
+        const float v = pl[0] * a0 + pl[1] * a1 + pl[2] * a2;
+        ok = v <= pl[3] + hull_tol;
+    }
+    if (!ok) inside_s[r] = 0;
+}
+
 __global__ __launch_bounds__(256) void mlp_query(const float *x, long n, const float *mu,
                                                  const float *sigma, const uint16_t *W1b,
                                                  const float *b1, const uint16_t *W2b,
@@ -260,13 +278,18 @@ __global__ __launch_bounds__(256) void mlp_query(const float *x, long n, const f
 {
     __shared__ uint16_t h1s[32 * kH];
     __shared__ float prod[32 * kH];
-    __shared__ float xs[32 * 3];
+    __shared__ float xs[32 * 3], xn[32 * 3];
+    __shared__ int inside_s[32];
     const int tid = (int)threadIdx.x;
     const long base = (long)blockIdx.x * 32;
     if (tid < 96) {
         const long row = base + tid / 3;
-        xs[tid] = row < n ? x[row * 3 + tid % 3] : 0.0f;
+        const int c = tid % 3;
+        const float v = row < n ? x[row * 3 + c] : 0.0f;
+        xs[tid] = v;
+        xn[tid] = from_bf16(to_bf16((v - mu[c]) / sigma[c]));   // once per input, not per unit
     }
+    if (tid < 32) inside_s[tid] = 1;
     __syncthreads();
     {
         const int j = tid;
@@ -274,12 +297,13 @@ __global__ __launch_bounds__(256) void mlp_query(const float *x, long n, const f
         const float bj = b1[j];
         for (int r = 0; r < 32; ++r) {
             float acc = bj;
-            acc = fmaf(from_bf16(to_bf16((xs[r * 3 + 0] - mu[0]) / sigma[0])), w0, acc);
-            acc = fmaf(from_bf16(to_bf16((xs[r * 3 + 1] - mu[1]) / sigma[1])), w1, acc);
-            acc = fmaf(from_bf16(to_bf16((xs[r * 3 + 2] - mu[2]) / sigma[2])), w2, acc);
+            acc = fmaf(xn[r * 3 + 0], w0, acc);
+            acc = fmaf(xn[r * 3 + 1], w1, acc);
+            acc = fmaf(xn[r * 3 + 2], w2, acc);
             h1s[r * kH + j] = to_bf16(acc > 0.0f ? acc : 0.0f);
         }
     }
+    if (use) hull_test(xs, planes, n_planes, hull_tol, inside_s);
     __syncthreads();
     const int lane = tid & 63, wave = tid >> 6;
     const int rc = lane & 31, half = lane >> 5;
@@ -315,12 +339,7 @@ __global__ __launch_bounds__(256) void mlp_query(const float *x, long n, const f
         if (row < n) {
             p_out[row] = p;
             if (use) {
-                bool inside = n_planes > 0;
-                for (int f = 0; f < n_planes && inside; ++f) {
-                    const float *pl = planes + 4 * f;
-                    const float v = pl[0] * xs[tid * 3] + pl[1] * xs[tid * 3 + 1] + pl[2] * xs[tid * 3 + 2];
-                    inside = v <= pl[3] + hull_tol;
-                }
+                const bool inside = n_planes > 0 && inside_s[tid] != 0;
                 use[row] = (inside && fabsf(p - threshold) >= margin) ? 1 : 0;
             }
         }
@@ -337,7 +356,11 @@ __global__ __launch_bounds__(256) void mlp_query(const float *x, long n, const f
 // with shuffles, and the four waves' partial sums are added in wave order.
 // Same gate as mlp_query.
 // ---------------------------------------------------------------------------
-constexpr size_t kQueryLds = (size_t)kH * kH * 2 + 32 * kH * 2 + 4 * 32 * 4 + 96 * 4;
+// LDS rows (a column of W2, a row of h1) are padded by 8 bfloat16 values, so
+// that the 16-byte operand reads of the 32 lanes of a half-wave (one row each)
+// start on different banks instead of all on the same one.
+constexpr int kQRow = kH + 8;
+constexpr size_t kQueryLds = (size_t)kH * kQRow * 2 + 32 * kQRow * 2 + 4 * 32 * 4 + 2 * 96 * 4 + 32 * 4;
 
 __global__ __launch_bounds__(256) void mlp_query_staged(const float *x, long n, const float *mu,
                                                         const float *sigma, const uint16_t *W1b,
@@ -348,21 +371,22 @@ __global__ __launch_bounds__(256) void mlp_query_staged(const float *x, long n, 
                                                         float margin, float *p_out, uint8_t *use)
 {
     extern __shared__ uint16_t qsm[];
-    uint16_t *W2s = qsm;                                  // [col][k], as W2b
-    uint16_t *h1s = W2s + kH * kH;                        // [row][k]
+    uint16_t *W2s = qsm;                                  // [col][k] (row stride kQRow), as W2b
+    uint16_t *h1s = W2s + kH * kQRow;                     // [row][k] (row stride kQRow)
     float *zpart = reinterpret_cast<float *>(h1s + 32 * kH);   // [wave][row]
-    float *xs = zpart + 4 * 32;                           // [row][3]
+    float *xs = zpart + 4 * 32;                           // [row][3], as given
+    float *xn = xs + 96;                                  // [row][3], normalised, bfloat16-rounded
+    int *inside_s = reinterpret_cast<int *>(xn + 96);     // [row]
     const int tid = (int)threadIdx.x;
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(W2b);
         uint4 *dst = reinterpret_cast<uint4 *>(W2s);
-        for (int i = tid; i < kH * kH / 8; i += 256) dst[i] = src[i];
+        for (int i = tid; i < kH * kH / 8; i += 256) dst[(i / (kH / 8)) * (kQRow / 8) + i % (kH / 8)] = src[i];
     }
     const int lane = tid & 63, wave = tid >> 6;
     const int rc = lane & 31, half = lane >> 5;
     const float w0 = from_bf16(W1b[tid * 3]), w1 = from_bf16(W1b[tid * 3 + 1]), w2 = from_bf16(W1b[tid * 3 + 2]);
     const float bj = b1[tid];
-    const float m0 = mu[0], m1 = mu[1], m2 = mu[2], s0 = sigma[0], s1 = sigma[1], s2 = sigma[2];
     float b2c[2], w3c[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
@@ -377,39 +401,44 @@ __global__ __launch_bounds__(256) void mlp_query_staged(const float *x, long n, 
         __syncthreads();   // W2s staged; the previous tile's h1s, zpart and xs are consumed
         if (tid < 96) {
             const long row = base + tid / 3;
-            xs[tid] = row < n ? x[row * 3 + tid % 3] : 0.0f;
+            const int c = tid % 3;
+            const float v = row < n ? x[row * 3 + c] : 0.0f;
+            xs[tid] = v;
+            xn[tid] = from_bf16(to_bf16((v - mu[c]) / sigma[c]));
         }
+        if (tid < 32) inside_s[tid] = 1;
         __syncthreads();
         for (int r = 0; r < 32; ++r) {
             float acc = bj;
-            acc = fmaf(from_bf16(to_bf16((xs[r * 3 + 0] - m0) / s0)), w0, acc);
-            acc = fmaf(from_bf16(to_bf16((xs[r * 3 + 1] - m1) / s1)), w1, acc);
-            acc = fmaf(from_bf16(to_bf16((xs[r * 3 + 2] - m2) / s2)), w2, acc);
-            h1s[r * kH + tid] = to_bf16(acc > 0.0f ? acc : 0.0f);
+            acc = fmaf(xn[r * 3 + 0], w0, acc);
+            acc = fmaf(xn[r * 3 + 1], w1, acc);
+            acc = fmaf(xn[r * 3 + 2], w2, acc);
+            h1s[r * kQRow + tid] = to_bf16(acc > 0.0f ? acc : 0.0f);
         }
+        if (use) hull_test(xs, planes, n_planes, hull_tol, inside_s);
         __syncthreads();
+        // the wave's two 32-column groups share each A operand read; their
+        // accumulators are independent, so the MFMAs overlap
+        floatx16 acc0 = {}, acc1 = {};
+        {
+            const uint16_t *arow = h1s + rc * kQRow + 8 * half;
+            const uint16_t *b0row = W2s + (wave * 64 + rc) * kQRow + 8 * half;
+            const uint16_t *b1row = b0row + 32 * kQRow;
+#pragma unroll 4
+            for (int kb = 0; kb < kH; kb += 16) {
+                const bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(arow + kb));
+                const bf16x8 b0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(b0row + kb));
+                const bf16x8 b1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(b1row + kb));
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
+            }
+        }
         float part[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) part[r] = 0.0f;
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            const int col = wave * 64 + t * 32 + rc;
-            floatx16 acc = {};
-            for (int kb = 0; kb < kH; kb += 16) {
-                bf16x8 a, b;
-                const int k0 = kb + 8 * half;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    a[e] = __builtin_bit_cast(__bf16, h1s[rc * kH + k0 + e]);
-                    b[e] = __builtin_bit_cast(__bf16, W2s[col * kH + k0 + e]);
-                }
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-            }
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const float v = acc[r] + b2c[t];
-                part[r] += from_bf16(to_bf16(v > 0.0f ? v : 0.0f)) * w3c[t];
-            }
+        for (int r = 0; r < 16; ++r) {
+            const float v0 = acc0[r] + b2c[0], v1 = acc1[r] + b2c[1];
+            part[r] = from_bf16(to_bf16(v0 > 0.0f ? v0 : 0.0f)) * w3c[0];
+            part[r] += from_bf16(to_bf16(v1 > 0.0f ? v1 : 0.0f)) * w3c[1];
         }
         // sum over the 32 columns of the lane's half: rows 8 (r / 4) + 4 half + r % 4
 #pragma unroll
@@ -427,12 +456,7 @@ __global__ __launch_bounds__(256) void mlp_query_staged(const float *x, long n, 
             if (row < n) {
                 p_out[row] = p;
                 if (use) {
-                    bool inside = n_planes > 0;
-                    for (int f = 0; f < n_planes && inside; ++f) {
-                        const float *pl = planes + 4 * f;
-                        const float v = pl[0] * xs[tid * 3] + pl[1] * xs[tid * 3 + 1] + pl[2] * xs[tid * 3 + 2];
-                        inside = v <= pl[3] + hull_tol;
-                    }
+                    const bool inside = n_planes > 0 && inside_s[tid] != 0;
                     use[row] = (inside && fabsf(p - threshold) >= margin) ? 1 : 0;
                 }
             }
@@ -519,7 +543,7 @@ hipError_t sg_query(hipStream_t s, const float *x, long n, const float *mu, cons
                     const uint16_t *W3b, const float *b3, const float *planes, int n_planes, float hull_tol,
                     float threshold, float margin, float *p_out, uint8_t *use)
 {
-    // the staged form needs 145 KB of LDS per block; it runs where the device
+    // the staged form needs 150 KB of LDS per block; it runs where the device
     // allows it (CDNA4: 160 KB per CU), one block per CU over all tiles
     static int staged = -1, n_blocks = 0;
     if (staged < 0) {
