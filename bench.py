@@ -69,6 +69,14 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}))
 
 
+_T_START = time.perf_counter()
+
+
+def progress(what):
+    """One line on stderr per finished section (the JSON line stays alone on stdout)."""
+    print(f"[bench {time.perf_counter() - _T_START:7.1f} s] {what} done", file=sys.stderr, flush=True)
+
+
 def cpu_baseline(net, text, sample):
     import oracle
     threads = oracle.default_threads()
@@ -249,6 +257,7 @@ def main():
         # launch configuration chosen by the library's autotuner (pilot runs,
         # before the timed region; estimates do not depend on it)
         tune = ctx.autotune(nh, fh, p, pilot_n=N_TRAJ)
+        progress("autotune")
 
     for _ in range(args.warmup):
         ctx.estimate(nh, fh, p)
@@ -296,6 +305,7 @@ def main():
                      "kernel": kernel_name, "kernel_ms": 1e3 * kernel_s,
                      "work_slots_per_event": WORK_SLOTS_PER_EVENT_C2},
     }
+    progress("C2 steps")
     if not args.no_c1:
         c1 = W.immigration_death()
         n1 = ctx.network(c1)
@@ -313,14 +323,20 @@ def main():
                              "n": r1["n"], "batches": r1["batches"], "p_hat": r1["p_hat"],
                              "interval": [r1["lo"], r1["hi"]], "seconds": w1,
                              "verified_trajectories_per_s": r1["n"] / w1, "events_per_s": r1["events"] / w1}
+        progress("C1 Wilson run")
     if not args.no_large:
         line["c3_random_network"] = random_network_run(ctx, B, W)
+        progress("C3 random network")
         line["c4_batched_sweep"] = batched_sweep_run(ctx, B, W)
+        progress("C4 batched sweep")
     if not args.no_surrogate:
-        line["surrogate_vs_plain"] = [surrogate_vs_plain(ctx, B, W, t)
-                                      for t in (W.C2_FORMULA, W.MM_COMPANION_FORMULA)]
+        line["surrogate_vs_plain"] = []
+        for t in (W.C2_FORMULA, W.MM_COMPANION_FORMULA):
+            line["surrogate_vs_plain"].append(surrogate_vs_plain(ctx, B, W, t))
+            progress(f"surrogate vs plain SMC, {t}")
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(net, W.C2_FORMULA, args.cpu_sample)
+        progress("CPU baseline")
     print(json.dumps(line), flush=True)
 
 

@@ -328,7 +328,6 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
     hipStream_t s = ctx->stream;
     HIP_TRY(ctx, hipMemcpyAsync(ctx->d_jobs, jobs, n * sizeof(Job), hipMemcpyHostToDevice, s));
     HIP_TRY(ctx, hipMemsetAsync(ctx->d_states, 0, n * sizeof(JobState), s));
-    HIP_TRY(ctx, launch_init(s, ctx->d_jobs, n));
     *ctx->cancel_host = 0;
     ctx->cancel_req.store(0);
 
@@ -370,6 +369,18 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
     const int variant = m_max <= 4 ? 0 : 1;
     hipFunction_t spec_fn = nullptr;
     if (const int rc = pick_spec_kernel(ctx, P, n_iter > 0, &spec_fn)) return rc;
+    // Static first shares (see init_jobs) only where they cannot hold work
+    // back: every job of fixed size, so that idle waves leave at once, and a
+    // grid that fits on the device at once.  A wave that is not yet resident
+    // would keep its share until resident waves leave, and an iterative batch
+    // would wait for it.
+    bool static_first = false;
+    if (n_iter == 0) {
+        const int per_cu = spec_fn ? module_blocks_per_cu(spec_fn, wpb)
+                                   : persistent_blocks_per_cu(variant, false, wpb, lds_wave * wpb);
+        static_first = per_cu > 0 && (long long)per_cu * ctx->n_cu >= grid;
+    }
+    HIP_TRY(ctx, launch_init(s, ctx->d_jobs, n, static_first ? grid * wpb : 0));
     ctx->last_kernel = spec_fn ? SMC_KERNEL_SPECIALIZED : (variant == 0 ? SMC_KERNEL_GENERIC_SMALL : SMC_KERNEL_GENERIC);
     res.assign(n, JobResult{});
     double total_ms = 0.0;
@@ -388,10 +399,10 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
         HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
         if (spec_fn)
             HIP_TRY(ctx, launch_module(spec_fn, grid, wpb, s, ctx->d_jobs, n, s_max, ctx->d_ctl,
-                                       ctx->cancel_dev, 1 << 18));
+                                       ctx->cancel_dev, 1 << 18, static_first && launch == 0));
         else
             HIP_TRY(ctx, launch_persistent(variant, n_iter > 0, grid, wpb, lds_wave * wpb, s, ctx->d_jobs, n, s_max,
-                                           ctx->d_ctl, ctx->cancel_dev, 1 << 18));
+                                           ctx->d_ctl, ctx->cancel_dev, 1 << 18, static_first && launch == 0));
         HIP_TRY(ctx, launch_finalize(s, ctx->d_jobs, n, ctx->d_results));
         HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
         // wait under the watchdog

@@ -129,6 +129,7 @@ constexpr unsigned long long kMaxBatchSize = 1ull << 30;
 struct JobState {
     unsigned long long next;                 // relative indices issued
     unsigned long long limit;                // indices below this may be issued
+    unsigned long long static_end;           // [0, static_end): first shares of the waves, see init_jobs
     unsigned long long bound[kMaxBatches];
     unsigned long long yes[kMaxBatches][kShards];    // fixed-sample jobs
     unsigned long long no[kMaxBatches][kShards];     // fixed-sample jobs

@@ -23,14 +23,17 @@ void compile_formula(const std::string &text, const std::vector<std::string> &na
 // ssa_kernel.hip
 hipError_t launch_persistent(int nb_variant, bool iterative, int grid, int waves_per_block, size_t lds_bytes,
                              hipStream_t stream, const Job *jobs, int n_jobs, int s_max,
-                             Control *ctl, const volatile int32_t *cancel, int spin_limit);
+                             Control *ctl, const volatile int32_t *cancel, int spin_limit, int static_first);
 hipError_t launch_sample_state(int nb_variant, hipStream_t stream, const Job *job, double T,
                                unsigned long long count, int32_t *out, int s_max);
 // a specialised persistent kernel (spec.cpp) with the generic kernel's arguments
 hipError_t launch_module(hipFunction_t fn, int grid, int waves_per_block, hipStream_t stream,
                          const Job *jobs, int n_jobs, int s_max, Control *ctl,
-                         const volatile int32_t *cancel, int spin_limit);
-hipError_t launch_init(hipStream_t stream, const Job *jobs, int n_jobs);
+                         const volatile int32_t *cancel, int spin_limit, int static_first);
+int persistent_blocks_per_cu(int variant, bool iterative, int waves_per_block, size_t lds_bytes);
+int module_blocks_per_cu(hipFunction_t fn, int waves_per_block);
+// n_waves: waves of the first launch (their static first shares), 0 for none
+hipError_t launch_init(hipStream_t stream, const Job *jobs, int n_jobs, int n_waves);
 hipError_t launch_finalize(hipStream_t stream, const Job *jobs, int n_jobs, JobResult *out);
 hipError_t launch_wilson_table(hipStream_t stream, const unsigned long long *yes,
                                const unsigned long long *n, int count, double eps, double z,

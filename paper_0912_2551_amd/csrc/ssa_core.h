@@ -1099,6 +1099,7 @@ struct KArgs {
     const volatile int32_t *cancel;   // host-visible stop word
     int spin_limit;
     int waves_per_block;
+    int static_first;                 // first launch: waves start on their static shares
 };
 
 // Add a wave's counts for batch b of its job to the sharded counters.
@@ -1122,7 +1123,9 @@ template <class Pol, bool kIter>
 __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
 {
     const int lane = lane_id();
-    const int wid = (int)(threadIdx.x / kWave);
+    // wave-uniform (the compiler cannot know that threadIdx.x / 64 is): keeps
+    // the home job, the shard and everything loaded from them in scalar registers
+    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     typename Pol::Counts X = Pol::counts(lds, wid, A.s_max, lane);
     const int gwave = (int)blockIdx.x * A.waves_per_block + wid;
     const int shard = gwave & (kShards - 1);
@@ -1145,6 +1148,22 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
     // fixed-sample jobs: per-lane counts, added to the job once per wave
     uint32_t my_yes = 0, my_no = 0, my_trunc = 0;
     unsigned long long my_events = 0;
+    if (A.static_first && start < A.n_jobs) {
+        // First launch: start on the home job with this wave's own share of its
+        // first indices, [64 r, 64 r + 64) below static_end for the wave's rank
+        // r among the waves of that home (set up by init_jobs).  Thousands of
+        // first claims on one counter would otherwise queue for tens of
+        // microseconds.
+        cur = start;
+        V.load(A.jobs, cur);
+        const long long g0 = ((long long)start * n_waves + A.n_jobs - 1) / A.n_jobs;
+        const unsigned long long lo = (unsigned long long)(gwave - g0) * kWave;
+        const unsigned long long se = uniform_u64(ld_relaxed(&V.st->static_end));
+        if (lo < se) {
+            pool_next = lo;
+            pool_end = lo + kWave < se ? lo + kWave : se;
+        }
+    }
 
     for (uint32_t it = 0;; ++it) {
         // Stop requests, checked once per 4096 iterations.  The host's stop

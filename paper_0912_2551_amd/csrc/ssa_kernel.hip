@@ -62,7 +62,11 @@ __global__ __launch_bounds__(256) void ssa_sample_state(const Job *jobp, double 
 // bound is at least the Fig. 2 bound at the estimate's extremes (p = 0 or 1),
 // so indices below it are issued at once instead of after the first
 // completions.
-__global__ void init_jobs(const Job *jobs, int n_jobs)
+// The first launch hands every wave a share of its home job's first indices
+// without atomics: the waves whose home is job j (ranks 0 .. W_j - 1, see
+// persistent_body) take [64 r, 64 r + 64) below static_end, and the job's
+// issue counter starts at static_end.  n_waves = 0: no static shares.
+__global__ void init_jobs(const Job *jobs, int n_jobs, int n_waves)
 {
     const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (j >= n_jobs) return;
@@ -79,6 +83,15 @@ __global__ void init_jobs(const Job *jobs, int n_jobs)
         if (g > lim) lim = g;
     }
     st->limit = lim;
+    unsigned long long se = 0;
+    if (n_waves > 0) {
+        const long long g0 = ((long long)j * n_waves + n_jobs - 1) / n_jobs;
+        const long long g1 = ((long long)(j + 1) * n_waves + n_jobs - 1) / n_jobs;
+        se = (unsigned long long)(g1 - g0) * kWave;
+        if (se > lim) se = lim;
+    }
+    st->static_end = se;
+    st->next = se;
 }
 
 // Sum the counter shards of every job into its final numbers (fixed-sample
@@ -137,7 +150,7 @@ namespace smc {
 // the launch holds jobs with the Fig. 2 stopping rule
 hipError_t launch_persistent(int variant, bool iterative, int grid, int waves_per_block, size_t lds_bytes,
                              hipStream_t stream, const Job *jobs, int n_jobs, int s_max,
-                             Control *ctl, const volatile int32_t *cancel, int spin_limit)
+                             Control *ctl, const volatile int32_t *cancel, int spin_limit, int static_first)
 {
     KArgs a;
     a.jobs = jobs;
@@ -147,6 +160,7 @@ hipError_t launch_persistent(int variant, bool iterative, int grid, int waves_pe
     a.cancel = cancel;
     a.spin_limit = spin_limit;
     a.waves_per_block = waves_per_block;
+    a.static_first = static_first;
     const dim3 block(kWave * waves_per_block);
     if (variant == 0 && iterative)
         hipLaunchKernelGGL((ssa_persistent<4, true>), dim3(grid), block, lds_bytes, stream, a);
@@ -159,9 +173,33 @@ hipError_t launch_persistent(int variant, bool iterative, int grid, int waves_pe
     return hipGetLastError();
 }
 
+// Blocks of a persistent kernel that fit on one CU at once (0 if unknown).
+int persistent_blocks_per_cu(int variant, bool iterative, int waves_per_block, size_t lds_bytes)
+{
+    int nb = 0;
+    const int threads = kWave * waves_per_block;
+    hipError_t e;
+    if (variant == 0 && iterative)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ssa_persistent<4, true>, threads, lds_bytes);
+    else if (variant == 0)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ssa_persistent<4, false>, threads, lds_bytes);
+    else if (iterative)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ssa_persistent<kBlocks, true>, threads, lds_bytes);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ssa_persistent<kBlocks, false>, threads, lds_bytes);
+    return e == hipSuccess ? nb : 0;
+}
+
+int module_blocks_per_cu(hipFunction_t fn, int waves_per_block)
+{
+    int nb = 0;
+    const hipError_t e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kWave * waves_per_block, 0);
+    return e == hipSuccess ? nb : 0;
+}
+
 hipError_t launch_module(hipFunction_t fn, int grid, int waves_per_block, hipStream_t stream,
                          const Job *jobs, int n_jobs, int s_max, Control *ctl,
-                         const volatile int32_t *cancel, int spin_limit)
+                         const volatile int32_t *cancel, int spin_limit, int static_first)
 {
     KArgs a;
     a.jobs = jobs;
@@ -171,6 +209,7 @@ hipError_t launch_module(hipFunction_t fn, int grid, int waves_per_block, hipStr
     a.cancel = cancel;
     a.spin_limit = spin_limit;
     a.waves_per_block = waves_per_block;
+    a.static_first = static_first;
     void *params[] = {&a};
     return hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, (unsigned)(kWave * waves_per_block), 1, 1, 0,
                                  stream, params, nullptr);
@@ -191,9 +230,9 @@ hipError_t launch_sample_state(int variant, hipStream_t stream, const Job *job, 
     return hipGetLastError();
 }
 
-hipError_t launch_init(hipStream_t stream, const Job *jobs, int n_jobs)
+hipError_t launch_init(hipStream_t stream, const Job *jobs, int n_jobs, int n_waves)
 {
-    hipLaunchKernelGGL(init_jobs, dim3((n_jobs + 63) / 64), dim3(64), 0, stream, jobs, n_jobs);
+    hipLaunchKernelGGL(init_jobs, dim3((n_jobs + 63) / 64), dim3(64), 0, stream, jobs, n_jobs, n_waves);
     return hipGetLastError();
 }
 

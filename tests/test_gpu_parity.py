@@ -184,6 +184,42 @@ def test_batch_matches_single_jobs(ctx):
             (o["n"], o["successes"], o["events"], len(o["bounds"])), (mid, r, o)
 
 
+@pytest.mark.parametrize("waves_per_cu", [1, 16, 32])
+def test_fixed_batch_matches_oracle(ctx, waves_per_cu):
+    """Fixed-size jobs of many sizes in one launch.  A launch of fixed-size jobs
+    whose grid fits on the device starts each wave on a static share of its
+    home job's first indices: sizes below, at and above one share (64) and
+    above all shares together must still give the oracle's counts exactly,
+    whatever the number of waves."""
+    B = _B()
+    sizes = [1, 63, 64, 65, 1000, 5000, 70000]
+    keep, jobs, refs = [], [], []
+    net = W.michaelis_menten()
+    nh = ctx.network(net)
+    fh = ctx.formula(nh, W.C2_FORMULA)
+    keep.append((nh, fh))
+    for k, m in enumerate(sizes):
+        jobs.append((nh, fh, B.params(fixed_n=m, seed=5, model_id=k)))
+        refs.append((net, W.C2_FORMULA, m, k))
+    small = W.immigration_death()
+    nh2 = ctx.network(small)
+    fh2 = ctx.formula(nh2, W.C1_FORMULA)
+    keep.append((nh2, fh2))
+    for k, m in enumerate([100, 3000]):
+        jobs.append((nh2, fh2, B.params(fixed_n=m, seed=5, model_id=50 + k)))
+        refs.append((small, W.C1_FORMULA, m, 50 + k))
+    ctx.set_waves_per_cu(waves_per_cu)
+    try:
+        same = ctx.estimate_batch(jobs[:len(sizes)])      # one structure: specialised kernel
+        mixed = ctx.estimate_batch(jobs)                   # two structures: generic kernel
+    finally:
+        ctx.set_waves_per_cu(0)
+    for res, n_jobs in ((same, len(sizes)), (mixed, len(jobs))):
+        for r, (net_k, text, m, mid) in zip(res, refs[:n_jobs]):
+            o = oracle.estimate(net_k, text, fixed_n=m, seed=5, model_id=mid)
+            assert (r["n"], r["successes"], r["events"]) == (o["n"], o["successes"], o["events"]), (m, mid)
+
+
 def test_device_stopping_rule_matches_host(ctx):
     rng = np.random.default_rng(0)
     z = wilson.z_value(0.95)
