@@ -21,8 +21,8 @@
  * The Wilson formulas (Sec. 3.3, eqs. 3-4, Fig. 2) live in oracle/wilson.py.
  *
  * Numeric contract shared (by specification, not by code) with the GPU path:
- *   - Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key = (trajectory
- *     index, model id), counter = (event index, 0, seed lo, seed hi);
+ *   - Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key = (seed lo,
+ *     seed hi), counter = (event index, trajectory index, model id, 0);
  *   - u1 = ((x0<<21 | x1>>11) + 1) * 2^-53 in (0,1], u2 = (x2<<21 | x3>>11) * 2^-53;
  *   - log built from IEEE +,-,*,/ only (atanh series, ln2 split hi/lo);
  *   - one rounding per propensity; sequential prefix sum in reaction order;
@@ -161,8 +161,8 @@ static double ssa_step(const onet *n, uint64_t idx, uint32_t model_id, uint64_t 
     double a0 = acc;
     if (a0_out) *a0_out = a0;
     if (!(a0 > 0.0)) return INFINITY;            /* absorbing: tau = +inf */
-    uint32_t ctr[4] = {k, 0u, (uint32_t)seed, (uint32_t)(seed >> 32)};
-    uint32_t key[2] = {(uint32_t)idx, model_id};
+    uint32_t ctr[4] = {k, (uint32_t)idx, model_id, 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t r[4];
     oracle_philox4x32_10(ctr, key, r);
     double u1 = u53_open0_closed1(r[0], r[1]);

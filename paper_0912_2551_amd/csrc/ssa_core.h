@@ -9,7 +9,8 @@
 // trajectory is decided, so the wave stays full until the job runs out of
 // issuable indices.  Per event and lane:
 //   a_j and the running sum S_j in reaction order (Sec. 2.2, template step 1);
-//   one Philox4x32-10 block keyed by (trajectory, model), counter = event;
+//   one Philox4x32-10 block per event, keyed by the job's seed, counter =
+//   (event, trajectory, model);
 //   tau = -log(u1) / a0 (eq. 2a); j = min{j : S_j > u2 a0} (eq. 2b);
 //   x += v_j, t += tau (step 4); monitor update (Sec. 3.2).
 // Time and propensity sums are FP64, with no contraction (built with
@@ -580,7 +581,8 @@ __device__ __forceinline__ void mon_init(MonState &ms)
 
 // ---------------------------------------------------------------------------
 // The random numbers of event k of a trajectory: one Philox4x32-10 block
-// keyed by (trajectory, model), counter (k, 0, seed); nl = -ln(u1) with u1 in
+// keyed by the seed (wave-uniform: its key schedule runs on the scalar unit),
+// counter (k, trajectory, model, 0); nl = -ln(u1) with u1 in
 // (0,1], and u2 in [0,1).  They depend on nothing but (trajectory, k), so the
 // persistent loop draws those of a lane's next event while the current event
 // is still being computed (the two dependency chains overlap).
@@ -591,8 +593,7 @@ struct Draw {
 
 __device__ __forceinline__ Draw event_uniforms(const JobView &V, unsigned long long abs_idx, uint32_t k)
 {
-    const U4 r = philox10(k, 0u, (uint32_t)V.seed, (uint32_t)(V.seed >> 32), (uint32_t)abs_idx,
-                          V.model_id);
+    const U4 r = philox10(k, (uint32_t)abs_idx, V.model_id, 0u, (uint32_t)V.seed, (uint32_t)(V.seed >> 32));
     Draw d;
     d.nl = -ctr_log(unif_oc(r.a, r.b));
     d.u2 = unif_co(r.c, r.d);
