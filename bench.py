@@ -28,14 +28,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Vector issue slots per SSA event (per lane) that the direct method needs, a
-# quarter-rate instruction counting 4: Philox4x32-10 100 (ten rounds of two
-# 32x32->64 multiplies and two three-input XORs; the key schedule is
-# wave-uniform), two 53-bit uniforms 13, ln 41, tau divide 10, time update and
+# quarter-rate instruction counting 4: Philox4x32-10 96 (nineteen 32x32->64
+# multiplies and twenty XORs: the first round's product of the model id is the
+# job's, and the key schedule is wave-uniform), two 53-bit uniforms 13, ln 41, tau divide 10, time update and
 # tests 3, loop control 4; then, for the Michaelis-Menten formula (C2) and the
 # immigration-death formula (C1): propensities 7 / 2, prefix and target 3 / 2,
 # channel selection 4 / 2, state update 7 / 3, monitor 18 / 8.
-WORK_SLOTS_PER_EVENT_C2 = 210
-WORK_SLOTS_PER_EVENT_C1 = 188
+WORK_SLOTS_PER_EVENT_C2 = 206
+WORK_SLOTS_PER_EVENT_C1 = 184
 PEAK_VALU_SLOTS = 256 * 64 * 2.4e9    # CUs x lanes x clock: 3.93e13 lane-slots/s
 N_TRAJ = 10**6
 

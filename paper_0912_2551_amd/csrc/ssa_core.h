@@ -49,11 +49,13 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 32x32->64 multiplies, key bumped by the Weyl constants between rounds.
-__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                       uint32_t k0, uint32_t k1)
+// philox_rounds<R> runs the last R rounds from a given state and round key.
+template <int R>
+__device__ __forceinline__ U4 philox_rounds(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                            uint32_t k0, uint32_t k1)
 {
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
+    for (int r = 0; r < R; ++r) {
         const uint64_t m0 = (uint64_t)c0 * 0xD2511F53ull;
         const uint64_t m1 = (uint64_t)c2 * 0xCD9E8D57ull;
         const uint32_t n0 = xor3((uint32_t)(m1 >> 32), c1, k0);
@@ -66,6 +68,14 @@ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
         k1 += 0xBB67AE85u;
     }
     return U4{c0, c1, c2, c3};
+}
+__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
+{
+    return philox_rounds<10>(c0, c1, c2, c3, k0, k1);
+}
+__device__ __forceinline__ U4 philox9(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
+{
+    return philox_rounds<9>(c0, c1, c2, c3, k0, k1);
 }
 
 // 53-bit uniforms: (0,1] for the waiting time, [0,1) for the channel.
@@ -232,7 +242,8 @@ struct JobView {
     cptr<uint32_t> chg;
     int S, M, Mp;
     unsigned long long seed, first, capacity;
-    uint32_t model_id, max_events;
+    uint32_t r1_hi, r1_lo;   // model id * 0xCD9E8D57: first Philox round's product (per job)
+    uint32_t max_events;
     double t_max;
     int iterative, literal;
     double eps, z;
@@ -257,7 +268,9 @@ struct JobView {
         seed = J->seed;
         first = J->first;
         capacity = J->capacity;
-        model_id = J->model_id;
+        const uint64_t m1 = (uint64_t)J->model_id * 0xCD9E8D57ull;
+        r1_hi = (uint32_t)(m1 >> 32);
+        r1_lo = (uint32_t)m1;
         max_events = J->max_events;
         t_max = J->t_max;
         iterative = J->iterative;
@@ -593,7 +606,16 @@ struct Draw {
 
 __device__ __forceinline__ Draw event_uniforms(const JobView &V, unsigned long long abs_idx, uint32_t k)
 {
-    const U4 r = philox10(k, (uint32_t)abs_idx, V.model_id, 0u, (uint32_t)V.seed, (uint32_t)(V.seed >> 32));
+    // philox10(k, idx, model, 0; seed) with the first round written out: its
+    // product of the model id is the job's (r1_hi, r1_lo), and the fourth
+    // counter word is 0
+    uint32_t k0 = (uint32_t)V.seed, k1 = (uint32_t)(V.seed >> 32);
+    const uint64_t m0 = (uint64_t)k * 0xD2511F53ull;
+    const uint32_t c0 = xor3(V.r1_hi, k0, (uint32_t)abs_idx);
+    const uint32_t c2 = (uint32_t)(m0 >> 32) ^ k1;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+    const U4 r = philox9(c0, V.r1_lo, c2, (uint32_t)m0, k0, k1);
     Draw d;
     d.nl = -ctr_log(unif_oc(r.a, r.b));
     d.u2 = unif_co(r.c, r.d);
