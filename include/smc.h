@@ -57,6 +57,13 @@ extern "C" {
 #define SMC_CONSERVATIVE_START 1u /* first sample from eq. 4 at p = 0.5 (Sec. 3.3.2)  */
 #define SMC_PAPER_ROUNDING 2u     /* Fig. 2 rounding exactly as printed: p +- eps may
                                      step across 0.5 (default: the step stops at 0.5) */
+#define SMC_NO_SPECULATION 4u     /* iterative jobs: issue only the indices each batch
+                                     needs.  Default: when every job of a launch is
+                                     iterative and their capacities together fit in one
+                                     pass over the device's lanes, every index up to each
+                                     capacity runs at once and Fig. 2 is applied to the
+                                     recorded outcomes in index order; results are
+                                     identical, the extra trajectories are discarded.  */
 
 typedef struct smc_ctx smc_ctx;
 typedef struct smc_net smc_net;
@@ -164,11 +171,12 @@ typedef struct {
     double half_width;   /* epsilon > 0: target interval [p - eps, p + eps]      */
     double z;            /* > 0: use this z_{1-alpha/2}; 0: derive from confidence */
     uint64_t fixed_n;    /* 0: iterative Wilson (Fig. 2); > 0: exactly this many  */
-    uint64_t seed;       /* Philox counter words 2..3                            */
-    uint32_t model_id;   /* Philox key word 1                                    */
+    uint64_t seed;       /* Philox key (words 0..1)                              */
+    uint32_t model_id;   /* Philox counter word 2 (word 1: trajectory index)      */
     uint32_t max_events; /* 0: no cap; else undecided after this many events: FALSE */
     double t_max;        /* pessimistic horizon for unbounded formulas (+inf: none) */
-    uint32_t flags;      /* SMC_CONSERVATIVE_START | SMC_PAPER_ROUNDING          */
+    uint32_t flags;      /* SMC_CONSERVATIVE_START | SMC_PAPER_ROUNDING |
+                            SMC_NO_SPECULATION                                   */
 } smc_params;
 
 typedef struct {

@@ -28,6 +28,7 @@ SMC_E_CANCELLED = -6
 SMC_E_TIMEOUT = -7
 SMC_CONSERVATIVE_START = 1
 SMC_PAPER_ROUNDING = 2
+SMC_NO_SPECULATION = 4
 REASON_STATE, REASON_TIME, REASON_ABSORB, REASON_CAP, REASON_TMAX = range(5)
 
 SPECIALIZE_AUTO, SPECIALIZE_OFF, SPECIALIZE_REQUIRED = 0, 1, 2
@@ -174,8 +175,9 @@ def _ptr(a, ct):
 
 
 def params(confidence=0.95, half_width=0.01, z=0.0, fixed_n=0, seed=1, model_id=0, max_events=0,
-           t_max=math.inf, conservative=False, paper_rounding=False) -> Params:
-    flags = (SMC_CONSERVATIVE_START if conservative else 0) | (SMC_PAPER_ROUNDING if paper_rounding else 0)
+           t_max=math.inf, conservative=False, paper_rounding=False, speculate=True) -> Params:
+    flags = ((SMC_CONSERVATIVE_START if conservative else 0) | (SMC_PAPER_ROUNDING if paper_rounding else 0)
+             | (0 if speculate else SMC_NO_SPECULATION))
     return Params(confidence, half_width, z, fixed_n, seed, model_id, max_events, t_max, flags)
 
 

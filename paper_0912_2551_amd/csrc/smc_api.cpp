@@ -184,6 +184,7 @@ struct Prepared {
     int S = 0, M = 0;
     uint64_t capacity = 0;
     double z = 0.0;
+    bool speculate = true;   // iterative job: may run as a speculative launch
 };
 
 int prepare(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_params *p,
@@ -245,6 +246,7 @@ int prepare(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_pa
     out.M = net->M;
     out.capacity = capacity;
     out.z = z;
+    out.speculate = (p->flags & SMC_NO_SPECULATION) == 0;
     return SMC_OK;
 }
 
@@ -314,7 +316,7 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
     if (ensure(ctx, ctx->d_jobs, ctx->cap_jobs, (size_t)n)) return SMC_E_NOMEM;
     if (ensure(ctx, ctx->d_states, ctx->cap_states, (size_t)n)) return SMC_E_NOMEM;
     if (ensure(ctx, ctx->d_results, ctx->cap_results, (size_t)n)) return SMC_E_NOMEM;
-    if (ensure_pinned(ctx, ctx->h_jobs, ctx->cap_h_jobs, (size_t)n)) return SMC_E_NOMEM;
+    if (ensure_pinned(ctx, ctx->h_jobs, ctx->cap_h_jobs, 2 * (size_t)n)) return SMC_E_NOMEM;
     if (ensure_pinned(ctx, ctx->h_results, ctx->cap_h_results, (size_t)n)) return SMC_E_NOMEM;
     int s_max = 1, m_max = 1, n_iter = 0;
     Job *jobs = ctx->h_jobs;   // the previous call's copies have completed
@@ -324,6 +326,40 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
         s_max = std::max(s_max, P[k].S);
         m_max = std::max(m_max, P[k].M);
         n_iter += jobs[k].iterative;
+    }
+    // Speculative launch: when every job is iterative and their capacities
+    // together fit in one pass over the device's lanes, every index up to each
+    // job's capacity runs at once, as a fixed-size launch that records
+    // per-index outcomes; replay_wilson then applies Fig. 2 to those outcomes
+    // in index order.  The results are the batch protocol's, bit for bit.  A
+    // lone Wilson run is latency-bound: its batches would follow one another,
+    // each as long as its longest trajectory, on a device that is mostly idle.
+    // jobs[n .. 2n) keep the iterative descriptions for the replay.
+    bool speculative = false;
+    if (n_iter == n && !ctx->tuning) {
+        unsigned long long cap_total = 0;
+        bool allow = true;
+        for (int k = 0; k < n; ++k) {
+            cap_total += P[k].capacity;
+            allow = allow && P[k].speculate;
+        }
+        const unsigned long long lanes = (unsigned long long)ctx->n_cu * pick_waves_per_cu(ctx) * kWave;
+        speculative = allow && cap_total <= lanes;
+        if (speculative) {
+            if (ensure(ctx, ctx->d_rec, ctx->cap_rec, (size_t)cap_total * (sizeof(uint32_t) + 1))) return SMC_E_NOMEM;
+            uint32_t *ev = reinterpret_cast<uint32_t *>(ctx->d_rec);
+            uint8_t *vr = reinterpret_cast<uint8_t *>(ev + cap_total);
+            unsigned long long off = 0;
+            for (int k = 0; k < n; ++k) {
+                jobs[k].rec_events = ev + off;
+                jobs[k].rec_vr = vr + off;
+                jobs[n + k] = jobs[k];
+                jobs[k].iterative = 0;
+                jobs[k].n_first = jobs[k].capacity;
+                off += jobs[k].capacity;
+            }
+            n_iter = 0;
+        }
     }
     hipStream_t s = ctx->stream;
     HIP_TRY(ctx, hipMemcpyAsync(ctx->d_jobs, jobs, n * sizeof(Job), hipMemcpyHostToDevice, s));
@@ -403,7 +439,12 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
         else
             HIP_TRY(ctx, launch_persistent(variant, n_iter > 0, grid, wpb, lds_wave * wpb, s, ctx->d_jobs, n, s_max,
                                            ctx->d_ctl, ctx->cancel_dev, 1 << 18, static_first && launch == 0));
-        HIP_TRY(ctx, launch_finalize(s, ctx->d_jobs, n, ctx->d_results));
+        if (speculative) {
+            HIP_TRY(ctx, hipMemcpyAsync(ctx->d_jobs, jobs + n, n * sizeof(Job), hipMemcpyHostToDevice, s));
+            HIP_TRY(ctx, launch_replay(s, ctx->d_jobs, n, ctx->d_results));
+        } else {
+            HIP_TRY(ctx, launch_finalize(s, ctx->d_jobs, n, ctx->d_results));
+        }
         HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
         // wait under the watchdog
         for (;;) {

@@ -35,6 +35,8 @@ int module_blocks_per_cu(hipFunction_t fn, int waves_per_block);
 // n_waves: waves of the first launch (their static first shares), 0 for none
 hipError_t launch_init(hipStream_t stream, const Job *jobs, int n_jobs, int n_waves);
 hipError_t launch_finalize(hipStream_t stream, const Job *jobs, int n_jobs, JobResult *out);
+// Fig. 2 over recorded per-index verdicts (speculative launches)
+hipError_t launch_replay(hipStream_t stream, const Job *jobs, int n_jobs, JobResult *out);
 hipError_t launch_wilson_table(hipStream_t stream, const unsigned long long *yes,
                                const unsigned long long *n, int count, double eps, double z,
                                int literal, unsigned long long *out);

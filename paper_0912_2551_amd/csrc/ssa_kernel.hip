@@ -129,6 +129,56 @@ __global__ void finalize_jobs(const Job *jobs, int n_jobs, JobResult *out)
     out[j] = r;
 }
 
+// Fig. 2 applied to verdicts recorded for every index up to a job's capacity
+// (a speculative launch ran them all at once): the same bounds, estimate and
+// counts as the batch protocol of the persistent kernel, which would see
+// exactly these verdicts of exactly these indices, with the same operations
+// (next_sample) deciding each bound.  One wave per job.
+__global__ __launch_bounds__(64) void replay_wilson(const Job *jobs, int n_jobs, JobResult *out)
+{
+    const int j = (int)blockIdx.x;
+    if (j >= n_jobs) return;
+    const Job &J = jobs[j];
+    const int lane = (int)threadIdx.x;
+    unsigned long long Y = 0, lo = 0, B = J.n_first;
+    int b = 0, overflow = 0;
+    for (;;) {
+        unsigned long long y = 0;   // TRUE verdicts among [lo, B)
+        for (unsigned long long i = lo + (unsigned long long)lane; i < B; i += kWave) y += J.rec_vr[i] & 1u;
+        Y += wave_sum_u64(y);
+        const double p_hat = (double)Y / (double)B;
+        const unsigned long long Np = next_sample(p_hat, J.eps, J.z, J.literal);
+        if (Np > B && b + 1 < kMaxBatches && Np <= J.capacity) {
+            lo = B;
+            B = Np;
+            ++b;
+            continue;
+        }
+        overflow = Np > B ? 1 : 0;
+        break;
+    }
+    unsigned long long ev = 0, tr = 0;
+    for (unsigned long long i = (unsigned long long)lane; i < B; i += kWave) {
+        ev += J.rec_events[i];
+        tr += ((J.rec_vr[i] >> 1) == (uint8_t)RS_CAP) ? 1u : 0u;
+    }
+    ev = wave_sum_u64(ev);
+    tr = wave_sum_u64(tr);
+    if (lane == 0) {
+        JobResult r;
+        r.n = B;
+        r.yes = Y;
+        r.events = ev;
+        r.trunc = tr;
+        r.issued = J.capacity;
+        r.batches = b + 1;
+        r.final_flag = 1;
+        r.overflow = overflow;
+        r.pad = 0;
+        out[j] = r;
+    }
+}
+
 // Device-side eq. 4 over a table of (successes, n): used to check that the
 // device and host stopping rules agree.
 __global__ void wilson_table(const unsigned long long *yes, const unsigned long long *n, int count,
@@ -240,6 +290,12 @@ hipError_t launch_finalize(hipStream_t stream, const Job *jobs, int n_jobs, JobR
 {
     hipLaunchKernelGGL(finalize_jobs, dim3((n_jobs + 63) / 64), dim3(64), 0, stream, jobs, n_jobs,
                        out);
+    return hipGetLastError();
+}
+
+hipError_t launch_replay(hipStream_t stream, const Job *jobs, int n_jobs, JobResult *out)
+{
+    hipLaunchKernelGGL(replay_wilson, dim3(n_jobs), dim3(kWave), 0, stream, jobs, n_jobs, out);
     return hipGetLastError();
 }
 

@@ -114,14 +114,21 @@ def test_large_network_parity(ctx):
     assert np.array_equal(ev, oev) and np.array_equal(vd, ovd) and np.array_equal(rs, ors)
 
 
+# speculative: every index up to the capacity runs in one launch and Fig. 2 is
+# applied to the recorded outcomes; batched: the persistent kernel's batch
+# protocol.  Both must give the oracle's iterative estimate exactly.
+SPECULATE = pytest.mark.parametrize("speculate", [True, False], ids=["speculative", "batched"])
+
+
+@SPECULATE
 @pytest.mark.parametrize("kw", [{}, {"conservative": True}, {"paper_rounding": True}],
                          ids=["iterative", "conservative", "paper-rounding"])
-def test_c1_wilson_estimate(ctx, kw):
+def test_c1_wilson_estimate(ctx, kw, speculate):
     B = _B()
     net = W.immigration_death()
     n = ctx.network(net)
     f = ctx.formula(n, W.C1_FORMULA)
-    r = ctx.estimate(n, f, B.params(confidence=0.95, half_width=0.01, seed=1, **kw))
+    r = ctx.estimate(n, f, B.params(confidence=0.95, half_width=0.01, seed=1, speculate=speculate, **kw))
     o = oracle.estimate(net, W.C1_FORMULA, confidence=0.95, eps=0.01, seed=1,
                         conservative=kw.get("conservative", False), literal=kw.get("paper_rounding", False))
     assert (r["n"], r["successes"], r["events"], r["batches"]) == (o["n"], o["successes"], o["events"], len(o["bounds"]))
@@ -157,7 +164,8 @@ def test_c2_full_size_fixed(ctx):
     assert r["p_hat"] == 0.0 and r["lo"] == 0.0 and abs(r["hi"] - 1.0827e-5) < 1e-8
 
 
-def test_batch_matches_single_jobs(ctx):
+@SPECULATE
+def test_batch_matches_single_jobs(ctx, speculate):
     B = _B()
     rates = W.mm_sweep(6, seed=11)
     jobs, singles = [], []
@@ -167,14 +175,14 @@ def test_batch_matches_single_jobs(ctx):
         nh = ctx.network(net)
         fh = ctx.formula(nh, W.MM_COMPANION_FORMULA)
         keep.append((nh, fh))
-        p = B.params(seed=1, model_id=k, half_width=0.05)
+        p = B.params(seed=1, model_id=k, half_width=0.05, speculate=speculate)
         jobs.append((nh, fh, p))
         singles.append((net, W.MM_COMPANION_FORMULA, k))
     for q, (net, text) in enumerate(W.c4_networks(2, seed=12)):
         nh = ctx.network(net)
         fh = ctx.formula(nh, text)
         keep.append((nh, fh))
-        p = B.params(seed=1, model_id=100 + q, half_width=0.1, max_events=20000)
+        p = B.params(seed=1, model_id=100 + q, half_width=0.1, max_events=20000, speculate=speculate)
         jobs.append((nh, fh, p))
         singles.append((net, text, 100 + q))
     res = ctx.estimate_batch(jobs)
@@ -345,7 +353,8 @@ def test_autotune_keeps_results(ctx):
     ctx.set_specialization(B.SPECIALIZE_AUTO)
 
 
-def test_mixed_batch_matches_oracle(ctx):
+@SPECULATE
+def test_mixed_batch_matches_oracle(ctx, speculate):
     """A launch of models of different structure and size (Michaelis-Menten
     rate sets and small random networks), each with its own Fig. 2 rule:
     every job's n, successes, events and truncations equal the oracle's
@@ -362,7 +371,8 @@ def test_mixed_batch_matches_oracle(ctx):
         nh = ctx.network(net)
         fh = ctx.formula(nh, text)
         keep.append((nh, fh))
-        jobs.append((nh, fh, B.params(confidence=0.95, half_width=0.05, seed=5, model_id=k, max_events=cap)))
+        jobs.append((nh, fh, B.params(confidence=0.95, half_width=0.05, seed=5, model_id=k, max_events=cap,
+                                      speculate=speculate)))
     res = ctx.estimate_batch(jobs)
     assert ctx.last_kernel() == B.KERNEL_GENERIC
     for k, ((net, text, cap), r) in enumerate(zip(models, res)):
