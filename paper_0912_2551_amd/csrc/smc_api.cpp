@@ -405,6 +405,8 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
     const int variant = m_max <= 4 ? 0 : 1;
     hipFunction_t spec_fn = nullptr;
     if (const int rc = pick_spec_kernel(ctx, P, n_iter > 0, &spec_fn)) return rc;
+    // wide specialised kernels keep counts in LDS like the generic ones
+    const size_t spec_lds = (spec_fn && spec_wide(P[0].S, P[0].M)) ? lds_wave * wpb : 0;
     // Static first shares (see init_jobs) only where they cannot hold work
     // back: every job of fixed size, so that idle waves leave at once, and a
     // grid that fits on the device at once.  A wave that is not yet resident
@@ -412,7 +414,7 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
     // would wait for it.
     bool static_first = false;
     if (n_iter == 0) {
-        const int per_cu = spec_fn ? module_blocks_per_cu(spec_fn, wpb)
+        const int per_cu = spec_fn ? module_blocks_per_cu(spec_fn, wpb, spec_lds)
                                    : persistent_blocks_per_cu(variant, false, wpb, lds_wave * wpb);
         static_first = per_cu > 0 && (long long)per_cu * ctx->n_cu >= grid;
     }
@@ -434,7 +436,7 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
         HIP_TRY(ctx, hipMemcpyAsync(ctx->d_ctl, ctx->h_ctl, sizeof(Control), hipMemcpyHostToDevice, s));
         HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
         if (spec_fn)
-            HIP_TRY(ctx, launch_module(spec_fn, grid, wpb, s, ctx->d_jobs, n, s_max, ctx->d_ctl,
+            HIP_TRY(ctx, launch_module(spec_fn, grid, wpb, spec_lds, s, ctx->d_jobs, n, s_max, ctx->d_ctl,
                                        ctx->cancel_dev, 1 << 18, static_first && launch == 0));
         else
             HIP_TRY(ctx, launch_persistent(variant, n_iter > 0, grid, wpb, lds_wave * wpb, s, ctx->d_jobs, n, s_max,

@@ -34,6 +34,8 @@ constexpr int kBlocks = 16;        // prefix-sum blocks for reaction selection
 constexpr int kSubBlock = 8;       // channels per unrolled step of the blocked prefix
 constexpr int kSpecMaxS = 16;      // specialised kernels: species counts in registers
 constexpr int kSpecMaxM = 8;       // specialised kernels: channels
+constexpr int kSpecWideMaxS = 128; // wide specialised kernels (counts in LDS): species
+constexpr int kSpecWideMaxM = 512; //   and channels
 
 enum CmpOp : int32_t { CMP_LT = 0, CMP_LE, CMP_GE, CMP_GT, CMP_EQ, CMP_NE };
 enum ValOp : int32_t { VO_VAR = 0, VO_CONST, VO_ADD, VO_SUB, VO_MUL, VO_DIV, VO_NEG, VO_SQRT };

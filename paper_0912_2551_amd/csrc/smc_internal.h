@@ -27,11 +27,11 @@ hipError_t launch_persistent(int nb_variant, bool iterative, int grid, int waves
 hipError_t launch_sample_state(int nb_variant, hipStream_t stream, const Job *job, double T,
                                unsigned long long count, int32_t *out, int s_max);
 // a specialised persistent kernel (spec.cpp) with the generic kernel's arguments
-hipError_t launch_module(hipFunction_t fn, int grid, int waves_per_block, hipStream_t stream,
+hipError_t launch_module(hipFunction_t fn, int grid, int waves_per_block, size_t lds_bytes, hipStream_t stream,
                          const Job *jobs, int n_jobs, int s_max, Control *ctl,
                          const volatile int32_t *cancel, int spin_limit, int static_first);
 int persistent_blocks_per_cu(int variant, bool iterative, int waves_per_block, size_t lds_bytes);
-int module_blocks_per_cu(hipFunction_t fn, int waves_per_block);
+int module_blocks_per_cu(hipFunction_t fn, int waves_per_block, size_t lds_bytes);
 // n_waves: waves of the first launch (their static first shares), 0 for none
 hipError_t launch_init(hipStream_t stream, const Job *jobs, int n_jobs, int n_waves);
 hipError_t launch_finalize(hipStream_t stream, const Job *jobs, int n_jobs, JobResult *out);
@@ -43,6 +43,8 @@ hipError_t launch_wilson_table(hipStream_t stream, const unsigned long long *yes
 
 // spec.cpp
 bool spec_supported(int S, int M, const MonProg &mp);
+// the specialised kernel of (S, M) keeps its counts in LDS (StaticWidePolicy)
+bool spec_wide(int S, int M);
 // waves_per_simd > 0: register budget for that many waves per SIMD
 std::string spec_source(int S, int M, const int32_t *reac, const uint32_t *chg, const MonProg &mp,
                         int waves_per_simd, bool iterative);

@@ -76,9 +76,14 @@ Cache &cache()
 
 }  // namespace
 
+// Small networks keep their counts in registers (StaticPolicy); wider ones,
+// up to kSpecWideMaxS species and kSpecWideMaxM channels, in LDS
+// (StaticWidePolicy).
+bool spec_wide(int S, int M) { return S > kSpecMaxS || M > kSpecMaxM; }
+
 bool spec_supported(int S, int M, const MonProg &mp)
 {
-    if (S < 1 || S > kSpecMaxS || M < 1 || M > kSpecMaxM) return false;
+    if (S < 1 || S > kSpecWideMaxS || M < 1 || M > kSpecWideMaxM) return false;
     for (int q = 0; q < mp.n_preds; ++q)
         if (mp.preds[q].kind == PK_RPN) return false;
     return true;
@@ -91,12 +96,20 @@ std::string spec_source(int S, int M, const int32_t *reac, const uint32_t *chg, 
     s.reserve(8192);
     s += "#include \"ssa_core.h\"\nnamespace smc {\nnamespace gen {\n";
     const std::string m = std::to_string(M);
-    s += "constexpr NetTab<" + m + "> make_net()\n{\n    NetTab<" + m + "> n{};\n";
-    for (int i = 0; i < 2 * M; ++i)
-        s += "    n.reac[" + std::to_string(i) + "] = " + fmt_i32(reac[i]) + ";\n";
-    for (int i = 0; i < 4 * M; ++i)
-        s += "    n.chg[" + std::to_string(i) + "] = " + std::to_string(chg[i]) + "u;\n";
-    s += "    return n;\n}\n";
+    const bool wide = spec_wide(S, M);
+    if (wide) {
+        s += "constexpr ReacTab<" + m + "> make_wide()\n{\n    ReacTab<" + m + "> n{};\n";
+        for (int i = 0; i < 2 * M; ++i)
+            s += "    n.reac[" + std::to_string(i) + "] = " + fmt_i32(reac[i]) + ";\n";
+        s += "    return n;\n}\n";
+    } else {
+        s += "constexpr NetTab<" + m + "> make_net()\n{\n    NetTab<" + m + "> n{};\n";
+        for (int i = 0; i < 2 * M; ++i)
+            s += "    n.reac[" + std::to_string(i) + "] = " + fmt_i32(reac[i]) + ";\n";
+        for (int i = 0; i < 4 * M; ++i)
+            s += "    n.chg[" + std::to_string(i) + "] = " + std::to_string(chg[i]) + "u;\n";
+        s += "    return n;\n}\n";
+    }
     s += "constexpr MonProg make_mon()\n{\n    MonProg m{};\n";
     s += "    m.n_preds = " + std::to_string(mp.n_preds) + ";\n";
     s += "    m.n_atoms = " + std::to_string(mp.n_atoms) + ";\n";
@@ -148,15 +161,22 @@ std::string spec_source(int S, int M, const int32_t *reac, const uint32_t *chg, 
     s += "struct Spec {\n";
     s += "    static constexpr int S = " + std::to_string(S) + ";\n";
     s += "    static constexpr int M = " + m + ";\n";
-    s += "    static constexpr NetTab<" + m + "> net = make_net();\n";
+    if (wide) s += "    static constexpr ReacTab<" + m + "> wide = make_wide();\n";
+    else s += "    static constexpr NetTab<" + m + "> net = make_net();\n";
     s += "    static constexpr MonProg mon = make_mon();\n";
     s += "};\n}  // namespace gen\n}  // namespace smc\n";
     std::string attr = "__launch_bounds__(256)";
     if (waves_per_simd > 0)
         attr += " __attribute__((amdgpu_waves_per_eu(" + std::to_string(waves_per_simd) + ", 8)))";
-    s += "extern \"C\" __global__ " + attr + " void smc_spec_kernel(smc::KArgs A)\n{\n"
-         "    smc::persistent_body<smc::StaticPolicy<smc::gen::Spec>, " +
-         std::string(iterative ? "true" : "false") + ">(A, nullptr);\n}\n";
+    if (wide)
+        s += "extern \"C\" __global__ " + attr + " void smc_spec_kernel(smc::KArgs A)\n{\n"
+             "    extern __shared__ int32_t smc_lds[];\n"
+             "    smc::persistent_body<smc::StaticWidePolicy<smc::gen::Spec>, " +
+             std::string(iterative ? "true" : "false") + ">(A, smc_lds);\n}\n";
+    else
+        s += "extern \"C\" __global__ " + attr + " void smc_spec_kernel(smc::KArgs A)\n{\n"
+             "    smc::persistent_body<smc::StaticPolicy<smc::gen::Spec>, " +
+             std::string(iterative ? "true" : "false") + ">(A, nullptr);\n}\n";
     return s;
 }
 

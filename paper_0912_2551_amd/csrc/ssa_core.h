@@ -629,6 +629,10 @@ __device__ __forceinline__ Draw event_uniforms(const JobView &V, unsigned long l
 // live: this lane steps its trajectory with the result (other lanes compute
 // along and discard it).
 template <int NB, class C>
+__device__ __forceinline__ double draw_tail(const JobView &V, const C &X, const Draw &d, double t,
+                                            Change *change, bool live, const double (&P)[NB], double acc);
+
+template <int NB, class C>
 __device__ __forceinline__ double ssa_draw(const JobView &V, const C &X, const Draw &d, double t,
                                            Change *change, bool live)
 {
@@ -686,6 +690,21 @@ __device__ __forceinline__ double ssa_draw(const JobView &V, const C &X, const D
             }
         }
     }
+    return draw_tail<NB>(V, X, d, t, change, live, P, acc);
+}
+
+// The draw after the first pass over the channels: P[q] holds the running
+// sum at the end of block q (the total for q >= nb), acc the total a0.
+// Selects the block whose running sum first exceeds u2 a0, re-runs the same
+// running sum inside it to find the channel, and returns t + tau.
+template <int NB, class C>
+__device__ __forceinline__ double draw_tail(const JobView &V, const C &X, const Draw &d, double t,
+                                            Change *change, bool live, const double (&P)[NB], double acc)
+{
+    const int M = __builtin_amdgcn_readfirstlane(V.M);
+    const int nb = __builtin_amdgcn_readfirstlane(V.nb), bs = __builtin_amdgcn_readfirstlane(V.bs);
+    cptr<int32_t> reac = uniform_ptr(V.reac);
+    cptr<double> rate = uniform_ptr(V.rate);
     const double a0 = acc;
     if (!(a0 > 0.0)) return __builtin_inf();
     const double target = d.u2 * a0;
@@ -885,6 +904,81 @@ struct StaticPolicy {
     }
     __device__ static __forceinline__ uint32_t advance(const JobView &, MonState &ms, double tn,
                                                        bool absorbing)
+    {
+        constexpr MonProg mp = Spec::mon;
+        return mon_advance(&mp, ms, tn, absorbing);
+    }
+};
+
+// Kernels specialised to a wide network (more channels or species than
+// StaticPolicy keeps in registers).  Counts live in LDS as in the generic
+// kernels; the first pass over the channels, the bulk of an event, reads
+// reactant indices as compile-time constants and every count once per event,
+// so each channel costs only its propensity arithmetic.  The block selection,
+// the re-run of the selected block and the state change are the generic
+// kernels' (per-lane table reads; the block differs between lanes).  The
+// operations and their order are the generic kernels', so results are
+// identical.
+template <int M>
+struct ReacTab {
+    int32_t reac[2 * M];
+};
+
+template <class Spec>
+struct StaticWidePolicy {
+    static constexpr int S = Spec::S;
+    static constexpr int M = Spec::M;
+    static constexpr int Mp = (M + kSubBlock - 1) / kSubBlock * kSubBlock;
+    // the generic kernels' blocking (JobView::load)
+    static constexpr int kNsub = Mp / kSubBlock;
+    static constexpr int kNb = kNsub < kBlocks ? kNsub : kBlocks;
+    static constexpr int kBs = (kNsub + kNb - 1) / kNb * kSubBlock;
+    using Counts = LdsCounts;
+    using Sel = Change;
+    __device__ static __forceinline__ Counts counts(int32_t *lds, int wid, int, int lane)
+    {
+        Counts X;
+        X.xs = lds + (size_t)wid * (size_t)S * kWave;
+        X.lane = lane;
+        return X;
+    }
+    __device__ static __forceinline__ void init(Counts &X, const JobView &V) { X.init(uniform_ptr(V.x0), S); }
+    __device__ static __forceinline__ double draw(const JobView &V, const Counts &X, const Draw &d,
+                                                  double t, Sel *s, bool live)
+    {
+        constexpr ReacTab<M> T = Spec::wide;
+        cptr<double> rate = uniform_ptr(V.rate);
+        int32_t x[S];
+#pragma unroll
+        for (int q = 0; q < S; ++q) x[q] = X.get(q);
+        double P[kBlocks];
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < kBlocks; ++q) {
+            P[q] = acc;
+            if (q < kNb) {
+#pragma unroll
+                for (int j = q * kBs; j < (q + 1) * kBs && j < Mp; ++j) {
+                    const int ra = j < M ? T.reac[2 * j] : -1;
+                    const int rb = j < M ? T.reac[2 * j + 1] : -1;
+                    acc = acc + propensity_x(ra, rb, rate[j], ra < 0 ? 0 : x[ra], rb < 0 ? 0 : x[rb]);
+                }
+                P[q] = acc;
+            }
+        }
+        return draw_tail<kBlocks>(V, X, d, t, s, live, P, acc);
+    }
+    __device__ static __forceinline__ void apply_if(Counts &X, const Sel &c, bool on)
+    {
+        if (on) X.apply(c.e0, c.e1, c.e2, c.e3);
+    }
+    __device__ static __forceinline__ uint32_t step(const JobView &, MonState &ms, const Counts &X, uint32_t k,
+                                                    double t)
+    {
+        constexpr MonProg mp = Spec::mon;
+        return mon_step(&mp, ms, X, k, t);
+    }
+    __device__ static __forceinline__ uint32_t advance(const JobView &, MonState &ms, double tn, bool absorbing)
     {
         constexpr MonProg mp = Spec::mon;
         return mon_advance(&mp, ms, tn, absorbing);

@@ -240,14 +240,15 @@ int persistent_blocks_per_cu(int variant, bool iterative, int waves_per_block, s
     return e == hipSuccess ? nb : 0;
 }
 
-int module_blocks_per_cu(hipFunction_t fn, int waves_per_block)
+int module_blocks_per_cu(hipFunction_t fn, int waves_per_block, size_t lds_bytes)
 {
     int nb = 0;
-    const hipError_t e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kWave * waves_per_block, 0);
+    const hipError_t e =
+        hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kWave * waves_per_block, lds_bytes);
     return e == hipSuccess ? nb : 0;
 }
 
-hipError_t launch_module(hipFunction_t fn, int grid, int waves_per_block, hipStream_t stream,
+hipError_t launch_module(hipFunction_t fn, int grid, int waves_per_block, size_t lds_bytes, hipStream_t stream,
                          const Job *jobs, int n_jobs, int s_max, Control *ctl,
                          const volatile int32_t *cancel, int spin_limit, int static_first)
 {
@@ -261,8 +262,8 @@ hipError_t launch_module(hipFunction_t fn, int grid, int waves_per_block, hipStr
     a.waves_per_block = waves_per_block;
     a.static_first = static_first;
     void *params[] = {&a};
-    return hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, (unsigned)(kWave * waves_per_block), 1, 1, 0,
-                                 stream, params, nullptr);
+    return hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, (unsigned)(kWave * waves_per_block), 1, 1,
+                                 (unsigned)lds_bytes, stream, params, nullptr);
 }
 
 hipError_t launch_sample_state(int variant, hipStream_t stream, const Job *job, double T,

@@ -90,26 +90,47 @@ def test_trajectory_parity(ctx, name, make, text, kw, count, mode):
         ctx.set_specialization(B.SPECIALIZE_AUTO)
 
 
-def test_c3_random_network_parity(ctx):
+def _wide_mode(ctx, B, mode):
+    """Run on the generic kernel or on the wide specialised kernel (counts in
+    LDS, constant reactant indices); both must equal the oracle."""
+    ctx.set_specialization(B.SPECIALIZE_OFF if mode == "generic" else B.SPECIALIZE_REQUIRED)
+
+
+WIDE_MODES = pytest.mark.parametrize("mode", ["generic", "specialized"])
+
+
+@WIDE_MODES
+def test_c3_random_network_parity(ctx, mode):
     B = _B()
     net = W.c3_network()
     text = W.c3_formula(net)
     n = ctx.network(net)
     f = ctx.formula(n, text)
     p = B.params(seed=1, max_events=W.C3_CAP)
-    ev, vd, rs = ctx.trajectories(n, f, p, 0, 96)
+    _wide_mode(ctx, B, mode)
+    try:
+        ev, vd, rs = ctx.trajectories(n, f, p, 0, 96)
+        assert ctx.last_kernel() == (B.KERNEL_GENERIC if mode == "generic" else B.KERNEL_SPECIALIZED)
+    finally:
+        ctx.set_specialization(B.SPECIALIZE_AUTO)
     oev, ovd, ors = oracle.trajectories(net, oracle.parse(text, net), 0, 96, seed=1, max_events=W.C3_CAP)
     assert np.array_equal(ev, oev) and np.array_equal(vd, ovd) and np.array_equal(rs, ors)
 
 
-def test_large_network_parity(ctx):
+@WIDE_MODES
+def test_large_network_parity(ctx, mode):
     B = _B()
     net = W.random_network(128, 512, seed=7)
     text = W.nested_until_formula(net, 15, W.c3_species(net))
     n = ctx.network(net)
     f = ctx.formula(n, text)
     p = B.params(seed=5, max_events=20000)
-    ev, vd, rs = ctx.trajectories(n, f, p, 0, 70)
+    _wide_mode(ctx, B, mode)
+    try:
+        ev, vd, rs = ctx.trajectories(n, f, p, 0, 70)
+        assert ctx.last_kernel() == (B.KERNEL_GENERIC if mode == "generic" else B.KERNEL_SPECIALIZED)
+    finally:
+        ctx.set_specialization(B.SPECIALIZE_AUTO)
     oev, ovd, ors = oracle.trajectories(net, oracle.parse(text, net), 0, 70, seed=5, max_events=20000)
     assert np.array_equal(ev, oev) and np.array_equal(vd, ovd) and np.array_equal(rs, ors)
 
