@@ -667,14 +667,18 @@ __device__ __forceinline__ double ssa_draw(const JobView &V, const C &X, const D
                     // Kept apart, each phase waits once: scalar loads can
                     // return out of order, so mixed with LDS reads on the
                     // same wait counter they would force a wait per read.
-                    const int jb = __builtin_amdgcn_readfirstlane(jj);
+                    // one base per step and unsigned offsets: the compiler
+                    // merges the step's entries into wide scalar loads
+                    const size_t jb = (size_t)(unsigned)__builtin_amdgcn_readfirstlane(jj);
+                    cptr<int32_t> rp = reac + 2 * jb;
+                    cptr<double> cp = rate + jb;
                     int ra[kSubBlock], rb[kSubBlock];
                     double cr[kSubBlock];
 #pragma unroll
                     for (int r = 0; r < kSubBlock; ++r) {
-                        ra[r] = reac[2 * (jb + r)];
-                        rb[r] = reac[2 * (jb + r) + 1];
-                        cr[r] = rate[jb + r];
+                        ra[r] = rp[2 * r];
+                        rb[r] = rp[2 * r + 1];
+                        cr[r] = cp[r];
                     }
                     int32_t xa[kSubBlock], xb[kSubBlock];
 #pragma unroll
