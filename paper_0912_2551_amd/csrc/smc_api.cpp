@@ -47,7 +47,7 @@ struct smc_ctx {
     int32_t *cancel_host = nullptr;   // pinned, read by kernels
     int32_t *cancel_dev = nullptr;
     std::atomic<int> cancel_req{0};
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
     // grow-only workspace
     Job *d_jobs = nullptr;
     size_t cap_jobs = 0;
@@ -448,9 +448,13 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
             HIP_TRY(ctx, launch_finalize(s, ctx->d_jobs, n, ctx->d_results));
         }
         HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
+        // the results travel back in the same stream, without a round trip
+        // through the host between the kernels' end and the copy
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->h_results, ctx->d_results, n * sizeof(JobResult), hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipEventRecord(ctx->ev2, s));
         // wait under the watchdog
         for (;;) {
-            const hipError_t q = hipEventQuery(ctx->ev1);
+            const hipError_t q = hipEventQuery(ctx->ev2);
             if (q == hipSuccess) break;
             if (q != hipErrorNotReady) return hip_fail(ctx, q, "kernel");
             const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
@@ -461,8 +465,6 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
         float ms = 0.0f;
         HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
         total_ms += ms;
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->h_results, ctx->d_results, n * sizeof(JobResult), hipMemcpyDeviceToHost, s));
-        HIP_TRY(ctx, hipStreamSynchronize(s));
         std::memcpy(res.data(), ctx->h_results, n * sizeof(JobResult));
         if (*ctx->cancel_host) {
             *seconds = total_ms * 1e-3;
@@ -550,7 +552,8 @@ int smc_ctx_create(int hip_device, void *hip_stream, smc_ctx **out)
         (e = hipHostGetDevicePointer((void **)&c->cancel_dev, c->cancel_host, 0)) != hipSuccess ||
         (e = hipMalloc((void **)&c->d_ctl, sizeof(Control))) != hipSuccess ||
         (e = hipHostMalloc((void **)&c->h_ctl, sizeof(Control), hipHostMallocDefault)) != hipSuccess ||
-        (e = hipEventCreate(&c->ev0)) != hipSuccess || (e = hipEventCreate(&c->ev1)) != hipSuccess) {
+        (e = hipEventCreate(&c->ev0)) != hipSuccess || (e = hipEventCreate(&c->ev1)) != hipSuccess ||
+        (e = hipEventCreate(&c->ev2)) != hipSuccess) {
         smc_ctx_destroy(c);
         return fail(nullptr, SMC_E_HIP, hipGetErrorString(e));
     }
@@ -575,6 +578,7 @@ void smc_ctx_destroy(smc_ctx *c)
     if (c->h_ctl) (void)hipHostFree(c->h_ctl);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->ev2) (void)hipEventDestroy(c->ev2);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
