@@ -363,7 +363,6 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
     }
     hipStream_t s = ctx->stream;
     HIP_TRY(ctx, hipMemcpyAsync(ctx->d_jobs, jobs, n * sizeof(Job), hipMemcpyHostToDevice, s));
-    HIP_TRY(ctx, hipMemsetAsync(ctx->d_states, 0, n * sizeof(JobState), s));
     *ctx->cancel_host = 0;
     ctx->cancel_req.store(0);
 
@@ -418,7 +417,7 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
                                    : persistent_blocks_per_cu(variant, false, wpb, lds_wave * wpb);
         static_first = per_cu > 0 && (long long)per_cu * ctx->n_cu >= grid;
     }
-    HIP_TRY(ctx, launch_init(s, ctx->d_jobs, n, static_first ? grid * wpb : 0));
+    HIP_TRY(ctx, launch_init(s, ctx->d_jobs, n, static_first ? grid * wpb : 0, ctx->d_ctl, n_iter));
     ctx->last_kernel = spec_fn ? SMC_KERNEL_SPECIALIZED : (variant == 0 ? SMC_KERNEL_GENERIC_SMALL : SMC_KERNEL_GENERIC);
     res.assign(n, JobResult{});
     double total_ms = 0.0;
@@ -430,10 +429,13 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
         if (launch == 0) open = n_iter;
         else
             for (int k = 0; k < n; ++k) open += (jobs[k].iterative && !res[k].final_flag);
-        // the previous launch (and its copies) completed before this point
-        *ctx->h_ctl = Control{};
-        ctx->h_ctl->open_jobs = open;
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->d_ctl, ctx->h_ctl, sizeof(Control), hipMemcpyHostToDevice, s));
+        // init_jobs set the first launch's control block; the previous launch
+        // (and its copies) completed before this point
+        if (launch > 0) {
+            *ctx->h_ctl = Control{};
+            ctx->h_ctl->open_jobs = open;
+            HIP_TRY(ctx, hipMemcpyAsync(ctx->d_ctl, ctx->h_ctl, sizeof(Control), hipMemcpyHostToDevice, s));
+        }
         HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
         if (spec_fn)
             HIP_TRY(ctx, launch_module(spec_fn, grid, wpb, spec_lds, s, ctx->d_jobs, n, s_max, ctx->d_ctl,

@@ -32,8 +32,10 @@ hipError_t launch_module(hipFunction_t fn, int grid, int waves_per_block, size_t
                          const volatile int32_t *cancel, int spin_limit, int static_first);
 int persistent_blocks_per_cu(int variant, bool iterative, int waves_per_block, size_t lds_bytes);
 int module_blocks_per_cu(hipFunction_t fn, int waves_per_block, size_t lds_bytes);
-// n_waves: waves of the first launch (their static first shares), 0 for none
-hipError_t launch_init(hipStream_t stream, const Job *jobs, int n_jobs, int n_waves);
+// Clears and sets up the jobs' state and the control block of the first
+// launch.  n_waves: waves of the first launch (their static first shares), 0
+// for none; open_jobs: iterative jobs of the launch.
+hipError_t launch_init(hipStream_t stream, const Job *jobs, int n_jobs, int n_waves, Control *ctl, int open_jobs);
 hipError_t launch_finalize(hipStream_t stream, const Job *jobs, int n_jobs, JobResult *out);
 // Fig. 2 over recorded per-index verdicts (speculative launches)
 hipError_t launch_replay(hipStream_t stream, const Job *jobs, int n_jobs, JobResult *out);

@@ -66,12 +66,25 @@ __global__ __launch_bounds__(256) void ssa_sample_state(const Job *jobp, double 
 // without atomics: the waves whose home is job j (ranks 0 .. W_j - 1, see
 // persistent_body) take [64 r, 64 r + 64) below static_end, and the job's
 // issue counter starts at static_end.  n_waves = 0: no static shares.
-__global__ void init_jobs(const Job *jobs, int n_jobs, int n_waves)
+// One block per job: the block clears the job's state, then one thread sets
+// it up; block 0 also sets the launch's control block.
+static_assert(sizeof(JobState) % sizeof(unsigned long long) == 0, "JobState is cleared in 8-byte words");
+
+__global__ void init_jobs(const Job *jobs, int n_jobs, int n_waves, Control *ctl, int open_jobs)
 {
-    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int j = (int)blockIdx.x;
     if (j >= n_jobs) return;
     const Job &J = jobs[j];
     JobState *st = J.st;
+    unsigned long long *words = reinterpret_cast<unsigned long long *>(st);
+    for (int i = (int)threadIdx.x; i < (int)(sizeof(JobState) / sizeof(unsigned long long)); i += (int)blockDim.x)
+        words[i] = 0ull;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    if (j == 0) {
+        ctl->open_jobs = open_jobs;
+        ctl->stop = 0;
+    }
     st->bound[0] = J.n_first;
     st->cnt[0] = kDoneFlag - J.n_first;   // batch 0's bound is published
     unsigned long long lim = J.n_first;
@@ -281,9 +294,9 @@ hipError_t launch_sample_state(int variant, hipStream_t stream, const Job *job, 
     return hipGetLastError();
 }
 
-hipError_t launch_init(hipStream_t stream, const Job *jobs, int n_jobs, int n_waves)
+hipError_t launch_init(hipStream_t stream, const Job *jobs, int n_jobs, int n_waves, Control *ctl, int open_jobs)
 {
-    hipLaunchKernelGGL(init_jobs, dim3((n_jobs + 63) / 64), dim3(64), 0, stream, jobs, n_jobs, n_waves);
+    hipLaunchKernelGGL(init_jobs, dim3(n_jobs), dim3(256), 0, stream, jobs, n_jobs, n_waves, ctl, open_jobs);
     return hipGetLastError();
 }
 
