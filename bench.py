@@ -235,7 +235,7 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the trajectory-index sharding across GPUs is a design note, not a measured path)",
               file=sys.stderr)
         sys.exit(2)
