@@ -226,8 +226,8 @@ int smc_sample_state(smc_ctx *ctx, const smc_net *net, const smc_params *p, doub
  * (pilot_n trajectories, 1..2^26, with a seed derived from p->seed, so the
  * estimate's own trajectories are not consumed) for each candidate
  * configuration: generic or specialised kernel, the specialised kernel's
- * register budget (compiler default, 5, 6 or 8 waves per SIMD) and waves per
- * compute unit (4, 8, 16, 24, 32).  The fastest, in SSA events per second of
+ * register budget (compiler default, 5, 6, 7 or 8 waves per SIMD) and waves
+ * per compute unit (4, 8, 16, 24, 28, 32).  The fastest, in SSA events per second of
  * device time, is recorded on the context for the model's structure (network
  * tables and formula; rates, initial state and parameters do not enter): later
  * launches of fixed-size jobs that all share that structure use it in place

@@ -631,8 +631,8 @@ int smc_autotune(smc_ctx *c, const smc_net *net, const smc_formula *f, const smc
     };
     std::vector<Cand> cands = {{SMC_SPECIALIZE_OFF, 0}};
     if (spec_supported(net->S, net->M, f->prog))
-        for (int occ : {0, 5, 6, 8}) cands.push_back({SMC_SPECIALIZE_REQUIRED, occ});
-    const int wpcs[] = {4, 8, 16, 24, 32};
+        for (int occ : {0, 5, 6, 7, 8}) cands.push_back({SMC_SPECIALIZE_REQUIRED, occ});
+    const int wpcs[] = {4, 8, 16, 24, 28, 32};
     smc_tune_result best{};
     best.events_per_s = -1.0;
     int tried = 0;
