@@ -147,6 +147,45 @@ def batched_sweep_run(ctx, B, W):
             "events_per_s": ev / wall, "max_batches": max(r["batches"] for r in res)}
 
 
+def fig3_sample_sizes(ctx, B, W, reps=32, eps=0.025, confidence=0.99):
+    """Sample sizes of Fig. 3: for p = 0, 0.1, ..., 1, a one-molecule death
+    process (rate 1) under F[0,T](X<=0) with T = -ln(1 - p) is a Bernoulli
+    source of exactly that p (T = 50 for p = 1).  Every (p, replicate) pair is
+    one iterative 99% +-0.025 Wilson job (the figure's setting) of one batched
+    launch; reported per p: the conservative size (eq. 4 at 0.5),
+    the mean iterative size (Fig. 2) over the replicates and the size for a
+    known p (eq. 4 at p), as in the figure's three bars."""
+    import torch
+    z = B.z_value(confidence)
+    keep, jobs, groups = [], [], []
+    net = W.from_reactions(["X"], [1], [(["X"], [], 1.0)], "death of one molecule")
+    nh = ctx.network(net)
+    for q in range(11):
+        p = q / 10.0
+        T = 50.0 if q == 10 else -math.log1p(-p)
+        fh = ctx.formula(nh, f"F[0,{T!r}](X<=0)")
+        keep.append(fh)
+        for r in range(reps):
+            jobs.append((nh, fh, B.params(confidence=confidence, half_width=eps, seed=1000 + r, model_id=q)))
+        groups.append(p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ctx.estimate_batch(jobs)
+    wall = time.perf_counter() - t0
+    cons = B.wilson_sample(0.5, eps, z)
+    rows = []
+    for q, p in enumerate(groups):
+        rr = res[q * reps:(q + 1) * reps]
+        n_it = sum(r["n"] for r in rr) / reps
+        covered = sum(1 for r in rr if r["lo"] <= p <= r["hi"]) / reps
+        rows.append({"p": p, "conservative": cons, "iterative_mean": n_it, "known_p": B.wilson_sample(p, eps, z),
+                     "reduction_vs_conservative": 1.0 - n_it / cons,
+                     "mean_batches": sum(r["batches"] for r in rr) / reps, "coverage": covered})
+    return {"workload": f"Fig. 3 setting: 99% Wilson +-{eps}, p = 0..1 by 0.1, {reps} replicates each, "
+                        "one batched launch (death of one molecule, F[0,T](X<=0), T = -ln(1-p))",
+            "seconds": wall, "jobs": len(jobs), "rows": rows}
+
+
 def surrogate_vs_plain(ctx, B, W, text, n_train=512, n_query=10**6, n_sub=4096, eps=0.01, margin=0.05,
                        steps=2000):
     """Answer n_query rate points either with plain batched SMC or with the
@@ -329,6 +368,8 @@ def main():
                              "interval": [r1["lo"], r1["hi"]], "seconds": w1,
                              "verified_trajectories_per_s": r1["n"] / w1, "events_per_s": r1["events"] / w1}
         progress("C1 Wilson run")
+    line["fig3_sample_sizes"] = fig3_sample_sizes(ctx, B, W)
+    progress("Fig. 3 sample sizes")
     if not args.no_large:
         line["c3_random_network"] = random_network_run(ctx, B, W)
         progress("C3 random network")

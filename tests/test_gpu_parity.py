@@ -249,6 +249,34 @@ def test_fixed_batch_matches_oracle(ctx, waves_per_cu):
             assert (r["n"], r["successes"], r["events"]) == (o["n"], o["successes"], o["events"]), (m, mid)
 
 
+@SPECULATE
+def test_fig3_bernoulli_sources(ctx, speculate):
+    """Fig. 3's setting (99%, +-0.025) on Bernoulli sources of known p: the
+    death of one molecule (rate 1) before T = -ln(1 - p).  The device's
+    iterative sample sizes equal the oracle's, and at p = 0 and p = 1 the
+    reduction against the conservative size is the paper's "up to 88%"."""
+    B = _B()
+    net = W.from_reactions(["X"], [1], [(["X"], [], 1.0)], "death of one molecule")
+    nh = ctx.network(net)
+    cons = B.wilson_sample(0.5, 0.025, B.z_value(0.99))
+    keep, jobs, refs = [], [], []
+    for q, p in enumerate((0.0, 0.3, 1.0)):
+        T = 50.0 if p == 1.0 else -math.log1p(-p)
+        text = f"F[0,{T!r}](X<=0)"
+        fh = ctx.formula(nh, text)
+        keep.append(fh)
+        for r in range(3):
+            jobs.append((nh, fh, B.params(confidence=0.99, half_width=0.025, seed=1000 + r, model_id=q,
+                                          speculate=speculate)))
+            refs.append((text, 1000 + r, q, p))
+    res = ctx.estimate_batch(jobs)
+    for r, (text, seed, q, p) in zip(res, refs):
+        o = oracle.estimate(net, text, confidence=0.99, eps=0.025, seed=seed, model_id=q)
+        assert (r["n"], r["successes"], r["batches"]) == (o["n"], o["successes"], len(o["bounds"]))
+        if p in (0.0, 1.0):
+            assert 0.88 <= 1.0 - r["n"] / cons < 0.89
+
+
 def test_device_stopping_rule_matches_host(ctx):
     rng = np.random.default_rng(0)
     z = wilson.z_value(0.95)
