@@ -80,6 +80,7 @@ struct smc_net {
     double *d_rate = nullptr;
     int32_t *d_reac = nullptr;
     uint32_t *d_chg = nullptr;
+    ChanDev *d_chan = nullptr;
 };
 
 struct smc_formula {
@@ -228,6 +229,7 @@ int prepare(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_pa
     J.net.rate = net->d_rate;
     J.net.reac = net->d_reac;
     J.net.chg = net->d_chg;
+    J.net.chan = net->d_chan;
     J.mon = f->d_prog;
     J.seed = p->seed;
     J.first = first;
@@ -390,7 +392,7 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
             ctx->spec_mode = it->second.specialization;
         }
     }
-    const size_t lds_wave = (size_t)s_max * kWave * sizeof(int32_t);
+    const size_t lds_wave = (size_t)(s_max + 1) * kWave * sizeof(int32_t);   // + the constant-1 row
     int wpb = (int)std::min<size_t>(4, std::max<size_t>(1, 65536 / lds_wave));
     if (lds_wave > 65536) return fail(ctx, SMC_E_INVALID, "network too large for one wave's LDS");
     const int wpc = pick_waves_per_cu(ctx);
@@ -725,6 +727,17 @@ static int upload_net(smc_net *n)
     HIP_TRY(c, hipMemcpy(n->d_rate, rate.data(), Mp * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(n->d_reac, reac.data(), 2 * Mp * sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(n->d_chg, chg.data(), 4 * Mp * sizeof(uint32_t), hipMemcpyHostToDevice));
+    // the generic kernels' form of each channel (padding: zero-order, rate 0)
+    std::vector<ChanDev> chan(Mp);
+    const int32_t row = kWave * (int32_t)sizeof(int32_t);
+    for (int j = 0; j < Mp; ++j) {
+        const int ra = j < n->M ? n->reac[2 * j] : -1, rb = j < n->M ? n->reac[2 * j + 1] : -1;
+        ChanDev &e = chan[j];
+        e.a_off = (ra < 0 ? n->S : ra) * row;
+        e.b_code = (rb < 0 ? n->S : rb) * row + ((ra >= 0 && ra == rb) ? 1 : 0);
+    }
+    HIP_TRY(c, hipMalloc((void **)&n->d_chan, Mp * sizeof(ChanDev)));
+    HIP_TRY(c, hipMemcpy(n->d_chan, chan.data(), Mp * sizeof(ChanDev), hipMemcpyHostToDevice));
     return SMC_OK;
 }
 
@@ -823,6 +836,7 @@ void smc_net_destroy(smc_net *n)
     if (n->d_rate) (void)hipFree(n->d_rate);
     if (n->d_reac) (void)hipFree(n->d_reac);
     if (n->d_chg) (void)hipFree(n->d_chg);
+    if (n->d_chan) (void)hipFree(n->d_chan);
     delete n;
 }
 
@@ -947,7 +961,7 @@ int smc_sample_state(smc_ctx *c, const smc_net *net, const smc_params *p, double
     if (count == 0) return SMC_OK;
     if (!(T >= 0.0)) return fail(c, SMC_E_INVALID, "T must be >= 0");
     if (first + count > (1ull << 32)) return fail(c, SMC_E_INVALID, "trajectory indices must stay below 2^32");
-    if ((size_t)net->S * kWave * sizeof(int32_t) > 65536) return fail(c, SMC_E_INVALID, "network too large");
+    if ((size_t)(net->S + 1) * kWave * sizeof(int32_t) > 65536) return fail(c, SMC_E_INVALID, "network too large");
     HIP_TRY(c, hipSetDevice(c->device));
     Job J;
     std::memset(&J, 0, sizeof(J));
@@ -958,6 +972,7 @@ int smc_sample_state(smc_ctx *c, const smc_net *net, const smc_params *p, double
     J.net.rate = net->d_rate;
     J.net.reac = net->d_reac;
     J.net.chg = net->d_chg;
+    J.net.chan = net->d_chan;
     J.seed = p->seed;
     J.first = first;
     J.model_id = p->model_id;

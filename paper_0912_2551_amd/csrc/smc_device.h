@@ -103,6 +103,17 @@ struct MonProg {
 //              ra == rb homodimer; otherwise two distinct reactants.
 //   chg[4j+q] = four packed entries ((species & 0xFFFF) << 16) | (delta & 0xFFFF),
 //              species 0xFFFF = unused.
+// Channel j of a network for the generic kernels: h_j = (x_a (x_b - delta))
+// gamma, c_j h_j being the propensity (Sec. 2.2).  a_off and the multiple of
+// 256 in b_code are the byte offsets of the reactant rows in a wave's LDS
+// slice; a missing reactant names row S, which holds the constant 1.  Bit 0
+// of b_code marks x_a (x_a - 1) / 2, (delta, gamma) = (1, 1/2); otherwise
+// (0, 1) for x_a x_b, x_a and 1.  Every factor is an integer or half-integer,
+// so h_j is exact and c_j h_j rounds once.
+struct ChanDev {
+    int32_t a_off, b_code;
+};
+
 struct NetDev {
     int32_t S, M;
     int32_t Mp;   // M rounded up to kSubBlock: the tables hold Mp channels, the
@@ -112,6 +123,7 @@ struct NetDev {
     const double *rate;
     const int32_t *reac;
     const uint32_t *chg;
+    const ChanDev *chan;   // Mp entries
 };
 
 // Per-job accounting (device memory).  Batch b covers relative trajectory

@@ -240,6 +240,7 @@ struct JobView {
     cptr<double> rate;
     cptr<int32_t> reac;
     cptr<uint32_t> chg;
+    cptr<ChanDev> chan;
     int S, M, Mp;
     unsigned long long seed, first, capacity;
     uint32_t r1_hi, r1_lo;   // model id * 0xCD9E8D57: first Philox round's product (per job)
@@ -262,6 +263,7 @@ struct JobView {
         rate = as_const(J->net.rate);
         reac = as_const(J->net.reac);
         chg = as_const(J->net.chg);
+        chan = as_const(J->net.chan);
         S = J->net.S;
         M = J->net.M;
         Mp = J->net.Mp;
@@ -295,9 +297,16 @@ struct LdsCounts {
     int32_t *xs;
     int lane;
     __device__ __forceinline__ int32_t get(int s) const { return xs[s * kWave + lane]; }
+    // counts of x0, and the constant-1 row S that missing reactants name
     __device__ __forceinline__ void init(cptr<int32_t> x0, int S)
     {
         for (int s = 0; s < S; ++s) xs[s * kWave + lane] = x0[s];
+        xs[S * kWave + lane] = 1;
+    }
+    // the count in the row at byte offset off of the slice
+    __device__ __forceinline__ int32_t at(int32_t off) const
+    {
+        return *reinterpret_cast<const int32_t *>(reinterpret_cast<const char *>(xs + lane) + off);
     }
     // four packed (species, delta) entries
     __device__ __forceinline__ void apply(uint32_t e0, uint32_t e1, uint32_t e2, uint32_t e3)
@@ -336,6 +345,25 @@ __device__ __forceinline__ double propensity_x(int ra, int rb, double c, int32_t
     const double hetero = da * db;
     const double homo = (da * (double)(xa - 1)) * 0.5;
     const double h = ra < 0 ? 1.0 : (rb < 0 ? da : (ra == rb ? homo : hetero));
+    return c * h;
+}
+
+// field by field (the tables may sit in the constant address space)
+__device__ __forceinline__ ChanDev load_chan(cptr<ChanDev> p)
+{
+    ChanDev e;
+    e.a_off = p->a_off;
+    e.b_code = p->b_code;
+    return e;
+}
+
+// c h with h = (x_a (x_b - delta)) gamma (ChanDev): the same value as
+// propensity_x for the channel's form, every factor being exact
+__device__ __forceinline__ double chan_propensity(const ChanDev &e, double c, int32_t xa, int32_t xb)
+{
+    const bool homo = (e.b_code & 1) != 0;
+    const double delta = homo ? 1.0 : 0.0, gamma = homo ? 0.5 : 1.0;
+    const double h = ((double)xa * ((double)xb - delta)) * gamma;
     return c * h;
 }
 
@@ -639,6 +667,7 @@ __device__ __forceinline__ double ssa_draw(const JobView &V, const C &X, const D
     const int M = __builtin_amdgcn_readfirstlane(V.M);
     const int nb = __builtin_amdgcn_readfirstlane(V.nb), bs = __builtin_amdgcn_readfirstlane(V.bs);
     cptr<int32_t> reac = uniform_ptr(V.reac);
+    cptr<ChanDev> chan = uniform_ptr(V.chan);
     cptr<double> rate = uniform_ptr(V.rate);
     double P[NB];
     double acc = 0.0;
@@ -662,33 +691,32 @@ __device__ __forceinline__ double ssa_draw(const JobView &V, const C &X, const D
                 const int j0 = q * bs;
                 const int j1 = (j0 + bs < Mp) ? j0 + bs : Mp;
                 for (int jj = j0; jj < j1; jj += kSubBlock) {
-                    // Three phases per step: the table entries (scalar loads),
-                    // then the counts they name (LDS), then the arithmetic.
-                    // Kept apart, each phase waits once: scalar loads can
-                    // return out of order, so mixed with LDS reads on the
-                    // same wait counter they would force a wait per read.
-                    // one base per step and unsigned offsets: the compiler
-                    // merges the step's entries into wide scalar loads
+                    // Three phases per step: the channel entries (scalar
+                    // loads), then the counts they name (LDS), then the
+                    // arithmetic.  Kept apart, each phase waits once: scalar
+                    // loads can return out of order, so mixed with LDS reads
+                    // on the same wait counter they would force a wait per
+                    // read.  One base per step and unsigned offsets let the
+                    // compiler merge the step's entries into wide scalar loads.
                     const size_t jb = (size_t)(unsigned)__builtin_amdgcn_readfirstlane(jj);
-                    cptr<int32_t> rp = reac + 2 * jb;
+                    cptr<ChanDev> ep = chan + jb;
                     cptr<double> cp = rate + jb;
-                    int ra[kSubBlock], rb[kSubBlock];
+                    ChanDev e[kSubBlock];
                     double cr[kSubBlock];
 #pragma unroll
                     for (int r = 0; r < kSubBlock; ++r) {
-                        ra[r] = rp[2 * r];
-                        rb[r] = rp[2 * r + 1];
+                        e[r] = load_chan(ep + r);
                         cr[r] = cp[r];
                     }
                     int32_t xa[kSubBlock], xb[kSubBlock];
 #pragma unroll
                     for (int r = 0; r < kSubBlock; ++r) {
-                        xa[r] = X.get(ra[r] < 0 ? 0 : ra[r]);   // species 0 stands in (unused)
-                        xb[r] = X.get(rb[r] < 0 ? 0 : rb[r]);
+                        xa[r] = X.at(e[r].a_off);
+                        xb[r] = X.at(e[r].b_code & ~1);
                     }
 #pragma unroll
                     for (int r = 0; r < kSubBlock; ++r)
-                        acc = acc + propensity_x(ra[r], rb[r], cr[r], xa[r], xb[r]);
+                        acc = acc + chan_propensity(e[r], cr[r], xa[r], xb[r]);
                 }
                 P[q] = acc;
             }
@@ -739,24 +767,24 @@ __device__ __forceinline__ double draw_tail(const JobView &V, const C &X, const 
         double s = base;
         jsel = j1 - 1;
         bool got = !live;
+        cptr<ChanDev> chan = V.chan;
         for (int jj = j0; jj < j1; jj += kSubBlock) {
-            int ra[kSubBlock], rb[kSubBlock];
+            ChanDev e[kSubBlock];
             double cr[kSubBlock];
 #pragma unroll
             for (int r = 0; r < kSubBlock; ++r) {
-                ra[r] = reac[2 * (jj + r)];
-                rb[r] = reac[2 * (jj + r) + 1];
+                e[r] = load_chan(chan + (jj + r));
                 cr[r] = rate[jj + r];
             }
             int32_t xa[kSubBlock], xb[kSubBlock];
 #pragma unroll
             for (int r = 0; r < kSubBlock; ++r) {
-                xa[r] = X.get(ra[r] < 0 ? 0 : ra[r]);
-                xb[r] = X.get(rb[r] < 0 ? 0 : rb[r]);
+                xa[r] = X.at(e[r].a_off);
+                xb[r] = X.at(e[r].b_code & ~1);
             }
 #pragma unroll
             for (int r = 0; r < kSubBlock; ++r) {
-                s = s + propensity_x(ra[r], rb[r], cr[r], xa[r], xb[r]);
+                s = s + chan_propensity(e[r], cr[r], xa[r], xb[r]);
                 const bool hit = !got && s > target;
                 jsel = hit ? jj + r : jsel;
                 got = got || hit;
@@ -809,7 +837,7 @@ struct DynPolicy {
     __device__ static __forceinline__ Counts counts(int32_t *lds, int wid, int s_max, int lane)
     {
         Counts X;
-        X.xs = lds + (size_t)wid * (size_t)s_max * kWave;
+        X.xs = lds + (size_t)wid * (size_t)(s_max + 1) * kWave;   // + the constant-1 row
         X.lane = lane;
         return X;
     }
@@ -942,7 +970,7 @@ struct StaticWidePolicy {
     __device__ static __forceinline__ Counts counts(int32_t *lds, int wid, int, int lane)
     {
         Counts X;
-        X.xs = lds + (size_t)wid * (size_t)S * kWave;
+        X.xs = lds + (size_t)wid * (size_t)(S + 1) * kWave;   // + the constant-1 row
         X.lane = lane;
         return X;
     }

@@ -28,7 +28,7 @@ __global__ __launch_bounds__(256) void ssa_sample_state(const Job *jobp, double 
     const int lane = lane_id();
     const int wid = (int)(threadIdx.x / kWave);
     C X;
-    X.xs = lds + (size_t)wid * (size_t)s_max * kWave;
+    X.xs = lds + (size_t)wid * (size_t)(s_max + 1) * kWave;   // + the constant-1 row
     X.lane = lane;
     JobView V;
     V.load(jobp, 0);
@@ -284,7 +284,7 @@ hipError_t launch_sample_state(int variant, hipStream_t stream, const Job *job, 
 {
     const int threads = kWave;
     const unsigned long long blocks = (count + threads - 1) / threads;
-    const size_t lds = (size_t)s_max * kWave * sizeof(int32_t);
+    const size_t lds = (size_t)(s_max + 1) * kWave * sizeof(int32_t);
     if (variant == 0)
         hipLaunchKernelGGL((ssa_sample_state<4, LdsCounts>), dim3((unsigned)blocks), dim3(threads), lds,
                            stream, job, T, count, out, s_max);
