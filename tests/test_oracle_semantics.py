@@ -90,6 +90,8 @@ DUALITY = [
     ("G[0,{T}](X>={c})", "!F[0,{T}](X<{c})"),
     ("G[{a},{T}](X<={c})", "!F[{a},{T}](!(X<={c}))"),
     ("F[0,{T}](X>={c})", "true U[0,{T}] (X>={c})"),
+    # response and its dual, the identity the GPU monitor compiler relies on
+    ("F[{a},{T}]((X>={c}) & G[0,1](X<=5))", "!G[{a},{T}](!(X>={c}) | F[0,1](!(X<=5)))"),
 ]
 
 
@@ -107,6 +109,54 @@ def test_duality_on_random_traces(lhs, rhs):
             for nxt in (None, tm[m + 1] if m + 1 < len(tm) else nt):
                 assert oracle.eval_prefix(fa, st[: m + 1], tm[: m + 1], nxt) == \
                     oracle.eval_prefix(fb, st[: m + 1], tm[: m + 1], nxt)
+
+
+def _response_on_path(st, tm, lo, hi, d, p, q):
+    """G[lo,hi](p | F[0,d] q) on a complete path whose last state is
+    absorbing, straight from the definition: every position entered in
+    [lo, hi] satisfies p, or some position at or after it, entered at most d
+    later, satisfies q."""
+    n = len(st)
+    for i in range(n):
+        if lo <= tm[i] <= hi and not p(st[i]):
+            if not any(q(st[j]) and tm[j] - tm[i] <= d for j in range(i, n)):
+                return 0
+    return 1
+
+
+def _persistence_on_path(st, tm, lo, hi, d, p, q):
+    """F[lo,hi](p & G[0,d] q) on a complete path, from the definition: some
+    position entered in [lo, hi] satisfies p, and q holds at it and at every
+    later position entered at most d after it."""
+    n = len(st)
+    for i in range(n):
+        if lo <= tm[i] <= hi and p(st[i]):
+            if all(q(st[j]) for j in range(i, n) if tm[j] - tm[i] <= d):
+                return 1
+    return 0
+
+
+def test_response_forms_on_complete_paths():
+    """The oracle's nested evaluation of G I (p | F[0,d] q) and F I (p & G[0,d] q)
+    against the definitions above, on random absorbing paths; both values
+    occur often."""
+    rng = np.random.default_rng(5)
+    seen = {0: 0, 1: 0}
+    for _ in range(300):
+        st, tm, _ = _random_walk_trace(rng, 14)
+        lo = float(rng.choice([0.0, rng.uniform(0, 2)]))
+        hi = lo + float(rng.uniform(0.5, 6))
+        d = float(rng.uniform(0.2, 2.5))
+        c1, c2 = int(rng.integers(1, 6)), int(rng.integers(1, 6))
+        fr = bltlc.parse(f"G[{lo!r},{hi!r}](X<={c1} | F[0,{d!r}](X>={c2}))", ["X"])
+        fp = bltlc.parse(f"F[{lo!r},{hi!r}]((X>={c1}) & G[0,{d!r}](X<={c2}))", ["X"])
+        vr = oracle.eval_prefix(fr, st, tm, math.inf)
+        vp = oracle.eval_prefix(fp, st, tm, math.inf)
+        assert vr == _response_on_path(st, tm, lo, hi, d, lambda x: x[0] <= c1, lambda x: x[0] >= c2)
+        assert vp == _persistence_on_path(st, tm, lo, hi, d, lambda x: x[0] >= c1, lambda x: x[0] <= c2)
+        seen[vr] += 1
+        seen[vp] += 1
+    assert min(seen.values()) > 100, seen
 
 
 def test_kleene_monotone_on_prefixes():
