@@ -156,10 +156,12 @@ void smc_net_destroy(smc_net *net);
  *   I   ::= [a,b] | <= b | (omitted: [0, inf))      op: < <= >= > = !=
  * Precedence: unary (!, X, F, G) > U (right associative) > & > |.
  * GPU monitor classes: top-level boolean combinations of
- *   state predicates; F I p; G I p; p U I q; X I p; and the nested until
- *   p U[0,a] (q U[0,b] r), where p, q, r are boolean combinations of
- *   predicates.  Other nestings give SMC_E_UNSUPPORTED; text that does not
- *   parse gives SMC_E_PARSE. */
+ *   state predicates; F I p; G I p; p U I q; X I p; the nested until
+ *   p U[0,a] (q U[0,b] r); the response G I (p | F[0,d] q) and its dual
+ *   F I (p & G[0,d] q) (either operand order, p optional), where p, q, r
+ *   are boolean combinations of predicates.  At most two nested-until and
+ *   response monitors per formula.  Other nestings give SMC_E_UNSUPPORTED;
+ *   text that does not parse gives SMC_E_PARSE. */
 int smc_formula_compile(smc_ctx *ctx, const smc_net *net, const char *text, smc_formula **out);
 /* Time span of the path the formula can depend on (+inf if unbounded). */
 double smc_formula_horizon(const smc_formula *f);

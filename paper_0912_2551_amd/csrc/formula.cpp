@@ -488,8 +488,11 @@ class Compiler {
         }
         case Node::FIN:
         case Node::GLOB: {
-            if (!is_state_formula(n->a.get()))
+            if (!is_state_formula(n->a.get())) {
+                const int r = response(n);
+                if (r >= 0) return push_top(0, -1, -1, r);
                 throw Unsupported("F/G over a temporal formula is outside the GPU monitor classes");
+            }
             const int a = new_atom();
             Atom &A = p_.atoms[a];
             A.kind = AK_UNTIL;
@@ -531,10 +534,7 @@ class Compiler {
             const bool inner_fin = r->kind == Node::FIN && is_state_formula(r->a.get());
             if (!(inner_until || inner_fin) || n->lo != 0.0 || r->lo != 0.0)
                 throw Unsupported("nested until needs the form p U[0,a] (q U[0,b] r)");
-            int slot = 0;
-            for (int k = 0; k < p_.n_atoms; ++k)
-                if (p_.atoms[k].kind == AK_NESTED) ++slot;
-            if (slot >= kMaxNested) throw Unsupported("more than two nested untils");
+            const int slot = time_slot();
             const int a = new_atom();
             Atom &A = p_.atoms[a];
             A.kind = AK_NESTED;
@@ -554,6 +554,53 @@ class Compiler {
         }
         default: throw Unsupported("formula outside the GPU monitor classes");
         }
+    }
+
+    // A free per-lane time register for a nested or response monitor.
+    int time_slot() const
+    {
+        int slot = 0;
+        for (int k = 0; k < p_.n_atoms; ++k)
+            if (p_.atoms[k].kind == AK_NESTED || p_.atoms[k].kind == AK_RESP) ++slot;
+        if (slot >= kMaxNested) throw Unsupported("more than two nested or response monitors");
+        return slot;
+    }
+
+    // G[lo,hi](s1 | F[0,d] s2), with either operand order and s1 optional, or
+    // its dual F[lo,hi](a & G[0,d] b) = !G[lo,hi](!a | F[0,d] !b).  Returns the
+    // monitor, or -1 when the formula has neither form.
+    int response(const Node *n)
+    {
+        const bool glob = n->kind == Node::GLOB;
+        const Node *body = n->a.get();
+        const Node::Kind inner = glob ? Node::FIN : Node::GLOB;
+        const Node::Kind join = glob ? Node::OR : Node::AND;
+        auto is_inner = [&](const Node *m) {
+            return m->kind == inner && m->lo == 0.0 && is_state_formula(m->a.get());
+        };
+        const Node *side = nullptr, *tmp = nullptr;
+        if (is_inner(body)) {
+            tmp = body;
+        } else if (body->kind == join) {
+            const Node *x = body->a.get(), *y = body->b.get();
+            if (is_state_formula(x) && is_inner(y)) side = x, tmp = y;
+            else if (is_state_formula(y) && is_inner(x)) side = y, tmp = x;
+        }
+        if (!tmp) return -1;
+        const int slot = time_slot();
+        const int a = new_atom();
+        Atom &A = p_.atoms[a];
+        A.kind = AK_RESP;
+        A.neg = glob ? 0 : 1;
+        A.slot = slot;
+        A.lo = n->lo;
+        A.hi = n->hi;
+        A.hi2 = tmp->hi;
+        // the G form's operands as they are, the F form's negated; a missing
+        // side is s1 = false (G form) or a = true (F form), false either way
+        A.p1 = side ? prop(side, !glob) : prop_const(false);
+        A.p2 = prop(tmp->a.get(), !glob);
+        return a;
     }
 
     // ---- state formulas: truth tables over contiguous predicates ----------
@@ -610,6 +657,7 @@ class Compiler {
     }
 
     int prop_true() { return finish_prop(0, 0, 1u); }
+    int prop_const(bool v) { return finish_prop(0, 0, v ? 1u : 0u); }
 
     int prop(const Node *n, bool negate)
     {

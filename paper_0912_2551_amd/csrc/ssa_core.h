@@ -553,6 +553,19 @@ __device__ __forceinline__ uint32_t mon_step(MP mp, MonState &ms, const C &X, ui
             if (A->neg) v = v ? 3u - v : 0u;
         } else if (kind == AK_NEXT) {
             v = (k == 1u) ? (prop_val(mp, A->p1, pm) ? 1u : 2u) : 0u;
+        } else if (kind == AK_RESP) {
+            // a p2-state meets every open obligation (each one's time limit was
+            // checked when time advanced to this state); a position of the
+            // window where p1 and p2 both fail opens one
+            const bool s0 = A->slot == 0;
+            double tp = s0 ? ms.ts0 : ms.ts1;
+            const bool opens = (t >= A->lo) && (t <= A->hi) && !prop_val(mp, A->p1, pm);
+            tp = (opens && tp < 0.0) ? t : tp;
+            tp = prop_val(mp, A->p2, pm) ? -1.0 : tp;
+            v = (tp < 0.0 && t > A->hi) ? 1u : 0u;
+            if (A->neg) v = v ? 3u - v : 0u;
+            if (s0) ms.ts0 = open ? tp : ms.ts0;
+            else ms.ts1 = open ? tp : ms.ts1;
         } else {   // nested until
             const bool s0 = A->slot == 0;
             const uint32_t okb = (ms.ok >> a) & 1u;
@@ -587,6 +600,13 @@ __device__ __forceinline__ uint32_t mon_advance(MP mp, MonState &ms, double tn, 
             v = (absorbing || tn > A->hi) ? (A->neg ? 1u : 2u) : 0u;
         } else if (kind == AK_NEXT) {
             v = (absorbing || !(tn >= A->lo && tn <= A->hi)) ? 2u : 0u;
+        } else if (kind == AK_RESP) {
+            // the oldest open obligation fails first; with none open, the
+            // window's positions are all seen once time passes hi
+            const double tp = A->slot == 0 ? ms.ts0 : ms.ts1;
+            v = tp >= 0.0 ? ((absorbing || tn - tp > A->hi2) ? 2u : 0u)
+                          : ((absorbing || tn > A->hi) ? 1u : 0u);
+            if (A->neg) v = v ? 3u - v : 0u;
         } else if (kind == AK_NESTED) {
             const bool s0 = A->slot == 0;
             double tsv = s0 ? ms.ts0 : ms.ts1;

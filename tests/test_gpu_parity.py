@@ -53,6 +53,15 @@ TRAJ_CASES = [
     ("absorb-G", death_only, "G[0,100](X>=0) & F[0,200](X<=0)", {}, 777),
     ("cap", W.immigration_death, W.C1_FORMULA, {"max_events": 500}, 2000),
     ("tmax", W.immigration_death, "F(X>=1000)", {"t_max": 5.0}, 2000),
+    # response monitors: G I (p | F[0,d] q) and F I (p & G[0,d] q)
+    ("resp", W.immigration_death, "G[10,40]((F[0,1](X<=90)) | X<=105)", {}, 2000),
+    ("resp-dual", W.immigration_death, "F[5,30]((X>=95) & G[0,2](X>=90))", {}, 2000),
+    ("resp-dual-bare", W.immigration_death, "F[0,30](G[0,3](X>=95))", {}, 2000),
+    ("resp-two", W.isomerization, "G[0,2](A>=30 | F[0,0.3](B<=20)) | F[0,3](G[0,0.5](A<=18))", {}, 3000),
+    ("resp-iso", W.isomerization, "F[0.5,3]((A>=25) & G[0,0.3](A>=22))", {}, 3000),
+    ("resp-dimer", W.dimerization, "G[0,5](A>=30 | F[0,1](B>=8))", {}, 3000),
+    ("resp-absorb", death_only, "G[0,100](X>=10 | F[0,2](X<=0))", {}, 777),
+    ("resp-tmax", W.immigration_death, "G[5,inf](X<=130 | F[0,1](X<=120))", {"t_max": 30.0}, 1000),
 ]
 
 
@@ -313,7 +322,10 @@ def test_errors_and_edges(ctx):
         ctx.formula(n, "F[0,1](Y>1)")
     assert e.value.code == B.SMC_E_PARSE
     with pytest.raises(B.SmcError) as e:
-        ctx.formula(n, "F[0,10](G[0,1](X>1))")
+        ctx.formula(n, "F[0,10](G[1,2](X>1))")
+    assert e.value.code == B.SMC_E_UNSUPPORTED
+    with pytest.raises(B.SmcError) as e:
+        ctx.formula(n, "G[0,1](F[0,1](X>1)) & G[0,1](F[0,1](X>2)) & G[0,1](F[0,1](X>3))")
     assert e.value.code == B.SMC_E_UNSUPPORTED
     with pytest.raises(B.SmcError) as e:
         ctx.formula(n, "F[0,1](pow(X,2)>1)")
