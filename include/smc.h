@@ -157,7 +157,8 @@ void smc_net_destroy(smc_net *net);
  * Precedence: unary (!, X, F, G) > U (right associative) > & > |.
  * GPU monitor classes: top-level boolean combinations of
  *   state predicates; F I p; G I p; p U I q; X I p; the nested until
- *   p U[0,a] (q U[0,b] r); the response G I (p | F[0,d] q) and its dual
+ *   p U I (q U[0,c] r), also with F[0,c] r inside and as F I (q U[0,c] r);
+ *   the response G I (p | F[0,d] q) and its dual
  *   F I (p & G[0,d] q) (either operand order, p optional), where p, q, r
  *   are boolean combinations of predicates.  At most two nested-until and
  *   response monitors per formula.  Other nestings give SMC_E_UNSUPPORTED;

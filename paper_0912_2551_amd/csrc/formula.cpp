@@ -489,7 +489,9 @@ class Compiler {
         case Node::FIN:
         case Node::GLOB: {
             if (!is_state_formula(n->a.get())) {
-                const int r = response(n);
+                int r = response(n);
+                // F I (q U[0,b] r) and F I F[0,b] r: the nested until with p = true
+                if (r < 0 && n->kind == Node::FIN) r = nested(nullptr, n);
                 if (r >= 0) return push_top(0, -1, -1, r);
                 throw Unsupported("F/G over a temporal formula is outside the GPU monitor classes");
             }
@@ -528,32 +530,41 @@ class Compiler {
                 A.p2 = prop(r, false);
                 return push_top(0, -1, -1, a);
             }
-            // p U[0,a] (q U[0,b] r)  or  p U[0,a] F[0,b] r
-            const bool inner_until = r->kind == Node::UNTIL && is_state_formula(r->a.get()) &&
-                                     is_state_formula(r->b.get());
-            const bool inner_fin = r->kind == Node::FIN && is_state_formula(r->a.get());
-            if (!(inner_until || inner_fin) || n->lo != 0.0 || r->lo != 0.0)
-                throw Unsupported("nested until needs the form p U[0,a] (q U[0,b] r)");
-            const int slot = time_slot();
-            const int a = new_atom();
-            Atom &A = p_.atoms[a];
-            A.kind = AK_NESTED;
-            A.slot = slot;
-            A.lo = 0.0;
-            A.hi = n->hi;
-            A.hi2 = r->hi;
-            A.p1 = prop(l, false);
-            if (inner_until) {
-                A.p2 = prop(r->a.get(), false);
-                A.p3 = prop(r->b.get(), false);
-            } else {
-                A.p2 = prop_true();
-                A.p3 = prop(r->a.get(), false);
-            }
+            const int a = nested(l, n);
+            if (a < 0) throw Unsupported("nested until needs the form p U[a,b] (q U[0,c] r)");
             return push_top(0, -1, -1, a);
         }
         default: throw Unsupported("formula outside the GPU monitor classes");
         }
+    }
+
+    // p U[a,b] (q U[0,c] r) or p U[a,b] F[0,c] r, where n is the outer until
+    // (or the outer F, with l = nullptr standing for p = true).  Returns the
+    // monitor, or -1 when the inner formula has neither form.
+    int nested(const Node *l, const Node *n)
+    {
+        const Node *r = l ? n->b.get() : n->a.get();
+        const bool inner_until = r->kind == Node::UNTIL && is_state_formula(r->a.get()) &&
+                                 is_state_formula(r->b.get());
+        const bool inner_fin = r->kind == Node::FIN && is_state_formula(r->a.get());
+        if (!(inner_until || inner_fin) || r->lo != 0.0) return -1;
+        const int slot = time_slot();
+        const int a = new_atom();
+        Atom &A = p_.atoms[a];
+        A.kind = AK_NESTED;
+        A.slot = slot;
+        A.lo = n->lo;
+        A.hi = n->hi;
+        A.hi2 = r->hi;
+        A.p1 = l ? prop(l, false) : prop_true();
+        if (inner_until) {
+            A.p2 = prop(r->a.get(), false);
+            A.p3 = prop(r->b.get(), false);
+        } else {
+            A.p2 = prop_true();
+            A.p3 = prop(r->a.get(), false);
+        }
+        return a;
     }
 
     // A free per-lane time register for a nested or response monitor.

@@ -72,7 +72,7 @@ struct Prop {
 //  AK_PROP   : state formula p1 on the initial state.
 //  AK_UNTIL  : p1 U[lo,hi] p2, negated when neg = 1 (G I p = not(tt U I not p)).
 //  AK_NEXT   : X[lo,hi] p1.
-//  AK_NESTED : p1 U[0,hi] (p2 U[0,hi2] p3), registers (ok, latest start).
+//  AK_NESTED : p1 U[lo,hi] (p2 U[0,hi2] p3), registers (ok, latest start).
 //  AK_RESP   : G[lo,hi](p1 | F[0,hi2] p2), negated when neg = 1; register: the
 //              entry time of the oldest position whose obligation F[0,hi2] p2
 //              is still open (-1: none).  Later open positions need not be

@@ -570,11 +570,13 @@ __device__ __forceinline__ uint32_t mon_step(MP mp, MonState &ms, const C &X, ui
             const bool s0 = A->slot == 0;
             const uint32_t okb = (ms.ok >> a) & 1u;
             double tsv = s0 ? ms.ts0 : ms.ts1;
-            tsv = (okb && t <= A->hi) ? t : tsv;                   // new admissible start
+            tsv = (okb && t >= A->lo && t <= A->hi) ? t : tsv;     // new admissible start
             const bool hit = tsv >= 0.0 && prop_val(mp, A->p3, pm);
             tsv = (!hit && !prop_val(mp, A->p2, pm)) ? -1.0 : tsv; // inner left operand broken
             const uint32_t ok2 = okb & (prop_val(mp, A->p1, pm) ? 1u : 0u);
-            v = hit ? 1u : ((tsv < 0.0 && !ok2) ? 2u : 0u);
+            // with no start pending, false once p has failed or the state
+            // lies past the outer window (no later start is admissible)
+            v = hit ? 1u : ((tsv < 0.0 && (!ok2 || t > A->hi)) ? 2u : 0u);
             if (open && !hit) ms.ok = (ms.ok & ~(1u << a)) | (ok2 << a);
             if (s0) ms.ts0 = open ? tsv : ms.ts0;
             else ms.ts1 = open ? tsv : ms.ts1;

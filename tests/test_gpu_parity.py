@@ -43,6 +43,9 @@ TRAJ_CASES = [
     ("next-or", W.isomerization, "X[0,0.05](B>=1) | F[1,2](A<=15)", {}, 3000),
     ("nested", W.immigration_death, "(X<=60) U[0,20] ((X>=20) U[0,3] (X>=70))", {}, 3000),
     ("nested-fin", W.immigration_death, "(X<=80) U[0,30] F[0,4](X>=75)", {}, 2000),
+    ("nested-lo", W.isomerization, "(A<=60) U[1.5,2] ((A>=16) U[0,0.5] (A>=22))", {}, 3000),
+    ("nested-F", W.isomerization, "F[1.5,2.5]((A>=15) U[0,0.4] (A>=20))", {}, 3000),
+    ("nested-fin-lo", W.immigration_death, "(X<=95) U[10,30] F[0,2](X>=92)", {}, 2000),
     ("lower-bounds", W.immigration_death, "F[5,10](X>=60) & G[2,8](X<=90)", {}, 3000),
     ("not-or", W.immigration_death, "!(F[0,3](X>=25) | G[0,2](X<=18))", {}, 3000),
     ("arith", W.isomerization, "F[0,2](A*A <= sqrt(B*400) + 3)", {}, 3000),
