@@ -39,9 +39,28 @@ __device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float(
 // operands; the 16 results of lane l are rows 8 (r / 4) + 4 (l / 32) + r % 4
 // of column l % 32.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void gemm_bf16(const uint16_t *A, long sam, long sak,
-                                                 const uint16_t *B, long sbk, long sbn, float *C,
-                                                 long ldc, int M, int N, int K, int accumulate)
+// An operand whose k-slices are contiguous (unit stride along k, 16-byte
+// aligned rows) is read as one 16-byte load per lane; otherwise as eight
+// 2-byte loads, which are coalesced across the 32 lanes of a half-wave when
+// the other stride is 1.
+template <bool kContig>
+__device__ __forceinline__ bf16x8 load_slice(const uint16_t *p, long sk)
+{
+    bf16x8 v;
+    if constexpr (kContig) {
+        const uint4 w = *reinterpret_cast<const uint4 *>(p);
+        v = __builtin_bit_cast(bf16x8, w);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = __builtin_bit_cast(__bf16, p[(long)e * sk]);
+    }
+    return v;
+}
+
+template <bool kAc, bool kBc>
+__global__ __launch_bounds__(256) void gemm_bf16(const uint16_t *A, long sam, long sak, const uint16_t *B,
+                                                 long sbk, long sbn, float *C, long ldc, int M, int N, int K,
+                                                 int accumulate)
 {
     const int lane = (int)(threadIdx.x & 63);
     const int wave = (int)(blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
@@ -49,18 +68,24 @@ __global__ __launch_bounds__(256) void gemm_bf16(const uint16_t *A, long sam, lo
     const int tm = wave / tiles_n, tn = wave % tiles_n;
     if (tm >= M / 32) return;
     const int rc = lane & 31, half = lane >> 5;
-    const long arow = (long)(tm * 32 + rc) * sam;
-    const long bcol = (long)(tn * 32 + rc) * sbn;
+    const uint16_t *pa = A + (long)(tm * 32 + rc) * sam + (long)(8 * half) * sak;
+    const uint16_t *pb = B + (long)(tn * 32 + rc) * sbn + (long)(8 * half) * sbk;
     floatx16 acc = {};
-    for (int kb = 0; kb < K; kb += 16) {
-        bf16x8 a, b;
-        const int k0 = kb + 8 * half;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            a[e] = __builtin_bit_cast(__bf16, A[arow + (long)(k0 + e) * sak]);
-            b[e] = __builtin_bit_cast(__bf16, B[(long)(k0 + e) * sbk + bcol]);
-        }
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    // two 16-wide steps per trip, loads first, so both steps' loads are in
+    // flight together; the MFMAs still run in ascending k
+    int kb = 0;
+    for (; kb + 32 <= K; kb += 32) {
+        const bf16x8 a0 = load_slice<kAc>(pa + (long)kb * sak, sak);
+        const bf16x8 b0 = load_slice<kBc>(pb + (long)kb * sbk, sbk);
+        const bf16x8 a1 = load_slice<kAc>(pa + (long)(kb + 16) * sak, sak);
+        const bf16x8 b1 = load_slice<kBc>(pb + (long)(kb + 16) * sbk, sbk);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc, 0, 0, 0);
+    }
+    if (kb < K) {
+        const bf16x8 a0 = load_slice<kAc>(pa + (long)kb * sak, sak);
+        const bf16x8 b0 = load_slice<kBc>(pb + (long)kb * sbk, sbk);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc, 0, 0, 0);
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -473,8 +498,25 @@ hipError_t sg_gemm(hipStream_t s, const uint16_t *A, long sam, long sak, const u
                    long sbn, float *C, long ldc, int M, int N, int K, int accumulate)
 {
     const long waves = (long)(M / 32) * (N / 32);
-    hipLaunchKernelGGL(gemm_bf16, dim3(blocks_for(waves, 4)), dim3(256), 0, s, A, sam, sak, B, sbk, sbn,
-                       C, ldc, M, N, K, accumulate);
+    // unit stride along k, and every lane's first element 16-byte aligned
+    // (k offsets are multiples of 8 elements)
+    auto contig = [](const uint16_t *p, long sk, long so) {
+        return sk == 1 && so % 8 == 0 && (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
+    };
+    const bool ac = contig(A, sak, sam), bc = contig(B, sbk, sbn);
+    const dim3 grid(blocks_for(waves, 4)), block(256);
+    if (ac && bc)
+        hipLaunchKernelGGL((gemm_bf16<true, true>), grid, block, 0, s, A, sam, sak, B, sbk, sbn, C, ldc, M, N,
+                           K, accumulate);
+    else if (ac)
+        hipLaunchKernelGGL((gemm_bf16<true, false>), grid, block, 0, s, A, sam, sak, B, sbk, sbn, C, ldc, M,
+                           N, K, accumulate);
+    else if (bc)
+        hipLaunchKernelGGL((gemm_bf16<false, true>), grid, block, 0, s, A, sam, sak, B, sbk, sbn, C, ldc, M,
+                           N, K, accumulate);
+    else
+        hipLaunchKernelGGL((gemm_bf16<false, false>), grid, block, 0, s, A, sam, sak, B, sbk, sbn, C, ldc, M,
+                           N, K, accumulate);
     return hipGetLastError();
 }
 
