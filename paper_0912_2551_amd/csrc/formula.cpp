@@ -506,8 +506,11 @@ class Compiler {
             return push_top(0, -1, -1, a);
         }
         case Node::NEXT: {
-            if (!is_state_formula(n->a.get()))
+            if (!is_state_formula(n->a.get())) {
+                const int r = next_until(n);
+                if (r >= 0) return push_top(0, -1, -1, r);
                 throw Unsupported("X over a temporal formula is outside the GPU monitor classes");
+            }
             const int a = new_atom();
             Atom &A = p_.atoms[a];
             A.kind = AK_NEXT;
@@ -567,13 +570,44 @@ class Compiler {
         return a;
     }
 
-    // A free per-lane time register for a nested or response monitor.
+    // X I (p U J q), X I F J q and X I G J q, where n is the X node; -1 for
+    // any other operand.
+    int next_until(const Node *n)
+    {
+        const Node *u = n->a.get();
+        const bool until = u->kind == Node::UNTIL && is_state_formula(u->a.get()) &&
+                           is_state_formula(u->b.get());
+        const bool fin_glob = (u->kind == Node::FIN || u->kind == Node::GLOB) && is_state_formula(u->a.get());
+        if (!until && !fin_glob) return -1;
+        const int slot = time_slot();
+        const int a = new_atom();
+        Atom &A = p_.atoms[a];
+        A.kind = AK_NEXTU;
+        A.slot = slot;
+        A.lo = n->lo;
+        A.hi = n->hi;
+        A.lo2 = u->lo;
+        A.hi2 = u->hi;
+        A.neg = u->kind == Node::GLOB ? 1 : 0;
+        if (until) {
+            A.p1 = prop(u->a.get(), false);
+            A.p2 = prop(u->b.get(), false);
+        } else {
+            A.p1 = prop_true();
+            A.p2 = prop(u->a.get(), u->kind == Node::GLOB);
+        }
+        return a;
+    }
+
+    // A free per-lane time register for a nested, response or next-until
+    // monitor.
     int time_slot() const
     {
         int slot = 0;
         for (int k = 0; k < p_.n_atoms; ++k)
-            if (p_.atoms[k].kind == AK_NESTED || p_.atoms[k].kind == AK_RESP) ++slot;
-        if (slot >= kMaxNested) throw Unsupported("more than two nested or response monitors");
+            if (p_.atoms[k].kind == AK_NESTED || p_.atoms[k].kind == AK_RESP || p_.atoms[k].kind == AK_NEXTU)
+                ++slot;
+        if (slot >= kMaxNested) throw Unsupported("more than two nested, response or next-until monitors");
         return slot;
     }
 

@@ -131,6 +131,7 @@ std::string spec_source(int S, int M, const int32_t *reac, const uint32_t *chg, 
         s += p + "lo = " + fmt_double(A.lo) + ";\n";
         s += p + "hi = " + fmt_double(A.hi) + ";\n";
         s += p + "hi2 = " + fmt_double(A.hi2) + ";\n";
+        s += p + "lo2 = " + fmt_double(A.lo2) + ";\n";
     }
     for (int q = 0; q < mp.n_props; ++q) {
         const Prop &P = mp.props[q];

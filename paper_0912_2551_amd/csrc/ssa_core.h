@@ -553,6 +553,21 @@ __device__ __forceinline__ uint32_t mon_step(MP mp, MonState &ms, const C &X, ui
             if (A->neg) v = v ? 3u - v : 0u;
         } else if (kind == AK_NEXT) {
             v = (k == 1u) ? (prop_val(mp, A->p1, pm) ? 1u : 2u) : 0u;
+        } else if (kind == AK_NEXTU) {
+            // from state 1 on: the until at position 1, its window measured
+            // from state 1's entry time (the X window was checked when time
+            // advanced to state 1)
+            const bool s0 = A->slot == 0;
+            double t1 = s0 ? ms.ts0 : ms.ts1;
+            t1 = (k >= 1u && t1 < 0.0) ? t : t1;
+            const double rel = t - t1;
+            const bool hit = (rel >= A->lo2) && (rel <= A->hi2) && prop_val(mp, A->p2, pm);
+            const bool broken = !prop_val(mp, A->p1, pm);
+            v = hit ? 1u : (broken ? 2u : 0u);
+            if (A->neg) v = v ? 3u - v : 0u;
+            v = k >= 1u ? v : 0u;
+            if (s0) ms.ts0 = open ? t1 : ms.ts0;
+            else ms.ts1 = open ? t1 : ms.ts1;
         } else if (kind == AK_RESP) {
             // a p2-state meets every open obligation (each one's time limit was
             // checked when time advanced to this state); a position of the
@@ -602,6 +617,15 @@ __device__ __forceinline__ uint32_t mon_advance(MP mp, MonState &ms, double tn, 
             v = (absorbing || tn > A->hi) ? (A->neg ? 1u : 2u) : 0u;
         } else if (kind == AK_NEXT) {
             v = (absorbing || !(tn >= A->lo && tn <= A->hi)) ? 2u : 0u;
+        } else if (kind == AK_NEXTU) {
+            // before state 1: the X window; after: the until's window
+            const double t1 = A->slot == 0 ? ms.ts0 : ms.ts1;
+            if (t1 < 0.0) {
+                v = (absorbing || !(tn >= A->lo && tn <= A->hi)) ? 2u : 0u;
+            } else {
+                v = (absorbing || tn - t1 > A->hi2) ? 2u : 0u;
+                if (A->neg) v = v ? 3u - v : 0u;
+            }
         } else if (kind == AK_RESP) {
             // the oldest open obligation fails first; with none open, the
             // window's positions are all seen once time passes hi

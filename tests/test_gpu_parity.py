@@ -46,6 +46,10 @@ TRAJ_CASES = [
     ("nested-lo", W.isomerization, "(A<=60) U[1.5,2] ((A>=16) U[0,0.5] (A>=22))", {}, 3000),
     ("nested-F", W.isomerization, "F[1.5,2.5]((A>=15) U[0,0.4] (A>=20))", {}, 3000),
     ("nested-fin-lo", W.immigration_death, "(X<=95) U[10,30] F[0,2](X>=92)", {}, 2000),
+    ("next-until", W.isomerization, "X[0,0.05]((A>=38) U[0,0.25] (B>=12))", {}, 3000),
+    ("next-G", W.isomerization, "X[0,0.05](G[0,0.8](A>=30))", {}, 3000),
+    ("next-F-lo", W.immigration_death, "X[0,0.15](F[2,4](X>=40))", {}, 2000),
+    ("next-two", W.dimerization, "X[0,0.5](G[0,3](A>=20)) | X[0,0.2](F[0,1](B>=5))", {}, 3000),
     ("lower-bounds", W.immigration_death, "F[5,10](X>=60) & G[2,8](X<=90)", {}, 3000),
     ("not-or", W.immigration_death, "!(F[0,3](X>=25) | G[0,2](X<=18))", {}, 3000),
     ("arith", W.isomerization, "F[0,2](A*A <= sqrt(B*400) + 3)", {}, 3000),
@@ -329,6 +333,9 @@ def test_errors_and_edges(ctx):
     assert e.value.code == B.SMC_E_UNSUPPORTED
     with pytest.raises(B.SmcError) as e:
         ctx.formula(n, "G[0,1](F[0,1](X>1)) & G[0,1](F[0,1](X>2)) & G[0,1](F[0,1](X>3))")
+    assert e.value.code == B.SMC_E_UNSUPPORTED
+    with pytest.raises(B.SmcError) as e:
+        ctx.formula(n, "X[0,1](X[0,1](X>1))")
     assert e.value.code == B.SMC_E_UNSUPPORTED
     with pytest.raises(B.SmcError) as e:
         ctx.formula(n, "F[0,1](pow(X,2)>1)")
