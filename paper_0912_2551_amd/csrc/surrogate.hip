@@ -148,12 +148,14 @@ __global__ void layer3_forward_loss(const uint16_t *h2b, int n, const uint16_t *
 }
 
 // Batch reductions (column sums over the n rows of a [n][256] activation):
-// a block of 64 columns x 16 row slices; thread (c, q) accumulates rows q,
-// q + 16, q + 32, ... of column c in order (a wave reads 64 consecutive
-// columns of one row), then the 16 slice sums are added in slice order, so
-// the result does not depend on scheduling.
-constexpr int kColBlock = 64;
-constexpr int kSlices = 16;
+// a block of 16 columns x 64 row slices; thread (c, q) accumulates rows q,
+// q + 64, q + 128, ... of column c in order (a wave reads 16 consecutive
+// columns of 4 rows, 64 bytes each), then the 64 slice sums are added in
+// slice order, so the result does not depend on scheduling.  16 blocks for
+// the 256 columns keep the rows per thread short: with n = 512 the reduction
+// is latency bound, not bandwidth bound.
+constexpr int kColBlock = 16;
+constexpr int kSlices = 64;
 
 // dW3[j] = sum_b dz_b h2b[b][j], db3 = sum_b dz_b; d2 = dz W3b relu'(pre2)
 // stored as d2b = bf16(d2) (the operand of both layer-2 backward products);
