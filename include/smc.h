@@ -158,11 +158,12 @@ void smc_net_destroy(smc_net *net);
  * GPU monitor classes: top-level boolean combinations of
  *   state predicates; F I p; G I p; p U I q; X I p; the nested until
  *   p U I (q U[0,c] r), also with F[0,c] r inside and as F I (q U[0,c] r);
+ *   p U I (r & G[0,c] q), r optional;
  *   X I (p U J q), X I F J q and X I G J q;
  *   the response G I (p | F[0,d] q) and its dual
  *   F I (p & G[0,d] q) (either operand order, p optional), where p, q, r
- *   are boolean combinations of predicates.  At most two nested-until,
- *   next-until and response monitors per formula.  Other nestings give SMC_E_UNSUPPORTED;
+ *   are boolean combinations of predicates.  At most two of the nested,
+ *   next-until, until-G and response monitors per formula.  Other nestings give SMC_E_UNSUPPORTED;
  *   text that does not parse gives SMC_E_PARSE. */
 int smc_formula_compile(smc_ctx *ctx, const smc_net *net, const char *text, smc_formula **out);
 /* Time span of the path the formula can depend on (+inf if unbounded). */

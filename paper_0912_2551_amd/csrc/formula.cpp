@@ -533,8 +533,10 @@ class Compiler {
                 A.p2 = prop(r, false);
                 return push_top(0, -1, -1, a);
             }
-            const int a = nested(l, n);
-            if (a < 0) throw Unsupported("nested until needs the form p U[a,b] (q U[0,c] r)");
+            int a = nested(l, n);
+            if (a < 0) a = until_glob(l, n);
+            if (a < 0)
+                throw Unsupported("nested until needs the form p U[a,b] (q U[0,c] r) or p U[a,b] (r & G[0,c] q)");
             return push_top(0, -1, -1, a);
         }
         default: throw Unsupported("formula outside the GPU monitor classes");
@@ -570,6 +572,37 @@ class Compiler {
         return a;
     }
 
+    // p U[a,b] (r & G[0,c] q), either conjunct order, r optional, where n is
+    // the until and l its left operand; -1 for any other right operand.
+    int until_glob(const Node *l, const Node *n)
+    {
+        const Node *r = n->b.get();
+        auto is_g = [&](const Node *m) {
+            return m->kind == Node::GLOB && m->lo == 0.0 && is_state_formula(m->a.get());
+        };
+        const Node *g = nullptr, *side = nullptr;
+        if (is_g(r)) {
+            g = r;
+        } else if (r->kind == Node::AND) {
+            const Node *x = r->a.get(), *y = r->b.get();
+            if (is_state_formula(x) && is_g(y)) side = x, g = y;
+            else if (is_state_formula(y) && is_g(x)) side = y, g = x;
+        }
+        if (!g) return -1;
+        const int slot = time_slot();
+        const int a = new_atom();
+        Atom &A = p_.atoms[a];
+        A.kind = AK_UNTILG;
+        A.slot = slot;
+        A.lo = n->lo;
+        A.hi = n->hi;
+        A.hi2 = g->hi;
+        A.p1 = prop(l, false);
+        A.p2 = prop(g->a.get(), false);
+        A.p3 = side ? prop(side, false) : prop_true();
+        return a;
+    }
+
     // X I (p U J q), X I F J q and X I G J q, where n is the X node; -1 for
     // any other operand.
     int next_until(const Node *n)
@@ -599,15 +632,16 @@ class Compiler {
         return a;
     }
 
-    // A free per-lane time register for a nested, response or next-until
-    // monitor.
+    // A free per-lane time register for a nested, response, next-until or
+    // until-G monitor.
     int time_slot() const
     {
         int slot = 0;
         for (int k = 0; k < p_.n_atoms; ++k)
-            if (p_.atoms[k].kind == AK_NESTED || p_.atoms[k].kind == AK_RESP || p_.atoms[k].kind == AK_NEXTU)
+            if (p_.atoms[k].kind == AK_NESTED || p_.atoms[k].kind == AK_RESP || p_.atoms[k].kind == AK_NEXTU ||
+                p_.atoms[k].kind == AK_UNTILG)
                 ++slot;
-        if (slot >= kMaxNested) throw Unsupported("more than two nested, response or next-until monitors");
+        if (slot >= kMaxNested) throw Unsupported("more than two monitors with a time register");
         return slot;
     }
 

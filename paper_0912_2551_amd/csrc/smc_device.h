@@ -27,7 +27,7 @@ constexpr int kMaxPreds = 16;      // state predicates per formula
 constexpr int kMaxAtoms = 4;       // temporal monitors per formula
 constexpr int kMaxProps = 12;      // state formulas (operands of the monitors)
 constexpr int kMaxPropPreds = 5;   // predicates per state formula (truth table of 32 bits)
-constexpr int kMaxNested = 2;      // nested-until, response and next-until monitors per formula
+constexpr int kMaxNested = 2;      // monitors with a time register (nested, response, next-until, until-G)
 constexpr int kMaxValOps = 96;     // arithmetic predicate programs
 constexpr int kValStack = 4;       // arithmetic stack depth on the device
 constexpr int kBlocks = 16;        // prefix-sum blocks for reaction selection
@@ -40,7 +40,7 @@ constexpr int kSpecWideMaxM = 512; //   and channels
 enum CmpOp : int32_t { CMP_LT = 0, CMP_LE, CMP_GE, CMP_GT, CMP_EQ, CMP_NE };
 enum ValOp : int32_t { VO_VAR = 0, VO_CONST, VO_ADD, VO_SUB, VO_MUL, VO_DIV, VO_NEG, VO_SQRT };
 enum PredKind : int32_t { PK_VAR = 0, PK_LINEAR = 1, PK_RPN = 2 };
-enum AtomKind : int32_t { AK_PROP = 0, AK_UNTIL, AK_NEXT, AK_NESTED, AK_RESP, AK_NEXTU };
+enum AtomKind : int32_t { AK_PROP = 0, AK_UNTIL, AK_NEXT, AK_NESTED, AK_RESP, AK_NEXTU, AK_UNTILG };
 enum Reason : int32_t { RS_STATE = 0, RS_TIME = 1, RS_ABSORB = 2, RS_CAP = 3, RS_TMAX = 4 };
 
 // A state predicate over species counts x.
@@ -80,6 +80,10 @@ struct Prop {
 //  AK_NEXTU  : X[lo,hi](p1 U[lo2,hi2] p2), the until negated when neg = 1
 //              (X I G J p = X I not(tt U J not p)); register: the entry time
 //              of state 1 (-1 before it), the origin of the until's window.
+//  AK_UNTILG : p1 U[lo,hi] (p3 & G[0,hi2] p2); registers (ok, the entry time
+//              of the earliest start whose G still runs, -1: none).  A break
+//              of p2 ends every running start, and the earliest one's window
+//              closes first, so later starts need not be kept.
 struct Atom {
     int32_t kind;
     int32_t neg;

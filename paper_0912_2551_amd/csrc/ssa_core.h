@@ -553,6 +553,22 @@ __device__ __forceinline__ uint32_t mon_step(MP mp, MonState &ms, const C &X, ui
             if (A->neg) v = v ? 3u - v : 0u;
         } else if (kind == AK_NEXT) {
             v = (k == 1u) ? (prop_val(mp, A->p1, pm) ? 1u : 2u) : 0u;
+        } else if (kind == AK_UNTILG) {
+            // a p2-break ends the running start; an admissible state (p1 at
+            // every earlier one, inside [lo, hi]) with p2 and p3 starts one
+            // when none runs; false once none runs and no start can follow
+            const bool s0 = A->slot == 0;
+            double tc = s0 ? ms.ts0 : ms.ts1;
+            const bool q = prop_val(mp, A->p2, pm);
+            const uint32_t okb = (ms.ok >> a) & 1u;
+            tc = q ? tc : -1.0;
+            const bool start = tc < 0.0 && okb && (t >= A->lo) && (t <= A->hi) && q && prop_val(mp, A->p3, pm);
+            tc = start ? t : tc;
+            const uint32_t ok2 = okb & (prop_val(mp, A->p1, pm) ? 1u : 0u);
+            v = (tc < 0.0 && (!ok2 || t > A->hi)) ? 2u : 0u;
+            if (open) ms.ok = (ms.ok & ~(1u << a)) | (ok2 << a);
+            if (s0) ms.ts0 = open ? tc : ms.ts0;
+            else ms.ts1 = open ? tc : ms.ts1;
         } else if (kind == AK_NEXTU) {
             // from state 1 on: the until at position 1, its window measured
             // from state 1's entry time (the X window was checked when time
@@ -617,6 +633,13 @@ __device__ __forceinline__ uint32_t mon_advance(MP mp, MonState &ms, double tn, 
             v = (absorbing || tn > A->hi) ? (A->neg ? 1u : 2u) : 0u;
         } else if (kind == AK_NEXT) {
             v = (absorbing || !(tn >= A->lo && tn <= A->hi)) ? 2u : 0u;
+        } else if (kind == AK_UNTILG) {
+            // the running start holds once its G window is over (or on
+            // absorption); with none running, no start may be left
+            const double tc = A->slot == 0 ? ms.ts0 : ms.ts1;
+            const uint32_t okb = (ms.ok >> a) & 1u;
+            v = tc >= 0.0 ? ((absorbing || tn - tc > A->hi2) ? 1u : 0u)
+                          : ((!okb || absorbing || tn > A->hi) ? 2u : 0u);
         } else if (kind == AK_NEXTU) {
             // before state 1: the X window; after: the until's window
             const double t1 = A->slot == 0 ? ms.ts0 : ms.ts1;

@@ -50,6 +50,10 @@ TRAJ_CASES = [
     ("next-G", W.isomerization, "X[0,0.05](G[0,0.8](A>=30))", {}, 3000),
     ("next-F-lo", W.immigration_death, "X[0,0.15](F[2,4](X>=40))", {}, 2000),
     ("next-two", W.dimerization, "X[0,0.5](G[0,3](A>=20)) | X[0,0.2](F[0,1](B>=5))", {}, 3000),
+    ("until-G", W.isomerization, "(A>=15) U[0.5,3] G[0,0.5](A<=20)", {}, 3000),
+    ("until-and-G", W.isomerization, "(B<=40) U[0,2] ((A<=25) & G[0,0.3](A>=20))", {}, 3000),
+    ("until-G-and", W.immigration_death, "(X<=120) U[5,40] (G[0,3](X>=95) & X>=96)", {}, 2000),
+    ("until-G-absorb", death_only, "(X>=0) U[0,100] G[0,5](X<=3)", {}, 777),
     ("lower-bounds", W.immigration_death, "F[5,10](X>=60) & G[2,8](X<=90)", {}, 3000),
     ("not-or", W.immigration_death, "!(F[0,3](X>=25) | G[0,2](X<=18))", {}, 3000),
     ("arith", W.isomerization, "F[0,2](A*A <= sqrt(B*400) + 3)", {}, 3000),
