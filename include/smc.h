@@ -130,8 +130,11 @@ int smc_device_cus(const smc_ctx *ctx);
  * reactant combinations: 1, x_a, x_a x_b, or x_a (x_a - 1) / 2.
  * Errors (SMC_E_INVALID): S < 1, M < 1, a negative count or rate, a species
  * index out of range, or a change that consumes more of a species than the
- * reaction's reactants hold (counts could go negative).  names (S strings, or
- * NULL for X0, X1, ...) are the species names used by formulas. */
+ * reaction's reactants hold (counts could go negative), S > 16384.  names (S
+ * strings, or NULL for X0, X1, ...) are the species names used by formulas.
+ * Runs (estimates, trajectories, state samples) need S <= 255: a wave keeps
+ * the counts of its 64 trajectories, plus one constant row, in 64 KiB of
+ * LDS; larger networks give SMC_E_INVALID there. */
 typedef struct {
     int32_t n_species;
     int32_t n_reactions;
@@ -200,7 +203,7 @@ typedef struct {
 /* One model: estimate P(formula) to the requested interval.  The trajectory
  * indices used are 0..n-1.  Errors: SMC_E_INVALID (eps <= 0, confidence
  * outside (0,1), unbounded formula with neither t_max nor max_events, sample
- * size above 2^32), SMC_E_UNSUPPORTED, SMC_E_HIP, SMC_E_TIMEOUT,
+ * size above 2^32, more than 255 species), SMC_E_UNSUPPORTED, SMC_E_HIP, SMC_E_TIMEOUT,
  * SMC_E_CANCELLED. */
 int smc_estimate(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_params *p,
                  smc_result *out);
