@@ -95,6 +95,55 @@ __global__ __launch_bounds__(256) void gemm_bf16(const uint16_t *A, long sam, lo
     }
 }
 
+// The same product with k split over the four waves of a block, one 32 x 32
+// tile per block: wave w runs the MFMA chain over k in [w K/4, (w+1) K/4),
+// then the four partial tiles are added in wave order through LDS, so the
+// result is repeatable.  For the small products of training (64-128 tiles)
+// this gives four times the waves and a quarter of the dependent k-steps per
+// wave.  K must be a multiple of 64; the grid is exactly one block per tile.
+template <bool kAc, bool kBc>
+__global__ __launch_bounds__(256) void gemm_bf16_splitk(const uint16_t *A, long sam, long sak, const uint16_t *B,
+                                                        long sbk, long sbn, float *C, long ldc, int M, int N,
+                                                        int K, int accumulate)
+{
+    __shared__ float part[4][16][64];
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+    const int tiles_n = N / 32;
+    const int tm = (int)blockIdx.x / tiles_n, tn = (int)blockIdx.x % tiles_n;
+    const int rc = lane & 31, half = lane >> 5;
+    const int kq = K / 4;
+    const long k0 = (long)w * kq;
+    const uint16_t *pa = A + (long)(tm * 32 + rc) * sam + (k0 + 8 * half) * sak;
+    const uint16_t *pb = B + (long)(tn * 32 + rc) * sbn + (k0 + 8 * half) * sbk;
+    floatx16 acc = {};
+    int kb = 0;
+    for (; kb + 32 <= kq; kb += 32) {
+        const bf16x8 a0 = load_slice<kAc>(pa + (long)kb * sak, sak);
+        const bf16x8 b0 = load_slice<kBc>(pb + (long)kb * sbk, sbk);
+        const bf16x8 a1 = load_slice<kAc>(pa + (long)(kb + 16) * sak, sak);
+        const bf16x8 b1 = load_slice<kBc>(pb + (long)(kb + 16) * sbk, sbk);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc, 0, 0, 0);
+    }
+    if (kb < kq) {
+        const bf16x8 a0 = load_slice<kAc>(pa + (long)kb * sak, sak);
+        const bf16x8 b0 = load_slice<kBc>(pb + (long)kb * sbk, sbk);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) part[w][r][lane] = acc[r];
+    __syncthreads();
+    // wave w finishes result registers 4w .. 4w + 3 of every lane
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = 4 * w + i;
+        const float v = ((part[0][r][lane] + part[1][r][lane]) + part[2][r][lane]) + part[3][r][lane];
+        const long row = tm * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+        float *c = &C[row * ldc + tn * 32 + rc];
+        *c = accumulate ? *c + v : v;
+    }
+}
+
 // xb = bf16((x - mu) / sigma); pre1 = b1 + xb . W1b; h1b = bf16(relu(pre1)).
 // One thread per (row, unit).
 __global__ void layer1_forward(const float *x, int n, const float *mu, const float *sigma,
@@ -506,6 +555,23 @@ hipError_t sg_gemm(hipStream_t s, const uint16_t *A, long sam, long sak, const u
         return sk == 1 && so % 8 == 0 && (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
     };
     const bool ac = contig(A, sak, sam), bc = contig(B, sbk, sbn);
+    if (K % 64 == 0 && waves <= 1024) {
+        // few tiles: split k over the four waves of a block, one block per tile
+        const dim3 tgrid((unsigned)waves), tblock(256);
+        if (ac && bc)
+            hipLaunchKernelGGL((gemm_bf16_splitk<true, true>), tgrid, tblock, 0, s, A, sam, sak, B, sbk, sbn, C,
+                               ldc, M, N, K, accumulate);
+        else if (ac)
+            hipLaunchKernelGGL((gemm_bf16_splitk<true, false>), tgrid, tblock, 0, s, A, sam, sak, B, sbk, sbn, C,
+                               ldc, M, N, K, accumulate);
+        else if (bc)
+            hipLaunchKernelGGL((gemm_bf16_splitk<false, true>), tgrid, tblock, 0, s, A, sam, sak, B, sbk, sbn, C,
+                               ldc, M, N, K, accumulate);
+        else
+            hipLaunchKernelGGL((gemm_bf16_splitk<false, false>), tgrid, tblock, 0, s, A, sam, sak, B, sbk, sbn,
+                               C, ldc, M, N, K, accumulate);
+        return hipGetLastError();
+    }
     const dim3 grid(blocks_for(waves, 4)), block(256);
     if (ac && bc)
         hipLaunchKernelGGL((gemm_bf16<true, true>), grid, block, 0, s, A, sam, sak, B, sbk, sbn, C, ldc, M, N,

@@ -341,6 +341,13 @@ def test_errors_and_edges(ctx):
     with pytest.raises(B.SmcError) as e:
         ctx.formula(n, "X[0,1](X[0,1](X>1))")
     assert e.value.code == B.SMC_E_UNSUPPORTED
+    # more species than one wave's LDS holds: refused on the host, before any launch
+    big = W.from_reactions([f"S{i}" for i in range(300)], [5] + [0] * 299, [(["S0"], ["S1"], 1.0)], "wide")
+    nb = ctx.network(big)
+    fb = ctx.formula(nb, "F[0,1](S1>=1)")
+    with pytest.raises(B.SmcError) as e:
+        ctx.estimate(nb, fb, B.params(fixed_n=64))
+    assert e.value.code == B.SMC_E_INVALID
     with pytest.raises(B.SmcError) as e:
         ctx.formula(n, "F[0,1](pow(X,2)>1)")
     assert e.value.code == B.SMC_E_UNSUPPORTED
