@@ -171,6 +171,16 @@ void smc_net_destroy(smc_net *net);
 int smc_formula_compile(smc_ctx *ctx, const smc_net *net, const char *text, smc_formula **out);
 /* Time span of the path the formula can depend on (+inf if unbounded). */
 double smc_formula_horizon(const smc_formula *f);
+/* The same compilation (Sec. 3.1 syntax, the GPU monitor classes above) on
+ * the host only, with no context or device: for validating a formula over
+ * species names n_names (names[0 .. n_names-1]) before a run.  Returns
+ * SMC_OK, SMC_E_PARSE or SMC_E_UNSUPPORTED as smc_formula_compile would, or
+ * SMC_E_INVALID for a null text or name.  When msg is not NULL, the reason
+ * ("" on success) is copied into msg[0 .. cap-1], NUL-terminated and cut to
+ * fit.  On success *horizon (if not NULL) receives the formula's horizon.
+ * Nothing is allocated that outlives the call. */
+int smc_formula_check(const char *text, const char *const *names, int n_names, double *horizon, char *msg,
+                      size_t cap);
 void smc_formula_destroy(smc_formula *f);
 
 /* ---- estimation (Sec. 3.3) --------------------------------------------- */

@@ -38,7 +38,7 @@ EXPORTS = [
     "smc_ctx_create", "smc_ctx_destroy", "smc_last_error", "smc_set_watchdog",
     "smc_set_waves_per_cu", "smc_set_specialization", "smc_last_kernel",
     "smc_set_kernel_occupancy", "smc_autotune", "smc_cancel", "smc_device_cus", "smc_net_create",
-    "smc_net_set_rates", "smc_net_destroy", "smc_formula_compile", "smc_formula_horizon",
+    "smc_net_set_rates", "smc_net_destroy", "smc_formula_compile", "smc_formula_horizon", "smc_formula_check",
     "smc_formula_destroy", "smc_estimate", "smc_estimate_batch", "smc_trajectories",
     "smc_sample_state", "smc_z_value", "smc_wilson_sample_value", "smc_wilson_sample",
     "smc_wilson_interval", "smc_wilson_next_device", "smc_surrogate_create",
@@ -130,6 +130,8 @@ def lib():
             "smc_net_destroy": (None, [vp]),
             "smc_formula_compile": (i32, [vp, vp, ctypes.c_char_p, ctypes.POINTER(vp)]),
             "smc_formula_horizon": (dbl, [vp]),
+            "smc_formula_check": (i32, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_char_p), i32,
+                                        ctypes.POINTER(dbl), ctypes.c_char_p, ctypes.c_size_t]),
             "smc_formula_destroy": (None, [vp]),
             "smc_estimate": (i32, [vp, vp, vp, ctypes.POINTER(Params), ctypes.POINTER(Result)]),
             "smc_estimate_batch": (i32, [vp, ctypes.POINTER(JobDesc), ctypes.c_size_t, ctypes.POINTER(Result)]),
@@ -343,6 +345,18 @@ class Formula:
                 lib().smc_formula_destroy(self.h)
         except Exception:
             pass
+
+
+# -- formula validation on the host (no device) ------------------------------
+def formula_check(text: str, names):
+    """(code, reason, horizon) of compiling `text` over species `names` for the
+    GPU monitor, without a context: code is SMC_OK, SMC_E_PARSE,
+    SMC_E_UNSUPPORTED or SMC_E_INVALID; horizon is None unless SMC_OK."""
+    arr = (ctypes.c_char_p * max(len(names), 1))(*[n.encode() for n in names])
+    hz = ctypes.c_double(math.nan)
+    msg = ctypes.create_string_buffer(256)
+    rc = lib().smc_formula_check(text.encode(), arr, len(names), ctypes.byref(hz), msg, 256)
+    return rc, msg.value.decode(), (hz.value if rc == SMC_OK else None)
 
 
 # -- Wilson formulas (host functions of the library) ------------------------

@@ -873,6 +873,45 @@ int smc_formula_compile(smc_ctx *c, const smc_net *net, const char *text, smc_fo
 
 double smc_formula_horizon(const smc_formula *f) { return f ? f->horizon : NAN; }
 
+int smc_formula_check(const char *text, const char *const *names, int n_names, double *horizon, char *msg,
+                      size_t cap)
+{
+    auto put = [&](const char *m) {
+        if (msg && cap > 0) {
+            std::strncpy(msg, m, cap - 1);
+            msg[cap - 1] = '\0';
+        }
+    };
+    put("");
+    if (!text || n_names < 0 || (n_names > 0 && !names)) {
+        put("null argument");
+        return SMC_E_INVALID;
+    }
+    std::vector<std::string> nm;
+    for (int s = 0; s < n_names; ++s) {
+        if (!names[s]) {
+            put("null species name");
+            return SMC_E_INVALID;
+        }
+        nm.emplace_back(names[s]);
+    }
+    MonProg prog;
+    try {
+        compile_formula(text, nm, prog);
+    } catch (const ParseFailure &e) {
+        put(e.what());
+        return SMC_E_PARSE;
+    } catch (const Unsupported &e) {
+        put(e.what());
+        return SMC_E_UNSUPPORTED;
+    } catch (const std::exception &e) {
+        put(e.what());
+        return SMC_E_INVALID;
+    }
+    if (horizon) *horizon = prog.horizon;
+    return SMC_OK;
+}
+
 void smc_formula_destroy(smc_formula *f)
 {
     if (!f) return;
