@@ -46,10 +46,17 @@ def compile_oracle(force: bool = False) -> str:
 
 
 def lib():
+    """The compiled oracle.  ORACLE_LIB_OVERRIDE names another build of it to
+    load instead: the pin-strength test runs the pins against copies with a
+    planted mistake."""
     global _lib
     if _lib is None:
-        compile_oracle()
-        _lib = ctypes.CDLL(_LIB)
+        override = os.environ.get("ORACLE_LIB_OVERRIDE")
+        if override:
+            _lib = ctypes.CDLL(override)
+        else:
+            compile_oracle()
+            _lib = ctypes.CDLL(_LIB)
         _lib.oracle_log.restype = ctypes.c_double
         _lib.oracle_log.argtypes = [ctypes.c_double]
         _lib.oracle_path.restype = ctypes.c_int64
