@@ -1,7 +1,8 @@
-"""Strength of the oracle's pins: copies of the oracle's C source with one
-planted mistake each (the kind a transcription of the method could make) are
-compiled on the CPU, and the pin named beside each mistake must fail on that
-copy.  The same pins pass on the real oracle in the rest of the suite."""
+"""Strength of the oracle's pins: copies of the oracle with one planted
+mistake each (the kind a transcription of the method could make), and the pin
+named beside each mistake must fail on that copy.  C mistakes are compiled
+into a separate library on the CPU; Wilson-rule mistakes are loaded as a
+separate module.  The same pins pass on the real oracle."""
 import os
 import subprocess
 import sys
@@ -70,3 +71,52 @@ def test_pin_catches_planted_mistake(tmp_path, mistake, orig, planted, pin):
                        capture_output=True, text=True, timeout=300)
     # exit code 1: the pin ran and failed (2 and above: it did not run)
     assert r.returncode == 1, (mistake, r.returncode, r.stdout[-2000:])
+
+
+# The Wilson rule (Sec. 3.3, eqs. 3-4, Fig. 2) lives in oracle/wilson.py: its
+# mutants are loaded as modules and the pins are called with them in place.
+WILSON_MUTANTS = [
+    ("eq. 3 centre without z^2/2n",
+     "center = p + z2 / (2.0 * nd)", "center = p",
+     "test_table3_intervals"),
+    ("eq. 3 half-width with z^2/4n instead of z^2/4n^2",
+     "z2 / ((4.0 * nd) * nd)", "z2 / (4.0 * nd)",
+     "test_table3_intervals"),
+    ("eq. 4 with the sign of 2 eps^2 flipped",
+     "num = (pq - 2.0 * e2) + math.sqrt(rad)", "num = (pq + 2.0 * e2) + math.sqrt(rad)",
+     "test_conservative_sample_size"),
+    ("sample size rounded to nearest instead of up",
+     "return int(math.ceil(wilson_sample_value(p, eps, z)))", "return int(round(wilson_sample_value(p, eps, z)))",
+     "test_first_batch_closed_form"),
+    ("Fig. 2 moves the estimate away from 0.5",
+     "        q = p + eps\n", "        q = p - eps\n",
+     "test_rounding_towards_half"),
+    ("z as sqrt(2) erfinv((1 + confidence) / 2), mixing two quantile forms",
+     "mpmath.erfinv(mpmath.mpf(confidence))", "mpmath.erfinv(mpmath.mpf((1 + confidence) / 2))",
+     "test_z_values"),
+    ("first batch sized for p = 0.5 unless asked, and vice versa",
+     "n_run = wilson_sample(0.5 if conservative else 1.0, eps, z)",
+     "n_run = wilson_sample(1.0 if conservative else 0.5, eps, z)",
+     "test_iterative_reduction_claim"),
+]
+
+
+@pytest.mark.parametrize("mistake,orig,planted,pin", WILSON_MUTANTS, ids=[m[0] for m in WILSON_MUTANTS])
+def test_wilson_pin_catches_planted_mistake(monkeypatch, golden_dir, mistake, orig, planted, pin):
+    import inspect
+    import types
+
+    import test_oracle_wilson as pins
+    from oracle import wilson
+
+    text = open(wilson.__file__).read()
+    assert text.count(orig) == 1, "the Wilson oracle no longer has this text"
+    mutant = types.ModuleType("wilson_mutant")
+    exec(compile(text.replace(orig, planted), "wilson_mutant.py", "exec"), mutant.__dict__)
+    monkeypatch.setattr(pins, "wilson", mutant)
+    fn = getattr(pins, pin)
+    args = [golden_dir] if "golden_dir" in inspect.signature(fn).parameters else []
+    with pytest.raises(Exception):
+        fn(*args)
+    monkeypatch.undo()
+    fn(*args)      # the same pin passes with the real oracle
