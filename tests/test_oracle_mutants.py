@@ -120,3 +120,61 @@ def test_wilson_pin_catches_planted_mistake(monkeypatch, golden_dir, mistake, or
         fn(*args)
     monkeypatch.undo()
     fn(*args)      # the same pin passes with the real oracle
+
+
+# The MLP oracle (oracle/mlp.py) and the BLTLc parser (oracle/bltlc.py), the
+# same way.  A pin given as "module:function" is called once; as
+# "module:golden" it runs every hand-derived golden trace case.
+PY_MUTANTS = [
+    ("mlp", "layer-2 ReLU derivative dropped",
+     '* (f["pre2"] > 0.0)', "",
+     "test_oracle_mlp:test_exact_gradients_against_finite_differences"),
+    ("mlp", "dW2 transposed",
+     'dW2 = d2b.T @ f["h1"]', 'dW2 = f["h1"].T @ d2b',
+     "test_oracle_mlp:test_exact_gradients_against_finite_differences"),
+    ("mlp", "cross-entropy gradient with the wrong sign",
+     "dz = w * (p - y) / wsum", "dz = w * (y - p) / wsum",
+     "test_oracle_mlp:test_exact_gradients_against_finite_differences"),
+    ("mlp", "bfloat16 by truncation instead of ties-to-even",
+     "np.rint(np.ldexp(m, 8))", "np.trunc(np.ldexp(m, 8))",
+     "test_oracle_mlp:test_bf16_rounding"),
+    ("bltlc", "G rewritten without the inner negation (G p as not F p)",
+     "neg = self.f.node(N_NOT, arg)", "neg = arg",
+     "test_oracle_semantics:golden"),
+    ("bltlc", "| parsed as &",
+     "left = self.f.node(N_OR, left, right)", "left = self.f.node(N_AND, left, right)",
+     "test_oracle_semantics:golden"),
+]
+
+
+@pytest.mark.parametrize("module,mistake,orig,planted,pin", PY_MUTANTS, ids=[m[1] for m in PY_MUTANTS])
+def test_python_oracle_pin_catches_planted_mistake(monkeypatch, module, mistake, orig, planted, pin):
+    import importlib
+    import types
+
+    real = importlib.import_module("oracle." + module)
+    pins_name, fn_name = pin.split(":")
+    pins = importlib.import_module(pins_name)
+    text = open(real.__file__).read()
+    assert text.count(orig) == 1, "the oracle module no longer has this text"
+    mutant = types.ModuleType(module + "_mutant")
+    monkeypatch.setitem(sys.modules, mutant.__name__, mutant)     # dataclasses look their module up
+    exec(compile(text.replace(orig, planted), module + "_mutant.py", "exec"), mutant.__dict__)
+
+    def run():
+        if fn_name == "golden":
+            failed = 0
+            for case in pins._golden():
+                try:
+                    pins.test_golden_trace(*case.values)
+                except AssertionError:
+                    failed += 1
+            assert failed == 0, f"{failed} golden cases fail"
+        else:
+            getattr(pins, fn_name)()
+
+    monkeypatch.setattr(pins, module, mutant)
+    with pytest.raises(AssertionError):
+        run()
+    monkeypatch.undo()
+    run()          # the same pins pass with the real oracle
