@@ -122,8 +122,9 @@ def test_wilson_pin_catches_planted_mistake(monkeypatch, golden_dir, mistake, or
     fn(*args)      # the same pin passes with the real oracle
 
 
-# The MLP oracle (oracle/mlp.py) and the BLTLc parser (oracle/bltlc.py), the
-# same way.  A pin given as "module:function" is called once; as
+# The MLP oracle (oracle/mlp.py), the BLTLc parser (oracle/bltlc.py) and the
+# exact transient probabilities (oracle/uniformization.py), the same way.  A
+# pin given as "module:function[:argument]" is called once; as
 # "module:golden" it runs every hand-derived golden trace case.
 PY_MUTANTS = [
     ("mlp", "layer-2 ReLU derivative dropped",
@@ -144,6 +145,15 @@ PY_MUTANTS = [
     ("bltlc", "| parsed as &",
      "left = self.f.node(N_OR, left, right)", "left = self.f.node(N_AND, left, right)",
      "test_oracle_semantics:golden"),
+    ("uniformization", "Poisson weights with (k-1)! instead of k!",
+     "- lam - gammaln(k + 1))", "- lam - gammaln(k))",
+     "test_oracle_probability:test_c1_against_uniformization"),
+    ("uniformization", "master-equation homodimer rate without the -1",
+     "return c * x[ra] * (x[ra] - 1) / 2.0", "return c * x[ra] * x[ra] / 2.0",
+     "test_oracle_ssa:test_bimolecular_against_master_equation:homodimer"),
+    ("uniformization", "until: paths where the left operand fails not stopped",
+     "absorbing = lambda x: p2(x) or not p1(x)", "absorbing = lambda x: p2(x)",
+     "test_oracle_probability:test_until_two_independent_species"),
 ]
 
 
@@ -153,8 +163,9 @@ def test_python_oracle_pin_catches_planted_mistake(monkeypatch, module, mistake,
     import types
 
     real = importlib.import_module("oracle." + module)
-    pins_name, fn_name = pin.split(":")
+    pins_name, fn_name, *args = pin.split(":")
     pins = importlib.import_module(pins_name)
+    attr = next(k for k, v in vars(pins).items() if v is real)      # the name the pins use
     text = open(real.__file__).read()
     assert text.count(orig) == 1, "the oracle module no longer has this text"
     mutant = types.ModuleType(module + "_mutant")
@@ -171,9 +182,9 @@ def test_python_oracle_pin_catches_planted_mistake(monkeypatch, module, mistake,
                     failed += 1
             assert failed == 0, f"{failed} golden cases fail"
         else:
-            getattr(pins, fn_name)()
+            getattr(pins, fn_name)(*args)
 
-    monkeypatch.setattr(pins, module, mutant)
+    monkeypatch.setattr(pins, attr, mutant)
     with pytest.raises(AssertionError):
         run()
     monkeypatch.undo()

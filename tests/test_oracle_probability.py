@@ -54,6 +54,20 @@ def test_until_isomerization():
     estimate_contains(net, "(B<=30) U[0,1.5] (A<=20)", exact, 20000)
 
 
+def test_until_two_independent_species():
+    """The left operand can fail before the right one holds (Y and X evolve
+    independently), so the until's 'p1 at every earlier state' matters here:
+    without it the probability would be that of F, 0.63 instead of 0.43."""
+    net = W.from_reactions(["X", "Y"], [0, 0], [([], ["X"], 1.0), (["X"], [], 0.1),
+                                                  ([], ["Y"], 1.0), (["Y"], [], 0.1)], "two immigration-death")
+    exact = U.until_probability(net, lambda x: x[1] <= 3, lambda x: x[0] >= 4, 5.0, [40, 40])
+    exact2 = U.until_probability(net, lambda x: x[1] <= 3, lambda x: x[0] >= 4, 5.0, [40, 40], "expm")
+    fin = U.until_probability(net, lambda x: True, lambda x: x[0] >= 4, 5.0, [40, 40])
+    assert abs(exact - exact2) < 1e-10
+    assert 0.05 < exact < 0.95 and fin - exact > 0.1
+    estimate_contains(net, "(Y<=3) U[0,5] (X>=4)", exact, 20000)
+
+
 def test_globally_isomerization():
     net = W.isomerization(1.0, 0.5, 50)
     fin = U.until_probability(net, lambda x: True, lambda x: x[0] < 22, 1.0, [50, 50])
