@@ -50,6 +50,12 @@ MUTANTS = [
      "static int not3(int v) { return v == V_U ? V_U : (v == V_T ? V_F : V_T); }",
      "static int not3(int v) { return v; }",
      "tests/test_oracle_semantics.py::test_golden_trace[A:G[0,3](X<=2)]"),
+    ("absorption reported as a time decision",
+     "        else if (isinf(w->t[m + 1])) *reason = R_ABSORB;\n", "",
+     "tests/test_oracle_semantics.py::test_driver_matches_brute_force[death_only-F[0,100](X>=40)-0]"),
+    ("event cap one event early",
+     "(uint64_t)m == (uint64_t)pr->max_events", "(uint64_t)m + 1 == (uint64_t)pr->max_events",
+     "tests/test_oracle_semantics.py::test_tmax_pessimistic_rule_and_cap"),
     ("until's right operand accepted without the left one holding before it",
      "if (d >= lo) res = or3(res, and3(all1, eval3(f, f->b[node], j, P)));",
      "if (d >= lo) res = or3(res, eval3(f, f->b[node], j, P));",

@@ -175,6 +175,11 @@ def test_kleene_monotone_on_prefixes():
                     seen = v
 
 
+def death_only():
+    """X -> 0 at rate X from 30: absorbed at X = 0 after 30 events."""
+    return W.from_reactions(["X"], [30], [(["X"], [], 1.0)], "death")
+
+
 CASES = [
     (W.immigration_death, "F[0,10](X>=12)", 0),
     (W.immigration_death, "G[0,5](X<=30) & F[0,8](X>=40)", 0),
@@ -185,6 +190,8 @@ CASES = [
     (W.michaelis_menten, "F[0,0.2](ES>=60)", 0),
     (W.dimerization, "F[0,5](A<=10)", 0),
     (W.immigration_death, "F[0,100](X>=120)", 50),   # event cap
+    (death_only, "F[0,100](X>=40)", 0),               # decided only by absorption: FALSE
+    (death_only, "G[0,100](X>=0)", 0),                # decided only by absorption: TRUE
 ]
 
 
