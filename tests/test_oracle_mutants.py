@@ -50,6 +50,24 @@ MUTANTS = [
      "static int not3(int v) { return v == V_U ? V_U : (v == V_T ? V_F : V_T); }",
      "static int not3(int v) { return v; }",
      "tests/test_oracle_semantics.py::test_golden_trace[A:G[0,3](X<=2)]"),
+    ("model id in counter word 3 instead of 2",
+     "uint32_t ctr[4] = {k, (uint32_t)idx, model_id, 0u};",
+     "uint32_t ctr[4] = {k, (uint32_t)idx, 0u, model_id};",
+     "tests/test_oracle_primitives.py::test_first_event_follows_the_stream_contract"),
+    ("seed halves swapped in the key",
+     "uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};",
+     "uint32_t key[2] = {(uint32_t)(seed >> 32), (uint32_t)seed};",
+     "tests/test_oracle_primitives.py::test_first_event_follows_the_stream_contract"),
+    ("state sampled at 2T instead of T",
+     "if (tn > T) break;", "if (tn > 2.0 * T) break;",
+     "tests/test_oracle_ssa.py::test_isomerization_binomial[0.3]"),
+    ("arithmetic predicate: subtraction operands swapped",
+     "case E_SUB: sp--; st[sp - 1] = st[sp - 1] - st[sp]; break;",
+     "case E_SUB: sp--; st[sp - 1] = st[sp] - st[sp - 1]; break;",
+     "tests/test_oracle_semantics.py::test_golden_trace[B:(A > B) U[0,5] (B - A >= 1)]"),
+    ("<= evaluated as <",
+     "case OP_LE: return l <= r;", "case OP_LE: return l < r;",
+     "tests/test_oracle_semantics.py::test_golden_trace[A:G[0,3](X<=2)]"),
     ("absorption reported as a time decision",
      "        else if (isinf(w->t[m + 1])) *reason = R_ABSORB;\n", "",
      "tests/test_oracle_semantics.py::test_driver_matches_brute_force[death_only-F[0,100](X>=40)-0]"),

@@ -48,6 +48,40 @@ def test_philox_matches_rocrand(rocrand_ref):
         assert got == e, (r, got, e)
 
 
+def test_first_event_follows_the_stream_contract(rocrand_ref):
+    """The stream map, end to end: the first event of trajectory idx of a job
+    (seed, model) uses the Philox block at counter (0, idx, model, 0) and key
+    (seed_lo, seed_hi), u1 from words 0-1 for the holding time and u2 from
+    words 2-3 for the channel.  The block comes from rocRAND, ln from mpmath."""
+    from paper_0912_2551_amd import workloads as W
+    net = W.from_reactions(["X", "Y"], [5, 7], [(["X"], ["Y"], 1.0), (["Y"], ["X"], 0.75), ([], ["X"], 2.0)],
+                           "three channels")
+    a = [5.0, 5.25, 2.0]                      # propensities at (5, 7); their sums are exact
+    S = [5.0, 10.25, 12.25]
+    a0 = S[-1]
+    jobs = [(1, 0), (0x0000000500000003, 7), (0xFFFFFFFF00000001, 0x0BADCAFE)]
+    idxs = list(range(48)) + [1000, 123456, (1 << 30) - 1]
+    rows = [(0, i, m, 0, seed & 0xFFFFFFFF, seed >> 32) for seed, m in jobs for i in idxs]
+    inp = "\n".join(" ".join(str(v) for v in r) for r in rows) + "\n"
+    out = subprocess.run([rocrand_ref], input=inp, capture_output=True, text=True, check=True).stdout
+    words = [tuple(int(v) for v in line.split()) for line in out.strip().splitlines()]
+    assert len(words) == len(rows)
+    mpmath.mp.dps = 40
+    for r, w in zip(rows, words):
+        seed, m, i = r[4] | (r[5] << 32), r[2], r[1]
+        u1 = ((w[0] << 21 | w[1] >> 11) + 1) * 2.0**-53
+        u2 = (w[2] << 21 | w[3] >> 11) * 2.0**-53
+        tau = float(-mpmath.log(mpmath.mpf(u1)) / a0)
+        target = u2 * a0
+        j = next(k for k in range(3) if S[k] > target)
+        states, times, a0s, _ = oracle.path(net, i, 1, seed=seed, model_id=m)
+        assert a0s[0] == a0
+        assert abs(times[1] - tau) <= 2 * math.ulp(tau), (r, times[1], tau)
+        d = tuple(int(v) for v in states[1] - states[0])
+        assert d == [(-1, 1), (1, -1), (1, 0)][j], (r, d, j)
+    assert a[0] + a[1] + a[2] == a0
+
+
 def _ulp_error(x):
     mpmath.mp.dps = 50
     exact = mpmath.log(mpmath.mpf(x))
