@@ -68,6 +68,10 @@ MUTANTS = [
     ("<= evaluated as <",
      "case OP_LE: return l <= r;", "case OP_LE: return l < r;",
      "tests/test_oracle_semantics.py::test_golden_trace[A:G[0,3](X<=2)]"),
+    ("next operator measured in absolute time",
+     "        double d = P->t[i + 1] - P->t[i];\n        if (!(d >= lo && d <= hi)) return V_F;\n        return eval3",
+     "        double d = P->t[i + 1];\n        if (!(d >= lo && d <= hi)) return V_F;\n        return eval3",
+     "tests/test_oracle_semantics.py::test_golden_trace[A:F[0,10](X[0,2](X>=3))]"),
     ("absorption reported as a time decision",
      "        else if (isinf(w->t[m + 1])) *reason = R_ABSORB;\n", "",
      "tests/test_oracle_semantics.py::test_driver_matches_brute_force[death_only-F[0,100](X>=40)-0]"),
