@@ -83,3 +83,68 @@ def test_bad_arguments_and_message_truncation():
     buf = ctypes.create_string_buffer(8)
     rc = L.smc_formula_check(b"F[0,1](Q>1)", arr, 1, None, buf, 8)
     assert rc == B.SMC_E_PARSE and len(buf.value) == 7
+
+
+def _random_formula(r, depth=0):
+    """Random BLTLc text over X, Y and a species named F (Sec. 3.1 grammar)."""
+    def interval():
+        k = r.random()
+        if k < 0.4:
+            a = round(r.uniform(0, 3), 2)
+            return f"[{a},{round(a + r.uniform(0, 4), 2)}]"
+        if k < 0.7:
+            return f"<={round(r.uniform(0, 5), 2)}"
+        return "" if k < 0.8 else "[0,inf]"
+
+    def val(d):
+        k = r.random()
+        if d > 1 or k < 0.4:
+            return r.choice(["X", "Y", "F", "2", "3.5", "0"])
+        if k < 0.6:
+            return f"{val(d + 1)} {r.choice('+-*/')} {val(d + 1)}"
+        if k < 0.7:
+            return f"sqrt({val(d + 1)})"
+        return f"-{val(d + 1)}" if k < 0.8 else f"({val(d + 1)})"
+
+    k = r.random()
+    if depth > 3 or k < 0.3:
+        if r.random() < 0.9:
+            return f"{val(0)} {r.choice(['<', '<=', '>=', '>', '=', '!=', '=='])} {val(0)}"
+        return r.choice(["true", "false"])
+    sub = lambda: _random_formula(r, depth + 1)   # noqa: E731
+    if k < 0.4:
+        return f"!{sub()}"
+    if k < 0.5:
+        return f"{sub()} & {sub()}"
+    if k < 0.6:
+        return f"{sub()} | {sub()}"
+    if k < 0.75:
+        return f"{r.choice('FGX')}{interval()} {sub()}"
+    if k < 0.85:
+        return f"{sub()} U{interval()} {sub()}"
+    return f"({sub()})"
+
+
+def test_random_formulas_read_alike():
+    """The library's parser and the oracle's parser are separate code: on
+    random text they must reject the same formulas, and on every formula the
+    library accepts they must derive the same horizon (which depends on how
+    the operators nest)."""
+    import random
+    r = random.Random(7)
+    names = ["X", "Y", "F"]
+    codes = {}
+    for _ in range(2000):
+        text = _random_formula(r)
+        rc, msg, hz = B.formula_check(text, names)
+        codes[rc] = codes.get(rc, 0) + 1
+        try:
+            f = bltlc.parse(text, names)
+        except bltlc.ParseError:
+            assert rc == B.SMC_E_PARSE, (text, rc, msg)
+            continue
+        assert rc != B.SMC_E_PARSE, (text, msg)
+        if rc == B.SMC_OK:
+            h = oracle.horizon(f)
+            assert h == hz or (math.isinf(h) and math.isinf(hz)), (text, hz, h)
+    assert min(codes.get(c, 0) for c in (B.SMC_OK, B.SMC_E_PARSE, B.SMC_E_UNSUPPORTED)) > 100, codes
