@@ -122,6 +122,12 @@ WILSON_MUTANTS = [
     ("z as sqrt(2) erfinv((1 + confidence) / 2), mixing two quantile forms",
      "mpmath.erfinv(mpmath.mpf(confidence))", "mpmath.erfinv(mpmath.mpf((1 + confidence) / 2))",
      "test_z_values"),
+    ("Fig. 2 runs N' more trajectories instead of N' - N_tot",
+     "n_new = n_prime - n_tot", "n_new = n_prime",
+     "test_all_false_stream_95"),
+    ("p-hat from the last batch only, not all batches so far",
+     "yes += count_yes(n_tot, n_tot + n_run)", "yes = count_yes(n_tot, n_tot + n_run)",
+     "test_iterative_reduction_claim"),
     ("first batch sized for p = 0.5 unless asked, and vice versa",
      "n_run = wilson_sample(0.5 if conservative else 1.0, eps, z)",
      "n_run = wilson_sample(1.0 if conservative else 0.5, eps, z)",
