@@ -65,6 +65,14 @@ def lib():
     return _lib
 
 
+def set_plain_scan(on: bool) -> None:
+    """Evaluate until by scanning every position, as its definition reads
+    (True), or jump over positions that cannot change the scan (False, the
+    default; same values, linear instead of quadratic time for nested
+    untils)."""
+    lib().oracle_set_plain_scan(ctypes.c_int(1 if on else 0))
+
+
 def _p(a, ct):
     return a.ctypes.data_as(ctypes.POINTER(ct))
 

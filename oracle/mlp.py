@@ -14,6 +14,9 @@ the one the GPU computes (rounding treated as the identity in the backward
 pass).  With quantize=False it is the exact gradient of the FP64 network,
 which the tests check against finite differences.
 
+Training uses Adam (Kingma and Ba, "Adam: a method for stochastic
+optimization", ICLR 2015, Algorithm 1): adam_step below, in FP64.
+
 Parameter vector layout: W1[256*3] (unit-major), b1[256], W2[256*256]
 (output-major), b2[256], W3[256], b3, mu[3], sigma[3].
 """
@@ -103,3 +106,18 @@ def init_params(seed, mu=(0.0, 0.0, 0.0), sigma=(1.0, 1.0, 1.0)):
     b3 = rng.uniform(-0.1, 0.1)
     p = np.concatenate([W1.ravel(), b1, W2.ravel(), b2, W3, [b3], mu, sigma])
     return p.astype(np.float32).astype(np.float64)
+
+
+def adam_step(w, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba 2015, Algorithm 1) at step t >= 1:
+    biased moment estimates m <- beta1 m + (1 - beta1) g and
+    v <- beta2 v + (1 - beta2) g^2, their bias-corrected values
+    m / (1 - beta1^t) and v / (1 - beta2^t), then
+    w <- w - lr m_hat / (sqrt(v_hat) + eps).  Returns (w, m, v), FP64."""
+    w = np.asarray(w, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * (g * g)
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    return w - lr * m_hat / (np.sqrt(v_hat) + eps), m, v

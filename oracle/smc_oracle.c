@@ -264,9 +264,37 @@ typedef struct {
     const int32_t *states;  /* [n][S] */
     const double *t;        /* [n + 1] */
     uint8_t *memo;          /* [n_nodes][n], 0xFF = not computed */
+    int64_t *skip;          /* [n_nodes][n + 1], see until_skip (NULL: plain scan) */
+    uint8_t *skip_built;    /* [n_nodes] */
 } oprefix;
 
+/* 1: scan every position in until (the definition as written); 0: jump over
+ * positions that cannot change the scan (until_skip).  Both give the same
+ * values; the tests compare them on random paths. */
+static int g_plain_scan = 0;
+void oracle_set_plain_scan(int on) { g_plain_scan = on; }
+
 static int eval3(const oformula *f, int node, int64_t i, const oprefix *P);
+
+/* In the scan of eval_until, a position where the left operand is T and
+ * the right one F changes nothing: or3(res, F) = res and and3(all1, T) =
+ * all1.  Only the window test can end the scan there.  skip[k] is the first
+ * position >= k that is not of this kind (n if there is none).  Without it a
+ * nested until costs time quadratic in the prefix length, since the inner
+ * until is scanned from every position of the outer one. */
+static const int64_t *until_skip(const oformula *f, int node, const oprefix *P)
+{
+    int64_t *s = &P->skip[(int64_t)node * (P->n + 1)];
+    if (!P->skip_built[node]) {
+        s[P->n] = P->n;
+        for (int64_t k = P->n - 1; k >= 0; --k) {
+            int neutral = eval3(f, f->a[node], k, P) == V_T && eval3(f, f->b[node], k, P) == V_F;
+            s[k] = neutral ? s[k + 1] : k;
+        }
+        P->skip_built[node] = 1;
+    }
+    return s;
+}
 
 static int eval_until(const oformula *f, int node, int64_t i, const oprefix *P)
 {
@@ -274,7 +302,8 @@ static int eval_until(const oformula *f, int node, int64_t i, const oprefix *P)
      * sigma^j |= p2 and sigma^l |= p1 for all i <= l < j. */
     double lo = f->lo[node], hi = f->hi[node];
     int res = V_F, all1 = V_T;
-    for (int64_t j = i;; ++j) {
+    const int64_t *skip = P->skip ? until_skip(f, node, P) : NULL;
+    for (int64_t j = i;;) {
         if (j >= P->n) {
             /* State j is not in the prefix. */
             if (P->next_known) {
@@ -291,6 +320,13 @@ static int eval_until(const oformula *f, int node, int64_t i, const oprefix *P)
         if (res == V_T) break;
         all1 = and3(all1, eval3(f, f->a[node], j, P));
         if (all1 == V_F) break;
+        if (!skip) { ++j; continue; }
+        /* Positions j+1 .. nj-1 change nothing.  Entry times do not
+         * decrease, so the plain scan stops among them iff the last one
+         * lies past the window. */
+        int64_t nj = skip[j + 1];
+        if (nj > j + 1 && P->t[nj - 1] - P->t[i] > hi) break;
+        j = nj;
     }
     return res;
 }
@@ -344,12 +380,16 @@ static int eval3(const oformula *f, int node, int64_t i, const oprefix *P)
 int oracle_eval_prefix(const oformula *f, int S, int64_t n, int next_known,
                        const int32_t *states, const double *t)
 {
-    oprefix P = {S, n, next_known, states, t, NULL};
+    oprefix P = {S, n, next_known, states, t, NULL, NULL, NULL};
     size_t sz = (size_t)f->n_nodes * (size_t)n;
     P.memo = (uint8_t *)malloc(sz ? sz : 1);
     memset(P.memo, 0xFF, sz);
+    if (!g_plain_scan) {
+        P.skip = (int64_t *)malloc((size_t)f->n_nodes * (size_t)(n + 1) * sizeof(int64_t));
+        P.skip_built = (uint8_t *)calloc((size_t)f->n_nodes, 1);
+    }
     int v = eval3(f, f->root, 0, &P);
-    free(P.memo);
+    free(P.memo); free(P.skip); free(P.skip_built);
     return v;
 }
 
@@ -370,8 +410,10 @@ typedef struct {
     double *t;         /* [cap_states + 1] */
     double *S;         /* [M] prefix scratch */
     uint8_t *memo;
+    int64_t *skip;
+    uint8_t *skip_built;
     int64_t cap_states;
-    size_t memo_sz;
+    size_t memo_sz, skip_sz;
 } oworkspace;
 
 static void ws_reserve(oworkspace *w, int S, int64_t need)
@@ -400,7 +442,18 @@ static int decided_at(const oformula *f, const onet *n, const oparams *pr, owork
         w->memo_sz = need;
     }
     memset(w->memo, 0xFF, need);
-    oprefix P = {n->S, len, next_known, w->states, w->t, w->memo};
+    oprefix P = {n->S, len, next_known, w->states, w->t, w->memo, NULL, NULL};
+    if (!g_plain_scan) {
+        size_t need_skip = (size_t)f->n_nodes * (size_t)(len + 1);
+        if (need_skip > w->skip_sz) {
+            w->skip = (int64_t *)realloc(w->skip, need_skip * sizeof(int64_t));
+            w->skip_sz = need_skip;
+        }
+        if (!w->skip_built) w->skip_built = (uint8_t *)malloc((size_t)f->n_nodes);
+        memset(w->skip_built, 0, (size_t)f->n_nodes);
+        P.skip = w->skip;
+        P.skip_built = w->skip_built;
+    }
     int v = eval3(f, f->root, 0, &P);
     if (v != V_U) {
         *verdict = (v == V_T);
@@ -517,7 +570,7 @@ static void *worker(void *arg)
                 J->err = 1;
         }
     }
-    free(w.states); free(w.t); free(w.S); free(w.memo);
+    free(w.states); free(w.t); free(w.S); free(w.memo); free(w.skip); free(w.skip_built);
     return NULL;
 }
 

@@ -5,7 +5,9 @@
 - bfloat16 rounding against the definition (8 significant bits, ties to even)
   and against torch's float32 -> bfloat16 conversion;
 - the library's host convex hull (no GPU needed) against scipy's Delaunay
-  point location.
+  point location;
+- the Adam step: its first step and any step under a constant gradient in
+  closed form, and two steps worked out by hand.
 """
 import numpy as np
 import pytest
@@ -62,3 +64,30 @@ def test_library_hull_matches_scipy():
     flat = np.zeros((20, 3), dtype=np.float32)
     flat[:, :2] = rng.uniform(size=(20, 2))
     assert B.convex_hull(flat).shape[0] == 0
+
+
+def test_adam_first_step_and_constant_gradient():
+    """From zero moments the bias corrections make the first step
+    lr g / (|g| + eps) whatever beta1 and beta2 are; under a constant gradient
+    the corrected moments stay g and g^2, so every step is that size."""
+    g = np.array([3.0, -0.5, 1e-3, 0.0, -2e-9])
+    w0 = np.array([1.0, 2.0, -1.0, 0.5, 0.0])
+    lr, eps = 1e-2, 1e-8
+    for b1, b2 in ((0.9, 0.999), (0.5, 0.75), (0.0, 0.0)):
+        w, m, v = w0.copy(), np.zeros(5), np.zeros(5)
+        for t in range(1, 8):
+            w, m, v = mlp.adam_step(w, g, m, v, t, lr, b1, b2, eps)
+            expect = w0 - t * lr * g / (np.abs(g) + eps)
+            assert np.allclose(w, expect, rtol=1e-12, atol=1e-15), (b1, b2, t)
+
+
+def test_adam_two_steps_by_hand():
+    """g1 = 1, g2 = -3, beta1 = 1/2, beta2 = 3/4, eps = 0, lr = 1:
+    step 1 moves by -1; then m2 = 1/4 - 3/2 = -5/4, m_hat = (-5/4)/(3/4) = -5/3,
+    v2 = 3/16 + 9/4 = 39/16, v_hat = (39/16)/(7/16) = 39/7, so step 2 moves by
+    (5/3) / sqrt(39/7)."""
+    w, m, v = mlp.adam_step([0.0], [1.0], [0.0], [0.0], 1, 1.0, 0.5, 0.75, 0.0)
+    assert w[0] == -1.0 and m[0] == 0.5 and v[0] == 0.25
+    w, m, v = mlp.adam_step(w, [-3.0], m, v, 2, 1.0, 0.5, 0.75, 0.0)
+    assert m[0] == -1.25 and v[0] == 2.4375
+    assert abs(w[0] - (-1.0 + (5.0 / 3.0) / np.sqrt(39.0 / 7.0))) <= 1e-15

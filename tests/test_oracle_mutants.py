@@ -78,6 +78,13 @@ MUTANTS = [
     ("event cap one event early",
      "(uint64_t)m == (uint64_t)pr->max_events", "(uint64_t)m + 1 == (uint64_t)pr->max_events",
      "tests/test_oracle_semantics.py::test_tmax_pessimistic_rule_and_cap"),
+    ("until skip: the window is not checked over the skipped positions",
+     "        if (nj > j + 1 && P->t[nj - 1] - P->t[i] > hi) break;\n", "",
+     "tests/test_oracle_semantics.py::test_skip_scan_equals_plain_scan"),
+    ("until skip: a position where the right operand holds counted as neutral",
+     "int neutral = eval3(f, f->a[node], k, P) == V_T && eval3(f, f->b[node], k, P) == V_F;",
+     "int neutral = eval3(f, f->a[node], k, P) == V_T && eval3(f, f->b[node], k, P) != V_U;",
+     "tests/test_oracle_semantics.py::test_skip_scan_equals_plain_scan"),
     ("until's right operand accepted without the left one holding before it",
      "if (d >= lo) res = or3(res, and3(all1, eval3(f, f->b[node], j, P)));",
      "if (d >= lo) res = or3(res, eval3(f, f->b[node], j, P));",
@@ -173,6 +180,12 @@ PY_MUTANTS = [
     ("mlp", "bfloat16 by truncation instead of ties-to-even",
      "np.rint(np.ldexp(m, 8))", "np.trunc(np.ldexp(m, 8))",
      "test_oracle_mlp:test_bf16_rounding"),
+    ("mlp", "Adam without the bias corrections",
+     "m_hat = m / (1.0 - beta1 ** t)", "m_hat = m",
+     "test_oracle_mlp:test_adam_first_step_and_constant_gradient"),
+    ("mlp", "Adam second moment from g instead of g^2",
+     "(1.0 - beta2) * (g * g)", "(1.0 - beta2) * np.abs(g)",
+     "test_oracle_mlp:test_adam_two_steps_by_hand"),
     ("bltlc", "G rewritten without the inner negation (G p as not F p)",
      "neg = self.f.node(N_NOT, arg)", "neg = arg",
      "test_oracle_semantics:golden"),

@@ -244,3 +244,62 @@ def test_tmax_pessimistic_rule_and_cap():
     f2 = oracle.parse(W.C1_FORMULA, net)
     ev, vd, rs = oracle.trajectories(net, f2, 0, 16, max_events=10)
     assert (ev == 10).all() and (vd == 0).all() and (rs == oracle.R_CAP).all()
+
+
+def _random_formula(rng, depth):
+    """A random BLTLc formula over X and Y: predicates, boolean operators,
+    next and until with windows that may start above 0, nested to `depth`."""
+    if depth == 0 or rng.random() < 0.25:
+        sp = "XY"[int(rng.integers(0, 2))]
+        return f"{sp}{['<=', '>=', '<', '>'][int(rng.integers(0, 4))]}{int(rng.integers(0, 7))}"
+    lo = float(rng.choice([0.0, rng.uniform(0, 1.5)]))
+    hi = lo + float(rng.uniform(0.2, 4.0))
+    k = int(rng.integers(0, 8))
+    a = _random_formula(rng, depth - 1)
+    if k == 0:
+        return f"!({a})"
+    if k == 1:
+        return f"({a}) & ({_random_formula(rng, depth - 1)})"
+    if k == 2:
+        return f"({a}) | ({_random_formula(rng, depth - 1)})"
+    if k == 3:
+        return f"X[{lo!r},{hi!r}]({a})"
+    if k == 4:
+        return f"F[{lo!r},{hi!r}]({a})"
+    if k == 5:
+        return f"G[{lo!r},{hi!r}]({a})"
+    return f"({a}) U[{lo!r},{hi!r}] ({_random_formula(rng, depth - 1)})"
+
+
+def test_skip_scan_equals_plain_scan():
+    """The until evaluation that jumps over positions where the left operand
+    holds and the right one fails gives the same three-valued value as the
+    scan over every position (the definition as written), on every prefix of
+    random paths under random nested formulas, and the same stopping points
+    on SSA paths."""
+    rng = np.random.default_rng(23)
+    decided = 0
+    try:
+        for _ in range(400):
+            text = _random_formula(rng, 3)
+            f = bltlc.parse(text, ["X", "Y"])
+            st, tm, nt = _random_walk_trace(rng, 18, S=2)
+            for m in range(0, len(st), 3):
+                for nxt in (None, tm[m + 1] if m + 1 < len(tm) else nt, math.inf):
+                    oracle.set_plain_scan(False)
+                    fast = oracle.eval_prefix(f, st[: m + 1], tm[: m + 1], nxt)
+                    oracle.set_plain_scan(True)
+                    plain = oracle.eval_prefix(f, st[: m + 1], tm[: m + 1], nxt)
+                    assert fast == plain, (text, m, nxt)
+                    decided += fast != 2
+        net = W.c3_network()
+        for text in (W.nested_until_formula(net, 2), W.nested_until_formula(net, 5)):
+            oracle.set_plain_scan(True)
+            plain = oracle.trajectories(net, text, 0, 48, seed=1)
+            oracle.set_plain_scan(False)
+            fast = oracle.trajectories(net, text, 0, 48, seed=1)
+            for a, b in zip(plain, fast):
+                assert np.array_equal(a, b)
+    finally:
+        oracle.set_plain_scan(False)
+    assert decided > 1000
