@@ -1100,13 +1100,33 @@ __device__ unsigned long long sum_shards(unsigned long long (*arr)[kShards], int
 // A 64-bit value every lane holds identically, as a wave-uniform value.
 __device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) { return read_lane_u64(v, 0); }
 
-// Wait until this wave's earlier memory operations have been performed.  The
-// stopping-rule state is only ever accessed with device-scope atomic
-// operations (read-modify-writes, and loads and stores at agent scope), which
-// the hardware performs coherently for the whole device; so making one
-// atomic visible before the next needs no cache write-back or invalidation
-// (which is what a device-scope fence does, for the whole L2), only this.
-__device__ __forceinline__ void wait_performed() { __builtin_amdgcn_s_waitcnt(0); }
+// Ordering of the stopping-rule state.  Every access to it is an atomic
+// operation at agent scope (read-modify-writes, and atomic loads and stores),
+// so each location is coherent for the whole device; what needs care is the
+// order in which a wave sees writes to *different* locations.  The batch of a
+// finished trajectory is read from the published bounds, and an index of
+// batch c+1 can only be claimed once the issue limit has passed bound[c].  So
+// a wave that claims an index below a limit value must see every bound that
+// the wave which raised the limit had seen or written.  That is the
+// message-passing pattern of the HIP (C++) memory model:
+//  - every raise of the limit (evaluate_batches, speculate) comes after a
+//    release fence at agent scope;
+//  - the limit load of an iterative claim is an acquire;
+//  - a publishing wave also fences (release) before it stores the new bound,
+//    and a wave that reads a bound in order to raise the limit (speculate),
+//    or that completes a batch and evaluates it, fences (acquire) after the
+//    read; so the chain bound -> limit -> claim holds through any number of
+//    waves (read-read coherence covers the bound values read on the way).
+// A release fence writes back this XCD's L2 and an acquire fence
+// invalidates it; both run once per batch, per look-ahead step (one per 64
+// completions at most) or per claim (one per 64 indices at least), never per
+// event.  Fixed-size jobs never raise the limit and take none of them.
+__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+__device__ __forceinline__ unsigned long long ld_acquire(unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ __forceinline__ void st_relaxed(unsigned long long *p, unsigned long long v)
 {
@@ -1160,17 +1180,19 @@ __device__ void evaluate_batches(const JobView &V, Control *ctl, int b, unsigned
         if (Np > Bb && b + 1 < kMaxBatches && Np <= V.capacity) {
             unsigned long long old = 0;
             const unsigned long long flag = kDoneFlag - (Np - Bb);
+            fence_release();
             if (lane == 0) {
                 // the bound is in place before any index of the new batch can
                 // be claimed, and before the batch can be seen complete
                 st_relaxed(&st->bound[b + 1], Np);
                 st_relaxed_i32(&st->cur, b + 1);
-                wait_performed();
+                fence_release();
                 atomicMax(&st->limit, Np);
                 old = atomicAdd(&st->cnt[b + 1], flag);
             }
             const unsigned long long now = read_lane_u64(old, 0) + flag;
             if ((now & 0xFFFFFFFFull) == kDoneFlag) {
+                fence_acquire();
                 b = b + 1;
                 cw = now;
                 continue;
@@ -1223,6 +1245,8 @@ __device__ void speculate(const JobView &V, int c, unsigned long long cw)
     g = uniform_u64(g);
     if (g > Bc) {
         if (g > V.capacity) g = V.capacity;
+        fence_acquire();      // what the publisher of bound[c] had seen ...
+        fence_release();      // ... is seen by whoever claims below g
         if (lane_id() == 0) atomicMax(&st->limit, g);
     }
 }
@@ -1294,6 +1318,7 @@ __device__ int claim(JobState *st, bool iterative, int need, int n_waves, unsign
         *base = b;
         return (int)((lim - b) < want ? (lim - b) : want);
     }
+    lim = ld_acquire(&st->limit);   // see the ordering note at fence_release
     for (int tries = 0; tries < 16; ++tries) {
         if (cur >= lim) return 0;
         const unsigned long long w = (lim - cur) < want ? (lim - cur) : want;
@@ -1303,7 +1328,7 @@ __device__ int claim(JobState *st, bool iterative, int need, int n_waves, unsign
             return (int)w;
         }
         cur = prev;
-        lim = ld_relaxed(&st->limit);
+        lim = ld_acquire(&st->limit);
         __builtin_amdgcn_s_sleep(4);
     }
     return 0;
@@ -1556,6 +1581,7 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
                 old = read_lane_u64(old, L);
                 const unsigned long long now = old + delta;
                 if ((now & 0xFFFFFFFFull) == kDoneFlag) {
+                    fence_acquire();   // the bounds the batch's publisher had seen
                     evaluate_batches(V, A.ctl, b0, now);
                 } else if (b0 == uniform_i(ld_relaxed(&st->cur))) {
                     // the look-ahead only moves with the counts: refresh it on
