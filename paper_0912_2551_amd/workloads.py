@@ -11,7 +11,9 @@ non-zero entries.
 """
 from __future__ import annotations
 
+import json
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -150,25 +152,69 @@ def nested_until_formula(net, delta, species=(0, 1, 2, 3), T=100.0):
             f"({n[c]} >= {th[2]} & {n[d]} <= {th[3]}))")
 
 
-def c3_species(net, k=4):
-    """The four formula species of a random network: the ones with the
-    largest initial counts, so that every threshold stays positive."""
-    order = np.argsort(-net.x0.astype(np.int64), kind="stable")
-    return tuple(int(s) for s in order[:k])
-
-
 C3_SEED = 1
-C3_DELTA = 20
 C3_CAP = 100000
+# The offsets d of the random-network formulas are fixed once by an oracle
+# pilot (tests/golden/delta_pilot.py) and frozen in these files.
+CONFIG_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "configs")
+
+
+def _config(name):
+    with open(os.path.join(CONFIG_DIR, name)) as fh:
+        return json.load(fh)
 
 
 def c3_network():
     return random_network(64, 256, C3_SEED)
 
 
-def c3_formula(net=None, delta=C3_DELTA):
+def c3_delta():
+    return int(_config("c3.json")["delta"])
+
+
+def c3_formula(net=None, delta=None):
+    """The C3 formula over X0..X3 with the frozen offset."""
     net = net or c3_network()
-    return nested_until_formula(net, delta, c3_species(net))
+    return nested_until_formula(net, c3_delta() if delta is None else delta)
+
+
+def c4_random_networks(n_random=64, seed=5, s_min=8, s_max=128):
+    """Random networks of uneven size: S log-uniform in [s_min, s_max], M = 4 S."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(n_random):
+        S = int(round(10.0 ** rng.uniform(math.log10(s_min), math.log10(s_max))))
+        out.append(random_network(S, 4 * S, seed * 1000 + q))
+    return out
+
+
+def c4_deltas():
+    """Per-network (delta, qualifies) of the 64 random networks, in order."""
+    return [(int(r["delta"]), bool(r["qualifies"])) for r in _config("c4_networks.json")["networks"]]
+
+
+def c4_networks():
+    """The 64 random networks with their formulas (frozen offsets)."""
+    nets = c4_random_networks()
+    deltas = c4_deltas()
+    assert len(deltas) == len(nets)
+    return [(net, nested_until_formula(net, d)) for net, (d, _) in zip(nets, deltas)]
+
+
+def c4_jobs():
+    """The batched sweep: 512 Michaelis-Menten rate sets under the C2 formula
+    and the 64 random networks under their nested-until formulas, each an
+    iterative 95% +-0.01 Wilson job of seed 1 with its own model id (the
+    networks with the 10^5-event cap).  Returns [(network, formula text,
+    parameter dict), ...] in launch order."""
+    out = []
+    for k, rr in enumerate(mm_sweep(512, seed=4)):
+        out.append((michaelis_menten(*rr), C2_FORMULA,
+                    dict(confidence=0.95, half_width=0.01, seed=1, model_id=k)))
+    for k, (net, text) in enumerate(c4_networks()):
+        out.append((net, text, dict(confidence=0.95, half_width=0.01, seed=1, model_id=512 + k,
+                                    max_events=C3_CAP)))
+    return out
 
 
 def mm_sweep(n_sets=512, seed=4, decades=1.0):
@@ -177,17 +223,6 @@ def mm_sweep(n_sets=512, seed=4, decades=1.0):
     base = np.log10(np.asarray(MM_RATES))
     logs = base[None, :] + rng.uniform(-decades, decades, size=(n_sets, 3))
     return 10.0 ** logs
-
-
-def c4_networks(n_random=64, seed=5, s_min=8, s_max=128, delta=C3_DELTA):
-    """Random networks of uneven size: S log-uniform in [s_min, s_max], M = 4 S."""
-    rng = np.random.default_rng(seed)
-    out = []
-    for q in range(n_random):
-        S = int(round(10.0 ** rng.uniform(math.log10(s_min), math.log10(s_max))))
-        net = random_network(S, 4 * S, seed * 1000 + q)
-        out.append((net, nested_until_formula(net, delta, c3_species(net))))
-    return out
 
 
 def surrogate_queries(n=1_000_000, seed=6, decades=1.0):

@@ -119,8 +119,24 @@ def _wide_mode(ctx, B, mode):
 WIDE_MODES = pytest.mark.parametrize("mode", ["generic", "specialized"])
 
 
+C3_PARITY_N = 2048
+_c3_oracle = {}
+
+
+def _c3_expected(net, text):
+    """Oracle (events, verdict, reason) of C3's first trajectories (seed 1,
+    the 10^5-event cap), computed once for both kernel kinds."""
+    if text not in _c3_oracle:
+        _c3_oracle[text] = oracle.trajectories(net, oracle.parse(text, net), 0, C3_PARITY_N, seed=1,
+                                               max_events=W.C3_CAP)
+    return _c3_oracle[text]
+
+
 @WIDE_MODES
 def test_c3_random_network_parity(ctx, mode):
+    """C3 as configured (64 species, 256 channels, the nested until over
+    X0..X3 with the pilot's offset): the first 2048 trajectories are
+    bit-identical to the oracle's, and both verdicts occur."""
     B = _B()
     net = W.c3_network()
     text = W.c3_formula(net)
@@ -129,19 +145,23 @@ def test_c3_random_network_parity(ctx, mode):
     p = B.params(seed=1, max_events=W.C3_CAP)
     _wide_mode(ctx, B, mode)
     try:
-        ev, vd, rs = ctx.trajectories(n, f, p, 0, 96)
+        print(f"case c3 mode {mode} trajectories {C3_PARITY_N}", flush=True)
+        ev, vd, rs = ctx.trajectories(n, f, p, 0, C3_PARITY_N)
         assert ctx.last_kernel() == (B.KERNEL_GENERIC if mode == "generic" else B.KERNEL_SPECIALIZED)
     finally:
         ctx.set_specialization(B.SPECIALIZE_AUTO)
-    oev, ovd, ors = oracle.trajectories(net, oracle.parse(text, net), 0, 96, seed=1, max_events=W.C3_CAP)
-    assert np.array_equal(ev, oev) and np.array_equal(vd, ovd) and np.array_equal(rs, ors)
+    oev, ovd, ors = _c3_expected(net, text)
+    assert np.array_equal(rs, ors), np.nonzero(rs != ors)[0][:5]
+    assert np.array_equal(vd, ovd), np.nonzero(vd != ovd)[0][:5]
+    assert np.array_equal(ev, oev), np.nonzero(ev != oev)[0][:5]
+    assert 0.2 * C3_PARITY_N <= int(vd.sum()) <= 0.8 * C3_PARITY_N
 
 
 @WIDE_MODES
 def test_large_network_parity(ctx, mode):
     B = _B()
     net = W.random_network(128, 512, seed=7)
-    text = W.nested_until_formula(net, 15, W.c3_species(net))
+    text = W.nested_until_formula(net, 15)
     n = ctx.network(net)
     f = ctx.formula(n, text)
     p = B.params(seed=5, max_events=20000)
@@ -219,7 +239,8 @@ def test_batch_matches_single_jobs(ctx, speculate):
         p = B.params(seed=1, model_id=k, half_width=0.05, speculate=speculate)
         jobs.append((nh, fh, p))
         singles.append((net, W.MM_COMPANION_FORMULA, k))
-    for q, (net, text) in enumerate(W.c4_networks(2, seed=12)):
+    for q, net in enumerate(W.c4_random_networks(2, seed=12)):
+        text = W.nested_until_formula(net, 20)
         nh = ctx.network(net)
         fh = ctx.formula(nh, text)
         keep.append((nh, fh))
@@ -447,7 +468,7 @@ def test_mixed_batch_matches_oracle(ctx, speculate):
         models.append((W.michaelis_menten(*rr), W.MM_COMPANION_FORMULA, 0))
     for q in range(3):
         rn = W.random_network(8 + 4 * q, 4 * (8 + 4 * q), seed=77 + q)
-        models.append((rn, W.nested_until_formula(rn, W.C3_DELTA, W.c3_species(rn)), 3000))
+        models.append((rn, W.nested_until_formula(rn, 20), 3000))
     keep, jobs = [], []
     for k, (net, text, cap) in enumerate(models):
         nh = ctx.network(net)
