@@ -27,17 +27,30 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Vector issue slots per SSA event (per lane) that the direct method needs, a
-# quarter-rate instruction counting 4: Philox4x32-10 96 (nineteen 32x32->64
-# multiplies and twenty XORs: the first round's product of the model id is the
-# job's, and the key schedule is wave-uniform), two 53-bit uniforms 13, ln 41, tau divide 10, time update and
-# tests 3, loop control 4; then, for the Michaelis-Menten formula (C2) and the
-# immigration-death formula (C1): propensities 7 / 2, prefix and target 3 / 2,
-# channel selection 4 / 2, state update 7 / 3, monitor 18 / 8.
-WORK_SLOTS_PER_EVENT_C2 = 206
-WORK_SLOTS_PER_EVENT_C1 = 184
 PEAK_VALU_SLOTS = 256 * 64 * 2.4e9    # CUs x lanes x clock: 3.93e13 lane-slots/s
 N_TRAJ = 10**6
+C1_FIXED_N = 1 << 22
+
+
+def work_slots_per_event(net, n_preds):
+    """Vector issue slots per SSA event (per lane) that one direct-method step
+    needs, a quarter-rate instruction counting 4, part by part:
+      Philox4x32-10 (twenty 32x32->64 multiplies at quarter rate, XORs) 110,
+      two 53-bit uniforms 10, ln 30, the IEEE divide of tau 10, the time
+      update and bound tests 3                                   = 163;
+      propensities: 1 per zero-order, 2 per first-order (convert, multiply)
+      and 4 per second-order channel; the prefix sum M; r = u2 a0 1;
+      selection min(M, 3 ceil(log2 M)) (linear or binary search); the state
+      update 8 (at most four entries); the monitor 2 per predicate.
+    Michaelis-Menten with its three predicates: 192; immigration-death with
+    one: 181; a 256-channel half-bimolecular network with four: 1228."""
+    import numpy as np
+    reac = np.asarray(net.reactants).reshape(-1, 2)
+    order = (reac >= 0).sum(axis=1)
+    M = int(order.shape[0])
+    prop = int(np.sum(np.where(order == 0, 1, np.where(order == 1, 2, 4))))
+    search = min(M, 3 * int(math.ceil(math.log2(M)))) if M > 1 else 1
+    return 163 + prop + M + 1 + search + 8 + 2 * int(n_preds)
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ssa_spec_kernel_mm_c2_hbm_counters.txt")
@@ -49,18 +62,46 @@ def measured_traffic():
     """HBM bytes per launch from the committed counter summary (FETCH_SIZE and
     WRITE_SIZE scaled by the copy calibration), or None when the kernel
     sources have changed since the counters were taken."""
-    import hashlib
     try:
         fields = dict(l.split(": ", 1) for l in open(TRAFFIC_PROFILE).read().splitlines() if ": " in l)
     except OSError:
         return None
+    if fields.get("kernel_sources_sha256", "").strip() != kernel_sources_sha256():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
+SQ_PROFILE = os.path.join(ROOT, "profiles", "ssa_spec_kernel_mm_c2_sq_counters.txt")
+
+
+def kernel_sources_sha256():
+    import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    if fields.get("kernel_sources_sha256", "").strip() != h.hexdigest():
+    return h.hexdigest()
+
+
+def measured_valu_busy():
+    """VALU busy fraction of the C2 kernel from the committed shader-sequencer
+    counter summary (ACTIVE_INST_VALU x 4 / (BUSY_CU_CYCLES x 4 SIMDs)), or
+    None when the kernel sources have changed since the counters were taken."""
+    try:
+        fields = dict(l.split(": ", 1) for l in open(SQ_PROFILE).read().splitlines() if ": " in l)
+    except OSError:
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    if fields.get("kernel_sources_sha256", "").strip() != kernel_sources_sha256():
+        return None
+    return {"valu_busy": float(fields["valu_busy"]),
+            "vector_instructions_per_wave_event": float(fields["vector_instructions_per_wave_event"]),
+            "scalar_instructions_per_wave_event": float(fields["scalar_instructions_per_wave_event"])}
+
+
+def n_predicates(text):
+    """Comparisons in a formula's text (one per state predicate)."""
+    import re
+    return len(re.findall(r"<=|>=|!=|<|>|=", text))
 
 
 def copy_calibration():
@@ -82,16 +123,50 @@ def progress(what):
     print(f"[bench {time.perf_counter() - _T_START:7.1f} s] {what} done", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(net, text, sample):
+def host_cpu():
+    model = "unknown"
+    try:
+        for l in open("/proc/cpuinfo"):
+            if l.startswith("model name"):
+                model = l.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count(), len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(net, text, sample, sample_1core, c3_sample):
+    """The oracle on the host: the C2 sample on one thread per core (up to
+    16), a smaller C2 sample on one thread, and a prefix of the C3 random
+    network's trajectories."""
     import oracle
+    from paper_0912_2551_amd import workloads as W
     threads = oracle.default_threads()
     f = oracle.parse(text, net)
     t0 = time.perf_counter()
     ev, vd, rs = oracle.trajectories(net, f, 0, sample, seed=1, threads=threads)
     dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    ev1, _, _ = oracle.trajectories(net, f, 0, sample_1core, seed=1, threads=1)
+    dt1 = time.perf_counter() - t1
+    n3 = W.c3_network()
+    f3 = oracle.parse(W.c3_formula(n3), n3)
+    t3 = time.perf_counter()
+    ev3, vd3, _ = oracle.trajectories(n3, f3, 0, c3_sample, seed=1, max_events=W.C3_CAP, threads=threads)
+    dt3 = time.perf_counter() - t3
+    model, ncpu, affinity = host_cpu()
     return {"value": float(ev.sum()) / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
             "sample": f"first {sample} trajectories of the workload (seed 1), {int(ev.sum())} events, "
-                      f"{dt:.2f} s, {sample / dt:.0f} trajectories/s"}
+                      f"{dt:.2f} s, {sample / dt:.0f} trajectories/s",
+            "cpu_model": model, "nproc": ncpu, "affinity": affinity,
+            "one_core": {"value": float(ev1.sum()) / dt1, "unit": "events/s", "cores": 1,
+                         "sample": f"first {sample_1core} trajectories of the workload, {int(ev1.sum())} "
+                                   f"events, {dt1:.2f} s"},
+            "c3_prefix": {"value": float(ev3.sum()) / dt3, "unit": "events/s", "cores": threads,
+                          "trajectories_per_s": c3_sample / dt3,
+                          "sample": f"first {c3_sample} trajectories of the random network (seed 1, "
+                                    f"cap 10^5), {int(ev3.sum())} events, {dt3:.2f} s, "
+                                    f"p_hat {float(vd3.mean()):.4f}"}}
 
 
 def random_network_run(ctx, B, W, n=100_000):
@@ -108,10 +183,15 @@ def random_network_run(ctx, B, W, n=100_000):
     r = ctx.estimate(nh, fh, p)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return {"workload": "random network S=64 M=256 (seed 1), nested until, 10^5 trajectories, cap 10^5",
+    slots = work_slots_per_event(net, n_predicates(W.c3_formula(net)))
+    return {"workload": f"random network S=64 M=256 (seed 1), nested until over X0..X3 with d = {W.c3_delta()} "
+                        "(oracle pilot), 10^5 trajectories, cap 10^5",
             "seconds": wall, "device_seconds": r["device_seconds"], "events": r["events"],
-            "events_per_s": r["events"] / wall, "verified_trajectories_per_s": r["n"] / wall,
-            "truncated": r["truncated"], "p_hat": r["p_hat"], "interval_95": [r["lo"], r["hi"]]}
+            "events_per_s": r["events"] / wall, "trajectories_per_s": r["n"] / wall,
+            "truncated": r["truncated"], "p_hat": r["p_hat"], "interval_95": [r["lo"], r["hi"]],
+            "kernel": "specialised" if ctx.last_kernel() == B.KERNEL_SPECIALIZED else "generic",
+            "work_slots_per_event": slots,
+            "roofline_frac": slots * r["events"] / r["device_seconds"] / PEAK_VALU_SLOTS}
 
 
 def batched_sweep_run(ctx, B, W):
@@ -121,17 +201,11 @@ def batched_sweep_run(ctx, B, W):
     Wilson rule, in one persistent launch."""
     import torch
     keep, jobs = [], []
-    for k, rr in enumerate(W.mm_sweep(512, seed=4)):
-        a = ctx.network(W.michaelis_menten(*rr))
-        b = ctx.formula(a, W.C2_FORMULA)
+    for net, text, kw in W.c4_jobs():
+        a = ctx.network(net)
+        b = ctx.formula(a, text)
         keep.append((a, b))
-        jobs.append((a, b, B.params(confidence=0.95, half_width=0.01, seed=1, model_id=k)))
-    for k, (rn, rt) in enumerate(W.c4_networks(64, seed=5)):
-        a = ctx.network(rn)
-        b = ctx.formula(a, rt)
-        keep.append((a, b))
-        jobs.append((a, b, B.params(confidence=0.95, half_width=0.01, seed=1, model_id=512 + k,
-                                    max_events=W.C3_CAP)))
+        jobs.append((a, b, B.params(**kw)))
     ctx.estimate_batch(jobs[:1])   # kernel choice and warm-up outside the timed region
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -140,11 +214,16 @@ def batched_sweep_run(ctx, B, W):
     wall = time.perf_counter() - t0
     ev = sum(r["events"] for r in res)
     n = sum(r["n"] for r in res)
-    return {"workload": "512 Michaelis-Menten rate sets + 64 random networks (S 8..128, M = 4S), "
-                        "95% Wilson +-0.01 each, one launch",
+    nets = res[512:]
+    return {"workload": "512 Michaelis-Menten rate sets + 64 random networks (S 8..128, M = 4S, offsets d "
+                        "from the oracle pilot), 95% Wilson +-0.01 each, one launch",
             "models": len(jobs), "seconds": wall, "device_seconds": res[0]["device_seconds"],
             "verified_trajectories": n, "verified_trajectories_per_s": n / wall, "events": ev,
-            "events_per_s": ev / wall, "max_batches": max(r["batches"] for r in res)}
+            "events_per_s": ev / wall, "wasted": sum(r["wasted"] for r in res),
+            "max_batches": max(r["batches"] for r in res),
+            "networks": {"trajectories": sum(r["n"] for r in nets), "events": sum(r["events"] for r in nets),
+                         "truncated": sum(r["truncated"] for r in nets),
+                         "p_hat_in_0.2_0.8": sum(1 for r in nets if 0.2 <= r["p_hat"] <= 0.8)}}
 
 
 def fig3_sample_sizes(ctx, B, W, reps=32, eps=0.025, confidence=0.99):
@@ -186,14 +265,18 @@ def fig3_sample_sizes(ctx, B, W, reps=32, eps=0.025, confidence=0.99):
             "seconds": wall, "jobs": len(jobs), "rows": rows}
 
 
-def surrogate_vs_plain(ctx, B, W, text, n_train=512, n_query=10**6, n_sub=4096, eps=0.01, margin=0.05,
-                       steps=2000):
+def surrogate_vs_plain(ctx, B, W, text, n_train=512, n_cal=1024, n_query=10**6, n_sub=4096, eps=0.01,
+                       margin=0.05, steps=2000):
     """Answer n_query rate points either with plain batched SMC or with the
-    surrogate (plain SMC on n_train sweep points, training, one fused query
-    launch) plus SMC fallback on the points the gate rejects.  Plain SMC is
-    timed on the first n_sub query points (a uniform subsample, the points are
-    i.i.d.) and scaled to n_query; the fallback is timed the same way, as one
-    batch of the subsample's rejected points, scaled likewise."""
+    surrogate plus SMC fallback.  The surrogate path: plain SMC on the n_train
+    sweep points, training, plain SMC on n_cal held-out points that calibrate
+    the gate (the smallest margin, at least `margin`, at which no held-out
+    answer lies more than eps outside its Wilson interval), one fused query
+    launch, and SMC on the points the gate rejects.  Plain SMC is timed on the
+    first n_sub query points (a uniform subsample, the points are i.i.d.) and
+    scaled to n_query; the fallback is timed the same way, as one batch of the
+    subsample's rejected points, scaled likewise.  The answered subsample
+    points are then checked against their plain-SMC Wilson intervals."""
     import torch
     import numpy as np
     keep = []
@@ -207,13 +290,17 @@ def surrogate_vs_plain(ctx, B, W, text, n_train=512, n_query=10**6, n_sub=4096, 
             jobs.append((nh, fh, B.params(confidence=0.95, half_width=eps, seed=seed, model_id=k)))
         return jobs
 
+    def timed_batch(jobs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ctx.estimate_batch(jobs) if jobs else []
+        torch.cuda.synchronize()
+        return res, time.perf_counter() - t0
+
     train = W.mm_sweep(n_train, seed=4)
     jt = jobs_for(train, 1)
     ctx.estimate_batch(jt[:1])   # compiles the kernel for this structure outside the timed regions
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = ctx.estimate_batch(jt)
-    t_train_smc = time.perf_counter() - t0
+    res, t_train_smc = timed_batch(jt)
     x = np.log10(train).astype(np.float32)
     y = np.array([r["p_hat"] for r in res], dtype=np.float32)
     w = np.array([r["n"] for r in res], dtype=np.float32)
@@ -221,34 +308,36 @@ def surrogate_vs_plain(ctx, B, W, text, n_train=512, n_query=10**6, n_sub=4096, 
     sg = B.Surrogate(ctx, seed=4)
     losses = sg.train(x, y, w, steps=steps, lr=2e-3)
     t_fit = time.perf_counter() - t0
-    q = W.surrogate_queries(n_query, seed=6)
-    sg.query(q[:4096], margin=margin)
+    xc = W.surrogate_queries(n_cal, seed=7)
+    cal, t_cal_smc = timed_batch(jobs_for(10.0 ** xc.astype(np.float64), 3))
     t0 = time.perf_counter()
-    p, use = sg.query(q, margin=margin)
+    cal_margin, cal_share = sg.calibrate(xc, [r["lo"] for r in cal], [r["hi"] for r in cal], threshold=0.5,
+                                         bound=eps, min_margin=margin)
+    t_cal = time.perf_counter() - t0
+    q = W.surrogate_queries(n_query, seed=6)
+    sg.query(q[:4096])
+    t0 = time.perf_counter()
+    p, use = sg.query(q)
     t_query = time.perf_counter() - t0
     js = jobs_for(10.0 ** q[:n_sub].astype(np.float64), 2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plain = ctx.estimate_batch(js)
-    t_sub = time.perf_counter() - t0
+    plain, t_sub = timed_batch(js)
     u = use[:n_sub]
-    jf = [j for j, ui in zip(js, u) if not ui]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    if jf:
-        ctx.estimate_batch(jf)
-    t_fallback_sub = time.perf_counter() - t0
+    _, t_fallback_sub = timed_batch([j for j, ui in zip(js, u) if not ui])
     plain_total = t_sub * n_query / n_sub
     fallback_total = t_fallback_sub * n_query / n_sub
-    sur_total = t_train_smc + t_fit + t_query + fallback_total
+    sur_total = t_train_smc + t_fit + t_cal_smc + t_cal + t_query + fallback_total
     err = np.array([max(r["lo"] - pi, pi - r["hi"], 0.0) for r, pi, ui in zip(plain, p[:n_sub], u) if ui])
-    return {"formula": text, "queries": n_query, "train_points": n_train, "subsample": n_sub,
-            "plain_seconds_scaled": plain_total, "surrogate_plus_fallback_seconds": sur_total,
-            "speedup": plain_total / sur_total, "surrogate_share": float(use.mean()),
-            "train_smc_seconds": t_train_smc, "fit_seconds": t_fit, "fit_steps": steps,
-            "final_loss": float(losses[-1]), "query_seconds": t_query,
+    return {"formula": text, "queries": n_query, "train_points": n_train, "calibration_points": n_cal,
+            "subsample": n_sub, "plain_seconds_scaled": plain_total,
+            "surrogate_plus_fallback_seconds": sur_total, "speedup": plain_total / sur_total,
+            "surrogate_share": float(use.mean()), "train_smc_seconds": t_train_smc, "fit_seconds": t_fit,
+            "fit_steps": steps, "final_loss": float(losses[-1]), "calibration_smc_seconds": t_cal_smc,
+            "calibrated_margin": cal_margin, "calibration_share": cal_share, "query_seconds": t_query,
             "query_points_per_s": n_query / t_query, "fallback_seconds_scaled": fallback_total,
-            "error_vs_wilson": {"answered": int(err.size), "inside_interval": float(np.mean(err == 0)) if err.size else None,
+            "error_vs_wilson": {"answered": int(err.size),
+                                "inside_interval": float(np.mean(err == 0)) if err.size else None,
+                                "within_eps": float(np.mean(err <= eps)) if err.size else None,
+                                "within_2eps": float(np.mean(err <= 2 * eps)) if err.size else None,
                                 "within_margin": float(np.mean(err <= margin)) if err.size else None,
                                 "max_outside": float(err.max()) if err.size else None}}
 
@@ -262,6 +351,8 @@ def main():
     ap.add_argument("--no-c1", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the random-network and batched-sweep runs")
+    ap.add_argument("--no-c3", action="store_true", help="skip the random-network run")
+    ap.add_argument("--no-c4", action="store_true", help="skip the batched-sweep run")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=N_TRAJ)
     ap.add_argument("--waves-per-cu", type=int, default=0)
@@ -322,7 +413,8 @@ def main():
     kernel_name = ("smc_spec_kernel (specialised to the network and formula)"
                    if ctx.last_kernel() == B.KERNEL_SPECIALIZED else "ssa_persistent (generic)")
     ev_per_launch = events / args.steps
-    achieved = WORK_SLOTS_PER_EVENT_C2 * ev_per_launch / kernel_s
+    slots_c2 = work_slots_per_event(net, n_predicates(W.C2_FORMULA))
+    achieved = slots_c2 * ev_per_launch / kernel_s
     line = {
         "metric": "SSA events/s + verified trajectories/s at 95% Wilson +-0.01; surrogate vs plain",
         "value": value,
@@ -340,14 +432,17 @@ def main():
                                "(P<500) U[0,60] (S<=200) & G[0,60](E>=10), 10^6 trajectories per step",
                    "trajectories_per_step": N_TRAJ, "events_per_step": ev_per_launch,
                    "parallelism": "1 GPU, one trajectory per lane"},
-        "verified_trajectories_per_s": trajectories / wall,
+        # verdicts per second of the fixed-size steps above (not a Wilson-driven figure)
+        "trajectories_per_s_fixed_n": trajectories / wall,
+        "verified_trajectories_per_s": None,
         "autotune": tune,
         "p_hat": r["p_hat"], "interval_95": [r["lo"], r["hi"]],
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_SLOTS / 1e12,
                      "unit": "Tslot/s", "frac": achieved / PEAK_VALU_SLOTS, "traffic": measured_traffic(),
                      "traffic_unit": "bytes per launch",
                      "kernel": kernel_name, "kernel_ms": 1e3 * kernel_s,
-                     "work_slots_per_event": WORK_SLOTS_PER_EVENT_C2},
+                     "work_slots_per_event": slots_c2,
+                     "counters": measured_valu_busy()},
     }
     progress("C2 steps")
     if not args.no_c1:
@@ -363,16 +458,33 @@ def main():
             r1 = ctx.estimate(n1, f1, p1)
         torch.cuda.synchronize()
         w1 = (time.perf_counter() - t1) / reps
-        line["wilson_c1"] = {"workload": "immigration-death F[0,100](X>=120), 95% Wilson +-0.01",
+        line["wilson_c1"] = {"workload": "immigration-death F[0,100](X>=120), 95% Wilson +-0.01 (Fig. 2)",
                              "n": r1["n"], "batches": r1["batches"], "p_hat": r1["p_hat"],
-                             "interval": [r1["lo"], r1["hi"]], "seconds": w1,
+                             "interval": [r1["lo"], r1["hi"]], "seconds": w1, "wasted": r1["wasted"],
                              "verified_trajectories_per_s": r1["n"] / w1, "events_per_s": r1["events"] / w1}
-        progress("C1 Wilson run")
+        # the metric's verified trajectories per second: the Wilson-driven run
+        line["verified_trajectories_per_s"] = r1["n"] / w1
+        # the same model at a fixed 2^22 trajectories: a launch that fills the device
+        pf = B.params(fixed_n=C1_FIXED_N, seed=1, confidence=0.95)
+        ctx.estimate(n1, f1, pf)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rf = ctx.estimate(n1, f1, pf)
+        torch.cuda.synchronize()
+        wf = time.perf_counter() - t1
+        slots_c1 = work_slots_per_event(c1, n_predicates(W.C1_FORMULA))
+        line["c1_fixed_n"] = {"workload": "immigration-death F[0,100](X>=120), 2^22 trajectories",
+                              "seconds": wf, "device_seconds": rf["device_seconds"], "events": rf["events"],
+                              "events_per_s": rf["events"] / wf, "p_hat": rf["p_hat"],
+                              "work_slots_per_event": slots_c1,
+                              "roofline_frac": slots_c1 * rf["events"] / rf["device_seconds"] / PEAK_VALU_SLOTS}
+        progress("C1 Wilson and fixed-N runs")
     line["fig3_sample_sizes"] = fig3_sample_sizes(ctx, B, W)
     progress("Fig. 3 sample sizes")
-    if not args.no_large:
+    if not args.no_large and not args.no_c3:
         line["c3_random_network"] = random_network_run(ctx, B, W)
         progress("C3 random network")
+    if not args.no_large and not args.no_c4:
         line["c4_batched_sweep"] = batched_sweep_run(ctx, B, W)
         progress("C4 batched sweep")
     if not args.no_surrogate:
@@ -381,7 +493,7 @@ def main():
             line["surrogate_vs_plain"].append(surrogate_vs_plain(ctx, B, W, t))
             progress(f"surrogate vs plain SMC, {t}")
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(net, W.C2_FORMULA, args.cpu_sample)
+        line["cpu_baseline"] = cpu_baseline(net, W.C2_FORMULA, args.cpu_sample, args.cpu_sample // 10, 1000)
         progress("CPU baseline")
     print(json.dumps(line), flush=True)
 

@@ -64,6 +64,14 @@ extern "C" {
                                      capacity runs at once and Fig. 2 is applied to the
                                      recorded outcomes in index order; results are
                                      identical, the extra trajectories are discarded.  */
+#define SMC_DEVICE_PTRS 8u        /* the large arrays of the call are device pointers
+                                     on the context's device (e.g. a torch tensor's
+                                     data_ptr()): smc_trajectories' events and
+                                     verdict_reason, smc_sample_state's counts.  The
+                                     kernels write them in place, with no host copy;
+                                     the call still returns once they are written.  For
+                                     smc_surrogate_query the same bit goes in its own
+                                     flags argument.                                 */
 
 typedef struct smc_ctx smc_ctx;
 typedef struct smc_net smc_net;
@@ -205,6 +213,10 @@ typedef struct {
     uint64_t events;       /* SSA events (applied transitions) over them         */
     uint64_t truncated;    /* trajectories stopped by max_events                 */
     uint64_t batches;      /* sample-size iterations (1 with fixed_n)            */
+    uint64_t wasted;       /* iterative jobs: trajectories issued past the final n
+                              (run ahead of a batch decision, or every index up to
+                              the capacity in a speculative launch) and discarded;
+                              0 with fixed_n                                     */
     double z;              /* z_{1-alpha/2} used                                 */
     double device_seconds; /* kernel time on the device (HIP events)             */
     int32_t status;        /* SMC_OK or the failure of this job                  */
@@ -230,12 +242,16 @@ int smc_estimate_batch(smc_ctx *ctx, const smc_job *jobs, size_t n_jobs, smc_res
 
 /* Per-trajectory results for indices first .. first+count-1 (the same
  * trajectories smc_estimate would draw): events[k] = applied transitions,
- * verdict_reason[k] = verdict | reason << 1.  Either output may be NULL. */
+ * verdict_reason[k] = verdict | reason << 1.  Either output may be NULL.
+ * With SMC_DEVICE_PTRS in p->flags both are device pointers (events 4-byte
+ * aligned) that the kernel writes directly; a NULL output is then skipped
+ * too.  Errors: SMC_E_INVALID, and those of smc_estimate. */
 int smc_trajectories(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_params *p,
                      uint64_t first, uint64_t count, uint32_t *events, uint8_t *verdict_reason);
 
 /* SSA probe: the state sigma@T of trajectories first .. first+count-1,
- * counts[k*S + s] (no formula involved). */
+ * counts[k*S + s] (no formula involved).  With SMC_DEVICE_PTRS in p->flags,
+ * counts is a device pointer written in place. */
 int smc_sample_state(smc_ctx *ctx, const smc_net *net, const smc_params *p, double T,
                      uint64_t first, uint64_t count, int32_t *counts);
 
@@ -319,9 +335,30 @@ int smc_surrogate_gradients(smc_surrogate *s, const float *x, const float *y, co
 int smc_surrogate_train(smc_surrogate *s, const float *x, const float *y, const float *w, size_t n,
                         const smc_train_opts *opts, float *loss_out);
 /* p_out[k] = network output at x[k]; use_surrogate[k] (optional) = 1 when
- * x[k] lies in the training hull and |p_out[k] - threshold| >= margin. */
+ * x[k] lies in the training hull and |p_out[k] - threshold| >= margin.
+ * flags: 0, or SMC_DEVICE_PTRS when x, p_out and use_surrogate are device
+ * pointers on the surrogate's device (read and written in place, no host
+ * copies). */
 int smc_surrogate_query(smc_surrogate *s, const float *x, size_t n, float threshold, float margin,
-                        float *p_out, uint8_t *use_surrogate);
+                        uint32_t flags, float *p_out, uint8_t *use_surrogate);
+/* Calibrate the gate on held-out plain-SMC estimates (points that were not
+ * trained on): x[n][3] log10 rates and each point's Wilson interval
+ * [lo[k], hi[k]] (eq. 3).  The calibrated margin is the smallest m >=
+ * min_margin such that every held-out point inside the training hull with
+ * |p(x) - threshold| >= m has p(x) within [lo - bound, hi + bound]; from
+ * then on smc_surrogate_query (at this threshold) answers only with a
+ * margin of at least m.  For points drawn like the held-out ones, an answer
+ * that lies more than `bound` outside that point's interval then has
+ * probability at most 1/(n+1) (exchangeability: it would have to be the
+ * largest of n+1 such levels).  If m would exceed 0.5, or no held-out point
+ * lies in the hull, the gate refuses every query (use_surrogate = 0) until
+ * the network is retrained or recalibrated; queries at another threshold
+ * are refused too.  Outputs (optional): *margin_out = m (-1 when refused),
+ * *share_out = share of the held-out points answered.  Training or setting
+ * parameters clears the calibration.  Errors: SMC_E_INVALID. */
+int smc_surrogate_calibrate(smc_surrogate *s, const float *x, const double *lo, const double *hi, size_t n,
+                            float threshold, float bound, float min_margin, float *margin_out,
+                            float *share_out);
 /* Facets of the training hull as planes (nx, ny, nz, d), inside: n.x <= d.
  * Writes up to cap planes; returns the number of facets. */
 int smc_surrogate_hull(const smc_surrogate *s, float *planes, size_t cap);

@@ -29,6 +29,7 @@ SMC_E_TIMEOUT = -7
 SMC_CONSERVATIVE_START = 1
 SMC_PAPER_ROUNDING = 2
 SMC_NO_SPECULATION = 4
+SMC_DEVICE_PTRS = 8
 REASON_STATE, REASON_TIME, REASON_ABSORB, REASON_CAP, REASON_TMAX = range(5)
 
 SPECIALIZE_AUTO, SPECIALIZE_OFF, SPECIALIZE_REQUIRED = 0, 1, 2
@@ -43,7 +44,8 @@ EXPORTS = [
     "smc_sample_state", "smc_z_value", "smc_wilson_sample_value", "smc_wilson_sample",
     "smc_wilson_interval", "smc_wilson_next_device", "smc_surrogate_create",
     "smc_surrogate_param_count", "smc_surrogate_set_params", "smc_surrogate_get_params",
-    "smc_surrogate_gradients", "smc_surrogate_train", "smc_surrogate_query", "smc_surrogate_hull",
+    "smc_surrogate_gradients", "smc_surrogate_train", "smc_surrogate_query", "smc_surrogate_calibrate",
+    "smc_surrogate_hull",
     "smc_surrogate_destroy", "smc_convex_hull",
 ]
 
@@ -83,7 +85,8 @@ class Params(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("p_hat", ctypes.c_double), ("lo", ctypes.c_double), ("hi", ctypes.c_double),
                 ("n", ctypes.c_uint64), ("successes", ctypes.c_uint64), ("events", ctypes.c_uint64),
-                ("truncated", ctypes.c_uint64), ("batches", ctypes.c_uint64), ("z", ctypes.c_double),
+                ("truncated", ctypes.c_uint64), ("batches", ctypes.c_uint64), ("wasted", ctypes.c_uint64),
+                ("z", ctypes.c_double),
                 ("device_seconds", ctypes.c_double), ("status", ctypes.c_int32)]
 
     def as_dict(self):
@@ -135,10 +138,8 @@ def lib():
             "smc_formula_destroy": (None, [vp]),
             "smc_estimate": (i32, [vp, vp, vp, ctypes.POINTER(Params), ctypes.POINTER(Result)]),
             "smc_estimate_batch": (i32, [vp, ctypes.POINTER(JobDesc), ctypes.c_size_t, ctypes.POINTER(Result)]),
-            "smc_trajectories": (i32, [vp, vp, vp, ctypes.POINTER(Params), u64, u64,
-                                       ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint8)]),
-            "smc_sample_state": (i32, [vp, vp, ctypes.POINTER(Params), dbl, u64, u64,
-                                       ctypes.POINTER(ctypes.c_int32)]),
+            "smc_trajectories": (i32, [vp, vp, vp, ctypes.POINTER(Params), u64, u64, vp, vp]),
+            "smc_sample_state": (i32, [vp, vp, ctypes.POINTER(Params), dbl, u64, u64, vp]),
             "smc_z_value": (dbl, [dbl]),
             "smc_wilson_sample_value": (dbl, [dbl, dbl, dbl]),
             "smc_wilson_sample": (u64, [dbl, dbl, dbl]),
@@ -156,9 +157,11 @@ def lib():
             "smc_surrogate_train": (i32, [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                                           ctypes.POINTER(ctypes.c_float), ctypes.c_size_t,
                                           ctypes.POINTER(TrainOpts), ctypes.POINTER(ctypes.c_float)]),
-            "smc_surrogate_query": (i32, [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t, ctypes.c_float,
-                                          ctypes.c_float, ctypes.POINTER(ctypes.c_float),
-                                          ctypes.POINTER(ctypes.c_uint8)]),
+            "smc_surrogate_query": (i32, [vp, vp, ctypes.c_size_t, ctypes.c_float, ctypes.c_float,
+                                          ctypes.c_uint32, vp, vp]),
+            "smc_surrogate_calibrate": (i32, [vp, vp, vp, vp, ctypes.c_size_t, ctypes.c_float, ctypes.c_float,
+                                              ctypes.c_float, ctypes.POINTER(ctypes.c_float),
+                                              ctypes.POINTER(ctypes.c_float)]),
             "smc_surrogate_hull": (i32, [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
             "smc_surrogate_destroy": (None, [vp]),
             "smc_convex_hull": (i32, [ctypes.POINTER(ctypes.c_float), ctypes.c_size_t,
@@ -174,6 +177,12 @@ def lib():
 
 def _ptr(a, ct):
     return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _dptr(t):
+    """Device address of an array object (anything with data_ptr(), such as a
+    torch tensor), or None."""
+    return None if t is None else ctypes.c_void_p(int(t.data_ptr()))
 
 
 def params(confidence=0.95, half_width=0.01, z=0.0, fixed_n=0, seed=1, model_id=0, max_events=0,
@@ -278,8 +287,16 @@ class Context:
         ev = np.zeros(count, dtype=np.uint32)
         vr = np.zeros(count, dtype=np.uint8)
         self._check(lib().smc_trajectories(self.h, network.h, formula.h, ctypes.byref(p), first, count,
-                                           _ptr(ev, ctypes.c_uint32), _ptr(vr, ctypes.c_uint8)))
+                                           ev.ctypes.data, vr.ctypes.data))
         return ev, vr & 1, vr >> 1
+
+    def trajectories_device(self, network, formula, p: Params, first: int, count: int, events, verdict_reason):
+        """smc_trajectories into device arrays (objects with data_ptr(), e.g.
+        torch tensors of int32/uint8 on the context's device, or None)."""
+        q = Params.from_buffer_copy(p)
+        q.flags |= SMC_DEVICE_PTRS
+        self._check(lib().smc_trajectories(self.h, network.h, formula.h, ctypes.byref(q), first, count,
+                                           _dptr(events), _dptr(verdict_reason)))
 
     def wilson_next_device(self, successes, n, eps: float, z: float, paper_rounding=False):
         y = np.ascontiguousarray(successes, dtype=np.uint64)
@@ -293,8 +310,15 @@ class Context:
     def sample_state(self, network, p: Params, T: float, first: int, count: int):
         out = np.zeros((count, network.S), dtype=np.int32)
         self._check(lib().smc_sample_state(self.h, network.h, ctypes.byref(p), float(T), first, count,
-                                           _ptr(out, ctypes.c_int32)))
+                                           out.ctypes.data))
         return out
+
+    def sample_state_device(self, network, p: Params, T: float, first: int, count: int, counts):
+        """smc_sample_state into a device array (data_ptr(), int32 [count, S])."""
+        q = Params.from_buffer_copy(p)
+        q.flags |= SMC_DEVICE_PTRS
+        self._check(lib().smc_sample_state(self.h, network.h, ctypes.byref(q), float(T), first, count,
+                                           _dptr(counts)))
 
 
 class Network:
@@ -437,9 +461,27 @@ class Surrogate:
         n = xx.shape[0]
         p = np.zeros(n, dtype=np.float32)
         use = np.zeros(n, dtype=np.uint8)
-        self.ctx._check(lib().smc_surrogate_query(self.h, _ptr(xx, ctypes.c_float), n, threshold, margin,
-                                                  _ptr(p, ctypes.c_float), _ptr(use, ctypes.c_uint8)))
+        self.ctx._check(lib().smc_surrogate_query(self.h, xx.ctypes.data, n, threshold, margin, 0,
+                                                  p.ctypes.data, use.ctypes.data))
         return p, use.astype(bool)
+
+    def query_device(self, x, n: int, p_out, use_out=None, threshold=0.5, margin=0.05):
+        """smc_surrogate_query on device arrays (data_ptr(): x float32 [n, 3],
+        p_out float32 [n], use_out uint8 [n] or None)."""
+        self.ctx._check(lib().smc_surrogate_query(self.h, _dptr(x), int(n), threshold, margin, SMC_DEVICE_PTRS,
+                                                  _dptr(p_out), _dptr(use_out)))
+
+    def calibrate(self, x, lo, hi, threshold=0.5, bound=0.01, min_margin=0.05):
+        """Calibrate the gate on held-out estimates; returns (margin, share
+        answered), margin -1 when the gate refuses every query."""
+        xx = np.ascontiguousarray(x, dtype=np.float32)
+        ll = np.ascontiguousarray(lo, dtype=np.float64)
+        hh = np.ascontiguousarray(hi, dtype=np.float64)
+        m, share = ctypes.c_float(), ctypes.c_float()
+        self.ctx._check(lib().smc_surrogate_calibrate(self.h, xx.ctypes.data, ll.ctypes.data, hh.ctypes.data,
+                                                      xx.shape[0], threshold, bound, min_margin,
+                                                      ctypes.byref(m), ctypes.byref(share)))
+        return m.value, share.value
 
     def hull(self) -> np.ndarray:
         nf = lib().smc_surrogate_hull(self.h, None, 0)

@@ -168,13 +168,13 @@ double wilson_value(double p, double eps, double z)
     return (z * z) * num / (2.0 * e2);
 }
 
-double resolve_z(smc_ctx *ctx, const smc_params &p)
+double resolve_z(smc_ctx *ctx, const smc_params &p, bool cache = true)
 {
     if (p.z > 0.0) return p.z;
     auto it = ctx->zcache.find(p.confidence);
     if (it != ctx->zcache.end()) return it->second;
     const double z = smc_z_value(p.confidence);
-    ctx->zcache.emplace(p.confidence, z);
+    if (cache) ctx->zcache.emplace(p.confidence, z);
     return z;
 }
 
@@ -189,7 +189,7 @@ struct Prepared {
 };
 
 int prepare(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_params *p,
-            uint64_t first, Prepared &out)
+            uint64_t first, Prepared &out, bool cache_z = true)
 {
     if (!net || !f || !p) return fail(ctx, SMC_E_INVALID, "null network, formula or parameters");
     if (net->ctx != ctx || f->ctx != ctx) return fail(ctx, SMC_E_INVALID, "handle from another context");
@@ -201,7 +201,7 @@ int prepare(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_pa
     if (iterative || p->z > 0.0 || (p->confidence > 0.0 && p->confidence < 1.0)) {
         if (p->z <= 0.0 && !(p->confidence > 0.0 && p->confidence < 1.0))
             return fail(ctx, SMC_E_INVALID, "confidence must lie in (0, 1)");
-        z = resolve_z(ctx, *p);
+        z = resolve_z(ctx, *p, cache_z);
     }
     uint64_t n_first, capacity;
     if (iterative) {
@@ -268,14 +268,14 @@ std::pair<uint64_t, uint64_t> structure_key(const smc_net *net, const smc_formul
 
 // The specialised kernel for a launch, if every job shares one network
 // structure and formula that the specialisation supports (else nullptr).
-int pick_spec_kernel(smc_ctx *ctx, const std::vector<Prepared> &P, bool iterative, hipFunction_t *fn)
+int pick_spec_kernel(smc_ctx *ctx, const Prepared *P, int n, bool iterative, bool may_compile, hipFunction_t *fn)
 {
     *fn = nullptr;
-    if (ctx->spec_mode == SMC_SPECIALIZE_OFF || P.empty()) return SMC_OK;
+    if (ctx->spec_mode == SMC_SPECIALIZE_OFF || n == 0) return SMC_OK;
     const smc_net *n0 = P[0].net;
     const smc_formula *f0 = P[0].f;
     bool ok = n0 && f0 && spec_supported(n0->S, n0->M, f0->prog);
-    for (size_t k = 1; ok && k < P.size(); ++k)
+    for (int k = 1; ok && k < n; ++k)
         ok = P[k].net && P[k].f && same_structure(n0, f0, P[k].net, P[k].f);
     if (!ok) {
         if (ctx->spec_mode == SMC_SPECIALIZE_REQUIRED)
@@ -286,6 +286,13 @@ int pick_spec_kernel(smc_ctx *ctx, const std::vector<Prepared> &P, bool iterativ
     const auto hit = ctx->spec_fns.find(key);
     if (hit != ctx->spec_fns.end()) {
         *fn = hit->second;
+        return SMC_OK;
+    }
+    if (!may_compile) {
+        // loading a new code object allocates device memory
+        if (ctx->spec_mode == SMC_SPECIALIZE_REQUIRED)
+            return fail(ctx, SMC_E_UNSUPPORTED, "no specialised kernel compiled yet for this structure "
+                                                "(an allocation-free call does not compile one)");
         return SMC_OK;
     }
     const std::string src =
@@ -310,8 +317,27 @@ int pick_waves_per_cu(const smc_ctx *ctx)
     return 16;
 }
 
-// Run prepared jobs to completion.  rec_base (optional) is a device buffer
-// laid out as [events u32 ...][verdict bytes ...] for job 0.
+// The buffers of one run: device job descriptors, job states, results and
+// control block, and their host-side staging (2n job descriptors).
+struct Workspace {
+    Job *d_jobs;
+    JobState *d_states;
+    JobResult *d_results;
+    Control *d_ctl;
+    Job *h_jobs;
+    JobResult *h_results;
+    Control *h_ctl;
+    // pinned host staging: the result copy is queued behind the kernels;
+    // otherwise it is made once they are done
+    bool pinned;
+    // allocate nothing: no speculative launch (it needs per-index records)
+    // and no run-time compilation of a specialised kernel
+    bool no_alloc;
+};
+
+int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult *res, double *seconds);
+
+// Run prepared jobs to completion in the context's (grow-only) workspace.
 int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res, double *seconds)
 {
     const int n = (int)P.size();
@@ -320,11 +346,19 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
     if (ensure(ctx, ctx->d_results, ctx->cap_results, (size_t)n)) return SMC_E_NOMEM;
     if (ensure_pinned(ctx, ctx->h_jobs, ctx->cap_h_jobs, 2 * (size_t)n)) return SMC_E_NOMEM;
     if (ensure_pinned(ctx, ctx->h_results, ctx->cap_h_results, (size_t)n)) return SMC_E_NOMEM;
+    const Workspace W{ctx->d_jobs, ctx->d_states, ctx->d_results, ctx->d_ctl,
+                      ctx->h_jobs, ctx->h_results, ctx->h_ctl, true, false};
+    res.assign(n, JobResult{});
+    return run_jobs_in(ctx, P.data(), n, W, res.data(), seconds);
+}
+
+int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult *res, double *seconds)
+{
     int s_max = 1, m_max = 1, n_iter = 0;
-    Job *jobs = ctx->h_jobs;   // the previous call's copies have completed
+    Job *jobs = W.h_jobs;   // the previous call's copies have completed
     for (int k = 0; k < n; ++k) {
         jobs[k] = P[k].job;
-        jobs[k].st = ctx->d_states + k;
+        jobs[k].st = W.d_states + k;
         s_max = std::max(s_max, P[k].S);
         m_max = std::max(m_max, P[k].M);
         n_iter += jobs[k].iterative;
@@ -338,7 +372,7 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
     // each as long as its longest trajectory, on a device that is mostly idle.
     // jobs[n .. 2n) keep the iterative descriptions for the replay.
     bool speculative = false;
-    if (n_iter == n && !ctx->tuning) {
+    if (n_iter == n && !ctx->tuning && !W.no_alloc) {
         unsigned long long cap_total = 0;
         bool allow = true;
         for (int k = 0; k < n; ++k) {
@@ -364,7 +398,7 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
         }
     }
     hipStream_t s = ctx->stream;
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_jobs, jobs, n * sizeof(Job), hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipMemcpyAsync(W.d_jobs, jobs, n * sizeof(Job), hipMemcpyHostToDevice, s));
     *ctx->cancel_host = 0;
     ctx->cancel_req.store(0);
 
@@ -405,7 +439,7 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
     const int grid = (int)std::max<unsigned long long>(1, (waves + wpb - 1) / wpb);
     const int variant = m_max <= 4 ? 0 : 1;
     hipFunction_t spec_fn = nullptr;
-    if (const int rc = pick_spec_kernel(ctx, P, n_iter > 0, &spec_fn)) return rc;
+    if (const int rc = pick_spec_kernel(ctx, P, n, n_iter > 0, !W.no_alloc, &spec_fn)) return rc;
     // wide specialised kernels keep counts in LDS like the generic ones
     const size_t spec_lds = (spec_fn && spec_wide(P[0].S, P[0].M)) ? lds_wave * wpb : 0;
     // Static first shares (see init_jobs) only where they cannot hold work
@@ -419,9 +453,9 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
                                    : persistent_blocks_per_cu(variant, false, wpb, lds_wave * wpb);
         static_first = per_cu > 0 && (long long)per_cu * ctx->n_cu >= grid;
     }
-    HIP_TRY(ctx, launch_init(s, ctx->d_jobs, n, static_first ? grid * wpb : 0, ctx->d_ctl, n_iter));
+    HIP_TRY(ctx, launch_init(s, W.d_jobs, n, static_first ? grid * wpb : 0, W.d_ctl, n_iter));
     ctx->last_kernel = spec_fn ? SMC_KERNEL_SPECIALIZED : (variant == 0 ? SMC_KERNEL_GENERIC_SMALL : SMC_KERNEL_GENERIC);
-    res.assign(n, JobResult{});
+    for (int k = 0; k < n; ++k) res[k] = JobResult{};
     double total_ms = 0.0;
     const auto t_start = std::chrono::steady_clock::now();
     unsigned long long last_progress = ~0ull;
@@ -434,27 +468,30 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
         // init_jobs set the first launch's control block; the previous launch
         // (and its copies) completed before this point
         if (launch > 0) {
-            *ctx->h_ctl = Control{};
-            ctx->h_ctl->open_jobs = open;
-            HIP_TRY(ctx, hipMemcpyAsync(ctx->d_ctl, ctx->h_ctl, sizeof(Control), hipMemcpyHostToDevice, s));
+            *W.h_ctl = Control{};
+            W.h_ctl->open_jobs = open;
+            HIP_TRY(ctx, hipMemcpyAsync(W.d_ctl, W.h_ctl, sizeof(Control), hipMemcpyHostToDevice, s));
         }
         HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
         if (spec_fn)
-            HIP_TRY(ctx, launch_module(spec_fn, grid, wpb, spec_lds, s, ctx->d_jobs, n, s_max, ctx->d_ctl,
+            HIP_TRY(ctx, launch_module(spec_fn, grid, wpb, spec_lds, s, W.d_jobs, n, s_max, W.d_ctl,
                                        ctx->cancel_dev, 1 << 18, static_first && launch == 0));
         else
-            HIP_TRY(ctx, launch_persistent(variant, n_iter > 0, grid, wpb, lds_wave * wpb, s, ctx->d_jobs, n, s_max,
-                                           ctx->d_ctl, ctx->cancel_dev, 1 << 18, static_first && launch == 0));
+            HIP_TRY(ctx, launch_persistent(variant, n_iter > 0, grid, wpb, lds_wave * wpb, s, W.d_jobs, n, s_max,
+                                           W.d_ctl, ctx->cancel_dev, 1 << 18, static_first && launch == 0));
         if (speculative) {
-            HIP_TRY(ctx, hipMemcpyAsync(ctx->d_jobs, jobs + n, n * sizeof(Job), hipMemcpyHostToDevice, s));
-            HIP_TRY(ctx, launch_replay(s, ctx->d_jobs, n, ctx->d_results));
+            HIP_TRY(ctx, hipMemcpyAsync(W.d_jobs, jobs + n, n * sizeof(Job), hipMemcpyHostToDevice, s));
+            HIP_TRY(ctx, launch_replay(s, W.d_jobs, n, W.d_results));
         } else {
-            HIP_TRY(ctx, launch_finalize(s, ctx->d_jobs, n, ctx->d_results));
+            HIP_TRY(ctx, launch_finalize(s, W.d_jobs, n, W.d_results));
         }
         HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
         // the results travel back in the same stream, without a round trip
-        // through the host between the kernels' end and the copy
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->h_results, ctx->d_results, n * sizeof(JobResult), hipMemcpyDeviceToHost, s));
+        // through the host between the kernels' end and the copy (a copy to
+        // pageable memory would hold the host until it is done, so there it
+        // follows the wait)
+        if (W.pinned)
+            HIP_TRY(ctx, hipMemcpyAsync(W.h_results, W.d_results, n * sizeof(JobResult), hipMemcpyDeviceToHost, s));
         HIP_TRY(ctx, hipEventRecord(ctx->ev2, s));
         // wait under the watchdog
         for (;;) {
@@ -469,7 +506,11 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
         float ms = 0.0f;
         HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
         total_ms += ms;
-        std::memcpy(res.data(), ctx->h_results, n * sizeof(JobResult));
+        if (!W.pinned) {
+            HIP_TRY(ctx, hipMemcpyAsync(W.h_results, W.d_results, n * sizeof(JobResult), hipMemcpyDeviceToHost, s));
+            HIP_TRY(ctx, hipStreamSynchronize(s));
+        }
+        std::memcpy(res, W.h_results, n * sizeof(JobResult));
         if (*ctx->cancel_host) {
             *seconds = total_ms * 1e-3;
             return ctx->cancel_req.load() ? fail(ctx, SMC_E_CANCELLED, "cancelled")
@@ -498,9 +539,10 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
     return SMC_OK;
 }
 
-void fill_result(const JobResult &r, double z, smc_result *out)
+void fill_result(const JobResult &r, double z, bool iterative, smc_result *out)
 {
     out->n = r.n;
+    out->wasted = (iterative && r.issued > r.n) ? r.issued - r.n : 0;
     out->successes = r.yes;
     out->events = r.events;
     out->truncated = r.trunc;
@@ -944,7 +986,7 @@ int smc_estimate_batch(smc_ctx *c, const smc_job *jobs, size_t n_jobs, smc_resul
         return rc;
     }
     for (size_t k = 0; k < n_jobs; ++k) {
-        fill_result(res[k], P[k].z, &out[k]);
+        fill_result(res[k], P[k].z, P[k].job.iterative != 0, &out[k]);
         out[k].device_seconds = secs;
         if (out[k].status != SMC_OK && first_err == SMC_OK) {
             first_err = out[k].status;
@@ -977,14 +1019,24 @@ int smc_trajectories(smc_ctx *c, const smc_net *net, const smc_formula *f, const
     std::vector<Prepared> P(1);
     int rc = prepare(c, net, f, &q, first, P[0]);
     if (rc != SMC_OK) return rc;
+    std::vector<JobResult> res;
+    double secs = 0.0;
+    if (p->flags & SMC_DEVICE_PTRS) {
+        // the caller's device arrays are the kernel's record arrays
+        if ((uintptr_t)events % alignof(uint32_t)) return fail(c, SMC_E_INVALID, "events must be 4-byte aligned");
+        P[0].job.rec_events = events;
+        P[0].job.rec_vr = verdict_reason;
+        rc = run_jobs(c, P, res, &secs);
+        if (rc != SMC_OK) return rc;
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        return SMC_OK;
+    }
     const size_t bytes = count * (sizeof(uint32_t) + sizeof(uint8_t)) + 16;
     if (ensure(c, c->d_rec, c->cap_rec, bytes)) return SMC_E_NOMEM;
     auto *d_ev = (uint32_t *)c->d_rec;
     auto *d_vr = (uint8_t *)(d_ev + count);
     P[0].job.rec_events = d_ev;
     P[0].job.rec_vr = d_vr;
-    std::vector<JobResult> res;
-    double secs = 0.0;
     rc = run_jobs(c, P, res, &secs);
     if (rc != SMC_OK) return rc;
     if (events) HIP_TRY(c, hipMemcpyAsync(events, d_ev, count * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
@@ -1016,12 +1068,14 @@ int smc_sample_state(smc_ctx *c, const smc_net *net, const smc_params *p, double
     J.first = first;
     J.model_id = p->model_id;
     if (ensure(c, c->d_jobs, c->cap_jobs, 1)) return SMC_E_NOMEM;
+    const bool on_device = (p->flags & SMC_DEVICE_PTRS) != 0;
+    if (on_device && (uintptr_t)counts % alignof(int32_t)) return fail(c, SMC_E_INVALID, "counts must be 4-byte aligned");
     const size_t bytes = count * (size_t)net->S * sizeof(int32_t);
-    if (ensure(c, c->d_rec, c->cap_rec, bytes)) return SMC_E_NOMEM;
+    if (!on_device && ensure(c, c->d_rec, c->cap_rec, bytes)) return SMC_E_NOMEM;
+    int32_t *d_out = on_device ? counts : (int32_t *)c->d_rec;
     HIP_TRY(c, hipMemcpyAsync(c->d_jobs, &J, sizeof(J), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, launch_sample_state(net->M <= 4 ? 0 : 1, c->stream, c->d_jobs, T, count,
-                                   (int32_t *)c->d_rec, net->S));
-    HIP_TRY(c, hipMemcpyAsync(counts, c->d_rec, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, launch_sample_state(net->M <= 4 ? 0 : 1, c->stream, c->d_jobs, T, count, d_out, net->S));
+    if (!on_device) HIP_TRY(c, hipMemcpyAsync(counts, c->d_rec, bytes, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return SMC_OK;
 }

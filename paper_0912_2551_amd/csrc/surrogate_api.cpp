@@ -68,6 +68,12 @@ struct smc_surrogate {
     long qcap = 0;
     float *qx = nullptr, *qp = nullptr;
     uint8_t *quse = nullptr;
+    // gate calibrated on held-out estimates (smc_surrogate_calibrate): the
+    // smallest margin at which no held-out answer was off; refuse: none was
+    bool calibrated = false;
+    bool refuse = false;
+    float cal_margin = 0.0f;
+    float cal_threshold = 0.5f;
 };
 
 extern "C" const char *smc_last_error(const smc_ctx *ctx);
@@ -245,6 +251,7 @@ int smc_surrogate_set_params(smc_surrogate *s, const float *params, size_t count
     SG_TRY(s, hipMemsetAsync(s->v, 0, N_PARAMS * 4, s->stream));
     SG_TRY(s, hipStreamSynchronize(s->stream));
     s->step = 0;
+    s->calibrated = false;
     return SMC_OK;
 }
 
@@ -280,6 +287,7 @@ int smc_surrogate_train(smc_surrogate *s, const float *x, const float *y, const 
 {
     if (!s || !x || !y || !opts || n < 4 || n > (1u << 20)) return sfail(s, SMC_E_INVALID, "bad training set");
     if (!(opts->lr > 0.0f) || opts->steps == 0) return sfail(s, SMC_E_INVALID, "need lr > 0 and steps > 0");
+    s->calibrated = false;   // a retrained network needs a new calibration
     // input normalisation from the training points
     double mu[3] = {0, 0, 0}, var[3] = {0, 0, 0};
     for (size_t i = 0; i < n; ++i)
@@ -329,12 +337,16 @@ int smc_surrogate_train(smc_surrogate *s, const float *x, const float *y, const 
     return SMC_OK;
 }
 
-int smc_surrogate_query(smc_surrogate *s, const float *x, size_t n, float threshold, float margin, float *p_out,
-                        uint8_t *use_surrogate)
+int smc_surrogate_query(smc_surrogate *s, const float *x, size_t n, float threshold, float margin, uint32_t flags,
+                        float *p_out, uint8_t *use_surrogate)
 {
     if (!s || (n && (!x || !p_out))) return sfail(s, SMC_E_INVALID, "null argument");
+    if (flags & ~SMC_DEVICE_PTRS) return sfail(s, SMC_E_INVALID, "unknown flags");
     if (n == 0) return SMC_OK;
-    if ((long)n > s->qcap) {
+    const bool on_device = (flags & SMC_DEVICE_PTRS) != 0;
+    if (on_device && ((uintptr_t)x % 4 || (uintptr_t)p_out % 4))
+        return sfail(s, SMC_E_INVALID, "x and p_out must be 4-byte aligned");
+    if (!on_device && (long)n > s->qcap) {
         SG_TRY(s, dalloc(s->qx, n * 3));
         SG_TRY(s, dalloc(s->qp, n));
         SG_TRY(s, dalloc(s->quse, n));
@@ -344,13 +356,64 @@ int smc_surrogate_query(smc_surrogate *s, const float *x, size_t n, float thresh
         SG_TRY(s, dalloc(s->planes, 4));
         s->n_planes = 0;
     }
-    SG_TRY(s, hipMemcpyAsync(s->qx, x, n * 12, hipMemcpyHostToDevice, s->stream));
-    SG_TRY(s, sg_query(s->stream, s->qx, (long)n, s->norm, s->norm + 3, s->wb + OFF_W1, s->w + OFF_B1,
+    const float *d_x = on_device ? x : s->qx;
+    float *d_p = on_device ? p_out : s->qp;
+    uint8_t *d_use = use_surrogate ? (on_device ? use_surrogate : s->quse) : nullptr;
+    if (!on_device) SG_TRY(s, hipMemcpyAsync(s->qx, x, n * 12, hipMemcpyHostToDevice, s->stream));
+    // a calibrated gate never answers closer to its threshold than the
+    // calibrated margin, and answers nothing when calibration refused it
+    float m = margin;
+    if (s->calibrated && threshold == s->cal_threshold) m = std::max(m, s->cal_margin);
+    if (s->calibrated && (s->refuse || threshold != s->cal_threshold)) m = 2.0f;   // |p - t| < 2 always
+    SG_TRY(s, sg_query(s->stream, d_x, (long)n, s->norm, s->norm + 3, s->wb + OFF_W1, s->w + OFF_B1,
                        s->wb + OFF_W2, s->w + OFF_B2, s->wb + OFF_W3, s->w + OFF_B3, s->planes, s->n_planes,
-                       1e-6f, threshold, margin, s->qp, use_surrogate ? s->quse : nullptr));
-    SG_TRY(s, hipMemcpyAsync(p_out, s->qp, n * 4, hipMemcpyDeviceToHost, s->stream));
-    if (use_surrogate) SG_TRY(s, hipMemcpyAsync(use_surrogate, s->quse, n, hipMemcpyDeviceToHost, s->stream));
+                       1e-6f, threshold, m, d_p, d_use));
+    if (!on_device) {
+        SG_TRY(s, hipMemcpyAsync(p_out, s->qp, n * 4, hipMemcpyDeviceToHost, s->stream));
+        if (use_surrogate) SG_TRY(s, hipMemcpyAsync(use_surrogate, s->quse, n, hipMemcpyDeviceToHost, s->stream));
+    }
     SG_TRY(s, hipStreamSynchronize(s->stream));
+    return SMC_OK;
+}
+
+int smc_surrogate_calibrate(smc_surrogate *s, const float *x, const double *lo, const double *hi, size_t n,
+                            float threshold, float bound, float min_margin, float *margin_out, float *share_out)
+{
+    if (!s || (n && (!x || !lo || !hi))) return sfail(s, SMC_E_INVALID, "null argument");
+    if (!(bound >= 0.0f) || !(min_margin >= 0.0f) || !(threshold >= 0.0f && threshold <= 1.0f))
+        return sfail(s, SMC_E_INVALID, "need bound >= 0, min_margin >= 0, threshold in [0, 1]");
+    for (size_t i = 0; i < n; ++i)
+        if (!(lo[i] <= hi[i])) return sfail(s, SMC_E_INVALID, "need lo <= hi");
+    s->calibrated = false;
+    std::vector<float> p(n);
+    std::vector<uint8_t> in_hull(n);
+    if (n) {
+        // network outputs and hull membership (margin 0: every point in the hull)
+        const int rc = smc_surrogate_query(s, x, n, threshold, 0.0f, 0, p.data(), in_hull.data());
+        if (rc != SMC_OK) return rc;
+    }
+    // The margin must exceed |p - threshold| at every held-out point in the
+    // hull whose answer lies more than `bound` outside its interval.
+    double need = min_margin;
+    size_t inside = 0;
+    for (size_t i = 0; i < n; ++i) {
+        if (!in_hull[i]) continue;
+        ++inside;
+        const double pi = p[i];
+        const bool off = pi < lo[i] - bound || pi > hi[i] + bound;
+        if (off) need = std::max(need, (double)std::nextafter(std::fabs(p[i] - threshold), 2.0f));
+    }
+    const bool refuse = inside == 0 || need > 0.5;
+    size_t answered = 0;
+    if (!refuse)
+        for (size_t i = 0; i < n; ++i)
+            if (in_hull[i] && std::fabs(p[i] - threshold) >= (float)need) ++answered;
+    s->calibrated = true;
+    s->refuse = refuse;
+    s->cal_margin = refuse ? 2.0f : (float)need;
+    s->cal_threshold = threshold;
+    if (margin_out) *margin_out = refuse ? -1.0f : (float)need;
+    if (share_out) *share_out = n ? (float)((double)answered / (double)n) : 0.0f;
     return SMC_OK;
 }
 
