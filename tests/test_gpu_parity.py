@@ -517,3 +517,72 @@ def test_watchdog_and_cancel_stop_cleanly(ctx):
     r = ctx.estimate(n1, f1, B.params(fixed_n=4096, seed=1))
     o = oracle.estimate(small, W.C1_FORMULA, fixed_n=4096, seed=1)
     assert (r["n"], r["successes"], r["events"]) == (o["n"], o["successes"], o["events"])
+
+
+# ---------------------------------------------------------------------------
+# The batched sweep at its full configuration
+# ---------------------------------------------------------------------------
+def _c4_expected():
+    import json
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    with open(os.path.join(here, "c4_expected.json")) as fh:
+        doc = json.load(fh)
+    arrays = np.load(os.path.join(here, "c4_trajectories.npz"))
+    return doc, arrays
+
+
+@pytest.fixture(scope="module")
+def c4_run(ctx):
+    """One launch of all 576 jobs, as the benchmark runs them."""
+    B = _B()
+    keep, jobs = [], []
+    for net, text, kw in W.c4_jobs():
+        nh = ctx.network(net)
+        fh = ctx.formula(nh, text)
+        keep.append((nh, fh))
+        jobs.append((nh, fh, B.params(**kw)))
+    print("c4: 576 jobs in one launch", flush=True)
+    res = ctx.estimate_batch(jobs)
+    return res, keep
+
+
+def test_c4_every_job_matches_oracle(c4_run):
+    """All 576 jobs of the sweep (512 Michaelis-Menten rate sets at +-0.01 and
+    64 random networks): n, successes, events, truncations, batches and the
+    Wilson interval equal the oracle's Fig. 2 estimates (stored by
+    tests/golden/c4_expected.py)."""
+    res, _ = c4_run
+    doc, _ = _c4_expected()
+    exp = doc["jobs"]
+    assert len(exp) == len(res) == 576
+    keys = ("n", "successes", "events", "truncated", "batches", "p_hat", "lo", "hi")
+    bad = [(e["job"], {k: (r[k], e[k]) for k in keys if r[k] != e[k]}) for r, e in zip(res, exp)
+           if any(r[k] != e[k] for k in keys)]
+    assert not bad, bad[:5]
+    assert all(r["status"] == 0 for r in res)
+
+
+@WIDE_MODES
+def test_c4_network_trajectories_match_oracle(ctx, mode):
+    """Per-trajectory parity on eight of the sweep's random networks (8 to 128
+    species), indices 0..1023 with each job's own stream, on the generic and
+    the wide specialised kernel."""
+    B = _B()
+    doc, arrays = _c4_expected()
+    jobs = W.c4_jobs()
+    count = doc["per_trajectory_count"]
+    for q in doc["per_trajectory_networks"]:
+        net, text, kw = jobs[512 + q]
+        nh = ctx.network(net)
+        fh = ctx.formula(nh, text)
+        p = B.params(**kw)
+        _wide_mode(ctx, B, mode)
+        try:
+            print(f"case c4 network {q} ({net.label}) mode {mode}", flush=True)
+            ev, vd, rs = ctx.trajectories(nh, fh, p, 0, count)
+        finally:
+            ctx.set_specialization(B.SPECIALIZE_AUTO)
+        vr = (vd | (rs << 1)).astype(np.uint8)
+        assert np.array_equal(vr, arrays[f"vr_{q}"]), (q, np.nonzero(vr != arrays[f"vr_{q}"])[0][:5])
+        assert np.array_equal(ev, arrays[f"events_{q}"]), (q, np.nonzero(ev != arrays[f"events_{q}"])[0][:5])
