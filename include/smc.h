@@ -240,6 +240,26 @@ typedef struct {
 } smc_job;
 int smc_estimate_batch(smc_ctx *ctx, const smc_job *jobs, size_t n_jobs, smc_result *out);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * estimates as smc_estimate_batch (bit for bit) for at most
+ * SMC_NOALLOC_MAX_JOBS jobs, with no device or pinned-host allocation and no
+ * run-time kernel compilation.  The job descriptors, per-job counters and
+ * results live in a fixed device array of the library (about 1.1 MB per GPU,
+ * held until the process ends, its address looked up when a context is
+ * created on that GPU); the kernels clear what must start at zero.  Every
+ * call on one GPU shares that array, so calls that overlap on one GPU (from
+ * any context or thread) race and must be serialised by the caller.
+ * Differences from smc_estimate_batch: iterative jobs always use the batch
+ * protocol (a speculative launch would need per-index records); a
+ * specialised kernel is used only if one was already compiled on this
+ * context for the jobs' structure (SMC_SPECIALIZE_REQUIRED without one gives
+ * SMC_E_UNSUPPORTED).  Errors: SMC_E_INVALID (n_jobs above
+ * SMC_NOALLOC_MAX_JOBS, or as smc_estimate_batch), and those of
+ * smc_estimate_batch. */
+#define SMC_NOALLOC_MAX_JOBS 64
+int smc_estimate_batch_noalloc(smc_ctx *ctx, const smc_job *jobs, size_t n_jobs, smc_result *out);
+
 /* Per-trajectory results for indices first .. first+count-1 (the same
  * trajectories smc_estimate would draw): events[k] = applied transitions,
  * verdict_reason[k] = verdict | reason << 1.  Either output may be NULL.

@@ -30,6 +30,7 @@ SMC_CONSERVATIVE_START = 1
 SMC_PAPER_ROUNDING = 2
 SMC_NO_SPECULATION = 4
 SMC_DEVICE_PTRS = 8
+NOALLOC_MAX_JOBS = 64
 REASON_STATE, REASON_TIME, REASON_ABSORB, REASON_CAP, REASON_TMAX = range(5)
 
 SPECIALIZE_AUTO, SPECIALIZE_OFF, SPECIALIZE_REQUIRED = 0, 1, 2
@@ -40,7 +41,8 @@ EXPORTS = [
     "smc_set_waves_per_cu", "smc_set_specialization", "smc_last_kernel",
     "smc_set_kernel_occupancy", "smc_autotune", "smc_cancel", "smc_device_cus", "smc_net_create",
     "smc_net_set_rates", "smc_net_destroy", "smc_formula_compile", "smc_formula_horizon", "smc_formula_check",
-    "smc_formula_destroy", "smc_estimate", "smc_estimate_batch", "smc_trajectories",
+    "smc_formula_destroy", "smc_estimate", "smc_estimate_batch", "smc_estimate_batch_noalloc",
+    "smc_trajectories",
     "smc_sample_state", "smc_z_value", "smc_wilson_sample_value", "smc_wilson_sample",
     "smc_wilson_interval", "smc_wilson_next_device", "smc_surrogate_create",
     "smc_surrogate_param_count", "smc_surrogate_set_params", "smc_surrogate_get_params",
@@ -138,6 +140,8 @@ def lib():
             "smc_formula_destroy": (None, [vp]),
             "smc_estimate": (i32, [vp, vp, vp, ctypes.POINTER(Params), ctypes.POINTER(Result)]),
             "smc_estimate_batch": (i32, [vp, ctypes.POINTER(JobDesc), ctypes.c_size_t, ctypes.POINTER(Result)]),
+            "smc_estimate_batch_noalloc": (i32, [vp, ctypes.POINTER(JobDesc), ctypes.c_size_t,
+                                                 ctypes.POINTER(Result)]),
             "smc_trajectories": (i32, [vp, vp, vp, ctypes.POINTER(Params), u64, u64, vp, vp]),
             "smc_sample_state": (i32, [vp, vp, ctypes.POINTER(Params), dbl, u64, u64, vp]),
             "smc_z_value": (dbl, [dbl]),
@@ -282,6 +286,17 @@ class Context:
         res = (Result * len(jobs))()
         self._check(lib().smc_estimate_batch(self.h, arr, len(jobs), res))
         return [r.as_dict() for r in res]
+
+    def estimate_batch_noalloc(self, jobs) -> list:
+        """smc_estimate_batch_noalloc: at most NOALLOC_MAX_JOBS jobs, no allocation."""
+        arr = (JobDesc * max(len(jobs), 1))()
+        for k, (n, f, p) in enumerate(jobs):
+            arr[k].net = n.h
+            arr[k].formula = f.h
+            arr[k].params = p
+        res = (Result * max(len(jobs), 1))()
+        self._check(lib().smc_estimate_batch_noalloc(self.h, arr, len(jobs), res))
+        return [r.as_dict() for r in res[:len(jobs)]]
 
     def trajectories(self, network, formula, p: Params, first: int, count: int):
         ev = np.zeros(count, dtype=np.uint32)

@@ -65,6 +65,9 @@ struct smc_ctx {
     JobResult *h_results = nullptr;
     size_t cap_h_results = 0;
     Control *h_ctl = nullptr;
+    // the device's fixed job array for smc_estimate_batch_noalloc (mapped
+    // when the context is created)
+    void *noalloc_base = nullptr;
 };
 
 struct smc_net {
@@ -604,6 +607,10 @@ int smc_ctx_create(int hip_device, void *hip_stream, smc_ctx **out)
         return fail(nullptr, SMC_E_HIP, hipGetErrorString(e));
     }
     *c->cancel_host = 0;
+    if ((e = noalloc_scratch(hip_device, &c->noalloc_base)) != hipSuccess) {
+        smc_ctx_destroy(c);
+        return fail(nullptr, SMC_E_HIP, std::string("fixed job array: ") + hipGetErrorString(e));
+    }
     *out = c;
     return SMC_OK;
 }
@@ -985,6 +992,59 @@ int smc_estimate_batch(smc_ctx *c, const smc_job *jobs, size_t n_jobs, smc_resul
         for (size_t k = 0; k < n_jobs; ++k) out[k].status = rc;
         return rc;
     }
+    for (size_t k = 0; k < n_jobs; ++k) {
+        fill_result(res[k], P[k].z, P[k].job.iterative != 0, &out[k]);
+        out[k].device_seconds = secs;
+        if (out[k].status != SMC_OK && first_err == SMC_OK) {
+            first_err = out[k].status;
+            c->err = res[k].overflow == 1 ? "stopping rule ran out of batch slots"
+                                          : "stopping rule: a batch bound fell below the issued look-ahead";
+        }
+    }
+    return first_err;
+}
+
+int smc_estimate_batch_noalloc(smc_ctx *c, const smc_job *jobs, size_t n_jobs, smc_result *out)
+{
+    static_assert(SMC_NOALLOC_MAX_JOBS == kNoallocJobs, "the fixed array holds kNoallocJobs jobs");
+    if (!c || (!jobs && n_jobs) || (!out && n_jobs)) return fail(c, SMC_E_INVALID, "null argument");
+    if (n_jobs > (size_t)SMC_NOALLOC_MAX_JOBS)
+        return fail(c, SMC_E_INVALID, "smc_estimate_batch_noalloc takes at most SMC_NOALLOC_MAX_JOBS (64) jobs");
+    if (n_jobs == 0) return SMC_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (!c->noalloc_base) return fail(c, SMC_E_HIP, "the fixed job array of this device is not mapped");
+    // [Control | Job x kNoallocJobs | JobState x kNoallocJobs | JobResult x kNoallocJobs]
+    char *base = static_cast<char *>(c->noalloc_base);
+    Workspace W;
+    W.d_ctl = reinterpret_cast<Control *>(base + kNoallocCtlOff);
+    W.d_jobs = reinterpret_cast<Job *>(base + kNoallocJobsOff);
+    W.d_states = reinterpret_cast<JobState *>(base + kNoallocStatesOff);
+    W.d_results = reinterpret_cast<JobResult *>(base + kNoallocResultsOff);
+    Job h_jobs[2 * kNoallocJobs];
+    JobResult h_results[kNoallocJobs];
+    Control h_ctl;
+    W.h_jobs = h_jobs;
+    W.h_results = h_results;
+    W.h_ctl = &h_ctl;
+    W.pinned = false;
+    W.no_alloc = true;
+    Prepared P[kNoallocJobs];
+    for (size_t k = 0; k < n_jobs; ++k) {
+        std::memset(&out[k], 0, sizeof(smc_result));
+        const int rc = prepare(c, jobs[k].net, jobs[k].formula, &jobs[k].params, 0, P[k], false);
+        if (rc != SMC_OK) {
+            out[k].status = rc;
+            return rc;
+        }
+    }
+    JobResult res[kNoallocJobs];
+    double secs = 0.0;
+    const int rc = run_jobs_in(c, P, (int)n_jobs, W, res, &secs);
+    if (rc != SMC_OK) {
+        for (size_t k = 0; k < n_jobs; ++k) out[k].status = rc;
+        return rc;
+    }
+    int first_err = SMC_OK;
     for (size_t k = 0; k < n_jobs; ++k) {
         fill_result(res[k], P[k].z, P[k].job.iterative != 0, &out[k]);
         out[k].device_seconds = secs;

@@ -39,6 +39,20 @@ hipError_t launch_init(hipStream_t stream, const Job *jobs, int n_jobs, int n_wa
 hipError_t launch_finalize(hipStream_t stream, const Job *jobs, int n_jobs, JobResult *out);
 // Fig. 2 over recorded per-index verdicts (speculative launches)
 hipError_t launch_replay(hipStream_t stream, const Job *jobs, int n_jobs, JobResult *out);
+// Allocation-free runs (smc_estimate_batch_noalloc): the device address of the
+// library's fixed job array on `device`, which must be the current device.
+// The address is looked up once per device and kept.  Layout: the control
+// block, then kNoallocJobs job descriptors, job states and results at the
+// offsets below.
+constexpr int kNoallocJobs = 64;
+constexpr size_t kNoallocAlign = 256;
+constexpr size_t noalloc_round(size_t b) { return (b + kNoallocAlign - 1) / kNoallocAlign * kNoallocAlign; }
+constexpr size_t kNoallocCtlOff = 0;
+constexpr size_t kNoallocJobsOff = kNoallocCtlOff + noalloc_round(sizeof(Control));
+constexpr size_t kNoallocStatesOff = kNoallocJobsOff + noalloc_round(kNoallocJobs * sizeof(Job));
+constexpr size_t kNoallocResultsOff = kNoallocStatesOff + noalloc_round(kNoallocJobs * sizeof(JobState));
+constexpr size_t kNoallocBytes = kNoallocResultsOff + noalloc_round(kNoallocJobs * sizeof(JobResult));
+hipError_t noalloc_scratch(int device, void **ptr);
 hipError_t launch_wilson_table(hipStream_t stream, const unsigned long long *yes,
                                const unsigned long long *n, int count, double eps, double z,
                                int literal, unsigned long long *out);

@@ -1,5 +1,8 @@
 // ssa_kernel.hip -- the generic (table-driven) kernels of the SSA path and
 // their host-side launchers.  The device code itself is in ssa_core.h.
+#include <mutex>
+
+#include "smc_internal.h"
 #include "ssa_core.h"
 
 namespace smc {
@@ -320,6 +323,35 @@ hipError_t launch_wilson_table(hipStream_t stream, const unsigned long long *yes
     hipLaunchKernelGGL(wilson_table, dim3((count + 255) / 256), dim3(256), 0, stream, yes, n, count,
                        eps, z, literal, out);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The fixed job array of allocation-free runs (smc_estimate_batch_noalloc):
+// job descriptors, per-job counters and results, and the control block, for
+// at most kNoallocJobs jobs.  Every GPU holds its own copy at its own address
+// until the process ends.  In host code `scratch` names a host-side stand-in,
+// not device memory: kernels are given the device address that
+// hipGetSymbolAddress returns for it, looked up once per device with that
+// device current.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+hipError_t noalloc_scratch(int device, void **ptr)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
 }
 
 }  // namespace smc
