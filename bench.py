@@ -84,16 +84,17 @@ def kernel_sources_sha256():
 
 
 def measured_valu_busy():
-    """VALU busy fraction of the C2 kernel from the committed shader-sequencer
-    counter summary (ACTIVE_INST_VALU x 4 / (BUSY_CU_CYCLES x 4 SIMDs)), or
-    None when the kernel sources have changed since the counters were taken."""
+    """VALU issue share of the C2 kernel from the committed shader-sequencer
+    counter summary (wave64 VALU instructions x 4 cycles over the kernel's
+    SIMD-cycles), with instructions per wave-event, or None when the kernel
+    sources have changed since the counters were taken."""
     try:
         fields = dict(l.split(": ", 1) for l in open(SQ_PROFILE).read().splitlines() if ": " in l)
     except OSError:
         return None
     if fields.get("kernel_sources_sha256", "").strip() != kernel_sources_sha256():
         return None
-    return {"valu_busy": float(fields["valu_busy"]),
+    return {"valu_issue_share": float(fields["valu_issue_share"]),
             "vector_instructions_per_wave_event": float(fields["vector_instructions_per_wave_event"]),
             "scalar_instructions_per_wave_event": float(fields["scalar_instructions_per_wave_event"])}
 

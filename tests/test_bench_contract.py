@@ -38,9 +38,9 @@ def test_valu_busy_only_for_the_profiled_sources(tmp_path, monkeypatch):
     prof = tmp_path / "sq.txt"
     monkeypatch.setattr(bench, "SQ_PROFILE", str(prof))
     assert bench.measured_valu_busy() is None
-    body = ("valu_busy: 0.8\nvector_instructions_per_wave_event: 250\nscalar_instructions_per_wave_event: 130\n")
+    body = ("valu_issue_share: 0.8\nvector_instructions_per_wave_event: 250\nscalar_instructions_per_wave_event: 130\n")
     prof.write_text(body + f"kernel_sources_sha256: {_sources_hash()}\n")
-    assert bench.measured_valu_busy()["valu_busy"] == 0.8
+    assert bench.measured_valu_busy()["valu_issue_share"] == 0.8
     prof.write_text(body + "kernel_sources_sha256: " + "0" * 64 + "\n")
     assert bench.measured_valu_busy() is None
 
