@@ -333,7 +333,8 @@ def surrogate_vs_plain(ctx, B, W, text, n_train=512, n_cal=1024, n_query=10**6, 
             "surrogate_plus_fallback_seconds": sur_total, "speedup": plain_total / sur_total,
             "surrogate_share": float(use.mean()), "train_smc_seconds": t_train_smc, "fit_seconds": t_fit,
             "fit_steps": steps, "final_loss": float(losses[-1]), "calibration_smc_seconds": t_cal_smc,
-            "calibrated_margin": cal_margin, "calibration_share": cal_share, "query_seconds": t_query,
+            "calibrated_margin": cal_margin, "calibrated_neighbourhood": sg.neighbourhood(),
+            "calibration_share": cal_share, "query_seconds": t_query,
             "query_points_per_s": n_query / t_query, "fallback_seconds_scaled": fallback_total,
             "error_vs_wilson": {"answered": int(err.size),
                                 "inside_interval": float(np.mean(err == 0)) if err.size else None,

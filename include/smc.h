@@ -112,16 +112,33 @@ int smc_set_waves_per_cu(smc_ctx *ctx, int waves_per_cu);
 int smc_set_specialization(smc_ctx *ctx, int mode);
 /* Which SSA kernel the last estimation call on ctx launched: -1 none yet,
  * SMC_KERNEL_GENERIC_SMALL (table-driven, <= 4 channels), SMC_KERNEL_GENERIC
- * (table-driven, blocked prefix), SMC_KERNEL_SPECIALIZED. */
+ * (table-driven, blocked prefix), SMC_KERNEL_SPECIALIZED,
+ * SMC_KERNEL_GENERIC_GROUPED (table-driven, several lanes per trajectory). */
 #define SMC_KERNEL_GENERIC_SMALL 0
 #define SMC_KERNEL_GENERIC 1
 #define SMC_KERNEL_SPECIALIZED 2
+#define SMC_KERNEL_GENERIC_GROUPED 3
 int smc_last_kernel(const smc_ctx *ctx);
 /* Register budget of specialised kernels: compile them so that
  * `waves_per_simd` waves fit on one SIMD (1..8; registers beyond the budget
  * go to scratch memory), or 0 for the compiler's own choice (default).
  * Results do not depend on it.  Errors: SMC_E_INVALID. */
 int smc_set_kernel_occupancy(smc_ctx *ctx, int waves_per_simd);
+
+/* Lanes per trajectory (1, 2, 4, 8 or 16; 0 = automatic) for networks of
+ * more than four channels on the generic kernels.  A group of that many
+ * consecutive lanes runs one trajectory: the channels' propensities are
+ * shared out over the group and added in channel order lane after lane, so
+ * every sum, selection and result is bit-identical to one lane per
+ * trajectory; an event takes fewer instructions on each lane but the
+ * device holds fewer trajectories at once.  It pays where trajectories are
+ * few and long (a launch that leaves lanes idle).  A job's own
+ * smc_params.lanes overrides the setting.  The group size is raised where
+ * needed so that a group covers the channels in at most 8 rounds of 8 per
+ * lane (e.g. at least 8 lanes for 512 channels); networks of more than 1024
+ * channels and launches on specialised kernels use one lane.  Results do
+ * not depend on it.  Errors: SMC_E_INVALID. */
+int smc_set_lanes_per_trajectory(smc_ctx *ctx, int lanes);
 
 /* Ask a running call on ctx (from another thread) to stop: it returns
  * SMC_E_CANCELLED. */
@@ -202,7 +219,9 @@ typedef struct {
     uint32_t max_events; /* 0: no cap; else undecided after this many events: FALSE */
     double t_max;        /* pessimistic horizon for unbounded formulas (+inf: none) */
     uint32_t flags;      /* SMC_CONSERVATIVE_START | SMC_PAPER_ROUNDING |
-                            SMC_NO_SPECULATION                                   */
+                            SMC_NO_SPECULATION | SMC_DEVICE_PTRS                 */
+    uint32_t lanes;      /* lanes per trajectory: 0 = the context's choice
+                            (smc_set_lanes_per_trajectory), else 1, 2, 4, 8 or 16 */
 } smc_params;
 
 typedef struct {
@@ -363,22 +382,30 @@ int smc_surrogate_query(smc_surrogate *s, const float *x, size_t n, float thresh
                         uint32_t flags, float *p_out, uint8_t *use_surrogate);
 /* Calibrate the gate on held-out plain-SMC estimates (points that were not
  * trained on): x[n][3] log10 rates and each point's Wilson interval
- * [lo[k], hi[k]] (eq. 3).  The calibrated margin is the smallest m >=
- * min_margin such that every held-out point inside the training hull with
- * |p(x) - threshold| >= m has p(x) within [lo - bound, hi + bound]; from
- * then on smc_surrogate_query (at this threshold) answers only with a
- * margin of at least m.  For points drawn like the held-out ones, an answer
- * that lies more than `bound` outside that point's interval then has
- * probability at most 1/(n+1) (exchangeability: it would have to be the
- * largest of n+1 such levels).  If m would exceed 0.5, or no held-out point
- * lies in the hull, the gate refuses every query (use_surrogate = 0) until
- * the network is retrained or recalibrated; queries at another threshold
- * are refused too.  Outputs (optional): *margin_out = m (-1 when refused),
- * *share_out = share of the held-out points answered.  Training or setting
- * parameters clears the calibration.  Errors: SMC_E_INVALID. */
+ * [lo[k], hi[k]] (eq. 3).  The gate answers a point only if the network's
+ * output there, and at the six neighbours x +- delta e_k (delta in log10
+ * units, 0 = the point alone), all lie on the same side of the threshold at
+ * least m away from it: the point's stability is the least such distance.
+ * For each delta in {0, 0.01, 0.02, 0.05, 0.1, 0.2}, m is the smallest value
+ * >= min_margin above the stability of every held-out point in the training
+ * hull whose output lies more than `bound` outside its interval; the delta
+ * that answers the largest share of the held-out points is kept, with its m.
+ * From then on smc_surrogate_query (at this threshold) applies that gate.
+ * For points drawn like the held-out ones, an answer that lies more than
+ * `bound` outside that point's interval has probability at most 1/(n+1)
+ * for a fixed delta (exchangeability: it would have to be the largest of
+ * n+1 stabilities), at most 6/(n+1) over the six choices.  If no delta
+ * gives m <= 0.5, or no held-out point lies in the hull, the gate refuses
+ * every query (use_surrogate = 0) until the network is retrained or
+ * recalibrated; queries at another threshold are refused too.  Outputs
+ * (optional): *margin_out = m (-1 when refused), *share_out = share of the
+ * held-out points answered.  Training or setting parameters clears the
+ * calibration.  Errors: SMC_E_INVALID. */
 int smc_surrogate_calibrate(smc_surrogate *s, const float *x, const double *lo, const double *hi, size_t n,
                             float threshold, float bound, float min_margin, float *margin_out,
                             float *share_out);
+/* The calibrated neighbourhood size delta (0 if none or not calibrated). */
+float smc_surrogate_neighbourhood(const smc_surrogate *s);
 /* Facets of the training hull as planes (nx, ny, nz, d), inside: n.x <= d.
  * Writes up to cap planes; returns the number of facets. */
 int smc_surrogate_hull(const smc_surrogate *s, float *planes, size_t cap);

@@ -34,12 +34,12 @@ NOALLOC_MAX_JOBS = 64
 REASON_STATE, REASON_TIME, REASON_ABSORB, REASON_CAP, REASON_TMAX = range(5)
 
 SPECIALIZE_AUTO, SPECIALIZE_OFF, SPECIALIZE_REQUIRED = 0, 1, 2
-KERNEL_GENERIC_SMALL, KERNEL_GENERIC, KERNEL_SPECIALIZED = 0, 1, 2
+KERNEL_GENERIC_SMALL, KERNEL_GENERIC, KERNEL_SPECIALIZED, KERNEL_GENERIC_GROUPED = 0, 1, 2, 3
 
 EXPORTS = [
     "smc_ctx_create", "smc_ctx_destroy", "smc_last_error", "smc_set_watchdog",
     "smc_set_waves_per_cu", "smc_set_specialization", "smc_last_kernel",
-    "smc_set_kernel_occupancy", "smc_autotune", "smc_cancel", "smc_device_cus", "smc_net_create",
+    "smc_set_kernel_occupancy", "smc_set_lanes_per_trajectory", "smc_autotune", "smc_cancel", "smc_device_cus", "smc_net_create",
     "smc_net_set_rates", "smc_net_destroy", "smc_formula_compile", "smc_formula_horizon", "smc_formula_check",
     "smc_formula_destroy", "smc_estimate", "smc_estimate_batch", "smc_estimate_batch_noalloc",
     "smc_trajectories",
@@ -47,6 +47,7 @@ EXPORTS = [
     "smc_wilson_interval", "smc_wilson_next_device", "smc_surrogate_create",
     "smc_surrogate_param_count", "smc_surrogate_set_params", "smc_surrogate_get_params",
     "smc_surrogate_gradients", "smc_surrogate_train", "smc_surrogate_query", "smc_surrogate_calibrate",
+    "smc_surrogate_neighbourhood",
     "smc_surrogate_hull",
     "smc_surrogate_destroy", "smc_convex_hull",
 ]
@@ -81,7 +82,7 @@ class Params(ctypes.Structure):
     _fields_ = [("confidence", ctypes.c_double), ("half_width", ctypes.c_double),
                 ("z", ctypes.c_double), ("fixed_n", ctypes.c_uint64), ("seed", ctypes.c_uint64),
                 ("model_id", ctypes.c_uint32), ("max_events", ctypes.c_uint32),
-                ("t_max", ctypes.c_double), ("flags", ctypes.c_uint32)]
+                ("t_max", ctypes.c_double), ("flags", ctypes.c_uint32), ("lanes", ctypes.c_uint32)]
 
 
 class Result(ctypes.Structure):
@@ -127,6 +128,7 @@ def lib():
             "smc_set_specialization": (i32, [vp, i32]),
             "smc_last_kernel": (i32, [vp]),
             "smc_set_kernel_occupancy": (i32, [vp, i32]),
+            "smc_set_lanes_per_trajectory": (i32, [vp, i32]),
             "smc_autotune": (i32, [vp, vp, vp, ctypes.POINTER(Params), ctypes.c_uint64, ctypes.POINTER(TuneResult)]),
             "smc_cancel": (None, [vp]),
             "smc_device_cus": (i32, [vp]),
@@ -166,6 +168,7 @@ def lib():
             "smc_surrogate_calibrate": (i32, [vp, vp, vp, vp, ctypes.c_size_t, ctypes.c_float, ctypes.c_float,
                                               ctypes.c_float, ctypes.POINTER(ctypes.c_float),
                                               ctypes.POINTER(ctypes.c_float)]),
+            "smc_surrogate_neighbourhood": (ctypes.c_float, [vp]),
             "smc_surrogate_hull": (i32, [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
             "smc_surrogate_destroy": (None, [vp]),
             "smc_convex_hull": (i32, [ctypes.POINTER(ctypes.c_float), ctypes.c_size_t,
@@ -190,10 +193,10 @@ def _dptr(t):
 
 
 def params(confidence=0.95, half_width=0.01, z=0.0, fixed_n=0, seed=1, model_id=0, max_events=0,
-           t_max=math.inf, conservative=False, paper_rounding=False, speculate=True) -> Params:
+           t_max=math.inf, conservative=False, paper_rounding=False, speculate=True, lanes=0) -> Params:
     flags = ((SMC_CONSERVATIVE_START if conservative else 0) | (SMC_PAPER_ROUNDING if paper_rounding else 0)
              | (0 if speculate else SMC_NO_SPECULATION))
-    return Params(confidence, half_width, z, fixed_n, seed, model_id, max_events, t_max, flags)
+    return Params(confidence, half_width, z, fixed_n, seed, model_id, max_events, t_max, flags, lanes)
 
 
 class Context:
@@ -242,6 +245,10 @@ class Context:
     def set_specialization(self, mode: int):
         """SPECIALIZE_AUTO, SPECIALIZE_OFF or SPECIALIZE_REQUIRED."""
         self._check(lib().smc_set_specialization(self.h, int(mode)))
+
+    def set_lanes_per_trajectory(self, lanes: int):
+        """1, 2, 4, 8 or 16 lanes per trajectory (0: automatic)."""
+        self._check(lib().smc_set_lanes_per_trajectory(self.h, int(lanes)))
 
     def set_kernel_occupancy(self, waves_per_simd: int):
         """Register budget of specialised kernels (0 = compiler default)."""
@@ -497,6 +504,10 @@ class Surrogate:
                                                       xx.shape[0], threshold, bound, min_margin,
                                                       ctypes.byref(m), ctypes.byref(share)))
         return m.value, share.value
+
+    def neighbourhood(self) -> float:
+        """The calibrated gate's neighbourhood size (log10 units; 0: none)."""
+        return float(lib().smc_surrogate_neighbourhood(self.h))
 
     def hull(self) -> np.ndarray:
         nf = lib().smc_surrogate_hull(self.h, None, 0)

@@ -34,6 +34,7 @@ struct smc_ctx {
     int waves_per_cu = 0;
     int spec_mode = SMC_SPECIALIZE_AUTO;
     int spec_waves_per_simd = 0;
+    int lanes = 0;   // lanes per trajectory (0: automatic)
     // autotuned configurations per model structure (see smc_autotune)
     std::map<std::pair<uint64_t, uint64_t>, smc_tune_result> tuned;
     // specialised kernels per (network structure, formula structure,
@@ -181,6 +182,22 @@ double resolve_z(smc_ctx *ctx, const smc_params &p, bool cache = true)
     return z;
 }
 
+// Lanes per trajectory of a job: the request (the job's own, else the
+// context's; 0 = automatic, which is one lane for now), on the generic kernels
+// for networks of more than four channels only, raised so that the group
+// covers the padded channels in at most kMaxGroupRounds rounds of kSubBlock
+// channels per lane.
+int job_lanes(const smc_ctx *ctx, const smc_params *p, int M)
+{
+    const int want = p->lanes ? (int)p->lanes : ctx->lanes;
+    if (want <= 1 || M <= 4) return 1;
+    const int Mp = padded_channels(M);
+    if (Mp > kMaxGroupRounds * kSubBlock * 16) return 1;
+    int L = want;
+    while (L < 16 && Mp > kMaxGroupRounds * kSubBlock * L) L *= 2;
+    return L;
+}
+
 struct Prepared {
     Job job;
     const smc_net *net = nullptr;
@@ -197,6 +214,8 @@ int prepare(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_pa
     if (!net || !f || !p) return fail(ctx, SMC_E_INVALID, "null network, formula or parameters");
     if (net->ctx != ctx || f->ctx != ctx) return fail(ctx, SMC_E_INVALID, "handle from another context");
     if (std::isnan(p->t_max) || p->t_max < 0.0) return fail(ctx, SMC_E_INVALID, "t_max must be >= 0");
+    if (p->lanes != 0 && p->lanes != 1 && p->lanes != 2 && p->lanes != 4 && p->lanes != 8 && p->lanes != 16)
+        return fail(ctx, SMC_E_INVALID, "lanes per trajectory must be 0, 1, 2, 4, 8 or 16");
     if (std::isinf(f->horizon) && std::isinf(p->t_max) && p->max_events == 0)
         return fail(ctx, SMC_E_INVALID, "an unbounded formula needs t_max or max_events");
     const bool iterative = p->fixed_n == 0;
@@ -243,6 +262,7 @@ int prepare(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_pa
     J.t_max = p->t_max;
     J.iterative = iterative ? 1 : 0;
     J.literal = (p->flags & SMC_PAPER_ROUNDING) ? 1 : 0;
+    J.lanes = job_lanes(ctx, p, net->M);
     J.eps = p->half_width;
     J.z = z;
     out.net = net;
@@ -280,6 +300,8 @@ int pick_spec_kernel(smc_ctx *ctx, const Prepared *P, int n, bool iterative, boo
     bool ok = n0 && f0 && spec_supported(n0->S, n0->M, f0->prog);
     for (int k = 1; ok && k < n; ++k)
         ok = P[k].net && P[k].f && same_structure(n0, f0, P[k].net, P[k].f);
+    // lane groups run on the generic kernels only
+    for (int k = 0; ok && k < n; ++k) ok = P[k].job.lanes == 1;
     if (!ok) {
         if (ctx->spec_mode == SMC_SPECIALIZE_REQUIRED)
             return fail(ctx, SMC_E_UNSUPPORTED, "jobs do not share one structure the specialised kernels support");
@@ -357,7 +379,7 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
 
 int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult *res, double *seconds)
 {
-    int s_max = 1, m_max = 1, n_iter = 0;
+    int s_max = 1, m_max = 1, n_iter = 0, group = 1;
     Job *jobs = W.h_jobs;   // the previous call's copies have completed
     for (int k = 0; k < n; ++k) {
         jobs[k] = P[k].job;
@@ -365,6 +387,14 @@ int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult 
         s_max = std::max(s_max, P[k].S);
         m_max = std::max(m_max, P[k].M);
         n_iter += jobs[k].iterative;
+        group = std::max(group, (int)jobs[k].lanes);
+    }
+    // One group size per launch (one grouped kernel per size): jobs that run
+    // several lanes per trajectory take the largest requested, which is at
+    // least what each of them needs; the results do not depend on it.
+    for (int k = 0; k < n; ++k) {
+        if (jobs[k].lanes > 1) jobs[k].lanes = group;
+        P[k].job.lanes = jobs[k].lanes;
     }
     // Speculative launch: when every job is iterative and their capacities
     // together fit in one pass over the device's lanes, every index up to each
@@ -379,7 +409,7 @@ int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult 
         unsigned long long cap_total = 0;
         bool allow = true;
         for (int k = 0; k < n; ++k) {
-            cap_total += P[k].capacity;
+            cap_total += P[k].capacity * (unsigned long long)P[k].job.lanes;
             allow = allow && P[k].speculate;
         }
         const unsigned long long lanes = (unsigned long long)ctx->n_cu * pick_waves_per_cu(ctx) * kWave;
@@ -436,11 +466,11 @@ int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult 
     // No more waves than there are trajectories to run at once: idle waves
     // only poll the job table.
     unsigned long long lanes_needed = 0;
-    for (int k = 0; k < n; ++k) lanes_needed += P[k].capacity;
+    for (int k = 0; k < n; ++k) lanes_needed += P[k].capacity * (unsigned long long)P[k].job.lanes;
     const unsigned long long waves_needed = (lanes_needed + kWave - 1) / kWave;
     const unsigned long long waves = std::min<unsigned long long>((unsigned long long)ctx->n_cu * wpc, waves_needed);
     const int grid = (int)std::max<unsigned long long>(1, (waves + wpb - 1) / wpb);
-    const int variant = m_max <= 4 ? 0 : 1;
+    const int variant = group > 1 ? 1 + __builtin_ctz((unsigned)group) : (m_max <= 4 ? 0 : 1);
     hipFunction_t spec_fn = nullptr;
     if (const int rc = pick_spec_kernel(ctx, P, n, n_iter > 0, !W.no_alloc, &spec_fn)) return rc;
     // wide specialised kernels keep counts in LDS like the generic ones
@@ -457,7 +487,9 @@ int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult 
         static_first = per_cu > 0 && (long long)per_cu * ctx->n_cu >= grid;
     }
     HIP_TRY(ctx, launch_init(s, W.d_jobs, n, static_first ? grid * wpb : 0, W.d_ctl, n_iter));
-    ctx->last_kernel = spec_fn ? SMC_KERNEL_SPECIALIZED : (variant == 0 ? SMC_KERNEL_GENERIC_SMALL : SMC_KERNEL_GENERIC);
+    ctx->last_kernel = spec_fn ? SMC_KERNEL_SPECIALIZED
+                               : (variant == 0 ? SMC_KERNEL_GENERIC_SMALL
+                                               : (variant == 1 ? SMC_KERNEL_GENERIC : SMC_KERNEL_GENERIC_GROUPED));
     for (int k = 0; k < n; ++k) res[k] = JobResult{};
     double total_ms = 0.0;
     const auto t_start = std::chrono::steady_clock::now();
@@ -727,6 +759,15 @@ int smc_autotune(smc_ctx *c, const smc_net *net, const smc_formula *f, const smc
     c->spec_mode = save_mode;
     c->tuned[key] = best;
     *out = best;
+    return SMC_OK;
+}
+
+int smc_set_lanes_per_trajectory(smc_ctx *c, int lanes)
+{
+    if (!c) return SMC_E_INVALID;
+    if (lanes != 0 && lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8 && lanes != 16)
+        return fail(c, SMC_E_INVALID, "lanes per trajectory must be 0, 1, 2, 4, 8 or 16");
+    c->lanes = lanes;
     return SMC_OK;
 }
 

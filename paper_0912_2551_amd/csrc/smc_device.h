@@ -32,6 +32,7 @@ constexpr int kMaxValOps = 96;     // arithmetic predicate programs
 constexpr int kValStack = 4;       // arithmetic stack depth on the device
 constexpr int kBlocks = 16;        // prefix-sum blocks for reaction selection
 constexpr int kSubBlock = 8;       // channels per unrolled step of the blocked prefix
+constexpr int kMaxGroupRounds = 8; // lane groups: rounds of 8 x lanes channels per event, at most
 constexpr int kSpecMaxS = 16;      // specialised kernels: species counts in registers
 constexpr int kSpecMaxM = 8;       // specialised kernels: channels
 constexpr int kSpecWideMaxS = 128; // wide specialised kernels (counts in LDS): species
@@ -180,6 +181,8 @@ struct Job {
     double t_max;
     int32_t iterative;            // 1 = Fig. 2 rule, 0 = fixed sample
     int32_t literal;              // paper's rounding step without the stop at 0.5
+    int32_t lanes;                // lanes per trajectory: 1, or 2/4/8/16 (generic kernel, > 4 channels)
+    int32_t pad_;
     double eps, z;
     JobState *st;
     uint32_t *rec_events;         // optional per-index outputs (relative index)

@@ -249,6 +249,7 @@ struct JobView {
     int iterative, literal;
     double eps, z;
     int nb, bs;   // prefix blocks and reactions per block
+    int lanes;    // lanes per trajectory
     uint32_t *rec_events;   // optional per-index outputs
     uint8_t *rec_vr;
 
@@ -284,6 +285,7 @@ struct JobView {
         const int nsub = Mp / kSubBlock;
         nb = nsub < kBlocks ? nsub : kBlocks;
         bs = (nsub + nb - 1) / nb * kSubBlock;
+        lanes = J->lanes;
         rec_events = J->rec_events;
         rec_vr = J->rec_vr;
     }
@@ -884,6 +886,166 @@ __device__ __forceinline__ double draw_tail(const JobView &V, const C &X, const 
 }
 
 // ---------------------------------------------------------------------------
+// Several lanes per trajectory (generic kernels, networks of more than four
+// channels).
+//
+// A lane group is L consecutive lanes of one 16-lane row (L = 2, 4, 8 or 16)
+// running one trajectory.  Every lane of the group holds the same time,
+// event index, random numbers and monitor state, and its own copy of the
+// counts, so the state change and the monitor run alike on each lane; only
+// the pass over the channels is shared out.  The channels are taken in
+// rounds of 8 L: in round q, rank r (the lane's index within its group) owns
+// the 8 channels from 8 (q L + r) on.  First every lane computes the
+// propensities of its 8 channels, all lanes at once.  Then the ranks add
+// theirs to the running sum one after the other: rank r starts from the sum
+// that rank r - 1 ended with (moved one lane up the row), and rank 0 of the
+// next round from the sum that the round's last rank ended with.  These are
+// exactly the additions of the sequential prefix in channel order, so the
+// total a0 and every partial sum are the one-lane results bit for bit.
+// Each lane keeps the sum at the end of its segment of each round.  The
+// selected segment is the first whose end exceeds u2 a0 (one ballot per
+// round); the group fetches the sum it starts from (the end of the segment
+// before it) and re-runs it, every lane alike, to find the channel.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double dpp_f64_shr1(double v)
+{
+    // lane i of a 16-lane row receives lane i - 1
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xFFFFFFFFll), 0x111, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x111, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Rank 0 of each group of L lanes receives rank L - 1 of the same group: a
+// rotation of the 16-lane row by 17 - L (lane i receives lane i - (17 - L)
+// modulo 16, which is i + L - 1 within the group).
+template <int L>
+__device__ __forceinline__ double dpp_f64_last_to_first(double v)
+{
+    constexpr int ctrl = 0x120 + (17 - L) % 16;
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xFFFFFFFFll), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), ctrl, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ int shfl_i32(int v, int src_lane)
+{
+    return __builtin_amdgcn_ds_bpermute(src_lane << 2, v);
+}
+
+__device__ __forceinline__ double shfl_f64(double v, int src_lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = shfl_i32((int)(unsigned)(b & 0xFFFFFFFFll), src_lane);
+    const int hi = shfl_i32((int)(b >> 32), src_lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// The propensities of the 8 channels from j0 on (0 for a segment past the
+// tables; such lanes read channels 0..7 and discard them).
+template <class C>
+__device__ __forceinline__ void segment_propensities(cptr<ChanDev> chan, cptr<double> rate, const C &X, int j0,
+                                                     int Mp, double (&a)[kSubBlock])
+{
+    const bool in = j0 < Mp;
+    const int jb = in ? j0 : 0;
+    ChanDev e[kSubBlock];
+    double cr[kSubBlock];
+#pragma unroll
+    for (int r = 0; r < kSubBlock; ++r) {
+        e[r] = load_chan(chan + (jb + r));
+        cr[r] = rate[jb + r];
+    }
+    int32_t xa[kSubBlock], xb[kSubBlock];
+#pragma unroll
+    for (int r = 0; r < kSubBlock; ++r) {
+        xa[r] = X.at(e[r].a_off);
+        xb[r] = X.at(e[r].b_code & ~1);
+    }
+#pragma unroll
+    for (int r = 0; r < kSubBlock; ++r) a[r] = in ? chan_propensity(e[r], cr[r], xa[r], xb[r]) : 0.0;
+}
+
+template <int L, class C>
+__device__ __forceinline__ double ssa_draw_group(const JobView &V, const C &X, const Draw &d, double t,
+                                                 Change *change)
+{
+    const int Mp = __builtin_amdgcn_readfirstlane(V.Mp);
+    const int lane = lane_id();
+    const int rank = lane & (L - 1);
+    const int gbase = lane - rank;
+    const int rounds = (Mp + kSubBlock * L - 1) / (kSubBlock * L);   // at most kMaxGroupRounds (host)
+    cptr<ChanDev> chan = V.chan;
+    cptr<double> rate = V.rate;
+    double seg_hi[kMaxGroupRounds];   // the running sum at the end of this lane's segment of each round
+    double cur = 0.0;                 // the running sum this lane last ended a segment with
+#pragma unroll
+    for (int q = 0; q < kMaxGroupRounds; ++q) {
+        seg_hi[q] = 0.0;
+        if (q < rounds) {
+            double a[kSubBlock];
+            segment_propensities(chan, rate, X, (q * L + rank) * kSubBlock, Mp, a);
+            // rank 0 continues from the sum the previous round's last rank ended with
+            double in = q == 0 ? 0.0 : dpp_f64_last_to_first<L>(cur);
+#pragma unroll
+            for (int rr = 0; rr < L; ++rr) {
+                if (rr > 0) in = dpp_f64_shr1(cur);   // rank rr: the sum rank rr - 1 ended with
+                double s = in;
+#pragma unroll
+                for (int r = 0; r < kSubBlock; ++r) s = s + a[r];
+                cur = rank == rr ? s : cur;
+            }
+            seg_hi[q] = cur;
+        }
+    }
+    // the total: the end of the last rank's segment of the last round
+    const double a0 = shfl_f64(cur, gbase + L - 1);
+    const double target = d.u2 * a0;
+    // first segment (round, rank) whose end exceeds the target
+    const uint64_t gbits = (1ull << L) - 1ull;
+    int qsel = 0, rsel = L - 1;
+    bool found = false;
+#pragma unroll
+    for (int q = 0; q < kMaxGroupRounds; ++q) {
+        if (q < rounds) {
+            const uint64_t g = (__ballot(seg_hi[q] > target) >> gbase) & gbits;
+            const bool hit = !found && g != 0ull;
+            qsel = hit ? q : qsel;
+            rsel = hit ? ffs64(g) : rsel;
+            found = found || hit;
+        }
+    }
+    // The selected segment starts where the previous one ended: rank rsel - 1
+    // of round qsel, or the last rank of round qsel - 1 (0 before the first).
+    // Every lane of the group fetches that sum and re-runs the selected
+    // segment with identical operations.
+    const int qprev = rsel > 0 ? qsel : qsel - 1;
+    double prov = 0.0;
+#pragma unroll
+    for (int q = 0; q < kMaxGroupRounds; ++q) prov = q == qprev ? seg_hi[q] : prov;
+    double s = shfl_f64(prov, gbase + (rsel > 0 ? rsel - 1 : L - 1));
+    s = qprev < 0 ? 0.0 : s;
+    const int j0 = (qsel * L + rsel) * kSubBlock;
+    double a[kSubBlock];
+    segment_propensities(chan, rate, X, j0, Mp, a);
+    int jsel = j0 + kSubBlock - 1;
+    bool got = false;
+#pragma unroll
+    for (int r = 0; r < kSubBlock; ++r) {
+        s = s + a[r];
+        const bool hit = !got && s > target;
+        jsel = hit ? j0 + r : jsel;
+        got = got || hit;
+    }
+    jsel = jsel < Mp ? jsel : Mp - 1;   // only where nothing fires (a0 = 0, the change is unused)
+    cptr<uint32_t> chg = V.chg;
+    *change = Change{chg[4 * jsel], chg[4 * jsel + 1], chg[4 * jsel + 2], chg[4 * jsel + 3]};
+    const double tau = d.nl / a0;
+    return a0 > 0.0 ? t + tau : __builtin_inf();
+}
+
+// ---------------------------------------------------------------------------
 // Access policies of the persistent loop.
 //
 // DynPolicy: the generic kernels.  Network and monitor tables are read from
@@ -899,10 +1061,14 @@ __device__ __forceinline__ double draw_tail(const JobView &V, const C &X, const 
 // live in registers; every table index is an immediate.  The arithmetic is
 // the same sequence of operations as the generic path.
 // ---------------------------------------------------------------------------
-template <int NB>
+// G > 1: the kernel also runs jobs with G lanes per trajectory (kernels of
+// their own, one per group size, so that each keeps its registers: the
+// one-lane kernels as before, and a grouped kernel without spills).
+template <int NB, int G = 1>
 struct DynPolicy {
     using Counts = LdsCounts;
     using Sel = Change;
+    static constexpr bool kGroups = G > 1 && NB > 4;
     __device__ static __forceinline__ Counts counts(int32_t *lds, int wid, int s_max, int lane)
     {
         Counts X;
@@ -917,6 +1083,8 @@ struct DynPolicy {
     __device__ static __forceinline__ double draw(const JobView &V, const Counts &X, const Draw &d,
                                                   double t, Sel *s, bool live)
     {
+        if (kGroups && __builtin_amdgcn_readfirstlane(V.lanes) == G)
+            return ssa_draw_group<(G > 1 ? G : 2)>(V, X, d, t, s);
         return ssa_draw<NB>(V, X, d, t, s, live);
     }
     __device__ static __forceinline__ void apply_if(Counts &X, const Sel &c, bool on)
@@ -951,6 +1119,7 @@ template <class Spec>
 struct StaticPolicy {
     static constexpr int S = Spec::S;
     static constexpr int M = Spec::M;
+    static constexpr bool kGroups = false;
     using Counts = RegCounts<S>;
     using Sel = int;
     __device__ static __forceinline__ Counts counts(int32_t *, int, int, int) { return Counts{}; }
@@ -1034,6 +1203,7 @@ struct StaticWidePolicy {
     static constexpr int kNsub = Mp / kSubBlock;
     static constexpr int kNb = kNsub < kBlocks ? kNsub : kBlocks;
     static constexpr int kBs = (kNsub + kNb - 1) / kNb * kSubBlock;
+    static constexpr bool kGroups = false;
     using Counts = LdsCounts;
     using Sel = Change;
     __device__ static __forceinline__ Counts counts(int32_t *lds, int wid, int, int lane)
@@ -1454,8 +1624,13 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
             }
         }
         // -------- refill idle lanes with new trajectory indices --------
+        // With lane groups (L > 1) the L lanes of a group start, run and end
+        // one trajectory together; the group is counted by its first lane.
+        const int L = Pol::kGroups ? __builtin_amdgcn_readfirstlane(V.lanes) : 1;
+        const int gbase = lane & ~(L - 1);
+        const bool lead = lane == gbase;
         bool entered = false;   // this lane entered a state in this iteration
-        const uint64_t need = __ballot(!active);
+        const uint64_t need = __ballot(!active && lead);
         if (need) {
             const int n_need = __popcll(need);
             if (pool_next == pool_end) {
@@ -1469,7 +1644,8 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
             }
             const unsigned long long avail = pool_end - pool_next;
             const int give = (unsigned long long)n_need < avail ? n_need : (int)avail;
-            const int r = rank_in(need);
+            // rank of this lane's group among the idle groups
+            const int r = L == 1 ? rank_in(need) : __popcll(need & ((1ull << gbase) - 1ull));
             if (!active && r < give) {
                 ridx = pool_next + (unsigned long long)r;
                 Pol::init(X, V);
@@ -1532,18 +1708,22 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
         reason = dec_state ? (uint32_t)RS_STATE : reason;
 
         // -------- accounting of decided trajectories --------
-        uint64_t fm = __ballot(fin);
+        // (counted once per trajectory: by the first lane of its group)
+        const bool fin_c = fin && lead;
+        uint64_t fm = __ballot(fin_c);
         if (fm) {
-            if (fin) {
+            if (fin_c) {
                 if (V.rec_events) V.rec_events[ridx] = k;
                 if (V.rec_vr) V.rec_vr[ridx] = (uint8_t)(verdict | (reason << 1));
             }
             if (!kIter || !V.iterative) {
-                if (fin) {
+                if (fin_c) {
                     my_yes += verdict;
                     my_no += 1u - verdict;
                     my_trunc += (reason == RS_CAP) ? 1u : 0u;
                     my_events += k;
+                }
+                if (fin) {
                     fin = false;
                     active = false;
                 }
@@ -1554,7 +1734,7 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
             int b = 0;
             {
                 const unsigned long long bq = lane < kMaxBatches ? ld_relaxed(&V.st->bound[lane]) : 0ull;
-                if (fin) {
+                if (fin_c) {
                     for (int q = 0; q < kMaxBatches - 1; ++q) {
                         const unsigned long long bb = read_lane_u64(bq, q);
                         if (bb == 0ull || ridx < bb) break;
@@ -1563,9 +1743,9 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
                 }
             }
             while (fm) {
-                const int L = ffs64(fm);
-                const int b0 = __builtin_amdgcn_readlane(b, L);
-                const bool sel = fin && (b == b0);
+                const int Lf = ffs64(fm);
+                const int b0 = __builtin_amdgcn_readlane(b, Lf);
+                const bool sel = fin_c && (b == b0);
                 const uint64_t sm = __ballot(sel);
                 const uint32_t ny = (uint32_t)__popcll(__ballot(sel && verdict));
                 const uint32_t nn = (uint32_t)__popcll(sm) - ny;
@@ -1574,11 +1754,11 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
                 JobState *st = V.st;
                 const unsigned long long delta = ((unsigned long long)ny << 32) | (unsigned long long)(ny + nn);
                 unsigned long long old = 0;
-                if (lane == L) {
+                if (lane == Lf) {
                     add_counts(st, b0, shard, 0, 0, nt, ev);
                     old = atomicAdd(&st->cnt[b0], delta);
                 }
-                old = read_lane_u64(old, L);
+                old = read_lane_u64(old, Lf);
                 const unsigned long long now = old + delta;
                 if ((now & 0xFFFFFFFFull) == kDoneFlag) {
                     fence_acquire();   // the bounds the batch's publisher had seen
@@ -1590,10 +1770,10 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
                         speculate(V, b0, now);
                 }
                 fm &= ~sm;
-                if (sel) {
-                    fin = false;
-                    active = false;
-                }
+            }
+            if (fin) {
+                fin = false;
+                active = false;
             }
         }
     }

@@ -12,11 +12,27 @@ namespace smc {
 #endif
 
 // Persistent SSA + monitor kernel reading its tables from device memory.
-template <int NB, bool kIter>
+template <int NB, bool kIter, int G = 1>
 __global__ __launch_bounds__(256, SMC_MIN_WAVES_PER_EU) void ssa_persistent(KArgs A)
 {
     extern __shared__ int32_t lds[];
-    persistent_body<DynPolicy<NB>, kIter>(A, lds);
+    persistent_body<DynPolicy<NB, G>, kIter>(A, lds);
+}
+
+// The persistent kernel of a launch variant: 0 = at most 4 reaction channels,
+// 1 = any network, 2..5 = any network, with jobs of 2, 4, 8 or 16 lanes per
+// trajectory.
+template <bool kIter>
+static const void *persistent_kernel(int variant)
+{
+    switch (variant) {
+    case 0: return reinterpret_cast<const void *>(&ssa_persistent<4, kIter>);
+    case 1: return reinterpret_cast<const void *>(&ssa_persistent<kBlocks, kIter>);
+    case 2: return reinterpret_cast<const void *>(&ssa_persistent<kBlocks, kIter, 2>);
+    case 3: return reinterpret_cast<const void *>(&ssa_persistent<kBlocks, kIter, 4>);
+    case 4: return reinterpret_cast<const void *>(&ssa_persistent<kBlocks, kIter, 8>);
+    default: return reinterpret_cast<const void *>(&ssa_persistent<kBlocks, kIter, 16>);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -212,7 +228,7 @@ __global__ void wilson_table(const unsigned long long *yes, const unsigned long 
 // ---------------------------------------------------------------------------
 namespace smc {
 
-// variant: 0 = at most 4 reaction channels, 1 = any network; iterative:
+// variant: see persistent_kernel; iterative:
 // the launch holds jobs with the Fig. 2 stopping rule
 hipError_t launch_persistent(int variant, bool iterative, int grid, int waves_per_block, size_t lds_bytes,
                              hipStream_t stream, const Job *jobs, int n_jobs, int s_max,
@@ -228,14 +244,10 @@ hipError_t launch_persistent(int variant, bool iterative, int grid, int waves_pe
     a.waves_per_block = waves_per_block;
     a.static_first = static_first;
     const dim3 block(kWave * waves_per_block);
-    if (variant == 0 && iterative)
-        hipLaunchKernelGGL((ssa_persistent<4, true>), dim3(grid), block, lds_bytes, stream, a);
-    else if (variant == 0)
-        hipLaunchKernelGGL((ssa_persistent<4, false>), dim3(grid), block, lds_bytes, stream, a);
-    else if (iterative)
-        hipLaunchKernelGGL((ssa_persistent<kBlocks, true>), dim3(grid), block, lds_bytes, stream, a);
-    else
-        hipLaunchKernelGGL((ssa_persistent<kBlocks, false>), dim3(grid), block, lds_bytes, stream, a);
+    const void *fn = iterative ? persistent_kernel<true>(variant) : persistent_kernel<false>(variant);
+    void *args[] = {&a};
+    const hipError_t e = hipLaunchKernel(fn, dim3(grid), block, args, lds_bytes, stream);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
@@ -244,15 +256,8 @@ int persistent_blocks_per_cu(int variant, bool iterative, int waves_per_block, s
 {
     int nb = 0;
     const int threads = kWave * waves_per_block;
-    hipError_t e;
-    if (variant == 0 && iterative)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ssa_persistent<4, true>, threads, lds_bytes);
-    else if (variant == 0)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ssa_persistent<4, false>, threads, lds_bytes);
-    else if (iterative)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ssa_persistent<kBlocks, true>, threads, lds_bytes);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ssa_persistent<kBlocks, false>, threads, lds_bytes);
+    const void *fn = iterative ? persistent_kernel<true>(variant) : persistent_kernel<false>(variant);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, lds_bytes);
     return e == hipSuccess ? nb : 0;
 }
 

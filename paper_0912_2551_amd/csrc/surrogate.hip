@@ -648,6 +648,47 @@ hipError_t sg_round(hipStream_t s, const float *w, uint16_t *wb, long count)
     return hipGetLastError();
 }
 
+// The neighbourhood gate: the six points x +- delta e_k of every query point
+// (log10 rate constants), and the test that the network's output at each of
+// them lies on the same side of the threshold as at the point itself, at
+// least `margin` away from it.
+__global__ void expand_neighbours(const float *x, long n, float delta, float *x6)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 6 * n) return;
+    const long pnt = i / 6;
+    const int k = (int)(i % 6);
+    const int axis = k >> 1;
+    const float step = (k & 1) ? -delta : delta;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x6[3 * i + a] = x[3 * pnt + a] + (a == axis ? step : 0.0f);
+}
+
+__global__ void neighbour_gate(const float *p, const float *p6, long n, float threshold, float margin, uint8_t *use)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !use[i]) return;
+    const float side = p[i] >= threshold ? 1.0f : -1.0f;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ok = ok && (p6[6 * i + k] - threshold) * side >= margin;
+    use[i] = ok ? 1 : 0;
+}
+
+hipError_t sg_expand_neighbours(hipStream_t s, const float *x, long n, float delta, float *x6)
+{
+    hipLaunchKernelGGL(expand_neighbours, dim3(blocks_for(6 * n, 256)), dim3(256), 0, s, x, n, delta, x6);
+    return hipGetLastError();
+}
+
+hipError_t sg_neighbour_gate(hipStream_t s, const float *p, const float *p6, long n, float threshold, float margin,
+                             uint8_t *use)
+{
+    hipLaunchKernelGGL(neighbour_gate, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, p6, n, threshold, margin,
+                       use);
+    return hipGetLastError();
+}
+
 hipError_t sg_query(hipStream_t s, const float *x, long n, const float *mu, const float *sigma,
                     const uint16_t *W1b, const float *b1, const uint16_t *W2b, const float *b2,
                     const uint16_t *W3b, const float *b3, const float *planes, int n_planes, float hull_tol,

@@ -34,6 +34,9 @@ hipError_t sg_loss_sum(hipStream_t s, const float *loss_row, int n, float *out);
 hipError_t sg_adam(hipStream_t s, float *w, const float *g, float *m, float *v, uint16_t *wb, long count,
                    float lr, float beta1, float beta2, float eps, float bc1, float bc2);
 hipError_t sg_round(hipStream_t s, const float *w, uint16_t *wb, long count);
+hipError_t sg_expand_neighbours(hipStream_t s, const float *x, long n, float delta, float *x6);
+hipError_t sg_neighbour_gate(hipStream_t s, const float *p, const float *p6, long n, float threshold, float margin,
+                             uint8_t *use);
 hipError_t sg_query(hipStream_t s, const float *x, long n, const float *mu, const float *sigma,
                     const uint16_t *W1b, const float *b1, const uint16_t *W2b, const float *b2,
                     const uint16_t *W3b, const float *b3, const float *planes, int n_planes, float hull_tol,
@@ -74,6 +77,11 @@ struct smc_surrogate {
     bool refuse = false;
     float cal_margin = 0.0f;
     float cal_threshold = 0.5f;
+    // neighbourhood of the calibrated gate (0: none): an answer also needs
+    // the six points x +- delta e_k on the same side, `margin` away
+    float cal_delta = 0.0f;
+    long nbcap = 0;
+    float *nbx = nullptr, *nbp = nullptr;
 };
 
 extern "C" const char *smc_last_error(const smc_ctx *ctx);
@@ -368,6 +376,19 @@ int smc_surrogate_query(smc_surrogate *s, const float *x, size_t n, float thresh
     SG_TRY(s, sg_query(s->stream, d_x, (long)n, s->norm, s->norm + 3, s->wb + OFF_W1, s->w + OFF_B1,
                        s->wb + OFF_W2, s->w + OFF_B2, s->wb + OFF_W3, s->w + OFF_B3, s->planes, s->n_planes,
                        1e-6f, threshold, m, d_p, d_use));
+    if (d_use && s->calibrated && !s->refuse && s->cal_delta > 0.0f && threshold == s->cal_threshold) {
+        // the neighbourhood gate: the network at x +- delta e_k
+        if ((long)n > s->nbcap) {
+            SG_TRY(s, dalloc(s->nbx, n * 18));
+            SG_TRY(s, dalloc(s->nbp, n * 6));
+            s->nbcap = (long)n;
+        }
+        SG_TRY(s, sg_expand_neighbours(s->stream, d_x, (long)n, s->cal_delta, s->nbx));
+        SG_TRY(s, sg_query(s->stream, s->nbx, 6L * (long)n, s->norm, s->norm + 3, s->wb + OFF_W1, s->w + OFF_B1,
+                           s->wb + OFF_W2, s->w + OFF_B2, s->wb + OFF_W3, s->w + OFF_B3, s->planes, 0, 1e-6f,
+                           threshold, 0.0f, s->nbp, nullptr));
+        SG_TRY(s, sg_neighbour_gate(s->stream, d_p, s->nbp, (long)n, threshold, m, d_use));
+    }
     if (!on_device) {
         SG_TRY(s, hipMemcpyAsync(p_out, s->qp, n * 4, hipMemcpyDeviceToHost, s->stream));
         if (use_surrogate) SG_TRY(s, hipMemcpyAsync(use_surrogate, s->quse, n, hipMemcpyDeviceToHost, s->stream));
@@ -392,29 +413,64 @@ int smc_surrogate_calibrate(smc_surrogate *s, const float *x, const double *lo, 
         const int rc = smc_surrogate_query(s, x, n, threshold, 0.0f, 0, p.data(), in_hull.data());
         if (rc != SMC_OK) return rc;
     }
-    // The margin must exceed |p - threshold| at every held-out point in the
-    // hull whose answer lies more than `bound` outside its interval.
-    double need = min_margin;
+    // For each neighbourhood size delta (log10 units, 0 = the point alone),
+    // the stability of each held-out point: the least signed distance from
+    // the threshold, on the point's side, of the outputs at x and at x +-
+    // delta e_k.  The margin must exceed the stability of every held-out point
+    // in the hull whose answer lies more than `bound` outside its interval;
+    // the delta that leaves the largest share answered is kept.
+    static const float kDeltas[] = {0.0f, 0.01f, 0.02f, 0.05f, 0.1f, 0.2f};
+    std::vector<float> x6(n * 18), p6(n * 6);
+    double best_m = 2.0, best_share = -1.0;
+    float best_delta = 0.0f;
     size_t inside = 0;
-    for (size_t i = 0; i < n; ++i) {
-        if (!in_hull[i]) continue;
-        ++inside;
-        const double pi = p[i];
-        const bool off = pi < lo[i] - bound || pi > hi[i] + bound;
-        if (off) need = std::max(need, (double)std::nextafter(std::fabs(p[i] - threshold), 2.0f));
-    }
-    const bool refuse = inside == 0 || need > 0.5;
-    size_t answered = 0;
-    if (!refuse)
+    for (size_t i = 0; i < n; ++i) inside += in_hull[i] ? 1 : 0;
+    for (float delta : kDeltas) {
+        std::vector<double> stab(n);
+        for (size_t i = 0; i < n; ++i) stab[i] = std::fabs((double)p[i] - threshold);
+        if (delta > 0.0f && n) {
+            for (size_t i = 0; i < n; ++i)
+                for (int k = 0; k < 6; ++k)
+                    for (int a = 0; a < 3; ++a)
+                        x6[18 * i + 3 * k + a] = x[3 * i + a] + (a == (k >> 1) ? ((k & 1) ? -delta : delta) : 0.0f);
+            const int rc = smc_surrogate_query(s, x6.data(), 6 * n, threshold, 0.0f, 0, p6.data(), nullptr);
+            if (rc != SMC_OK) return rc;
+            for (size_t i = 0; i < n; ++i) {
+                const double side = p[i] >= threshold ? 1.0 : -1.0;
+                for (int k = 0; k < 6; ++k) stab[i] = std::min(stab[i], ((double)p6[6 * i + k] - threshold) * side);
+            }
+        }
+        double need = min_margin;
+        for (size_t i = 0; i < n; ++i) {
+            if (!in_hull[i]) continue;
+            const bool off = p[i] < lo[i] - bound || p[i] > hi[i] + bound;
+            if (off) need = std::max(need, (double)std::nextafter((float)stab[i], 2.0f));
+        }
+        if (need > 0.5) continue;
+        size_t answered = 0;
         for (size_t i = 0; i < n; ++i)
-            if (in_hull[i] && std::fabs(p[i] - threshold) >= (float)need) ++answered;
+            if (in_hull[i] && stab[i] >= (double)(float)need) ++answered;
+        const double share = n ? (double)answered / (double)n : 0.0;
+        if (share > best_share) {
+            best_share = share;
+            best_m = need;
+            best_delta = delta;
+        }
+    }
+    const bool refuse = inside == 0 || best_share < 0.0;
     s->calibrated = true;
     s->refuse = refuse;
-    s->cal_margin = refuse ? 2.0f : (float)need;
+    s->cal_margin = refuse ? 2.0f : (float)best_m;
+    s->cal_delta = refuse ? 0.0f : best_delta;
     s->cal_threshold = threshold;
-    if (margin_out) *margin_out = refuse ? -1.0f : (float)need;
-    if (share_out) *share_out = n ? (float)((double)answered / (double)n) : 0.0f;
+    if (margin_out) *margin_out = refuse ? -1.0f : (float)best_m;
+    if (share_out) *share_out = refuse ? 0.0f : (float)best_share;
     return SMC_OK;
+}
+
+float smc_surrogate_neighbourhood(const smc_surrogate *s)
+{
+    return (s && s->calibrated && !s->refuse) ? s->cal_delta : 0.0f;
 }
 
 int smc_surrogate_hull(const smc_surrogate *s, float *planes, size_t cap)
@@ -443,7 +499,7 @@ void smc_surrogate_destroy(smc_surrogate *s)
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     for (float *p : {s->w, s->g, s->m, s->v, s->norm, s->planes, s->x, s->y, s->wt, s->pre1, s->pre2,
-                     s->dh1, s->p, s->loss_row, s->dz, s->qx, s->qp})
+                     s->dh1, s->p, s->loss_row, s->dz, s->qx, s->qp, s->nbx, s->nbp})
         if (p) (void)hipFree(p);
     for (uint16_t *p : {s->wb, s->xb, s->h1b, s->h2b, s->d2b})
         if (p) (void)hipFree(p);

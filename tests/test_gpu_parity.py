@@ -586,3 +586,87 @@ def test_c4_network_trajectories_match_oracle(ctx, mode):
         vr = (vd | (rs << 1)).astype(np.uint8)
         assert np.array_equal(vr, arrays[f"vr_{q}"]), (q, np.nonzero(vr != arrays[f"vr_{q}"])[0][:5])
         assert np.array_equal(ev, arrays[f"events_{q}"]), (q, np.nonzero(ev != arrays[f"events_{q}"])[0][:5])
+
+
+# ---------------------------------------------------------------------------
+# Several lanes per trajectory (generic kernels): the same results as one lane
+# ---------------------------------------------------------------------------
+_group_oracle = {}
+
+
+def _group_case(name):
+    if name == "c3":
+        net = W.c3_network()
+        return net, W.c3_formula(net), 1, W.C3_CAP, 1024
+    S, seed, d, cap, count = {"s8": (8, 41, 5, 20000, 2000), "s20": (20, 42, 10, 20000, 2000),
+                              "s128": (128, 7, 15, 20000, 140)}[name]
+    net = W.random_network(S, 4 * S, seed=seed)
+    return net, W.nested_until_formula(net, d), seed, cap, count
+
+
+@pytest.mark.parametrize("lanes", [2, 4, 8, 16])
+@pytest.mark.parametrize("name", ["s8", "s20", "c3", "s128"])
+def test_lane_group_trajectory_parity(ctx, name, lanes):
+    """Per-trajectory (events, verdict, reason) with 2..16 lanes per
+    trajectory equal the oracle's (the canonical sequential prefix is kept)."""
+    B = _B()
+    net, text, seed, cap, count = _group_case(name)
+    n = ctx.network(net)
+    f = ctx.formula(n, text)
+    model = 0 if name == "c3" else 2       # the C3 expectation is model 0's
+    p = B.params(seed=seed, model_id=model, max_events=cap, lanes=lanes)
+    print(f"case lanes {lanes} network {name} trajectories {count}", flush=True)
+    ev, vd, rs = ctx.trajectories(n, f, p, 0, count)
+    assert ctx.last_kernel() == B.KERNEL_GENERIC_GROUPED
+    if name == "c3":
+        oev, ovd, ors = (a[:count] for a in _c3_expected(net, text))
+    else:
+        if name not in _group_oracle:
+            _group_oracle[name] = oracle.trajectories(net, oracle.parse(text, net), 0, count, seed=seed, model_id=2,
+                                                      max_events=cap)
+        oev, ovd, ors = _group_oracle[name]
+    assert np.array_equal(rs, ors), np.nonzero(rs != ors)[0][:5]
+    assert np.array_equal(vd, ovd), np.nonzero(vd != ovd)[0][:5]
+    assert np.array_equal(ev, oev), np.nonzero(ev != oev)[0][:5]
+
+
+@pytest.mark.parametrize("lanes", [4, 16])
+def test_lane_groups_in_the_batched_sweep(ctx, lanes):
+    """The whole batched sweep with its random networks on lane groups (the
+    Michaelis-Menten jobs keep one lane) gives the oracle's estimates for all
+    576 jobs."""
+    B = _B()
+    doc, _ = _c4_expected()
+    keep, jobs = [], []
+    for net, text, kw in W.c4_jobs():
+        nh = ctx.network(net)
+        fh = ctx.formula(nh, text)
+        keep.append((nh, fh))
+        jobs.append((nh, fh, B.params(lanes=lanes, **kw)))
+    print(f"c4 with {lanes} lanes per network trajectory", flush=True)
+    res = ctx.estimate_batch(jobs)
+    assert ctx.last_kernel() == B.KERNEL_GENERIC_GROUPED
+    keys = ("n", "successes", "events", "truncated", "batches", "p_hat", "lo", "hi")
+    bad = [(e["job"], {k: (r[k], e[k]) for k in keys if r[k] != e[k]}) for r, e in zip(res, doc["jobs"])
+           if any(r[k] != e[k] for k in keys)]
+    assert not bad, bad[:5]
+
+
+def test_lane_group_settings(ctx):
+    B = _B()
+    with pytest.raises(B.SmcError):
+        ctx.set_lanes_per_trajectory(3)
+    net = W.immigration_death()
+    n = ctx.network(net)
+    f = ctx.formula(n, W.C1_FORMULA)
+    with pytest.raises(B.SmcError):
+        ctx.estimate(n, f, B.params(fixed_n=64, lanes=5))
+    # networks of at most four channels always run one lane per trajectory
+    ctx.set_lanes_per_trajectory(8)
+    try:
+        r = ctx.estimate(n, f, B.params(fixed_n=4096, seed=1))
+        assert ctx.last_kernel() in (B.KERNEL_SPECIALIZED, B.KERNEL_GENERIC_SMALL)
+    finally:
+        ctx.set_lanes_per_trajectory(0)
+    o = oracle.estimate(net, W.C1_FORMULA, fixed_n=4096, seed=1)
+    assert (r["n"], r["successes"], r["events"]) == (o["n"], o["successes"], o["events"])
