@@ -199,7 +199,10 @@ def batched_sweep_run(ctx, B, W):
     """512 Michaelis-Menten rate sets (each rate within +-1 decade) under the
     workload formula plus 64 random networks (8..128 species, 4 channels per
     species) under nested-until formulas, every model with its own 95% +-0.01
-    Wilson rule, in one persistent launch."""
+    Wilson rule, in one persistent launch.  The launch is autotuned first
+    (smc_autotune_batch: lanes per trajectory for the random networks and
+    waves per CU, from pilots of the batch as it runs), outside the timed
+    region; the pilots' own time is reported beside it."""
     import torch
     keep, jobs = [], []
     for net, text, kw in W.c4_jobs():
@@ -208,6 +211,9 @@ def batched_sweep_run(ctx, B, W):
         keep.append((a, b))
         jobs.append((a, b, B.params(**kw)))
     ctx.estimate_batch(jobs[:1])   # kernel choice and warm-up outside the timed region
+    t0 = time.perf_counter()
+    tune = ctx.autotune_batch(jobs, pilot_widen=1.0)
+    tune_wall = time.perf_counter() - t0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = ctx.estimate_batch(jobs)
@@ -219,6 +225,7 @@ def batched_sweep_run(ctx, B, W):
     return {"workload": "512 Michaelis-Menten rate sets + 64 random networks (S 8..128, M = 4S, offsets d "
                         "from the oracle pilot), 95% Wilson +-0.01 each, one launch",
             "models": len(jobs), "seconds": wall, "device_seconds": res[0]["device_seconds"],
+            "autotune": dict(tune, wall_seconds=tune_wall), "kernel": ctx.last_kernel(),
             "verified_trajectories": n, "verified_trajectories_per_s": n / wall, "events": ev,
             "events_per_s": ev / wall, "wasted": sum(r["wasted"] for r in res),
             "max_batches": max(r["batches"] for r in res),
@@ -267,17 +274,23 @@ def fig3_sample_sizes(ctx, B, W, reps=32, eps=0.025, confidence=0.99):
 
 
 def surrogate_vs_plain(ctx, B, W, text, n_train=512, n_cal=1024, n_query=10**6, n_sub=4096, eps=0.01,
-                       margin=0.05, steps=2000):
+                       margin=0.05, steps=2000, probe=64, n_probe_sample=32768):
     """Answer n_query rate points either with plain batched SMC or with the
     surrogate plus SMC fallback.  The surrogate path: plain SMC on the n_train
     sweep points, training, plain SMC on n_cal held-out points that calibrate
     the gate (the smallest margin, at least `margin`, at which no held-out
     answer lies more than eps outside its Wilson interval), one fused query
-    launch, and SMC on the points the gate rejects.  Plain SMC is timed on the
-    first n_sub query points (a uniform subsample, the points are i.i.d.) and
-    scaled to n_query; the fallback is timed the same way, as one batch of the
-    subsample's rejected points, scaled likewise.  The answered subsample
-    points are then checked against their plain-SMC Wilson intervals."""
+    launch, `probe` confirming trajectories per answered point (an answer
+    stands only if they all fall on its side, smc_surrogate_confirm), and SMC
+    on the points the gate rejects or the probes withdraw.  Plain SMC is
+    timed on the first n_sub query points (a uniform subsample, the points are
+    i.i.d.) and scaled to n_query; the fallback is timed the same way, as one
+    batch of the subsample's refused points, scaled likewise.  The probes are
+    timed as one batch over the answered points among the first
+    n_probe_sample query points (about as many trajectories as the plain
+    subsample, so that both batches fill the device alike), scaled to
+    n_query.  The answered subsample points are then checked against their
+    plain-SMC Wilson intervals."""
     import torch
     import numpy as np
     keep = []
@@ -322,16 +335,40 @@ def surrogate_vs_plain(ctx, B, W, text, n_train=512, n_cal=1024, n_query=10**6, 
     t_query = time.perf_counter() - t0
     js = jobs_for(10.0 ** q[:n_sub].astype(np.float64), 2)
     plain, t_sub = timed_batch(js)
-    u = use[:n_sub]
+    # probes: `probe` trajectories per answered point, on a seed of their own
+    n_ps = max(n_sub, min(n_query, n_probe_sample))
+    ans = np.nonzero(use[:n_ps])[0]
+    jp = []
+    for i in ans:
+        if i < n_sub:
+            nh, fh = js[i][0], js[i][1]
+        else:
+            nh = ctx.network(W.michaelis_menten(*(10.0 ** q[i].astype(np.float64))))
+            fh = ctx.formula(nh, text)
+            keep.append((nh, fh))
+        jp.append((nh, fh, B.params(fixed_n=probe, seed=5, model_id=int(i))))
+    pr, t_probe_sample = timed_batch(jp)
+    succ = np.zeros(n_ps, dtype=np.uint64)
+    trials = np.zeros(n_ps, dtype=np.uint64)
+    succ[ans] = [r["successes"] for r in pr]
+    trials[ans] = [r["n"] for r in pr]
+    confirmed = sg.confirm(p[:n_ps], use[:n_ps], succ, trials, threshold=0.5)
+    gate, u = use[:n_sub], confirmed[:n_sub]
     _, t_fallback_sub = timed_batch([j for j, ui in zip(js, u) if not ui])
     plain_total = t_sub * n_query / n_sub
+    probe_total = t_probe_sample * n_query / n_ps
     fallback_total = t_fallback_sub * n_query / n_sub
-    sur_total = t_train_smc + t_fit + t_cal_smc + t_cal + t_query + fallback_total
+    sur_total = t_train_smc + t_fit + t_cal_smc + t_cal + t_query + probe_total + fallback_total
     err = np.array([max(r["lo"] - pi, pi - r["hi"], 0.0) for r, pi, ui in zip(plain, p[:n_sub], u) if ui])
+    err_gate = np.array([max(r["lo"] - pi, pi - r["hi"], 0.0) for r, pi, ui in zip(plain, p[:n_sub], gate) if ui])
     return {"formula": text, "queries": n_query, "train_points": n_train, "calibration_points": n_cal,
             "subsample": n_sub, "plain_seconds_scaled": plain_total,
             "surrogate_plus_fallback_seconds": sur_total, "speedup": plain_total / sur_total,
-            "surrogate_share": float(use.mean()), "train_smc_seconds": t_train_smc, "fit_seconds": t_fit,
+            "surrogate_share": float(confirmed.mean()), "gate_share": float(use.mean()),
+            "probe_trajectories": probe, "probe_sample": n_ps, "probe_seconds_scaled": probe_total,
+            "withdrawn_by_probes": int(use[:n_ps].sum() - confirmed.sum()),
+            "max_outside_before_probes": float(err_gate.max()) if err_gate.size else None,
+            "train_smc_seconds": t_train_smc, "fit_seconds": t_fit,
             "fit_steps": steps, "final_loss": float(losses[-1]), "calibration_smc_seconds": t_cal_smc,
             "calibrated_margin": cal_margin, "calibrated_neighbourhood": sg.neighbourhood(),
             "calibration_share": cal_share, "query_seconds": t_query,

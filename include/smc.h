@@ -73,6 +73,24 @@ extern "C" {
                                      smc_surrogate_query the same bit goes in its own
                                      flags argument.                                 */
 
+#define SMC_TREE_SUMS 16u         /* jobs that run in lane groups (smc_params.lanes,
+                                     smc_set_lanes_per_trajectory) add their
+                                     propensities in a tree over the group instead
+                                     of in channel order: each lane sums its own
+                                     block of channels and the group scans the block
+                                     sums in log2(lanes) steps.  The direct method's
+                                     distribution is unchanged (channel j with
+                                     probability a_j/a0, tau ~ Exp(a0), Sec. 2.1),
+                                     but a0 and the boundaries are rounded
+                                     differently, so results equal the channel-order
+                                     kernels' in distribution, not bit for bit:
+                                     verdicts and event counts per trajectory agree
+                                     except where a draw falls within a few ulps of
+                                     a boundary, and event times differ in the last
+                                     bits.  No effect on one lane per trajectory.
+                                     The grouped jobs of one call must agree on it
+                                     (else SMC_E_INVALID).                          */
+
 typedef struct smc_ctx smc_ctx;
 typedef struct smc_net smc_net;
 typedef struct smc_formula smc_formula;
@@ -113,11 +131,13 @@ int smc_set_specialization(smc_ctx *ctx, int mode);
 /* Which SSA kernel the last estimation call on ctx launched: -1 none yet,
  * SMC_KERNEL_GENERIC_SMALL (table-driven, <= 4 channels), SMC_KERNEL_GENERIC
  * (table-driven, blocked prefix), SMC_KERNEL_SPECIALIZED,
- * SMC_KERNEL_GENERIC_GROUPED (table-driven, several lanes per trajectory). */
+ * SMC_KERNEL_GENERIC_GROUPED (table-driven, several lanes per trajectory),
+ * SMC_KERNEL_GENERIC_TREE (the same with SMC_TREE_SUMS). */
 #define SMC_KERNEL_GENERIC_SMALL 0
 #define SMC_KERNEL_GENERIC 1
 #define SMC_KERNEL_SPECIALIZED 2
 #define SMC_KERNEL_GENERIC_GROUPED 3
+#define SMC_KERNEL_GENERIC_TREE 4
 int smc_last_kernel(const smc_ctx *ctx);
 /* Register budget of specialised kernels: compile them so that
  * `waves_per_simd` waves fit on one SIMD (1..8; registers beyond the budget
@@ -219,7 +239,7 @@ typedef struct {
     uint32_t max_events; /* 0: no cap; else undecided after this many events: FALSE */
     double t_max;        /* pessimistic horizon for unbounded formulas (+inf: none) */
     uint32_t flags;      /* SMC_CONSERVATIVE_START | SMC_PAPER_ROUNDING |
-                            SMC_NO_SPECULATION | SMC_DEVICE_PTRS                 */
+                            SMC_NO_SPECULATION | SMC_DEVICE_PTRS | SMC_TREE_SUMS */
     uint32_t lanes;      /* lanes per trajectory: 0 = the context's choice
                             (smc_set_lanes_per_trajectory), else 1, 2, 4, 8 or 16 */
 } smc_params;
@@ -258,6 +278,41 @@ typedef struct {
     smc_params params;
 } smc_job;
 int smc_estimate_batch(smc_ctx *ctx, const smc_job *jobs, size_t n_jobs, smc_result *out);
+
+/* Autotuning of a batched launch (smc_estimate_batch), iterative and mixed
+ * jobs included (replica parallelism, Sec. 4): lanes per trajectory for the
+ * jobs whose lanes are automatic (smc_params.lanes = 0 and context setting
+ * 0) and waves per compute unit.  Pilot runs estimate the same jobs with
+ * each job's interval half-width widened by pilot_widen (1..64; iterative
+ * jobs, about pilot_widen^2 times fewer trajectories by eq. 4) or its fixed
+ * size divided by pilot_widen^2 (at least 64), on seeds derived from each
+ * job's, so the estimate's own trajectories are not consumed.  A wider
+ * interval makes the pilots cheaper but shifts the balance between the
+ * throughput-bound bulk of a launch and its latency-bound tail (the longest
+ * trajectories take as long either way), so pilot_widen = 1 (the batch as it
+ * will run) is the faithful choice.  Candidates: 1, 2, 4, 8 and 16 lanes
+ * (when the batch has automatic jobs of more than four channels; upwards until
+ * a pilot takes 15 % longer than the best so far) at 16 waves per compute
+ * unit, then 8 and 32 waves per compute unit at the best lanes; the shortest
+ * device time wins.  The choice
+ * is recorded on the context for the batch's signature (the structures of its
+ * jobs, in order, and their count; rates, initial states and stopping
+ * parameters do not enter): later smc_estimate_batch calls with that
+ * signature use it in place of the context's settings, which are otherwise
+ * left unchanged.  A second call with the same signature returns the recorded
+ * choice without pilots.  Results are identical under every choice (with
+ * SMC_TREE_SUMS: the same in distribution).  Errors: SMC_E_INVALID, and those
+ * of smc_estimate_batch. */
+typedef struct {
+    int32_t lanes;           /* lanes per trajectory for the automatic wide jobs */
+    int32_t waves_per_cu;    /* launch shape                                      */
+    int32_t candidates;      /* configurations timed                              */
+    int32_t pad_;
+    double seconds;          /* pilot device time of the choice                   */
+    double default_seconds;  /* pilot device time of one lane, 16 waves per CU    */
+} smc_batch_tune_result;
+int smc_autotune_batch(smc_ctx *ctx, const smc_job *jobs, size_t n_jobs, double pilot_widen,
+                       smc_batch_tune_result *out);
 
 /* For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
@@ -404,6 +459,24 @@ int smc_surrogate_query(smc_surrogate *s, const float *x, size_t n, float thresh
 int smc_surrogate_calibrate(smc_surrogate *s, const float *x, const double *lo, const double *hi, size_t n,
                             float threshold, float bound, float min_margin, float *margin_out,
                             float *share_out);
+/* Confirm answers with a few plain-SMC trajectories per answered point, which
+ * the caller runs (e.g. smc_estimate_batch with fixed_n = trials[i], on a
+ * seed of its own): p[i] is the surrogate's output and use_surrogate[i] its
+ * gate from smc_surrogate_query, successes[i] of trials[i] trajectories
+ * satisfied the formula.  An answer on the TRUE side (p >= threshold) stands
+ * only if all trials succeeded, one on the FALSE side only if none did; the
+ * others are withdrawn (use_surrogate[i] = 0, so the point goes to the SMC
+ * fallback).  Entries with use_surrogate[i] = 0 are left alone.  Whatever the
+ * network learned, a point whose true probability lies q or more on the other
+ * side of its answer (p_true >= q for a FALSE answer, <= 1 - q for a TRUE one)
+ * keeps its answer with probability at most (1 - q)^trials[i]: the trials are
+ * independent Bernoulli draws of the property (Sec. 3.3).  flags: 0, or
+ * SMC_DEVICE_PTRS when all four arrays are device pointers on the
+ * surrogate's device (then an entry with more successes than trials
+ * withdraws its answer).  Errors: SMC_E_INVALID (null array, unknown flag,
+ * threshold outside [0, 1], on host arrays more successes than trials). */
+int smc_surrogate_confirm(smc_surrogate *s, const float *p, const uint64_t *successes, const uint64_t *trials,
+                          size_t n, float threshold, uint32_t flags, uint8_t *use_surrogate);
 /* The calibrated neighbourhood size delta (0 if none or not calibrated). */
 float smc_surrogate_neighbourhood(const smc_surrogate *s);
 /* Facets of the training hull as planes (nx, ny, nz, d), inside: n.x <= d.

@@ -206,6 +206,25 @@ typedef struct {
     const double *prog_arg;  /* constant or species index */
 } oformula;
 
+/* pow(x, y) (Sec. 3.1, func).  The paper does not fix its rounding; read
+ * here: for an integral y in 0..64 the product of y factors x formed by
+ * binary powering, most significant of seven exponent bits first (square,
+ * then multiply where the bit is set, from r = 1), each step one rounded
+ * multiplication; any other y takes the C library's pow. */
+static double pow_read(double x, double y)
+{
+    if (y >= 0.0 && y <= 64.0 && y == floor(y)) {
+        const int k = (int)y;
+        double r = 1.0;
+        for (int b = 6; b >= 0; --b) {
+            r = r * r;
+            if ((k >> b) & 1) r = r * x;
+        }
+        return r;
+    }
+    return pow(x, y);
+}
+
 static double eval_val(const oformula *f, int off, int len, const int32_t *x)
 {
     double st[64];
@@ -220,7 +239,7 @@ static double eval_val(const oformula *f, int off, int len, const int32_t *x)
         case E_DIV: sp--; st[sp - 1] = st[sp - 1] / st[sp]; break;
         case E_NEG: st[sp - 1] = -st[sp - 1]; break;
         case E_SQRT: st[sp - 1] = sqrt(st[sp - 1]); break;
-        case E_POW: sp--; st[sp - 1] = pow(st[sp - 1], st[sp]); break;
+        case E_POW: sp--; st[sp - 1] = pow_read(st[sp - 1], st[sp]); break;
         }
     }
     return st[0];

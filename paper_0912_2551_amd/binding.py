@@ -30,16 +30,19 @@ SMC_CONSERVATIVE_START = 1
 SMC_PAPER_ROUNDING = 2
 SMC_NO_SPECULATION = 4
 SMC_DEVICE_PTRS = 8
+SMC_TREE_SUMS = 16
 NOALLOC_MAX_JOBS = 64
 REASON_STATE, REASON_TIME, REASON_ABSORB, REASON_CAP, REASON_TMAX = range(5)
 
 SPECIALIZE_AUTO, SPECIALIZE_OFF, SPECIALIZE_REQUIRED = 0, 1, 2
 KERNEL_GENERIC_SMALL, KERNEL_GENERIC, KERNEL_SPECIALIZED, KERNEL_GENERIC_GROUPED = 0, 1, 2, 3
+KERNEL_GENERIC_TREE = 4
 
 EXPORTS = [
     "smc_ctx_create", "smc_ctx_destroy", "smc_last_error", "smc_set_watchdog",
     "smc_set_waves_per_cu", "smc_set_specialization", "smc_last_kernel",
-    "smc_set_kernel_occupancy", "smc_set_lanes_per_trajectory", "smc_autotune", "smc_cancel", "smc_device_cus", "smc_net_create",
+    "smc_set_kernel_occupancy", "smc_set_lanes_per_trajectory", "smc_autotune", "smc_autotune_batch",
+    "smc_cancel", "smc_device_cus", "smc_net_create",
     "smc_net_set_rates", "smc_net_destroy", "smc_formula_compile", "smc_formula_horizon", "smc_formula_check",
     "smc_formula_destroy", "smc_estimate", "smc_estimate_batch", "smc_estimate_batch_noalloc",
     "smc_trajectories",
@@ -47,7 +50,7 @@ EXPORTS = [
     "smc_wilson_interval", "smc_wilson_next_device", "smc_surrogate_create",
     "smc_surrogate_param_count", "smc_surrogate_set_params", "smc_surrogate_get_params",
     "smc_surrogate_gradients", "smc_surrogate_train", "smc_surrogate_query", "smc_surrogate_calibrate",
-    "smc_surrogate_neighbourhood",
+    "smc_surrogate_neighbourhood", "smc_surrogate_confirm",
     "smc_surrogate_hull",
     "smc_surrogate_destroy", "smc_convex_hull",
 ]
@@ -57,6 +60,11 @@ class TuneResult(ctypes.Structure):
     _fields_ = [("waves_per_cu", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
                 ("specialization", ctypes.c_int32), ("candidates", ctypes.c_int32),
                 ("events_per_s", ctypes.c_double), ("default_events_per_s", ctypes.c_double)]
+
+
+class BatchTuneResult(ctypes.Structure):
+    _fields_ = [("lanes", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32), ("candidates", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("seconds", ctypes.c_double), ("default_seconds", ctypes.c_double)]
 
 
 class LibraryMissing(RuntimeError):
@@ -142,6 +150,8 @@ def lib():
             "smc_formula_destroy": (None, [vp]),
             "smc_estimate": (i32, [vp, vp, vp, ctypes.POINTER(Params), ctypes.POINTER(Result)]),
             "smc_estimate_batch": (i32, [vp, ctypes.POINTER(JobDesc), ctypes.c_size_t, ctypes.POINTER(Result)]),
+            "smc_autotune_batch": (i32, [vp, ctypes.POINTER(JobDesc), ctypes.c_size_t, ctypes.c_double,
+                                         ctypes.POINTER(BatchTuneResult)]),
             "smc_estimate_batch_noalloc": (i32, [vp, ctypes.POINTER(JobDesc), ctypes.c_size_t,
                                                  ctypes.POINTER(Result)]),
             "smc_trajectories": (i32, [vp, vp, vp, ctypes.POINTER(Params), u64, u64, vp, vp]),
@@ -169,6 +179,7 @@ def lib():
                                               ctypes.c_float, ctypes.POINTER(ctypes.c_float),
                                               ctypes.POINTER(ctypes.c_float)]),
             "smc_surrogate_neighbourhood": (ctypes.c_float, [vp]),
+            "smc_surrogate_confirm": (i32, [vp, vp, vp, vp, ctypes.c_size_t, ctypes.c_float, ctypes.c_uint32, vp]),
             "smc_surrogate_hull": (i32, [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
             "smc_surrogate_destroy": (None, [vp]),
             "smc_convex_hull": (i32, [ctypes.POINTER(ctypes.c_float), ctypes.c_size_t,
@@ -193,10 +204,27 @@ def _dptr(t):
 
 
 def params(confidence=0.95, half_width=0.01, z=0.0, fixed_n=0, seed=1, model_id=0, max_events=0,
-           t_max=math.inf, conservative=False, paper_rounding=False, speculate=True, lanes=0) -> Params:
+           t_max=math.inf, conservative=False, paper_rounding=False, speculate=True, lanes=0,
+           tree_sums=False) -> Params:
     flags = ((SMC_CONSERVATIVE_START if conservative else 0) | (SMC_PAPER_ROUNDING if paper_rounding else 0)
-             | (0 if speculate else SMC_NO_SPECULATION))
+             | (0 if speculate else SMC_NO_SPECULATION) | (SMC_TREE_SUMS if tree_sums else 0))
     return Params(confidence, half_width, z, fixed_n, seed, model_id, max_events, t_max, flags, lanes)
+
+
+def _torch_runtime_first():
+    """torch ships a HIP runtime of its own beside the one this library links.
+    Both can serve one process (device pointers pass between them), but only
+    if torch's starts first: started after the library's, it finds no
+    devices.  So start it, where torch is installed, before the library's
+    first HIP call."""
+    try:
+        import torch
+    except ImportError:
+        return
+    try:
+        torch.cuda.init()
+    except (RuntimeError, AssertionError):
+        pass
 
 
 class Context:
@@ -204,6 +232,7 @@ class Context:
     (or its integer handle) so that work is ordered with torch's."""
 
     def __init__(self, device: int = 0, stream=None):
+        _torch_runtime_first()
         L = lib()
         handle = None
         if stream is not None:
@@ -293,6 +322,17 @@ class Context:
         res = (Result * len(jobs))()
         self._check(lib().smc_estimate_batch(self.h, arr, len(jobs), res))
         return [r.as_dict() for r in res]
+
+    def autotune_batch(self, jobs, pilot_widen=1.0) -> dict:
+        """smc_autotune_batch; jobs as for estimate_batch."""
+        arr = (JobDesc * len(jobs))()
+        for k, (n, f, p) in enumerate(jobs):
+            arr[k].net = n.h
+            arr[k].formula = f.h
+            arr[k].params = p
+        r = BatchTuneResult()
+        self._check(lib().smc_autotune_batch(self.h, arr, len(jobs), float(pilot_widen), ctypes.byref(r)))
+        return {k: getattr(r, k) for k, _ in BatchTuneResult._fields_ if k != "pad_"}
 
     def estimate_batch_noalloc(self, jobs) -> list:
         """smc_estimate_batch_noalloc: at most NOALLOC_MAX_JOBS jobs, no allocation."""
@@ -504,6 +544,22 @@ class Surrogate:
                                                       xx.shape[0], threshold, bound, min_margin,
                                                       ctypes.byref(m), ctypes.byref(share)))
         return m.value, share.value
+
+    def confirm(self, p, use, successes, trials, threshold=0.5):
+        """smc_surrogate_confirm on host arrays; returns the confirmed gate."""
+        pp = np.ascontiguousarray(p, dtype=np.float32)
+        uu = np.ascontiguousarray(use, dtype=np.uint8).copy()
+        ss = np.ascontiguousarray(successes, dtype=np.uint64)
+        tt = np.ascontiguousarray(trials, dtype=np.uint64)
+        self.ctx._check(lib().smc_surrogate_confirm(self.h, pp.ctypes.data, ss.ctypes.data, tt.ctypes.data,
+                                                    pp.shape[0], threshold, 0, uu.ctypes.data))
+        return uu.astype(bool)
+
+    def confirm_device(self, p, successes, trials, n: int, use, threshold=0.5):
+        """smc_surrogate_confirm on device arrays (data_ptr(): p float32 [n],
+        successes and trials 64-bit [n], use uint8 [n], updated in place)."""
+        self.ctx._check(lib().smc_surrogate_confirm(self.h, _dptr(p), _dptr(successes), _dptr(trials), int(n),
+                                                    threshold, SMC_DEVICE_PTRS, _dptr(use)))
 
     def neighbourhood(self) -> float:
         """The calibrated gate's neighbourhood size (log10 units; 0: none)."""

@@ -847,7 +847,17 @@ class Compiler {
             val(e->a.get(), depth, maxd);
             emit_val(VO_SQRT, 0, 0.0, depth, maxd, 0);
             return;
-        case Expr::POW: throw Unsupported("pow() has no bit-reproducible GPU form");
+        case Expr::POW: {
+            // pow(v, k) with a constant integral k in 0..64: binary powering
+            // (see powi in the kernels); other exponents have no
+            // bit-reproducible form here
+            const Expr *k = e->b.get();
+            if (k->kind != Expr::CONST || !(k->c >= 0.0 && k->c <= 64.0) || k->c != std::floor(k->c))
+                throw Unsupported("pow() on the GPU takes a constant integral exponent in 0..64");
+            val(e->a.get(), depth, maxd);
+            emit_val(VO_POWI, (int)k->c, 0.0, depth, maxd, 0);
+            return;
+        }
         default: {
             val(e->a.get(), depth, maxd);
             val(e->b.get(), depth, maxd);

@@ -37,6 +37,8 @@ struct smc_ctx {
     int lanes = 0;   // lanes per trajectory (0: automatic)
     // autotuned configurations per model structure (see smc_autotune)
     std::map<std::pair<uint64_t, uint64_t>, smc_tune_result> tuned;
+    // autotuned configurations per batch signature (see smc_autotune_batch)
+    std::map<uint64_t, smc_batch_tune_result> tuned_batch;
     // specialised kernels per (network structure, formula structure,
     // iterative, occupancy hint): spares regenerating the kernel source
     std::map<std::tuple<uint64_t, uint64_t, int, int>, hipFunction_t> spec_fns;
@@ -187,15 +189,19 @@ double resolve_z(smc_ctx *ctx, const smc_params &p, bool cache = true)
 // for networks of more than four channels only, raised so that the group
 // covers the padded channels in at most kMaxGroupRounds rounds of kSubBlock
 // channels per lane.
-int job_lanes(const smc_ctx *ctx, const smc_params *p, int M)
+int lanes_for(int want, int M)
 {
-    const int want = p->lanes ? (int)p->lanes : ctx->lanes;
     if (want <= 1 || M <= 4) return 1;
     const int Mp = padded_channels(M);
     if (Mp > kMaxGroupRounds * kSubBlock * 16) return 1;
     int L = want;
     while (L < 16 && Mp > kMaxGroupRounds * kSubBlock * L) L *= 2;
     return L;
+}
+
+int job_lanes(const smc_ctx *ctx, const smc_params *p, int M)
+{
+    return lanes_for(p->lanes ? (int)p->lanes : ctx->lanes, M);
 }
 
 struct Prepared {
@@ -206,6 +212,8 @@ struct Prepared {
     uint64_t capacity = 0;
     double z = 0.0;
     bool speculate = true;   // iterative job: may run as a speculative launch
+    bool tree = false;       // SMC_TREE_SUMS: tree-ordered sums where the job runs in lane groups
+    bool auto_lanes = false; // lanes per trajectory left to the library (job and context: 0)
 };
 
 int prepare(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_params *p,
@@ -272,6 +280,8 @@ int prepare(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_pa
     out.capacity = capacity;
     out.z = z;
     out.speculate = (p->flags & SMC_NO_SPECULATION) == 0;
+    out.tree = (p->flags & SMC_TREE_SUMS) != 0;
+    out.auto_lanes = p->lanes == 0 && ctx->lanes == 0;
     return SMC_OK;
 }
 
@@ -377,8 +387,50 @@ int run_jobs(smc_ctx *ctx, std::vector<Prepared> &P, std::vector<JobResult> &res
     return run_jobs_in(ctx, P.data(), n, W, res.data(), seconds);
 }
 
+// Signature of a batch for smc_autotune_batch: the structures of its jobs in
+// order (FNV-1a over the structure ids and the job count).
+uint64_t batch_signature(const Prepared *P, int n)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](uint64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (v >> (8 * b)) & 0xFFull;
+            h *= 1099511628211ull;
+        }
+    };
+    mix((uint64_t)n);
+    for (int k = 0; k < n; ++k) {
+        mix(P[k].net ? P[k].net->sid : 0ull);
+        mix(P[k].f ? P[k].f->sid : 0ull);
+    }
+    return h;
+}
+
 int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult *res, double *seconds)
 {
+    // Tuned choices override the context's launch settings for this launch
+    // only; they are restored on return.
+    struct Restore {
+        smc_ctx *c;
+        int wpc, occ, mode;
+        ~Restore()
+        {
+            c->waves_per_cu = wpc;
+            c->spec_waves_per_simd = occ;
+            c->spec_mode = mode;
+        }
+    } restore{ctx, ctx->waves_per_cu, ctx->spec_waves_per_simd, ctx->spec_mode};
+    // A configuration tuned for this batch (smc_autotune_batch): its launch
+    // shape, and its lanes per trajectory for the jobs that leave that choice
+    // to the library.
+    if (!ctx->tuned_batch.empty() && !ctx->tuning) {
+        const auto it = ctx->tuned_batch.find(batch_signature(P, n));
+        if (it != ctx->tuned_batch.end()) {
+            ctx->waves_per_cu = it->second.waves_per_cu;
+            for (int k = 0; k < n; ++k)
+                if (P[k].auto_lanes) P[k].job.lanes = lanes_for(it->second.lanes, P[k].M);
+        }
+    }
     int s_max = 1, m_max = 1, n_iter = 0, group = 1;
     Job *jobs = W.h_jobs;   // the previous call's copies have completed
     for (int k = 0; k < n; ++k) {
@@ -392,10 +444,17 @@ int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult 
     // One group size per launch (one grouped kernel per size): jobs that run
     // several lanes per trajectory take the largest requested, which is at
     // least what each of them needs; the results do not depend on it.
+    // The grouped jobs of one launch also share the order of their sums.
+    int n_tree = 0, n_grouped = 0;
     for (int k = 0; k < n; ++k) {
         if (jobs[k].lanes > 1) jobs[k].lanes = group;
         P[k].job.lanes = jobs[k].lanes;
+        n_grouped += jobs[k].lanes > 1;
+        n_tree += jobs[k].lanes > 1 && P[k].tree;
     }
+    if (n_tree != 0 && n_tree != n_grouped)
+        return fail(ctx, SMC_E_INVALID, "jobs of one call that run in lane groups must agree on SMC_TREE_SUMS");
+    const bool tree = n_tree > 0;
     // Speculative launch: when every job is iterative and their capacities
     // together fit in one pass over the device's lanes, every index up to each
     // job's capacity runs at once, as a fixed-size launch that records
@@ -436,18 +495,7 @@ int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult 
     ctx->cancel_req.store(0);
 
     // A configuration tuned for this structure (fixed-size pilots) applies to
-    // launches of fixed-size jobs that all share it; the context's own
-    // settings are restored before returning.
-    struct Restore {
-        smc_ctx *c;
-        int wpc, occ, mode;
-        ~Restore()
-        {
-            c->waves_per_cu = wpc;
-            c->spec_waves_per_simd = occ;
-            c->spec_mode = mode;
-        }
-    } restore{ctx, ctx->waves_per_cu, ctx->spec_waves_per_simd, ctx->spec_mode};
+    // launches of fixed-size jobs that all share it.
     if (!ctx->tuned.empty() && !ctx->tuning && n_iter == 0 && P[0].net && P[0].f) {
         auto it = ctx->tuned.find(structure_key(P[0].net, P[0].f));
         bool same = it != ctx->tuned.end();
@@ -470,7 +518,7 @@ int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult 
     const unsigned long long waves_needed = (lanes_needed + kWave - 1) / kWave;
     const unsigned long long waves = std::min<unsigned long long>((unsigned long long)ctx->n_cu * wpc, waves_needed);
     const int grid = (int)std::max<unsigned long long>(1, (waves + wpb - 1) / wpb);
-    const int variant = group > 1 ? 1 + __builtin_ctz((unsigned)group) : (m_max <= 4 ? 0 : 1);
+    const int variant = group > 1 ? (tree ? 5 : 1) + __builtin_ctz((unsigned)group) : (m_max <= 4 ? 0 : 1);
     hipFunction_t spec_fn = nullptr;
     if (const int rc = pick_spec_kernel(ctx, P, n, n_iter > 0, !W.no_alloc, &spec_fn)) return rc;
     // wide specialised kernels keep counts in LDS like the generic ones
@@ -489,7 +537,9 @@ int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult 
     HIP_TRY(ctx, launch_init(s, W.d_jobs, n, static_first ? grid * wpb : 0, W.d_ctl, n_iter));
     ctx->last_kernel = spec_fn ? SMC_KERNEL_SPECIALIZED
                                : (variant == 0 ? SMC_KERNEL_GENERIC_SMALL
-                                               : (variant == 1 ? SMC_KERNEL_GENERIC : SMC_KERNEL_GENERIC_GROUPED));
+                                               : (variant == 1 ? SMC_KERNEL_GENERIC
+                                                                 : (tree ? SMC_KERNEL_GENERIC_TREE
+                                                                         : SMC_KERNEL_GENERIC_GROUPED)));
     for (int k = 0; k < n; ++k) res[k] = JobResult{};
     double total_ms = 0.0;
     const auto t_start = std::chrono::steady_clock::now();
@@ -758,6 +808,95 @@ int smc_autotune(smc_ctx *c, const smc_net *net, const smc_formula *f, const smc
     c->spec_waves_per_simd = save_occ;
     c->spec_mode = save_mode;
     c->tuned[key] = best;
+    *out = best;
+    return SMC_OK;
+}
+
+int smc_autotune_batch(smc_ctx *c, const smc_job *jobs, size_t n_jobs, double pilot_widen,
+                       smc_batch_tune_result *out)
+{
+    if (!c || !jobs || !out || n_jobs == 0) return fail(c, SMC_E_INVALID, "null argument or no jobs");
+    if (n_jobs > (1u << 20)) return fail(c, SMC_E_INVALID, "too many jobs");
+    if (!(pilot_widen >= 1.0 && pilot_widen <= 64.0)) return fail(c, SMC_E_INVALID, "pilot_widen must lie in [1, 64]");
+    HIP_TRY(c, hipSetDevice(c->device));
+    // the signature of the batch as it will be estimated
+    std::vector<Prepared> P(n_jobs);
+    for (size_t k = 0; k < n_jobs; ++k)
+        if (const int rc = prepare(c, jobs[k].net, jobs[k].formula, &jobs[k].params, 0, P[k])) return rc;
+    const uint64_t sig = batch_signature(P.data(), (int)n_jobs);
+    const auto hit = c->tuned_batch.find(sig);
+    if (hit != c->tuned_batch.end()) {
+        *out = hit->second;
+        return SMC_OK;
+    }
+    // The pilot: the same jobs with the interval half-width widened by
+    // pilot_widen (about pilot_widen^2 times fewer trajectories, eq. 4), or
+    // fixed sizes divided by pilot_widen^2 (at least 64), on seeds of their
+    // own, so that the estimate's own trajectories are not consumed.
+    std::vector<smc_job> pj(jobs, jobs + n_jobs);
+    bool wide = false;
+    for (size_t k = 0; k < n_jobs; ++k) {
+        smc_params &q = pj[k].params;
+        q.seed ^= 0xD1B54A32D192ED03ull;
+        if (q.fixed_n == 0) {
+            q.half_width = std::min(0.45, q.half_width * pilot_widen);
+        } else {
+            q.fixed_n = std::max<uint64_t>(64, (uint64_t)((double)q.fixed_n / (pilot_widen * pilot_widen)));
+        }
+        wide = wide || (P[k].auto_lanes && P[k].M > 4);
+    }
+    const int save_wpc = c->waves_per_cu, save_lanes = c->lanes;
+    struct Tuning {
+        smc_ctx *c;
+        int wpc, lanes;
+        ~Tuning()
+        {
+            c->tuning = false;
+            c->waves_per_cu = wpc;
+            c->lanes = lanes;
+        }
+    } tuning_scope{c, save_wpc, save_lanes};
+    c->tuning = true;
+    std::vector<smc_result> r(n_jobs);
+    auto pilot = [&](int lanes, int wpc, double *secs) {
+        c->lanes = lanes;
+        c->waves_per_cu = wpc;
+        const int rc = smc_estimate_batch(c, pj.data(), n_jobs, r.data());
+        *secs = r[0].device_seconds;
+        return rc;
+    };
+    double t = 0.0;
+    if (const int rc = pilot(1, 16, &t)) return rc;   // warm-up: specialised kernels compile here
+    smc_batch_tune_result best{};
+    best.lanes = 1;
+    best.waves_per_cu = 16;
+    best.seconds = 1e300;
+    int tried = 0;
+    // coordinate search: lanes per trajectory at 16 waves per CU (upwards
+    // until a pilot takes 15 % longer than the best so far), then the waves
+    // per CU at the best lanes
+    for (int L : {1, 2, 4, 8, 16}) {
+        if (L > 1 && !wide) break;
+        if (const int rc = pilot(L, 16, &t)) return rc;
+        ++tried;
+        if (L == 1) best.default_seconds = t;
+        if (t < best.seconds) {
+            best.seconds = t;
+            best.lanes = L;
+        } else if (t > 1.15 * best.seconds) {
+            break;
+        }
+    }
+    for (int w : {8, 32}) {
+        if (const int rc = pilot(best.lanes, w, &t)) return rc;
+        ++tried;
+        if (t < best.seconds) {
+            best.seconds = t;
+            best.waves_per_cu = w;
+        }
+    }
+    best.candidates = tried;
+    c->tuned_batch[sig] = best;
     *out = best;
     return SMC_OK;
 }

@@ -39,7 +39,7 @@ constexpr int kSpecWideMaxS = 128; // wide specialised kernels (counts in LDS): 
 constexpr int kSpecWideMaxM = 512; //   and channels
 
 enum CmpOp : int32_t { CMP_LT = 0, CMP_LE, CMP_GE, CMP_GT, CMP_EQ, CMP_NE };
-enum ValOp : int32_t { VO_VAR = 0, VO_CONST, VO_ADD, VO_SUB, VO_MUL, VO_DIV, VO_NEG, VO_SQRT };
+enum ValOp : int32_t { VO_VAR = 0, VO_CONST, VO_ADD, VO_SUB, VO_MUL, VO_DIV, VO_NEG, VO_SQRT, VO_POWI };
 enum PredKind : int32_t { PK_VAR = 0, PK_LINEAR = 1, PK_RPN = 2 };
 enum AtomKind : int32_t { AK_PROP = 0, AK_UNTIL, AK_NEXT, AK_NESTED, AK_RESP, AK_NEXTU, AK_UNTILG };
 enum Reason : int32_t { RS_STATE = 0, RS_TIME = 1, RS_ABSORB = 2, RS_CAP = 3, RS_TMAX = 4 };

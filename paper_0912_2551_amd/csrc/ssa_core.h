@@ -394,6 +394,21 @@ struct MonAccess<cptr<MonProg>> {
     static constexpr bool kMemory = true;
 };
 
+// pow(x, k) for an integral k in 0..64 (Sec. 3.1, func), by binary powering:
+// from r = 1, for the seven exponent bits from the most significant, square r
+// and multiply by x where the bit is set; each step is one rounded FP64
+// multiplication, so the value is fixed by k and x alone.
+__device__ __forceinline__ double powi(double x, int k)
+{
+    double r = 1.0;
+#pragma unroll
+    for (int b = 6; b >= 0; --b) {
+        r = r * r;
+        r = ((k >> b) & 1) ? r * x : r;
+    }
+    return r;
+}
+
 template <class C>
 __device__ __noinline__ double val_eval(cptr<MonProg> mp, int off, int len, const C &X)
 {
@@ -411,9 +426,9 @@ __device__ __noinline__ double val_eval(cptr<MonProg> mp, int off, int len, cons
             ++sp;
             continue;
         }
-        if (op == VO_NEG || op == VO_SQRT) {
+        if (op == VO_NEG || op == VO_SQRT || op == VO_POWI) {
             const double a = sp == 1 ? s0 : sp == 2 ? s1 : sp == 3 ? s2 : s3;
-            v = (op == VO_NEG) ? -a : sqrt(a);
+            v = (op == VO_NEG) ? -a : (op == VO_SQRT) ? sqrt(a) : powi(a, mp->vvar[o]);
             if (sp == 1) s0 = v;
             else if (sp == 2) s1 = v;
             else if (sp == 3) s2 = v;
@@ -1046,6 +1061,120 @@ __device__ __forceinline__ double ssa_draw_group(const JobView &V, const C &X, c
 }
 
 // ---------------------------------------------------------------------------
+// A direct-method variant for wide networks with tree-ordered sums (selected
+// per job with SMC_TREE_SUMS; the statistical contract).
+//
+// Lane r of a group of L owns one contiguous block of the channels, at most
+// kMaxGroupRounds steps of kSubBlock.  It adds its block's propensities in
+// channel order and keeps the running sum at the end of each step.  The group
+// forms the sums before and through each lane's block with a Hillis-Steele
+// scan (log2 L DPP steps inside the 16-lane row); a0 is the scan's last value.
+// The first lane whose scan value exceeds u2 a0 holds the channel: it looks up
+// the step, and then the channel, against the local target u2 a0 - (sum before
+// its block), and the re-run of that step reproduces its kept sums exactly.
+//
+// Channel j is still drawn with probability a_j / a0 and tau from Exp(a0), but
+// a0 and the boundaries are associated differently from the sequential prefix
+// of Sec. 2.1 and differ from it in the last bits.  The results therefore
+// agree with the sequential kernels in distribution, and trajectory by
+// trajectory except where a draw falls within a few ulps of a boundary; event
+// times differ in the last bits.  Where re-association leaves a target just
+// outside the selected block's own sums, the choice falls on the block's first
+// or last channel of positive propensity, so a channel that cannot fire is
+// never drawn.
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ __forceinline__ double dpp_f64_shr(double v)
+{
+    // lane i of a 16-lane row receives lane i - K (0 where that leaves the row)
+    constexpr int ctrl = 0x110 + K;
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xFFFFFFFFll), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), ctrl, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int L, class C>
+__device__ __forceinline__ double ssa_draw_tree(const JobView &V, const C &X, const Draw &d, double t,
+                                                Change *change)
+{
+    const int Mp = __builtin_amdgcn_readfirstlane(V.Mp);
+    const int lane = lane_id();
+    const int rank = lane & (L - 1);
+    const int gbase = lane - rank;
+    const int nsub = (Mp + kSubBlock * L - 1) / (kSubBlock * L);   // at most kMaxGroupRounds (host)
+    const int jb = rank * nsub * kSubBlock;
+    cptr<ChanDev> chan = V.chan;
+    cptr<double> rate = V.rate;
+    double sub[kMaxGroupRounds];   // this lane's running block sum at the end of each step
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < kMaxGroupRounds; ++q) {
+        if (q < nsub) {
+            double a[kSubBlock];
+            segment_propensities(chan, rate, X, jb + q * kSubBlock, Mp, a);
+#pragma unroll
+            for (int r = 0; r < kSubBlock; ++r) acc = acc + a[r];
+        }
+        sub[q] = acc;
+    }
+    // inclusive scan of the block sums over the group
+    double inc = acc;
+    if (L > 1) { const double v = dpp_f64_shr<1>(inc); inc = rank >= 1 ? inc + v : inc; }
+    if (L > 2) { const double v = dpp_f64_shr<2>(inc); inc = rank >= 2 ? inc + v : inc; }
+    if (L > 4) { const double v = dpp_f64_shr<4>(inc); inc = rank >= 4 ? inc + v : inc; }
+    if (L > 8) { const double v = dpp_f64_shr<8>(inc); inc = rank >= 8 ? inc + v : inc; }
+    double excl = dpp_f64_shr<1>(inc);
+    excl = rank >= 1 ? excl : 0.0;
+    const double a0 = shfl_f64(inc, gbase + L - 1);
+    const double target = d.u2 * a0;
+    // the block: the first lane of positive sum whose scan value exceeds the
+    // target, else the last lane of positive sum
+    const uint64_t gbits = (1ull << L) - 1ull;
+    const uint64_t pos = (__ballot(acc > 0.0) >> gbase) & gbits;
+    const uint64_t hit = (__ballot(acc > 0.0 && inc > target) >> gbase) & gbits;
+    const int rsel = hit ? ffs64(hit) : (pos ? 63 - __builtin_clzll(pos) : L - 1);
+    // every lane finds the step and channel in its own block; the group takes
+    // lane rsel's.  Step: the first whose kept sum exceeds the local target,
+    // else the last that adds a positive amount.
+    const double tl = target - excl;
+    int qs = 0;
+    bool found = false;
+    double prev = 0.0;
+#pragma unroll
+    for (int q = 0; q < kMaxGroupRounds; ++q) {
+        if (q < nsub && !found) {
+            const bool grows = sub[q] > prev;
+            qs = grows ? q : qs;
+            found = grows && sub[q] > tl;
+            prev = sub[q];
+        }
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kMaxGroupRounds; ++q) s = q + 1 == qs ? sub[q] : s;
+    const int j0 = jb + qs * kSubBlock;
+    double a[kSubBlock];
+    segment_propensities(chan, rate, X, j0, Mp, a);
+    int js = j0;
+    bool got = false;
+#pragma unroll
+    for (int r = 0; r < kSubBlock; ++r) {
+        s = s + a[r];
+        if (!got) {
+            js = a[r] > 0.0 ? j0 + r : js;
+            got = a[r] > 0.0 && s > tl;
+        }
+    }
+    int jsel = shfl_i32(js, gbase + rsel);
+    jsel = jsel < Mp ? jsel : Mp - 1;   // only where nothing fires (a0 = 0, the change is unused)
+    cptr<uint32_t> chg = V.chg;
+    *change = Change{chg[4 * jsel], chg[4 * jsel + 1], chg[4 * jsel + 2], chg[4 * jsel + 3]};
+    const double tau = d.nl / a0;
+    return a0 > 0.0 ? t + tau : __builtin_inf();
+}
+
+// ---------------------------------------------------------------------------
 // Access policies of the persistent loop.
 //
 // DynPolicy: the generic kernels.  Network and monitor tables are read from
@@ -1064,7 +1193,7 @@ __device__ __forceinline__ double ssa_draw_group(const JobView &V, const C &X, c
 // G > 1: the kernel also runs jobs with G lanes per trajectory (kernels of
 // their own, one per group size, so that each keeps its registers: the
 // one-lane kernels as before, and a grouped kernel without spills).
-template <int NB, int G = 1>
+template <int NB, int G = 1, bool kTree = false>
 struct DynPolicy {
     using Counts = LdsCounts;
     using Sel = Change;
@@ -1084,7 +1213,8 @@ struct DynPolicy {
                                                   double t, Sel *s, bool live)
     {
         if (kGroups && __builtin_amdgcn_readfirstlane(V.lanes) == G)
-            return ssa_draw_group<(G > 1 ? G : 2)>(V, X, d, t, s);
+            return kTree ? ssa_draw_tree<(G > 1 ? G : 2)>(V, X, d, t, s)
+                         : ssa_draw_group<(G > 1 ? G : 2)>(V, X, d, t, s);
         return ssa_draw<NB>(V, X, d, t, s, live);
     }
     __device__ static __forceinline__ void apply_if(Counts &X, const Sel &c, bool on)
@@ -1464,14 +1594,15 @@ __device__ int pick_job(const Job *jobs, int n_jobs, int start, int wph, int idl
 // Claim a chunk of consecutive relative indices below the job's issue limit;
 // returns the count, *base = first.  The chunk shrinks as the remaining work
 // shrinks (guided self-scheduling) so that the last trajectories spread over
-// the waves, but never below one index per lane of the wave (nor below
-// `need`) while that many remain: each claim is an atomic on one counter
-// shared by every wave of the job.
+// the waves, but never below what the wave runs at once (`slots`: one index
+// per lane, or per lane group; nor below `need`) while that many remain: each
+// claim is an atomic on one counter shared by every wave of the job.  Nor above
+// four times that: a wave would sit on indices that idle waves could run.
 //  - fixed-sample jobs: the limit never moves, so a fetch-add suffices (a
 //    claim past the end simply gets nothing);
 //  - iterative jobs: the limit rises while the job runs, so indices are
 //    claimed by compare-and-swap below the current limit, with back-off.
-__device__ int claim(JobState *st, bool iterative, int need, int n_waves, unsigned long long *base)
+__device__ int claim(JobState *st, bool iterative, int need, int slots, int n_waves, unsigned long long *base)
 {
     unsigned long long cur = ld_relaxed(&st->next);
     unsigned long long lim = ld_relaxed(&st->limit);
@@ -1480,8 +1611,8 @@ __device__ int claim(JobState *st, bool iterative, int need, int n_waves, unsign
     if (want < (unsigned long long)need) want = (unsigned long long)need;
     // At least a wave's worth: claims of a few indices at a time (when lanes
     // finish one by one) turn the issue counter into a contended hot spot.
-    if (want < (unsigned long long)kWave) want = kWave;
-    if (want > 256ull) want = 256ull;
+    if (want < (unsigned long long)slots) want = (unsigned long long)slots;
+    if (want > 4ull * (unsigned long long)slots) want = 4ull * (unsigned long long)slots;
     if (!iterative) {
         const unsigned long long b = atomicAdd(&st->next, want);
         if (b >= lim) return 0;
@@ -1563,18 +1694,20 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
     unsigned long long my_events = 0;
     if (A.static_first && start < A.n_jobs) {
         // First launch: start on the home job with this wave's own share of its
-        // first indices, [64 r, 64 r + 64) below static_end for the wave's rank
-        // r among the waves of that home (set up by init_jobs).  Thousands of
+        // first indices, [c r, c r + c) below static_end for the wave's rank r
+        // among the waves of that home, c = 64 / (lanes per trajectory) (set
+        // up by init_jobs).  Thousands of
         // first claims on one counter would otherwise queue for tens of
         // microseconds.
         cur = start;
         V.load(A.jobs, cur);
+        const unsigned long long per = (unsigned long long)(kWave / (Pol::kGroups ? __builtin_amdgcn_readfirstlane(V.lanes) : 1));
         const long long g0 = ((long long)start * n_waves + A.n_jobs - 1) / A.n_jobs;
-        const unsigned long long lo = (unsigned long long)(gwave - g0) * kWave;
+        const unsigned long long lo = (unsigned long long)(gwave - g0) * per;
         const unsigned long long se = uniform_u64(ld_relaxed(&V.st->static_end));
         if (lo < se) {
             pool_next = lo;
-            pool_end = lo + kWave < se ? lo + kWave : se;
+            pool_end = lo + per < se ? lo + per : se;
         }
     }
 
@@ -1636,7 +1769,7 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
             if (pool_next == pool_end) {
                 unsigned long long base = 0;
                 int got = 0;
-                if (lane == 0) got = claim(V.st, V.iterative != 0, n_need, n_waves, &base);
+                if (lane == 0) got = claim(V.st, V.iterative != 0, n_need, kWave / L, n_waves, &base);
                 got = __builtin_amdgcn_readfirstlane(got);
                 base = read_lane_u64(base, 0);
                 pool_next = base;

@@ -12,16 +12,16 @@ namespace smc {
 #endif
 
 // Persistent SSA + monitor kernel reading its tables from device memory.
-template <int NB, bool kIter, int G = 1>
+template <int NB, bool kIter, int G = 1, bool kTree = false>
 __global__ __launch_bounds__(256, SMC_MIN_WAVES_PER_EU) void ssa_persistent(KArgs A)
 {
     extern __shared__ int32_t lds[];
-    persistent_body<DynPolicy<NB, G>, kIter>(A, lds);
+    persistent_body<DynPolicy<NB, G, kTree>, kIter>(A, lds);
 }
 
 // The persistent kernel of a launch variant: 0 = at most 4 reaction channels,
 // 1 = any network, 2..5 = any network, with jobs of 2, 4, 8 or 16 lanes per
-// trajectory.
+// trajectory, 6..9 = the same with tree-ordered sums (SMC_TREE_SUMS).
 template <bool kIter>
 static const void *persistent_kernel(int variant)
 {
@@ -31,7 +31,11 @@ static const void *persistent_kernel(int variant)
     case 2: return reinterpret_cast<const void *>(&ssa_persistent<kBlocks, kIter, 2>);
     case 3: return reinterpret_cast<const void *>(&ssa_persistent<kBlocks, kIter, 4>);
     case 4: return reinterpret_cast<const void *>(&ssa_persistent<kBlocks, kIter, 8>);
-    default: return reinterpret_cast<const void *>(&ssa_persistent<kBlocks, kIter, 16>);
+    case 5: return reinterpret_cast<const void *>(&ssa_persistent<kBlocks, kIter, 16>);
+    case 6: return reinterpret_cast<const void *>(&ssa_persistent<kBlocks, kIter, 2, true>);
+    case 7: return reinterpret_cast<const void *>(&ssa_persistent<kBlocks, kIter, 4, true>);
+    case 8: return reinterpret_cast<const void *>(&ssa_persistent<kBlocks, kIter, 8, true>);
+    default: return reinterpret_cast<const void *>(&ssa_persistent<kBlocks, kIter, 16, true>);
     }
 }
 
@@ -119,7 +123,8 @@ __global__ void init_jobs(const Job *jobs, int n_jobs, int n_waves, Control *ctl
     if (n_waves > 0) {
         const long long g0 = ((long long)j * n_waves + n_jobs - 1) / n_jobs;
         const long long g1 = ((long long)(j + 1) * n_waves + n_jobs - 1) / n_jobs;
-        se = (unsigned long long)(g1 - g0) * kWave;
+        // a wave runs kWave / lanes trajectories at once
+        se = (unsigned long long)(g1 - g0) * (unsigned long long)(kWave / (J.lanes > 1 ? J.lanes : 1));
         if (se > lim) se = lim;
     }
     st->static_end = se;

@@ -681,6 +681,28 @@ hipError_t sg_expand_neighbours(hipStream_t s, const float *x, long n, float del
     return hipGetLastError();
 }
 
+// Confirmation of answered points by a few SMC trajectories each: an answer
+// on the FALSE side stands only if none of its trials satisfied the formula,
+// one on the TRUE side only if all of them did (an entry with more successes
+// than trials withdraws its answer).
+__global__ void confirm_answers(const float *p, const unsigned long long *succ, const unsigned long long *trials,
+                                long n, float threshold, uint8_t *use)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !use[i]) return;
+    const unsigned long long k = trials[i], y = succ[i];
+    const bool stands = k > 0 && y <= k && (p[i] >= threshold ? y == k : y == 0);
+    use[i] = stands ? 1 : 0;
+}
+
+hipError_t sg_confirm(hipStream_t s, const float *p, const unsigned long long *succ, const unsigned long long *trials,
+                      long n, float threshold, uint8_t *use)
+{
+    hipLaunchKernelGGL(confirm_answers, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, succ, trials, n, threshold,
+                       use);
+    return hipGetLastError();
+}
+
 hipError_t sg_neighbour_gate(hipStream_t s, const float *p, const float *p6, long n, float threshold, float margin,
                              uint8_t *use)
 {

@@ -35,6 +35,8 @@ hipError_t sg_adam(hipStream_t s, float *w, const float *g, float *m, float *v, 
                    float lr, float beta1, float beta2, float eps, float bc1, float bc2);
 hipError_t sg_round(hipStream_t s, const float *w, uint16_t *wb, long count);
 hipError_t sg_expand_neighbours(hipStream_t s, const float *x, long n, float delta, float *x6);
+hipError_t sg_confirm(hipStream_t s, const float *p, const unsigned long long *succ, const unsigned long long *trials,
+                      long n, float threshold, uint8_t *use);
 hipError_t sg_neighbour_gate(hipStream_t s, const float *p, const float *p6, long n, float threshold, float margin,
                              uint8_t *use);
 hipError_t sg_query(hipStream_t s, const float *x, long n, const float *mu, const float *sigma,
@@ -465,6 +467,33 @@ int smc_surrogate_calibrate(smc_surrogate *s, const float *x, const double *lo, 
     s->cal_threshold = threshold;
     if (margin_out) *margin_out = refuse ? -1.0f : (float)best_m;
     if (share_out) *share_out = refuse ? 0.0f : (float)best_share;
+    return SMC_OK;
+}
+
+int smc_surrogate_confirm(smc_surrogate *s, const float *p, const uint64_t *successes, const uint64_t *trials,
+                          size_t n, float threshold, uint32_t flags, uint8_t *use_surrogate)
+{
+    if (!s || (n && (!p || !successes || !trials || !use_surrogate))) return sfail(s, SMC_E_INVALID, "null argument");
+    if (flags & ~SMC_DEVICE_PTRS) return sfail(s, SMC_E_INVALID, "unknown flags");
+    if (!(threshold >= 0.0f && threshold <= 1.0f)) return sfail(s, SMC_E_INVALID, "threshold must lie in [0, 1]");
+    if (n == 0) return SMC_OK;
+    if (flags & SMC_DEVICE_PTRS) {
+        if ((uintptr_t)p % 4 || (uintptr_t)successes % 8 || (uintptr_t)trials % 8)
+            return sfail(s, SMC_E_INVALID, "p must be 4-byte and the counts 8-byte aligned");
+        SG_TRY(s, hipSetDevice(ctx_device(s->ctx)));
+        SG_TRY(s, sg_confirm(s->stream, p, reinterpret_cast<const unsigned long long *>(successes),
+                             reinterpret_cast<const unsigned long long *>(trials), (long)n, threshold,
+                             use_surrogate));
+        SG_TRY(s, hipStreamSynchronize(s->stream));
+        return SMC_OK;
+    }
+    for (size_t i = 0; i < n; ++i)
+        if (successes[i] > trials[i]) return sfail(s, SMC_E_INVALID, "more successes than trials");
+    for (size_t i = 0; i < n; ++i) {
+        if (!use_surrogate[i]) continue;
+        const bool stands = trials[i] > 0 && (p[i] >= threshold ? successes[i] == trials[i] : successes[i] == 0);
+        use_surrogate[i] = stands ? 1 : 0;
+    }
     return SMC_OK;
 }
 

@@ -31,6 +31,7 @@ ACCEPTED = [
     "(X<=9) U[0,5] G[0,2](Y>=1)",                       # until over G
     "(X<=9) U[0,5] ((Z>=1) & G[0,2](Y>=1))",            # until over a conjunction with G
     "(X<=9) U[0,5] (G[0,2](Y>=1) & Z>=1)",
+    "F[0,1](pow(X,2) + pow(Y/3,13) >= pow(Z,0) + pow(X,64))",   # pow with constant integral exponents
 ]
 
 UNSUPPORTED = [
@@ -40,7 +41,10 @@ UNSUPPORTED = [
     "(F[0,1](X>1)) U[0,5] (Y>1)",            # temporal left operand of U
     "F[0,1](F[0,1](F[0,1](X>1)))",           # nesting three levels deep
     "G[0,1](F[0,1](X>1)) & G[0,1](F[0,1](Y>1)) & G[0,1](F[0,1](Z>1))",   # three time registers
-    "F[0,1](pow(X,2)>1)",                    # no bit-reproducible pow on the device
+    "F[0,1](pow(X,0.5)>1)",                  # pow: only constant integral exponents 0..64
+    "F[0,1](pow(X,Y)>1)",
+    "F[0,1](pow(X,-2)>1)",
+    "F[0,1](pow(X,65)>1)",
 ]
 
 PARSE_ERRORS = [

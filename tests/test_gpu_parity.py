@@ -57,6 +57,7 @@ TRAJ_CASES = [
     ("lower-bounds", W.immigration_death, "F[5,10](X>=60) & G[2,8](X<=90)", {}, 3000),
     ("not-or", W.immigration_death, "!(F[0,3](X>=25) | G[0,2](X<=18))", {}, 3000),
     ("arith", W.isomerization, "F[0,2](A*A <= sqrt(B*400) + 3)", {}, 3000),
+    ("pow", W.isomerization, "F[0,2](pow(A,3) <= pow(B/7,2) * 200 + pow(A,1) + pow(B/50,11))", {}, 3000),
     ("linear", W.michaelis_menten, "F[0,1](2*ES + E >= 3*P - S + 1100)", {}, 2000),
     ("prop-only", W.michaelis_menten, "S >= 1000 & E = 100", {}, 129),
     ("dimer", W.dimerization, "F[0,5](A<=10)", {}, 3000),
@@ -77,7 +78,7 @@ TRAJ_CASES = [
 
 
 # formulas with arithmetic (RPN) predicates always run on the generic kernel
-GENERIC_ONLY = {"arith"}
+GENERIC_ONLY = {"arith", "pow"}
 
 
 @pytest.mark.parametrize("mode", ["generic", "specialized"])
@@ -370,7 +371,7 @@ def test_errors_and_edges(ctx):
         ctx.estimate(nb, fb, B.params(fixed_n=64))
     assert e.value.code == B.SMC_E_INVALID
     with pytest.raises(B.SmcError) as e:
-        ctx.formula(n, "F[0,1](pow(X,2)>1)")
+        ctx.formula(n, "F[0,1](pow(X,0.5)>1)")
     assert e.value.code == B.SMC_E_UNSUPPORTED
     f = ctx.formula(n, "F(X>=5)")
     assert math.isinf(f.horizon)
@@ -670,3 +671,142 @@ def test_lane_group_settings(ctx):
         ctx.set_lanes_per_trajectory(0)
     o = oracle.estimate(net, W.C1_FORMULA, fixed_n=4096, seed=1)
     assert (r["n"], r["successes"], r["events"]) == (o["n"], o["successes"], o["events"])
+
+
+# ---------------------------------------------------------------------------
+# Tree-ordered sums over a lane group (SMC_TREE_SUMS): the statistical contract
+# ---------------------------------------------------------------------------
+def _mismatch_bound(count):
+    # a draw lands within a few ulps of a re-associated boundary with
+    # probability of order M 2^-50 per event: in these runs, practically never
+    return max(1, count // 1000)
+
+
+@pytest.mark.parametrize("lanes", [2, 4, 8, 16])
+@pytest.mark.parametrize("name", ["s8", "s20", "c3", "s128"])
+def test_tree_sums_trajectory_agreement(ctx, name, lanes):
+    """With tree-ordered sums, per-trajectory (events, verdict, reason) equal
+    the oracle's on the same random numbers, apart from at most one trajectory
+    in a thousand (a draw within ulps of a boundary)."""
+    B = _B()
+    net, text, seed, cap, count = _group_case(name)
+    n = ctx.network(net)
+    f = ctx.formula(n, text)
+    model = 0 if name == "c3" else 2
+    p = B.params(seed=seed, model_id=model, max_events=cap, lanes=lanes, tree_sums=True)
+    print(f"case tree lanes {lanes} network {name} trajectories {count}", flush=True)
+    ev, vd, rs = ctx.trajectories(n, f, p, 0, count)
+    assert ctx.last_kernel() == B.KERNEL_GENERIC_TREE
+    if name == "c3":
+        oev, ovd, ors = (a[:count] for a in _c3_expected(net, text))
+    else:
+        if name not in _group_oracle:
+            _group_oracle[name] = oracle.trajectories(net, oracle.parse(text, net), 0, count, seed=seed, model_id=2,
+                                                      max_events=cap)
+        oev, ovd, ors = _group_oracle[name]
+    differ = (ev != oev) | (vd != ovd) | (rs != ors)
+    print(f"  trajectories that differ from the oracle: {int(differ.sum())} of {count}", flush=True)
+    assert int(differ.sum()) <= _mismatch_bound(count), np.nonzero(differ)[0][:5]
+
+
+_TREE_STAT_JOBS = (537, 553, 575)   # batched-sweep networks of 356, 292 and 188 channels
+
+
+@pytest.mark.parametrize("job", _TREE_STAT_JOBS)
+def test_tree_sums_distribution(ctx, job):
+    """Independent random numbers: the satisfaction probability and the mean
+    event count of 400000 tree-summed trajectories agree with 20000 oracle
+    trajectories of another seed (two-sample tests at the 99.9% level)."""
+    B = _B()
+    net, text, kw = W.c4_jobs()[job]
+    nh = ctx.network(net)
+    fh = ctx.formula(nh, text)
+    n_gpu, n_or = 400000, 20000
+    p = B.params(seed=9001, model_id=kw["model_id"], max_events=kw["max_events"], lanes=8, tree_sums=True)
+    print(f"case tree distribution job {job} ({net.label})", flush=True)
+    ev, vd, _ = ctx.trajectories(nh, fh, p, 0, n_gpu)
+    assert ctx.last_kernel() == B.KERNEL_GENERIC_TREE
+    oev, ovd, _ = oracle.trajectories(net, oracle.parse(text, net), 0, n_or, seed=77, model_id=kw["model_id"],
+                                      max_events=kw["max_events"])
+    z = 3.2905   # two-sided 99.9%
+    p1, p2 = vd.mean(), ovd.mean()
+    pool = (vd.sum() + ovd.sum()) / (n_gpu + n_or)
+    se = math.sqrt(pool * (1 - pool) * (1 / n_gpu + 1 / n_or))
+    assert abs(p1 - p2) <= z * se, (p1, p2, se)
+    e1, e2 = ev.astype(np.float64), oev.astype(np.float64)
+    se_e = math.sqrt(e1.var(ddof=1) / n_gpu + e2.var(ddof=1) / n_or)
+    assert abs(e1.mean() - e2.mean()) <= z * se_e, (e1.mean(), e2.mean(), se_e)
+
+
+def test_tree_sums_in_the_batched_sweep(ctx):
+    """The batched sweep with its random networks on 16-lane groups with tree
+    sums: every job's estimate equals the oracle's, apart from at most two jobs,
+    whose estimates then lie within the oracle's interval."""
+    B = _B()
+    doc, _ = _c4_expected()
+    keep, jobs = [], []
+    for net, text, kw in W.c4_jobs():
+        nh = ctx.network(net)
+        fh = ctx.formula(nh, text)
+        keep.append((nh, fh))
+        jobs.append((nh, fh, B.params(lanes=16, tree_sums=True, **kw)))
+    print("c4 with 16 lanes per network trajectory, tree sums", flush=True)
+    res = ctx.estimate_batch(jobs)
+    assert ctx.last_kernel() == B.KERNEL_GENERIC_TREE
+    keys = ("n", "successes", "events", "truncated", "batches", "p_hat", "lo", "hi")
+    bad = [(e["job"], r, e) for r, e in zip(res, doc["jobs"]) if any(r[k] != e[k] for k in keys)]
+    print(f"  jobs that differ from the oracle: {len(bad)}", flush=True)
+    assert len(bad) <= 2, [b[0] for b in bad]
+    for _, r, e in bad:
+        assert e["lo"] <= r["p_hat"] <= e["hi"], (r, e)
+
+
+def test_tree_sums_must_agree_within_a_call(ctx):
+    B = _B()
+    net = W.random_network(20, 80, seed=42)
+    text = W.nested_until_formula(net, 10)
+    n = ctx.network(net)
+    f = ctx.formula(n, text)
+    a = B.params(fixed_n=256, lanes=4, tree_sums=True, max_events=20000)
+    b = B.params(fixed_n=256, lanes=4, max_events=20000)
+    with pytest.raises(B.SmcError):
+        ctx.estimate_batch([(n, f, a), (n, f, b)])
+    # one lane per trajectory: the flag has no effect, results are the exact ones
+    r1 = ctx.estimate(n, f, B.params(fixed_n=512, lanes=1, tree_sums=True, max_events=20000))
+    r0 = ctx.estimate(n, f, B.params(fixed_n=512, lanes=1, max_events=20000))
+    assert (r1["n"], r1["successes"], r1["events"]) == (r0["n"], r0["successes"], r0["events"])
+
+
+def test_autotune_batch_keeps_the_estimates(ctx):
+    """smc_autotune_batch on the batched sweep picks lanes per trajectory and
+    waves per CU from pilots; the sweep then runs under that choice and gives
+    the oracle's estimates for all 576 jobs; a second call returns the
+    recorded choice without pilots."""
+    B = _B()
+    doc, _ = _c4_expected()
+    keep, jobs = [], []
+    for net, text, kw in W.c4_jobs():
+        nh = ctx.network(net)
+        fh = ctx.formula(nh, text)
+        keep.append((nh, fh))
+        jobs.append((nh, fh, B.params(**kw)))
+    print("autotune the batched sweep", flush=True)
+    tune = ctx.autotune_batch(jobs, pilot_widen=2.0)
+    print(f"  {tune}", flush=True)
+    assert tune["lanes"] in (1, 2, 4, 8, 16) and tune["waves_per_cu"] in (8, 16, 32)
+    assert 3 <= tune["candidates"] <= 7 and 0.0 < tune["seconds"] <= tune["default_seconds"]
+    assert ctx.autotune_batch(jobs, pilot_widen=2.0) == tune
+    res = ctx.estimate_batch(jobs)
+    expect = B.KERNEL_GENERIC if tune["lanes"] == 1 else B.KERNEL_GENERIC_GROUPED
+    assert ctx.last_kernel() == expect
+    keys = ("n", "successes", "events", "truncated", "batches", "p_hat", "lo", "hi")
+    bad = [(e["job"], {k: (r[k], e[k]) for k in keys if r[k] != e[k]}) for r, e in zip(res, doc["jobs"])
+           if any(r[k] != e[k] for k in keys)]
+    assert not bad, bad[:5]
+    # jobs that fix their own lanes keep them (the same signature: the tuned
+    # launch shape applies, the lanes do not)
+    if tune["lanes"] > 1:
+        jobs1 = [(nh, fh, B.params(**dict(kw, lanes=1))) for (nh, fh), (_, _, kw) in zip(keep, W.c4_jobs())]
+        res1 = ctx.estimate_batch(jobs1)
+        assert ctx.last_kernel() == B.KERNEL_GENERIC
+        assert [(r["n"], r["successes"]) for r in res1] == [(e["n"], e["successes"]) for e in doc["jobs"]]

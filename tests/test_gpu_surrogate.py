@@ -242,12 +242,36 @@ def test_training_fits_and_gate(ctx):
     assert 0.2 < use.mean() < 0.95
 
 
+def test_confirm_rule(ctx):
+    """smc_surrogate_confirm: an answer stands only if every trial fell on its
+    side; refused points stay refused; host and device arrays agree."""
+    import torch
+    from paper_0912_2551_amd import binding as B
+    s = B.Surrogate(ctx, seed=1)
+    p = np.array([0.01, 0.01, 0.99, 0.99, 0.3, 0.7, 0.01, 0.99, 0.5], dtype=np.float32)
+    gate = np.array([1, 1, 1, 1, 1, 1, 0, 0, 1], dtype=bool)
+    succ = np.array([0, 1, 64, 63, 0, 64, 5, 0, 64], dtype=np.uint64)
+    trials = np.array([64, 64, 64, 64, 64, 64, 64, 64, 64], dtype=np.uint64)
+    want = np.array([1, 0, 1, 0, 1, 1, 0, 0, 1], dtype=bool)
+    assert np.array_equal(s.confirm(p, gate, succ, trials), want)
+    # no trials: nothing stands
+    assert not s.confirm(p, gate, succ * 0, trials * 0).any()
+    with pytest.raises(B.SmcError):
+        s.confirm(p, gate, trials + 1, trials)
+    dp = torch.tensor(p, device="cuda")
+    du = torch.tensor(gate.astype(np.uint8), device="cuda")
+    ds = torch.tensor(succ.astype(np.int64), device="cuda")
+    dt = torch.tensor(trials.astype(np.int64), device="cuda")
+    s.confirm_device(dp, ds, dt, len(p), du)
+    assert np.array_equal(du.cpu().numpy().astype(bool), want)
+
+
 def test_surrogate_gain_over_plain_smc(ctx):
     """Rate sweep of the Michaelis-Menten model under the companion formula
     (p runs from ~0 to ~1 across the box): after training, the gate is
     calibrated on held-out plain-SMC estimates (no held-out answer more than
-    eps outside its interval).  On fresh query points the surrogate answers a
-    large share, the largest distance of an answer outside the point's own
+    eps outside its interval), and each answer is confirmed by 64 plain-SMC
+    trajectories.  On fresh query points the surrogate answers a large share, the largest distance of an answer outside the point's own
     plain-SMC Wilson interval stays within 2 eps, and the SMC work left over
     is a fraction of what plain SMC spends on the same queries."""
     from paper_0912_2551_amd import binding as B
@@ -278,14 +302,29 @@ def test_surrogate_gain_over_plain_smc(ctx):
                            min_margin=margin)
     assert margin <= m <= 0.5 and share > 0.3
     q = W.surrogate_queries(n_query, seed=22)
-    p, use = s.query(q, threshold=0.5, margin=margin)
-    assert np.all(np.abs(p[use] - 0.5) >= m)
+    p, gate = s.query(q, threshold=0.5, margin=margin)
+    assert np.all(np.abs(p[gate] - 0.5) >= m)
+    # 64 confirming trajectories per answered point, on a seed of their own
+    ans = np.nonzero(gate)[0]
+    probes = []
+    for i in ans:
+        nh = ctx.network(W.michaelis_menten(*(10.0 ** q[i].astype(np.float64))))
+        fh = ctx.formula(nh, text)
+        keep.append((nh, fh))
+        probes.append((nh, fh, B.params(fixed_n=64, seed=5, model_id=int(i))))
+    pr = ctx.estimate_batch(probes)
+    succ = np.zeros(n_query, dtype=np.uint64)
+    trials = np.zeros(n_query, dtype=np.uint64)
+    succ[ans] = [r["successes"] for r in pr]
+    trials[ans] = [r["n"] for r in pr]
+    use = s.confirm(p, gate, succ, trials, threshold=0.5)
+    assert not np.any(use & ~gate)
     plain = run(10.0 ** q.astype(np.float64), 2)
     plain_events = sum(r["events"] for r in plain)
-    fallback_events = sum(r["events"] for r, u in zip(plain, use) if not u)
+    fallback_events = sum(r["events"] for r, u in zip(plain, use) if not u) + sum(r["events"] for r in pr)
     err = np.array([max(r["lo"] - pi, pi - r["hi"], 0.0) for r, pi, u in zip(plain, p, use) if u])
-    print(f"margin={m:.3f} use={use.mean():.3f} within={np.mean(err == 0):.3f} max_err={err.max():.4f} "
-          f"work={fallback_events / plain_events:.3f}")
+    print(f"margin={m:.3f} gate={gate.mean():.3f} use={use.mean():.3f} within={np.mean(err == 0):.3f} "
+          f"max_err={err.max():.4f} work={fallback_events / plain_events:.3f}")
     assert use.mean() > 0.3
     assert err.max() <= 2 * eps
     assert fallback_events < 0.8 * plain_events

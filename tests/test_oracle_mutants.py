@@ -89,6 +89,14 @@ MUTANTS = [
      "if (d >= lo) res = or3(res, and3(all1, eval3(f, f->b[node], j, P)));",
      "if (d >= lo) res = or3(res, eval3(f, f->b[node], j, P));",
      "tests/test_oracle_semantics.py::test_golden_trace[A:(F[0,10](X>=3)) U[0,10] (X>=1)]"),
+    ("pow: exponent bits taken least significant first",
+     "if ((k >> b) & 1) r = r * x;",
+     "if ((k >> (6 - b)) & 1) r = r * x;",
+     "tests/test_oracle_pow.py::test_integer_powers_are_exact[2]"),
+    ("pow: a plain left-to-right product instead of binary powering",
+     "        double r = 1.0;\n        for (int b = 6; b >= 0; --b) {",
+     "        double r = 1.0;\n        for (int i = 0; i < k; ++i) r = r * x;\n        return r;\n        for (int b = 6; b >= 0; --b) {",
+     "tests/test_oracle_pow.py::test_multiplication_order_is_binary_powering[4]"),
 ]
 
 
