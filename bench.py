@@ -392,7 +392,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the random-network and batched-sweep runs")
     ap.add_argument("--no-c3", action="store_true", help="skip the random-network run")
     ap.add_argument("--no-c4", action="store_true", help="skip the batched-sweep run")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="skip smc_autotune of the C2 launch")
     ap.add_argument("--cpu-sample", type=int, default=N_TRAJ)
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--occupancy", type=int, default=0, help="waves per SIMD budget of specialised kernels")

@@ -132,12 +132,14 @@ int smc_set_specialization(smc_ctx *ctx, int mode);
  * SMC_KERNEL_GENERIC_SMALL (table-driven, <= 4 channels), SMC_KERNEL_GENERIC
  * (table-driven, blocked prefix), SMC_KERNEL_SPECIALIZED,
  * SMC_KERNEL_GENERIC_GROUPED (table-driven, several lanes per trajectory),
- * SMC_KERNEL_GENERIC_TREE (the same with SMC_TREE_SUMS). */
+ * SMC_KERNEL_GENERIC_TREE (the same with SMC_TREE_SUMS),
+ * SMC_KERNEL_GENERIC_TRACE (table-driven, the launch holds trace programs). */
 #define SMC_KERNEL_GENERIC_SMALL 0
 #define SMC_KERNEL_GENERIC 1
 #define SMC_KERNEL_SPECIALIZED 2
 #define SMC_KERNEL_GENERIC_GROUPED 3
 #define SMC_KERNEL_GENERIC_TREE 4
+#define SMC_KERNEL_GENERIC_TRACE 5
 int smc_last_kernel(const smc_ctx *ctx);
 /* Register budget of specialised kernels: compile them so that
  * `waves_per_simd` waves fit on one SIMD (1..8; registers beyond the budget
@@ -200,10 +202,14 @@ void smc_net_destroy(smc_net *net);
 /* Compile BLTLc text over the network's species names:
  *   phi ::= val op val | !phi | phi & phi | phi '|' phi | X I phi | phi U I phi
  *           | F I phi | G I phi | (phi) | true | false
- *   val ::= name | number | val (+ - * /) val | -val | sqrt(val) | (val)
+ *   val ::= name | number | val (+ - * /) val | -val | sqrt(val) | pow(val, k) | (val)
  *   I   ::= [a,b] | <= b | (omitted: [0, inf))      op: < <= >= > = !=
  * Precedence: unary (!, X, F, G) > U (right associative) > & > |.
- * GPU monitor classes: top-level boolean combinations of
+ * pow takes a constant integral exponent k in 0..64 and is evaluated by
+ * binary powering (from 1, for the seven exponent bits from the most
+ * significant: square, then multiply where the bit is set; one FP64 rounding
+ * per multiplication); other exponents give SMC_E_UNSUPPORTED.
+ * Compact GPU monitor classes (a few registers per trajectory): top-level boolean combinations of
  *   state predicates; F I p; G I p; p U I q; X I p; the nested until
  *   p U I (q U[0,c] r), also with F[0,c] r inside and as F I (q U[0,c] r);
  *   p U I (r & G[0,c] q), r optional;
@@ -211,8 +217,21 @@ void smc_net_destroy(smc_net *net);
  *   the response G I (p | F[0,d] q) and its dual
  *   F I (p & G[0,d] q) (either operand order, p optional), where p, q, r
  *   are boolean combinations of predicates.  At most two of the nested,
- *   next-until, until-G and response monitors per formula.  Other nestings give SMC_E_UNSUPPORTED;
- *   text that does not parse gives SMC_E_PARSE. */
+ *   next-until, until-G and response monitors per formula.
+ * Any other formula (deeper nesting, temporal left operands of U, inner
+ * windows that do not start at 0, ...) compiles to a trace program of at
+ * most 32 nodes (F and G count as 2 and 4): each lane records the states of
+ * its trajectory (entry time and predicate bits), the buffer of Sec. 3.2, and
+ * decides the formula on that prefix, at checkpoints, finding the first
+ * deciding state by bisection; the results are those of the compact monitors'
+ * semantics (stop at the earliest decision).  Runs with a trace program need
+ * max_events in 1..2^20 (states are recorded up to the cap), use one lane per
+ * trajectory, record areas of about (13 + nodes) bytes per state and lane
+ * within an 8 GiB budget (which bounds the lanes of the launch), and no
+ * specialised kernel or allocation-free call.  More than 16 predicates, an
+ * arithmetic predicate deeper than the GPU's stack, or a trace program of more
+ * than 32 nodes give SMC_E_UNSUPPORTED; text that does not parse gives
+ * SMC_E_PARSE. */
 int smc_formula_compile(smc_ctx *ctx, const smc_net *net, const char *text, smc_formula **out);
 /* Time span of the path the formula can depend on (+inf if unbounded). */
 double smc_formula_horizon(const smc_formula *f);

@@ -37,6 +37,7 @@ REASON_STATE, REASON_TIME, REASON_ABSORB, REASON_CAP, REASON_TMAX = range(5)
 SPECIALIZE_AUTO, SPECIALIZE_OFF, SPECIALIZE_REQUIRED = 0, 1, 2
 KERNEL_GENERIC_SMALL, KERNEL_GENERIC, KERNEL_SPECIALIZED, KERNEL_GENERIC_GROUPED = 0, 1, 2, 3
 KERNEL_GENERIC_TREE = 4
+KERNEL_GENERIC_TRACE = 5
 
 EXPORTS = [
     "smc_ctx_create", "smc_ctx_destroy", "smc_last_error", "smc_set_watchdog",

@@ -14,6 +14,10 @@
 // Decided atoms freeze; the combination is evaluated in three-valued logic
 // after every state and every time step, so a trajectory stops at the first
 // prefix that decides the formula (Sec. 3.2).
+//
+// Any other formula becomes a trace program: the formula tree itself, which
+// the kernel evaluates on the states it records (see trace_value).
+
 #include <hip/hip_runtime.h>
 
 #include <cctype>
@@ -413,6 +417,17 @@ class Compiler {
   public:
     explicit Compiler(MonProg &p) : p_(p) { std::memset(&p_, 0, sizeof(MonProg)); }
 
+    // A formula outside the compact monitor classes: the formula tree itself
+    // (a trace program), evaluated by the kernel on the states it records.
+    void compile_trace(const Node *root)
+    {
+        trace_node(root);
+        p_.trace = 1;
+        p_.horizon = horizon_of(root);
+        p_.all_var = 1;
+        for (int q = 0; q < p_.n_preds; ++q) p_.all_var &= p_.preds[q].kind == PK_VAR;
+    }
+
     void compile(const Node *root)
     {
         const int top = top_expr(root);
@@ -431,6 +446,61 @@ class Compiler {
     }
 
   private:
+    // ---- trace programs ---------------------------------------------------
+    int trace_push(int kind, int pred, int a, int b, double lo, double hi)
+    {
+        if (p_.tr_n >= kMaxTrace) throw Unsupported("formula too large for the GPU trace monitor (32 nodes)");
+        TraceNode &N = p_.tnodes[p_.tr_n];
+        N.kind = kind;
+        N.pred = pred;
+        N.a = a;
+        N.b = b;
+        N.lo = lo;
+        N.hi = hi;
+        return p_.tr_n++;
+    }
+
+    // children first; F I p = tt U I p, G I p = not(tt U I not p) (Sec. 3.1)
+    int trace_node(const Node *n)
+    {
+        switch (n->kind) {
+        case Node::TT: return trace_push(TN_TT, -1, -1, -1, 0.0, 0.0);
+        case Node::FF: return trace_push(TN_FF, -1, -1, -1, 0.0, 0.0);
+        case Node::PRED: return trace_push(TN_PRED, predicate(n), -1, -1, 0.0, 0.0);
+        case Node::NOT: {
+            const int a = trace_node(n->a.get());
+            return trace_push(TN_NOT, -1, a, -1, 0.0, 0.0);
+        }
+        case Node::AND:
+        case Node::OR: {
+            const int a = trace_node(n->a.get());
+            const int b = trace_node(n->b.get());
+            return trace_push(n->kind == Node::AND ? TN_AND : TN_OR, -1, a, b, 0.0, 0.0);
+        }
+        case Node::NEXT: {
+            const int a = trace_node(n->a.get());
+            return trace_push(TN_NEXT, -1, a, -1, n->lo, n->hi);
+        }
+        case Node::FIN: {
+            const int tt = trace_push(TN_TT, -1, -1, -1, 0.0, 0.0);
+            const int b = trace_node(n->a.get());
+            return trace_push(TN_UNTIL, -1, tt, b, n->lo, n->hi);
+        }
+        case Node::GLOB: {
+            const int tt = trace_push(TN_TT, -1, -1, -1, 0.0, 0.0);
+            const int c = trace_node(n->a.get());
+            const int nc = trace_push(TN_NOT, -1, c, -1, 0.0, 0.0);
+            const int u = trace_push(TN_UNTIL, -1, tt, nc, n->lo, n->hi);
+            return trace_push(TN_NOT, -1, u, -1, 0.0, 0.0);
+        }
+        default: {
+            const int a = trace_node(n->a.get());
+            const int b = trace_node(n->b.get());
+            return trace_push(TN_UNTIL, -1, a, b, n->lo, n->hi);
+        }
+        }
+    }
+
     // ---- top level: boolean combination of monitors ---------------------
     struct TNode {
         int kind;   // 0 atom, 1 not, 2 and, 3 or
@@ -880,8 +950,15 @@ void compile_formula(const std::string &text, const std::vector<std::string> &na
 {
     Parser ps(text, names);
     auto root = ps.parse();
-    Compiler cc(out);
-    cc.compile(root.get());
+    try {
+        Compiler cc(out);
+        cc.compile(root.get());
+    } catch (const Unsupported &) {
+        // outside the compact monitor classes: a trace program (its own
+        // limits, e.g. on predicates, still apply)
+        Compiler tc(out);
+        tc.compile_trace(root.get());
+    }
 }
 
 }  // namespace smc

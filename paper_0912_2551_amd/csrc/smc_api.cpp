@@ -61,6 +61,9 @@ struct smc_ctx {
     Control *d_ctl = nullptr;
     char *d_rec = nullptr;
     size_t cap_rec = 0;
+    // record areas of trace programs, one per lane of a launch (grow-only)
+    unsigned char *d_trace = nullptr;
+    size_t cap_trace = 0;
     // pinned staging for the per-launch copies (asynchronous DMA instead of
     // the staged copies of pageable memory)
     Job *h_jobs = nullptr;
@@ -226,6 +229,9 @@ int prepare(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_pa
         return fail(ctx, SMC_E_INVALID, "lanes per trajectory must be 0, 1, 2, 4, 8 or 16");
     if (std::isinf(f->horizon) && std::isinf(p->t_max) && p->max_events == 0)
         return fail(ctx, SMC_E_INVALID, "an unbounded formula needs t_max or max_events");
+    if (f->prog.trace && (p->max_events == 0 || p->max_events > kTraceMaxEvents))
+        return fail(ctx, SMC_E_INVALID, "a formula outside the compact monitor classes (a trace program) needs "
+                                        "max_events in 1..2^20: its states are recorded up to the cap");
     const bool iterative = p->fixed_n == 0;
     double z = 0.0;
     if (iterative || p->z > 0.0 || (p->confidence > 0.0 && p->confidence < 1.0)) {
@@ -270,7 +276,8 @@ int prepare(smc_ctx *ctx, const smc_net *net, const smc_formula *f, const smc_pa
     J.t_max = p->t_max;
     J.iterative = iterative ? 1 : 0;
     J.literal = (p->flags & SMC_PAPER_ROUNDING) ? 1 : 0;
-    J.lanes = job_lanes(ctx, p, net->M);
+    J.lanes = f->prog.trace ? 1 : job_lanes(ctx, p, net->M);
+    J.trace = f->prog.trace ? 1 : 0;
     J.eps = p->half_width;
     J.z = z;
     out.net = net;
@@ -431,7 +438,8 @@ int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult 
                 if (P[k].auto_lanes) P[k].job.lanes = lanes_for(it->second.lanes, P[k].M);
         }
     }
-    int s_max = 1, m_max = 1, n_iter = 0, group = 1;
+    int s_max = 1, m_max = 1, n_iter = 0, group = 1, n_trace = 0, tr_nodes = 0;
+    uint32_t tr_cap = 0;
     Job *jobs = W.h_jobs;   // the previous call's copies have completed
     for (int k = 0; k < n; ++k) {
         jobs[k] = P[k].job;
@@ -440,6 +448,45 @@ int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult 
         m_max = std::max(m_max, P[k].M);
         n_iter += jobs[k].iterative;
         group = std::max(group, (int)jobs[k].lanes);
+        if (jobs[k].trace) {
+            ++n_trace;
+            tr_cap = std::max(tr_cap, jobs[k].max_events + 1u);
+            tr_nodes = std::max(tr_nodes, (int)P[k].f->prog.tr_n);
+        }
+    }
+    const size_t lds_wave = (size_t)(s_max + 1) * kWave * sizeof(int32_t);   // + the constant-1 row
+    int wpb = (int)std::min<size_t>(4, std::max<size_t>(1, 65536 / lds_wave));
+    if (lds_wave > 65536) return fail(ctx, SMC_E_INVALID, "network too large for one wave's LDS");
+    // Trace programs: one record area per lane of the launch, within a budget
+    // of device memory, which bounds the launch's waves; every job of such a
+    // launch runs one lane per trajectory (on the trace-capable kernel).
+    unsigned long long tr_slots = 0;
+    if (n_trace > 0) {
+        if (W.no_alloc)
+            return fail(ctx, SMC_E_UNSUPPORTED, "trace programs need record areas, which an allocation-free call "
+                                                "does not allocate");
+        const unsigned long long stride = TraceArea::bytes(tr_cap, tr_nodes);
+        const unsigned long long per_block = (unsigned long long)kWave * wpb;
+        // no more lanes than the device holds, than the trajectories need, or
+        // than the budget allows
+        unsigned long long want = 0;
+        for (int k = 0; k < n; ++k) want += P[k].capacity;
+        want = (want + per_block - 1) / per_block * per_block;
+        tr_slots = std::min<unsigned long long>((unsigned long long)ctx->n_cu * 32ull * kWave, kTraceBudget / stride);
+        tr_slots -= tr_slots % per_block;
+        tr_slots = std::min(tr_slots, want);
+        if (tr_slots == 0)
+            return fail(ctx, SMC_E_NOMEM, "the record areas of one block of trace lanes exceed the 8 GiB budget "
+                                          "(lower max_events)");
+        if (ensure(ctx, ctx->d_trace, ctx->cap_trace, (size_t)(tr_slots * stride))) return SMC_E_NOMEM;
+        for (int k = 0; k < n; ++k) {
+            jobs[k].tr_base = ctx->d_trace;
+            jobs[k].tr_stride = stride;
+            jobs[k].tr_cap = tr_cap;
+            jobs[k].lanes = 1;
+            P[k].job.lanes = 1;
+        }
+        group = 1;
     }
     // One group size per launch (one grouped kernel per size): jobs that run
     // several lanes per trajectory take the largest requested, which is at
@@ -464,7 +511,7 @@ int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult 
     // each as long as its longest trajectory, on a device that is mostly idle.
     // jobs[n .. 2n) keep the iterative descriptions for the replay.
     bool speculative = false;
-    if (n_iter == n && !ctx->tuning && !W.no_alloc) {
+    if (n_iter == n && !ctx->tuning && !W.no_alloc && n_trace == 0) {
         unsigned long long cap_total = 0;
         bool allow = true;
         for (int k = 0; k < n; ++k) {
@@ -507,9 +554,6 @@ int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult 
             ctx->spec_mode = it->second.specialization;
         }
     }
-    const size_t lds_wave = (size_t)(s_max + 1) * kWave * sizeof(int32_t);   // + the constant-1 row
-    int wpb = (int)std::min<size_t>(4, std::max<size_t>(1, 65536 / lds_wave));
-    if (lds_wave > 65536) return fail(ctx, SMC_E_INVALID, "network too large for one wave's LDS");
     const int wpc = pick_waves_per_cu(ctx);
     // No more waves than there are trajectories to run at once: idle waves
     // only poll the job table.
@@ -517,8 +561,10 @@ int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult 
     for (int k = 0; k < n; ++k) lanes_needed += P[k].capacity * (unsigned long long)P[k].job.lanes;
     const unsigned long long waves_needed = (lanes_needed + kWave - 1) / kWave;
     const unsigned long long waves = std::min<unsigned long long>((unsigned long long)ctx->n_cu * wpc, waves_needed);
-    const int grid = (int)std::max<unsigned long long>(1, (waves + wpb - 1) / wpb);
-    const int variant = group > 1 ? (tree ? 5 : 1) + __builtin_ctz((unsigned)group) : (m_max <= 4 ? 0 : 1);
+    int grid = (int)std::max<unsigned long long>(1, (waves + wpb - 1) / wpb);
+    if (n_trace > 0) grid = (int)std::min<unsigned long long>((unsigned long long)grid, tr_slots / ((unsigned long long)kWave * wpb));
+    const int variant = n_trace > 0 ? 10
+                      : group > 1 ? (tree ? 5 : 1) + __builtin_ctz((unsigned)group) : (m_max <= 4 ? 0 : 1);
     hipFunction_t spec_fn = nullptr;
     if (const int rc = pick_spec_kernel(ctx, P, n, n_iter > 0, !W.no_alloc, &spec_fn)) return rc;
     // wide specialised kernels keep counts in LDS like the generic ones
@@ -536,10 +582,10 @@ int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult 
     }
     HIP_TRY(ctx, launch_init(s, W.d_jobs, n, static_first ? grid * wpb : 0, W.d_ctl, n_iter));
     ctx->last_kernel = spec_fn ? SMC_KERNEL_SPECIALIZED
-                               : (variant == 0 ? SMC_KERNEL_GENERIC_SMALL
-                                               : (variant == 1 ? SMC_KERNEL_GENERIC
-                                                                 : (tree ? SMC_KERNEL_GENERIC_TREE
-                                                                         : SMC_KERNEL_GENERIC_GROUPED)));
+                       : variant == 0 ? SMC_KERNEL_GENERIC_SMALL
+                       : variant == 1 ? SMC_KERNEL_GENERIC
+                       : variant == 10 ? SMC_KERNEL_GENERIC_TRACE
+                       : tree ? SMC_KERNEL_GENERIC_TREE : SMC_KERNEL_GENERIC_GROUPED;
     for (int k = 0; k < n; ++k) res[k] = JobResult{};
     double total_ms = 0.0;
     const auto t_start = std::chrono::steady_clock::now();
@@ -706,6 +752,7 @@ void smc_ctx_destroy(smc_ctx *c)
     if (c->d_states) (void)hipFree(c->d_states);
     if (c->d_results) (void)hipFree(c->d_results);
     if (c->d_rec) (void)hipFree(c->d_rec);
+    if (c->d_trace) (void)hipFree(c->d_trace);
     if (c->d_ctl) (void)hipFree(c->d_ctl);
     if (c->cancel_host) (void)hipHostFree(c->cancel_host);
     if (c->h_jobs) (void)hipHostFree(c->h_jobs);

@@ -33,6 +33,8 @@ constexpr int kValStack = 4;       // arithmetic stack depth on the device
 constexpr int kBlocks = 16;        // prefix-sum blocks for reaction selection
 constexpr int kSubBlock = 8;       // channels per unrolled step of the blocked prefix
 constexpr int kMaxGroupRounds = 8; // lane groups: rounds of 8 x lanes channels per event, at most
+constexpr int kMaxTrace = 32;      // nodes of a trace program (formulas outside the compact monitors)
+constexpr uint32_t kTraceMaxEvents = 1u << 20;   // event cap limit of a trace job
 constexpr int kSpecMaxS = 16;      // specialised kernels: species counts in registers
 constexpr int kSpecMaxM = 8;       // specialised kernels: channels
 constexpr int kSpecWideMaxS = 128; // wide specialised kernels (counts in LDS): species
@@ -43,6 +45,7 @@ enum ValOp : int32_t { VO_VAR = 0, VO_CONST, VO_ADD, VO_SUB, VO_MUL, VO_DIV, VO_
 enum PredKind : int32_t { PK_VAR = 0, PK_LINEAR = 1, PK_RPN = 2 };
 enum AtomKind : int32_t { AK_PROP = 0, AK_UNTIL, AK_NEXT, AK_NESTED, AK_RESP, AK_NEXTU, AK_UNTILG };
 enum Reason : int32_t { RS_STATE = 0, RS_TIME = 1, RS_ABSORB = 2, RS_CAP = 3, RS_TMAX = 4 };
+enum TraceKind : int32_t { TN_TT = 0, TN_FF, TN_PRED, TN_NOT, TN_AND, TN_OR, TN_NEXT, TN_UNTIL };
 
 // A state predicate over species counts x.
 //  PK_VAR    : x[var] (op) c32                         (int32 compare)
@@ -93,10 +96,21 @@ struct Atom {
     double lo, hi, hi2, lo2;
 };
 
+// A node of a trace program: the formula itself as a tree (F I p written as
+// tt U I p, G I p as not(tt U I not p), Sec. 3.1), children before parents,
+// the root last.  pred: predicate id of TN_PRED; a, b: operands; [lo, hi]:
+// the interval of TN_NEXT and TN_UNTIL.
+struct TraceNode {
+    int32_t kind, pred, a, b;
+    double lo, hi;
+};
+
 // Compiled formula.  The top-level boolean combination of the monitors is a
 // table: with t (f) the mask of monitors known true (false), bit t | f << n of
 // topT (topF) says whether the formula is already true (false) in Kleene
-// logic.
+// logic.  A formula outside the compact monitor classes is a trace program
+// instead (trace = 1, n_atoms = 0): the kernel keeps the trajectory's states
+// (entry times and predicate bits) and evaluates the formula on them.
 struct MonProg {
     int32_t n_preds, n_atoms, n_props;
     int32_t all_var;   // every predicate is PK_VAR
@@ -108,6 +122,8 @@ struct MonProg {
     int32_t vvar[kMaxValOps];
     double vconst[kMaxValOps];
     double horizon;
+    int32_t trace, tr_n;
+    TraceNode tnodes[kMaxTrace];
 };
 
 // Reaction network tables (device memory, read-only in kernels).
@@ -136,6 +152,23 @@ struct NetDev {
     const int32_t *reac;
     const uint32_t *chg;
     const ChanDev *chan;   // Mp entries
+};
+
+// The record area of one lane for a trace program of `cap` states and `n`
+// nodes (each part 256-byte aligned):
+//   double   t[cap + 1]        entry times; t[m + 1] is also the time state m is left
+//   uint32_t bits[cap]         predicate bits of each state (bit q: predicate q)
+//   int32_t  need[kMaxTrace]   how many positions each node is evaluated at
+//   uint8_t  val[n][cap]       three-valued node values by position
+struct TraceArea {
+    static constexpr unsigned long long align(unsigned long long x) { return (x + 255ull) & ~255ull; }
+    static constexpr unsigned long long bits_off(uint32_t cap) { return align(8ull * (cap + 1ull)); }
+    static constexpr unsigned long long need_off(uint32_t cap) { return bits_off(cap) + align(4ull * cap); }
+    static constexpr unsigned long long val_off(uint32_t cap) { return need_off(cap) + align(4ull * kMaxTrace); }
+    static constexpr unsigned long long bytes(uint32_t cap, int n)
+    {
+        return val_off(cap) + align((unsigned long long)n * cap);
+    }
 };
 
 // Per-job accounting (device memory).  Batch b covers relative trajectory
@@ -182,11 +215,17 @@ struct Job {
     int32_t iterative;            // 1 = Fig. 2 rule, 0 = fixed sample
     int32_t literal;              // paper's rounding step without the stop at 0.5
     int32_t lanes;                // lanes per trajectory: 1, or 2/4/8/16 (generic kernel, > 4 channels)
-    int32_t pad_;
+    int32_t trace;                // 1 = the formula is a trace program
     double eps, z;
     JobState *st;
     uint32_t *rec_events;         // optional per-index outputs (relative index)
     uint8_t *rec_vr;
+    // trace programs: one record area per lane of the launch (lane l at
+    // tr_base + l * tr_stride) for states 0 .. tr_cap - 1, see TraceArea
+    unsigned char *tr_base;
+    unsigned long long tr_stride;
+    uint32_t tr_cap;
+    uint32_t tr_pad;
 };
 
 // Compact per-job outcome copied back to the host.

@@ -17,6 +17,9 @@ struct Unsupported : std::runtime_error {
     using std::runtime_error::runtime_error;
 };
 
+// Device memory for the record areas of trace programs in one launch.
+constexpr unsigned long long kTraceBudget = 8ull << 30;
+
 // formula.cpp
 void compile_formula(const std::string &text, const std::vector<std::string> &names, MonProg &out);
 

@@ -84,6 +84,7 @@ bool spec_wide(int S, int M) { return S > kSpecMaxS || M > kSpecMaxM; }
 bool spec_supported(int S, int M, const MonProg &mp)
 {
     if (S < 1 || S > kSpecWideMaxS || M < 1 || M > kSpecWideMaxM) return false;
+    if (mp.trace) return false;   // trace programs run on the generic kernel
     for (int q = 0; q < mp.n_preds; ++q)
         if (mp.preds[q].kind == PK_RPN) return false;
     return true;

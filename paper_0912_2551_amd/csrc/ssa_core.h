@@ -250,8 +250,12 @@ struct JobView {
     double eps, z;
     int nb, bs;   // prefix blocks and reactions per block
     int lanes;    // lanes per trajectory
+    int trace;    // the formula is a trace program
     uint32_t *rec_events;   // optional per-index outputs
     uint8_t *rec_vr;
+    unsigned char *tr_base;   // trace programs: the lanes' record areas
+    unsigned long long tr_stride;
+    uint32_t tr_cap;
 
     __device__ void load(const Job *jobs, int j)
     {
@@ -286,8 +290,12 @@ struct JobView {
         nb = nsub < kBlocks ? nsub : kBlocks;
         bs = (nsub + nb - 1) / nb * kSubBlock;
         lanes = J->lanes;
+        trace = J->trace;
         rec_events = J->rec_events;
         rec_vr = J->rec_vr;
+        tr_base = J->tr_base;
+        tr_stride = J->tr_stride;
+        tr_cap = J->tr_cap;
     }
 };
 
@@ -704,6 +712,188 @@ __device__ __forceinline__ void mon_init(MonState &ms)
     ms.ok = 0xFFFFFFFFu;
     ms.ts0 = -1.0;
     ms.ts1 = -1.0;
+}
+
+// ---------------------------------------------------------------------------
+// Trace programs: formulas outside the compact monitors (deeper nesting,
+// temporal left operands of U, windows that do not start at 0 inside other
+// operators).  The lane records each state it enters (entry time, predicate
+// bits) in its record area, the buffer of Sec. 3.2, and decides the formula
+// on that finite prefix in three-valued (Kleene) logic.  Points p = 2m + w:
+// states 0..m are known, and with w = 1 also the time state m is left.  A
+// point is decided when the formula's value at position 0 is known there, or
+// by the t_max rule (the latest known time lies past t_max) or the event
+// cap (m = max_events).  Decided stays decided as the prefix grows, so the
+// lane tests points only at checkpoints (m + 1 a power of two from 16 on,
+// the cap, absorption, t_max) and then finds the first decided point by
+// bisection: the trajectory's result is the one it would have at that point.
+// ---------------------------------------------------------------------------
+enum : uint8_t { TV_F = 0, TV_T = 1, TV_U = 2 };
+
+__device__ __forceinline__ uint8_t tv_not(uint8_t v) { return v == TV_U ? TV_U : (uint8_t)(TV_T - v); }
+__device__ __forceinline__ uint8_t tv_and(uint8_t x, uint8_t y)
+{
+    return (x == TV_F || y == TV_F) ? TV_F : ((x == TV_T && y == TV_T) ? TV_T : TV_U);
+}
+__device__ __forceinline__ uint8_t tv_or(uint8_t x, uint8_t y)
+{
+    return (x == TV_T || y == TV_T) ? TV_T : ((x == TV_F && y == TV_F) ? TV_F : TV_U);
+}
+
+struct TraceRec {
+    double *t;
+    uint32_t *bits;
+    int32_t *need;
+    uint8_t *val;
+    uint32_t cap;
+};
+
+__device__ __forceinline__ TraceRec trace_rec(unsigned char *base, unsigned long long stride, uint32_t cap,
+                                              unsigned long long slot)
+{
+    unsigned char *a = base + slot * stride;
+    TraceRec R;
+    R.t = reinterpret_cast<double *>(a);
+    R.bits = reinterpret_cast<uint32_t *>(a + TraceArea::bits_off(cap));
+    R.need = reinterpret_cast<int32_t *>(a + TraceArea::need_off(cap));
+    R.val = a + TraceArea::val_off(cap);
+    R.cap = cap;
+    return R;
+}
+
+// Value at position 0 of the prefix of `len` states (next_known: t[len] is
+// the time the last one is left, +inf when it is absorbing).  Nodes are
+// evaluated children first, each at the positions its parents read: from
+// the root (position 0) down, a NOT, AND or OR reads its operands where it
+// is read, a NEXT one position further, an UNTIL every position its scans
+// reach (the scan from the last position reaches furthest).
+__device__ __noinline__ uint32_t trace_value(cptr<MonProg> mp, TraceRec R, int len, bool next_known)
+{
+    const int nn = mp->tr_n;
+    for (int q = 0; q < nn; ++q) R.need[q] = 0;
+    R.need[nn - 1] = 1;
+    for (int q = nn - 1; q >= 0; --q) {
+        const auto &N = mp->tnodes[q];
+        const int nq = R.need[q];
+        if (nq == 0) continue;
+        int e = nq;
+        if (N.kind == TN_NEXT) {
+            e = nq + 1 < len ? nq + 1 : len;
+        } else if (N.kind == TN_UNTIL) {
+            const double ti = R.t[nq - 1];
+            int j = nq - 1;
+            while (j + 1 < len && !(R.t[j + 1] - ti > N.hi)) ++j;
+            e = j + 1;
+        }
+        if (N.kind >= TN_NOT) R.need[N.a] = R.need[N.a] > e ? R.need[N.a] : e;
+        if (N.kind == TN_AND || N.kind == TN_OR || N.kind == TN_UNTIL)
+            R.need[N.b] = R.need[N.b] > e ? R.need[N.b] : e;
+    }
+    const unsigned long long cap = R.cap;
+    for (int q = 0; q < nn; ++q) {
+        const auto &N = mp->tnodes[q];
+        const int nq = R.need[q];
+        uint8_t *out = R.val + (unsigned long long)q * cap;
+        const uint8_t *va = N.a >= 0 ? R.val + (unsigned long long)N.a * cap : nullptr;
+        const uint8_t *vb = N.b >= 0 ? R.val + (unsigned long long)N.b * cap : nullptr;
+        for (int i = 0; i < nq; ++i) {
+            uint8_t r;
+            switch (N.kind) {
+            case TN_TT: r = TV_T; break;
+            case TN_FF: r = TV_F; break;
+            case TN_PRED: r = ((R.bits[i] >> N.pred) & 1u) ? TV_T : TV_F; break;
+            case TN_NOT: r = tv_not(va[i]); break;
+            case TN_AND: r = tv_and(va[i], vb[i]); break;
+            case TN_OR: r = tv_or(va[i], vb[i]); break;
+            case TN_NEXT: {
+                // X I a at i: the next state exists, is entered within I
+                // after state i, and satisfies a
+                if (i + 1 < len) {
+                    const double d = R.t[i + 1] - R.t[i];
+                    r = (d >= N.lo && d <= N.hi) ? va[i + 1] : TV_F;
+                } else if (next_known) {
+                    const double tn = R.t[len];
+                    const double d = tn - R.t[i];
+                    r = (__builtin_isinf(tn) || !(d >= N.lo && d <= N.hi)) ? TV_F : TV_U;
+                } else {
+                    r = TV_U;
+                }
+                break;
+            }
+            default: {
+                // a U I b at i: some j >= i entered within I after state i
+                // satisfies b, and a holds at i .. j - 1
+                uint8_t res = TV_F, all = TV_T;
+                for (int j = i;; ++j) {
+                    if (j >= len) {
+                        // state j lies past the prefix: it exists unless the
+                        // last state is absorbing, and may be in the window
+                        // unless its entry time is known to lie past it
+                        bool none = false;
+                        if (next_known) {
+                            const double tj = R.t[len];
+                            none = __builtin_isinf(tj) || tj - R.t[i] > N.hi;
+                        }
+                        if (!none && all != TV_F) res = tv_or(res, TV_U);
+                        break;
+                    }
+                    const double d = R.t[j] - R.t[i];
+                    if (d > N.hi) break;
+                    if (d >= N.lo) res = tv_or(res, tv_and(all, vb[j]));
+                    if (res == TV_T) break;
+                    all = tv_and(all, va[j]);
+                    if (all == TV_F) break;
+                }
+                r = res;
+                break;
+            }
+            }
+            out[i] = r;
+        }
+    }
+    return R.val[(unsigned long long)(nn - 1) * cap];
+}
+
+// Is point p decided?  Then its verdict and reason.
+__device__ __noinline__ bool trace_decided(cptr<MonProg> mp, TraceRec R, uint32_t p, double t_max,
+                                           uint32_t max_events, uint32_t *verdict, uint32_t *reason)
+{
+    const uint32_t m = p >> 1, w = p & 1u;
+    const uint32_t v = trace_value(mp, R, (int)m + 1, w != 0u);
+    if (v != TV_U) {
+        *verdict = v == TV_T ? 1u : 0u;
+        *reason = w == 0u ? (uint32_t)RS_STATE : (__builtin_isinf(R.t[m + 1]) ? (uint32_t)RS_ABSORB : (uint32_t)RS_TIME);
+        return true;
+    }
+    if (R.t[m + w] > t_max) {   // the pessimistic rule (Sec. 3.2)
+        *verdict = 0u;
+        *reason = RS_TMAX;
+        return true;
+    }
+    if (w == 0u && max_events != 0u && m == max_events) {
+        *verdict = 0u;
+        *reason = RS_CAP;
+        return true;
+    }
+    return false;
+}
+
+// The first decided point in [lo, hi], hi being decided: its state index
+// (the trajectory's event count), verdict and reason.
+__device__ __noinline__ void trace_first(cptr<MonProg> mp, TraceRec R, uint32_t lo, uint32_t hi, double t_max,
+                                         uint32_t max_events, uint32_t *events, uint32_t *verdict,
+                                         uint32_t *reason)
+{
+    uint32_t vd = 0, rs = 0;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2u;
+        if (trace_decided(mp, R, mid, t_max, max_events, &vd, &rs)) hi = mid;
+        else lo = mid + 1u;
+    }
+    trace_decided(mp, R, lo, t_max, max_events, &vd, &rs);
+    *events = lo >> 1;
+    *verdict = vd;
+    *reason = rs;
 }
 
 // ---------------------------------------------------------------------------
@@ -1663,7 +1853,8 @@ __device__ __forceinline__ void add_counts(JobState *st, int b, int shard, unsig
 // kIter: the launch may hold iterative (Fig. 2) jobs.  Launches of fixed-size
 // jobs only are compiled without the stopping-rule machinery, which would
 // otherwise cost registers (occupancy) in the event loop.
-template <class Pol, bool kIter>
+// kTrace: the launch may hold trace programs (one lane per trajectory).
+template <class Pol, bool kIter, bool kTrace = false>
 __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
 {
     const int lane = lane_id();
@@ -1686,6 +1877,7 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
     MonState ms;
     mon_init(ms);
     Draw dr{0.0, 0.0};   // random numbers of the lane's next event (index k)
+    uint32_t tr_lo = 0;  // trace programs: every point below this one is undecided
     int spins = 0;
     // wave-local pool of claimed, not yet started indices [pool_next, pool_end)
     unsigned long long pool_next = 0, pool_end = 0;
@@ -1785,6 +1977,7 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
                 t = 0.0;
                 k = 0;
                 mon_init(ms);
+                tr_lo = 0;
                 active = true;
                 entered = true;
             }
@@ -1803,42 +1996,86 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
         // them, so their computation overlaps the event.
         const Draw nxt = event_uniforms(V, V.first + ridx, entered ? 0u : k + 1u);
 
-        // -------- one event per running lane --------
-        const bool ev_lane = active && !entered;
-        const bool capped = V.max_events != 0u && k == V.max_events;
-        typename Pol::Sel ch;
-        const double tn = Pol::draw(V, X, dr, t, &ch, ev_lane);
-        const bool absorbing = __builtin_isinf(tn);
-        MonState ms_adv = ms;
-        const uint32_t va = Pol::advance(V, ms_adv, tn, absorbing);
-        const bool stepping = ev_lane && !capped;
-        const bool dec_time = stepping && va != 0u;
-        const bool dec_tmax = stepping && va == 0u && tn > V.t_max;
-        const bool applied = stepping && va == 0u && !(tn > V.t_max);
-        ms_select(ms, ms_adv, stepping);
-        Pol::apply_if(X, ch, applied);
-        t = applied ? tn : t;
-        k = applied ? k + 1u : k;
-        entered = entered || applied;
-        // capped, dec_time and dec_tmax exclude each other
-        const bool dec_cap = ev_lane && capped;
-        fin = fin || dec_cap || dec_time || dec_tmax;
-        verdict = dec_time ? (va == 1u ? 1u : 0u) : (dec_cap || dec_tmax ? 0u : verdict);
-        const uint32_t r_time = absorbing ? (uint32_t)RS_ABSORB : (uint32_t)RS_TIME;
-        reason = dec_tmax ? (uint32_t)RS_TMAX : reason;
-        reason = dec_time ? r_time : reason;
-        reason = dec_cap ? (uint32_t)RS_CAP : reason;
+        // -------- trace programs: record, test at checkpoints --------
+        if (kTrace && V.trace) {   // wave-uniform
+            const bool ev_lane = active && !entered;
+            typename Pol::Sel ch;
+            const double tn = Pol::draw(V, X, dr, t, &ch, ev_lane);
+            const TraceRec R = trace_rec(V.tr_base, V.tr_stride, V.tr_cap,
+                                         (unsigned long long)gwave * kWave + (unsigned long long)lane);
+            bool tfin = false;
+            uint32_t tk = k, tvd = 0, trs = 0;
+            if (ev_lane) {
+                R.t[k + 1u] = tn;   // the time state k is left
+                // absorption, or the t_max rule, decides point 2k + 1
+                if (__builtin_isinf(tn) || tn > V.t_max) {
+                    trace_first(V.mon, R, tr_lo, 2u * k + 1u, V.t_max, V.max_events, &tk, &tvd, &trs);
+                    tfin = true;
+                }
+            }
+            const bool applied = ev_lane && !tfin;
+            Pol::apply_if(X, ch, applied);
+            t = applied ? tn : t;
+            k = applied ? k + 1u : k;
+            entered = entered || applied;
+            if (entered) {
+                R.t[k] = t;
+                R.bits[k] = eval_preds(V.mon, X);
+                // checkpoints: state index k + 1 a power of two from 16 on, and the cap
+                const bool cp = (V.max_events != 0u && k == V.max_events) || (k >= 15u && ((k + 1u) & k) == 0u);
+                if (cp) {
+                    if (trace_decided(V.mon, R, 2u * k, V.t_max, V.max_events, &tvd, &trs)) {
+                        trace_first(V.mon, R, tr_lo, 2u * k, V.t_max, V.max_events, &tk, &tvd, &trs);
+                        tfin = true;
+                    } else {
+                        tr_lo = 2u * k + 1u;
+                    }
+                }
+            }
+            dr.nl = entered ? nxt.nl : dr.nl;
+            dr.u2 = entered ? nxt.u2 : dr.u2;
+            fin = fin || tfin;
+            verdict = tfin ? tvd : verdict;
+            reason = tfin ? trs : reason;
+            k = tfin ? tk : k;
+        } else {
+            // -------- one event per running lane --------
+            const bool ev_lane = active && !entered;
+            const bool capped = V.max_events != 0u && k == V.max_events;
+            typename Pol::Sel ch;
+            const double tn = Pol::draw(V, X, dr, t, &ch, ev_lane);
+            const bool absorbing = __builtin_isinf(tn);
+            MonState ms_adv = ms;
+            const uint32_t va = Pol::advance(V, ms_adv, tn, absorbing);
+            const bool stepping = ev_lane && !capped;
+            const bool dec_time = stepping && va != 0u;
+            const bool dec_tmax = stepping && va == 0u && tn > V.t_max;
+            const bool applied = stepping && va == 0u && !(tn > V.t_max);
+            ms_select(ms, ms_adv, stepping);
+            Pol::apply_if(X, ch, applied);
+            t = applied ? tn : t;
+            k = applied ? k + 1u : k;
+            entered = entered || applied;
+            // capped, dec_time and dec_tmax exclude each other
+            const bool dec_cap = ev_lane && capped;
+            fin = fin || dec_cap || dec_time || dec_tmax;
+            verdict = dec_time ? (va == 1u ? 1u : 0u) : (dec_cap || dec_tmax ? 0u : verdict);
+            const uint32_t r_time = absorbing ? (uint32_t)RS_ABSORB : (uint32_t)RS_TIME;
+            reason = dec_tmax ? (uint32_t)RS_TMAX : reason;
+            reason = dec_time ? r_time : reason;
+            reason = dec_cap ? (uint32_t)RS_CAP : reason;
 
-        // -------- inspect the state just entered (new or after an event) --------
-        MonState ms_st = ms;
-        const uint32_t vs = Pol::step(V, ms_st, X, k, t);
-        ms_select(ms, ms_st, entered);
-        dr.nl = entered ? nxt.nl : dr.nl;   // field by field: a select of whole
-        dr.u2 = entered ? nxt.u2 : dr.u2;   // structs would go through memory
-        const bool dec_state = entered && vs != 0u;
-        fin = fin || dec_state;
-        verdict = dec_state ? (vs == 1u ? 1u : 0u) : verdict;
-        reason = dec_state ? (uint32_t)RS_STATE : reason;
+            // -------- inspect the state just entered (new or after an event) --------
+            MonState ms_st = ms;
+            const uint32_t vs = Pol::step(V, ms_st, X, k, t);
+            ms_select(ms, ms_st, entered);
+            dr.nl = entered ? nxt.nl : dr.nl;   // field by field: a select of whole
+            dr.u2 = entered ? nxt.u2 : dr.u2;   // structs would go through memory
+            const bool dec_state = entered && vs != 0u;
+            fin = fin || dec_state;
+            verdict = dec_state ? (vs == 1u ? 1u : 0u) : verdict;
+            reason = dec_state ? (uint32_t)RS_STATE : reason;
+        }
 
         // -------- accounting of decided trajectories --------
         // (counted once per trajectory: by the first lane of its group)

@@ -19,9 +19,18 @@ __global__ __launch_bounds__(256, SMC_MIN_WAVES_PER_EU) void ssa_persistent(KArg
     persistent_body<DynPolicy<NB, G, kTree>, kIter>(A, lds);
 }
 
+// Launches that hold trace programs (one lane per trajectory, any network).
+template <bool kIter>
+__global__ __launch_bounds__(256, SMC_MIN_WAVES_PER_EU) void ssa_persistent_trace(KArgs A)
+{
+    extern __shared__ int32_t lds[];
+    persistent_body<DynPolicy<kBlocks>, kIter, true>(A, lds);
+}
+
 // The persistent kernel of a launch variant: 0 = at most 4 reaction channels,
 // 1 = any network, 2..5 = any network, with jobs of 2, 4, 8 or 16 lanes per
-// trajectory, 6..9 = the same with tree-ordered sums (SMC_TREE_SUMS).
+// trajectory, 6..9 = the same with tree-ordered sums (SMC_TREE_SUMS), 10 =
+// any network, the launch holding trace programs.
 template <bool kIter>
 static const void *persistent_kernel(int variant)
 {
@@ -35,7 +44,8 @@ static const void *persistent_kernel(int variant)
     case 6: return reinterpret_cast<const void *>(&ssa_persistent<kBlocks, kIter, 2, true>);
     case 7: return reinterpret_cast<const void *>(&ssa_persistent<kBlocks, kIter, 4, true>);
     case 8: return reinterpret_cast<const void *>(&ssa_persistent<kBlocks, kIter, 8, true>);
-    default: return reinterpret_cast<const void *>(&ssa_persistent<kBlocks, kIter, 16, true>);
+    case 9: return reinterpret_cast<const void *>(&ssa_persistent<kBlocks, kIter, 16, true>);
+    default: return reinterpret_cast<const void *>(&ssa_persistent_trace<kIter>);
     }
 }
 

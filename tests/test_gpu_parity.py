@@ -354,14 +354,11 @@ def test_errors_and_edges(ctx):
     with pytest.raises(B.SmcError) as e:
         ctx.formula(n, "F[0,1](Y>1)")
     assert e.value.code == B.SMC_E_PARSE
-    with pytest.raises(B.SmcError) as e:
-        ctx.formula(n, "F[0,10](G[1,2](X>1))")
+    with pytest.raises(B.SmcError) as e:           # more than 16 predicates
+        ctx.formula(n, " | ".join(f"F[0,1](X>={i})" for i in range(17)))
     assert e.value.code == B.SMC_E_UNSUPPORTED
-    with pytest.raises(B.SmcError) as e:
-        ctx.formula(n, "G[0,1](F[0,1](X>1)) & G[0,1](F[0,1](X>2)) & G[0,1](F[0,1](X>3))")
-    assert e.value.code == B.SMC_E_UNSUPPORTED
-    with pytest.raises(B.SmcError) as e:
-        ctx.formula(n, "X[0,1](X[0,1](X>1))")
+    with pytest.raises(B.SmcError) as e:           # a trace program of more than 32 nodes
+        ctx.formula(n, "F[0,1](" + " & ".join(f"G[0,{i + 1}](X>=1)" for i in range(7)) + ")")
     assert e.value.code == B.SMC_E_UNSUPPORTED
     # more species than one wave's LDS holds: refused on the host, before any launch
     big = W.from_reactions([f"S{i}" for i in range(300)], [5] + [0] * 299, [(["S0"], ["S1"], 1.0)], "wide")
@@ -810,3 +807,83 @@ def test_autotune_batch_keeps_the_estimates(ctx):
         res1 = ctx.estimate_batch(jobs1)
         assert ctx.last_kernel() == B.KERNEL_GENERIC
         assert [(r["n"], r["successes"]) for r in res1] == [(e["n"], e["successes"]) for e in doc["jobs"]]
+
+
+# ---------------------------------------------------------------------------
+# Trace programs: formulas outside the compact monitors, decided on the
+# recorded states; per-trajectory results must equal the oracle's
+# ---------------------------------------------------------------------------
+TRACE_CASES = [
+    ("window-not-at-0", W.immigration_death, "F[0,10](G[1,2](X>=65))", {"max_events": 5000}),
+    ("resp-lower", W.immigration_death, "G[0,10](X<=60 | F[1,2](X>=70))", {"max_events": 5000}),
+    ("X-over-X", W.isomerization, "X[0,0.1](X[0,0.1](A<=48))", {"max_events": 5000}),
+    ("temporal-left", W.immigration_death, "(F[0,1](X>=5)) U[0,5] (X>=30)", {"max_events": 5000}),
+    ("three-levels", W.immigration_death, "F[0,3](F[0,2](F[0,1](X>=40)))", {"max_events": 5000}),
+    ("three-registers", W.isomerization,
+     "G[0,1](F[0,0.5](A>=28)) & G[0,1](F[0,0.5](B>=12)) & G[0,1](F[0,1](A<=45))", {"max_events": 5000}),
+    ("tmax", W.immigration_death, "F(G[1,2](X>=95))", {"max_events": 5000, "t_max": 30.0}),
+    ("cap", W.immigration_death, "G[5,100](F[1,5](X>=90))", {"max_events": 150}),
+    ("absorb", death_only, "F[0,100](G[1,5](X<=3))", {"max_events": 5000}),
+    ("six-preds", W.isomerization, "(A>=1 & B<=45 & A+B>=2 & A>=10 & B<=40 & A<=50) U[0,2] (A<=18)",
+     {"max_events": 5000}),
+]
+
+
+@pytest.mark.parametrize("name,make,text,kw", TRACE_CASES, ids=[c[0] for c in TRACE_CASES])
+def test_trace_program_parity(ctx, name, make, text, kw):
+    B = _B()
+    net = make()
+    n = ctx.network(net)
+    f = ctx.formula(n, text)
+    for first, seed in ((0, 1), (123457, 99)):
+        p = B.params(seed=seed, model_id=3, **kw)
+        print(f"case trace {name} first {first} seed {seed}", flush=True)
+        ev, vd, rs = ctx.trajectories(n, f, p, first, 2000)
+        assert ctx.last_kernel() == B.KERNEL_GENERIC_TRACE
+        oev, ovd, ors = oracle.trajectories(net, oracle.parse(text, net), first, 2000, seed=seed, model_id=3, **kw)
+        assert np.array_equal(rs, ors), (name, np.nonzero(rs != ors)[0][:5])
+        assert np.array_equal(vd, ovd), (name, np.nonzero(vd != ovd)[0][:5])
+        assert np.array_equal(ev, oev), (name, np.nonzero(ev != oev)[0][:5])
+
+
+def test_trace_programs_in_a_batch(ctx):
+    """Trace programs and compact monitors in one iterative launch: every
+    job's estimate equals the oracle's."""
+    B = _B()
+    keep, jobs, singles = [], [], []
+    for q, (name, make, text, kw) in enumerate(TRACE_CASES[:6] + [("compact", W.immigration_death,
+                                                                   W.C1_FORMULA, {"max_events": 5000})]):
+        net = make()
+        nh = ctx.network(net)
+        fh = ctx.formula(nh, text)
+        keep.append((nh, fh))
+        jobs.append((nh, fh, B.params(seed=1, model_id=40 + q, half_width=0.05, **kw)))
+        singles.append((net, text, 40 + q, kw))
+    print("trace programs in a batch", flush=True)
+    res = ctx.estimate_batch(jobs)
+    assert ctx.last_kernel() == B.KERNEL_GENERIC_TRACE
+    for (net, text, mid, kw), r in zip(singles, res):
+        o = oracle.estimate(net, text, eps=0.05, seed=1, model_id=mid, **kw)
+        assert (r["n"], r["successes"], r["events"], r["batches"]) == \
+            (o["n"], o["successes"], o["events"], len(o["bounds"])), (mid, r, o)
+
+
+def test_trace_program_limits(ctx):
+    B = _B()
+    net = W.immigration_death()
+    n = ctx.network(net)
+    f = ctx.formula(n, "F[0,3](F[0,2](F[0,1](X>=40)))")
+    with pytest.raises(B.SmcError) as e:           # states are recorded up to the cap: one is needed
+        ctx.estimate(n, f, B.params(fixed_n=64))
+    assert e.value.code == B.SMC_E_INVALID
+    with pytest.raises(B.SmcError) as e:
+        ctx.estimate(n, f, B.params(fixed_n=64, max_events=(1 << 20) + 1))
+    assert e.value.code == B.SMC_E_INVALID
+    with pytest.raises(B.SmcError) as e:           # no record areas without allocation
+        ctx.estimate_batch_noalloc([(n, f, B.params(fixed_n=64, max_events=100))])
+    assert e.value.code == B.SMC_E_UNSUPPORTED
+    # lanes and specialisation requests fall back to the trace-capable kernel
+    r = ctx.estimate(n, f, B.params(fixed_n=4096, seed=2, max_events=5000, lanes=8))
+    assert ctx.last_kernel() == B.KERNEL_GENERIC_TRACE
+    o = oracle.estimate(net, "F[0,3](F[0,2](F[0,1](X>=40)))", fixed_n=4096, seed=2, max_events=5000)
+    assert (r["n"], r["successes"], r["events"]) == (o["n"], o["successes"], o["events"])
