@@ -1758,8 +1758,9 @@ __device__ __forceinline__ bool claimable(const Job *jobs, int j)
 // idle counts this wave's consecutive fruitless scans.  Without this, every
 // idle wave of a launch converges on the one job whose limit has just risen
 // (by a single index, say) and their claims serialise on its counter; the
-// idle term lets distant waves in when the nearby ones stay busy.
-__device__ int pick_job(const Job *jobs, int n_jobs, int start, int wph, int idle)
+// idle term lets distant waves in when the nearby ones stay busy.  any: take
+// the first job with issuable indices, at any distance.
+__device__ int pick_job(const Job *jobs, int n_jobs, int start, int wph, int idle, bool any = false)
 {
     const int lane = lane_id();
     const unsigned long long w = (unsigned long long)wph;
@@ -1773,7 +1774,7 @@ __device__ int pick_job(const Job *jobs, int n_jobs, int start, int wph, int idl
             JobState *st = jobs[j].st;
             const unsigned long long nx = ld_relaxed(&st->next), lm = ld_relaxed(&st->limit);
             if (nx < lm && ld_relaxed(&st->final_flag) == 0)
-                ok = (unsigned long long)q * w <= ((lm - nx) / 32ull + w) * age;
+                ok = any || (unsigned long long)q * w <= ((lm - nx) / 32ull + w) * age;
         }
         const uint64_t m = __ballot(ok);
         if (m) return __builtin_amdgcn_readlane(j, ffs64(m));
@@ -1922,7 +1923,12 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
             if (uniform_i(stop)) break;
         }
         if (__ballot(active) == 0ull && pool_next == pool_end) {
-            const int j = pick_job(A.jobs, A.n_jobs, start, wph, spins);
+            int j = pick_job(A.jobs, A.n_jobs, start, wph, spins);
+            // A launch of fixed-size jobs only: a wave leaves once nothing is
+            // near its home, so before leaving it takes any job with indices
+            // left, however far (with many more jobs than waves, some would
+            // otherwise lie out of every wave's reach).
+            if (j < 0 && ld_relaxed(&A.ctl->open_jobs) <= 0) j = pick_job(A.jobs, A.n_jobs, start, wph, spins, true);
             if (j != cur && cur >= 0 && !V.iterative) {
                 // leaving a fixed-sample job: publish this wave's counts
                 const unsigned long long ny = wave_sum_u64(my_yes), nn = wave_sum_u64(my_no);

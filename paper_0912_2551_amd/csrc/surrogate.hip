@@ -541,6 +541,129 @@ __global__ __launch_bounds__(256) void mlp_query_staged(const float *x, long n, 
 }
 
 // ---------------------------------------------------------------------------
+// Inference + gate, one tile of 32 points per wave: each block (eight waves,
+// two per SIMD, so that one wave's vector work overlaps the other's matrix
+// work) stages W2 in LDS once; every wave then runs its own tiles from start
+// to end, with no block barrier after the staging.  Per tile:
+//  - layers 1 and 2 step by step along k: for step s, lane l computes the 8
+//    hidden units its A operand holds (row l % 32, units 16 s + 8 (l / 32) ..
+//    + 7), from W1 and b1 in LDS as (w0, w1, w2, b1), straight into registers;
+//    then v_mfma_f32_32x32x16_bf16 adds the step to each of the eight 32-column
+//    groups' accumulators (B from LDS);
+//  - layer 3: every lane adds its columns' contributions to its 16 rows, then
+//    the 32 lanes of each half sum by shuffles;
+//  - the hull test spread over the two lanes of each point.
+// Same numeric contract and gate as the other query kernels.
+// ---------------------------------------------------------------------------
+constexpr int kQueryWaves = 8;
+constexpr size_t kWaveQueryLds = (size_t)kH * kQRow * 2 + (size_t)kH * 4 * sizeof(float);
+
+__global__ __launch_bounds__(64 * kQueryWaves) void mlp_query_waves(
+    const float *x, long n, const float *mu, const float *sigma, const uint16_t *W1b, const float *b1,
+    const uint16_t *W2b, const float *b2, const uint16_t *W3b, const float *b3, const float *planes, int n_planes,
+    float hull_tol, float threshold, float margin, float *p_out, uint8_t *use)
+{
+    extern __shared__ uint16_t qsm[];
+    uint16_t *W2s = qsm;                                                // [col][k] (row stride kQRow)
+    float4 *W1s = reinterpret_cast<float4 *>(W2s + kH * kQRow);         // [unit] = (w0, w1, w2, b1)
+    const int tid = (int)threadIdx.x;
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(W2b);
+        uint4 *dst = reinterpret_cast<uint4 *>(W2s);
+        for (int i = tid; i < kH * kH / 8; i += 64 * kQueryWaves)
+            dst[(i / (kH / 8)) * (kQRow / 8) + i % (kH / 8)] = src[i];
+        if (tid < kH)
+            W1s[tid] = make_float4(from_bf16(W1b[tid * 3]), from_bf16(W1b[tid * 3 + 1]), from_bf16(W1b[tid * 3 + 2]),
+                                   b1[tid]);
+    }
+    __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6;
+    const int rc = lane & 31, half = lane >> 5;
+    const float bias3 = b3[0];
+    const float mu0 = mu[0], mu1 = mu[1], mu2 = mu[2], sg0 = sigma[0], sg1 = sigma[1], sg2 = sigma[2];
+    const long n_tiles = (n + 31) / 32;
+    const long stride = (long)gridDim.x * kQueryWaves;
+    for (long tile = (long)blockIdx.x * kQueryWaves + wave; tile < n_tiles; tile += stride) {
+        const long row = tile * 32 + rc;   // this lane's point (both halves hold it)
+        float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+        if (row < n) {
+            x0 = x[row * 3];
+            x1 = x[row * 3 + 1];
+            x2 = x[row * 3 + 2];
+        }
+        const float n0 = from_bf16(to_bf16((x0 - mu0) / sg0));
+        const float n1 = from_bf16(to_bf16((x1 - mu1) / sg1));
+        const float n2 = from_bf16(to_bf16((x2 - mu2) / sg2));
+        // layers 1 and 2, step by step along k: the step's A operand (layer 1
+        // for the 8 hidden units this lane holds) feeds the eight 32-column
+        // groups' accumulators
+        floatx16 acc[8];
+#pragma unroll
+        for (int g = 0; g < 8; ++g) acc[g] = floatx16{};
+#pragma unroll 2
+        for (int s = 0; s < 16; ++s) {
+            bf16x8 a;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float4 w = W1s[16 * s + 8 * half + e];
+                float h = w.w;
+                h = fmaf(n0, w.x, h);
+                h = fmaf(n1, w.y, h);
+                h = fmaf(n2, w.z, h);
+                a[e] = __builtin_bit_cast(__bf16, to_bf16(h > 0.0f ? h : 0.0f));
+            }
+            const uint16_t *bcol = W2s + rc * kQRow + 8 * half + 16 * s;
+#pragma unroll
+            for (int g = 0; g < 8; ++g) {
+                const bf16x8 b = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(bcol + g * 32 * kQRow));
+                acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[g], 0, 0, 0);
+            }
+        }
+        // layer 3: rows 8 (r / 4) + 4 half + r % 4 of column 32 g + rc
+        float zr[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) zr[r] = 0.0f;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+            const float bg = b2[g * 32 + rc], wg = from_bf16(W3b[g * 32 + rc]);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const float v = acc[g][r] + bg;
+                zr[r] += from_bf16(to_bf16(v > 0.0f ? v : 0.0f)) * wg;
+            }
+        }
+        // sum over the 32 columns of each half: then every lane of half h
+        // holds the sums of rows 8 (r / 4) + 4 h + r % 4
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+#pragma unroll
+            for (int off = 16; off >= 1; off >>= 1) zr[r] += __shfl_xor(zr[r], off, 64);
+        }
+        // row rc's sum is held by the half whose rows include it
+        const int idx = 4 * (rc >> 3) + (rc & 3);
+        float mine = zr[0];
+#pragma unroll
+        for (int r = 1; r < 16; ++r) mine = idx == r ? zr[r] : mine;
+        const float z = bias3 + __shfl(mine, ((rc >> 2) & 1) * 32 + rc, 64);
+        // hull: the two lanes of a point take alternate facets
+        bool ok = true;
+        for (int f = half; f < n_planes && ok; f += 2) {
+            const float *pl = planes + 4 * f;
+            const float v = pl[0] * x0 + pl[1] * x1 + pl[2] * x2;
+            ok = v <= pl[3] + hull_tol;
+        }
+        // (the shuffle runs on every lane: the partner's value must be written)
+        const int other = __shfl(ok ? 1 : 0, lane ^ 32, 64);
+        const bool inside = n_planes > 0 && ok && other != 0;
+        if (half == 0 && row < n) {
+            const float p = 1.0f / (1.0f + expf(-z));
+            p_out[row] = p;
+            if (use) use[row] = (inside && fabsf(p - threshold) >= margin) ? 1 : 0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launch helpers.
 // ---------------------------------------------------------------------------
 static unsigned blocks_for(long n, int threads) { return (unsigned)((n + threads - 1) / threads); }
@@ -716,8 +839,8 @@ hipError_t sg_query(hipStream_t s, const float *x, long n, const float *mu, cons
                     const uint16_t *W3b, const float *b3, const float *planes, int n_planes, float hull_tol,
                     float threshold, float margin, float *p_out, uint8_t *use)
 {
-    // the staged form needs 150 KB of LDS per block; it runs where the device
-    // allows it (CDNA4: 160 KB per CU), one block per CU over all tiles
+    // the wave-tile form needs 139 KB of LDS per block; it runs where the
+    // device allows it (CDNA4: 160 KB per CU), one block per CU over all tiles
     static int staged = -1, n_blocks = 0;
     if (staged < 0) {
         int dev = 0, lds = 0, cus = 0;
@@ -725,18 +848,19 @@ hipError_t sg_query(hipStream_t s, const float *x, long n, const float *mu, cons
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-            (size_t)lds >= kQueryLds &&
-            hipFuncSetAttribute((const void *)mlp_query_staged, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)kQueryLds) == hipSuccess) {
+            (size_t)lds >= kWaveQueryLds &&
+            hipFuncSetAttribute((const void *)mlp_query_waves, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)kWaveQueryLds) == hipSuccess) {
             staged = 1;
             n_blocks = cus;
         }
     }
     if (staged == 1 && n >= 32L * 1024) {
         const long n_tiles = (n + 31) / 32;
-        const unsigned grid = (unsigned)(n_tiles < n_blocks ? n_tiles : n_blocks);
-        hipLaunchKernelGGL(mlp_query_staged, dim3(grid), dim3(256), kQueryLds, s, x, n, mu, sigma, W1b, b1, W2b,
-                           b2, W3b, b3, planes, n_planes, hull_tol, threshold, margin, p_out, use);
+        const long want = (n_tiles + kQueryWaves - 1) / kQueryWaves;
+        const unsigned grid = (unsigned)(want < n_blocks ? want : n_blocks);
+        hipLaunchKernelGGL(mlp_query_waves, dim3(grid), dim3(64 * kQueryWaves), kWaveQueryLds, s, x, n, mu, sigma,
+                           W1b, b1, W2b, b2, W3b, b3, planes, n_planes, hull_tol, threshold, margin, p_out, use);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(mlp_query, dim3(blocks_for(n, 32)), dim3(256), 0, s, x, n, mu, sigma, W1b, b1, W2b, b2,

@@ -291,6 +291,34 @@ def test_fixed_batch_matches_oracle(ctx, waves_per_cu):
             assert (r["n"], r["successes"], r["events"]) == (o["n"], o["successes"], o["events"]), (m, mid)
 
 
+@pytest.mark.parametrize("kind", ["generic", "specialized"])
+def test_many_more_fixed_jobs_than_waves(ctx, kind):
+    """A fixed-size launch of 20000 jobs of 64 trajectories on 256 waves (one
+    per CU): most jobs lie far from every wave's home, and each must still be
+    run in full (a wave scans every job before it leaves); sampled jobs give
+    the oracle's counts."""
+    B = _B()
+    net = W.isomerization()
+    text = "G[0,1](A>=22)"
+    nh = ctx.network(net)
+    fh = ctx.formula(nh, text)
+    jobs = [(nh, fh, B.params(fixed_n=64, seed=7, model_id=k)) for k in range(20000)]
+    ctx.set_waves_per_cu(1)
+    ctx.set_specialization(B.SPECIALIZE_OFF if kind == "generic" else B.SPECIALIZE_REQUIRED)
+    try:
+        print(f"case many fixed jobs {kind}", flush=True)
+        res = ctx.estimate_batch(jobs)
+    finally:
+        ctx.set_waves_per_cu(0)
+        ctx.set_specialization(B.SPECIALIZE_AUTO)
+    assert all(r["n"] == 64 for r in res)
+    rng = np.random.default_rng(3)
+    for k in rng.choice(20000, size=40, replace=False):
+        o = oracle.estimate(net, text, fixed_n=64, seed=7, model_id=int(k))
+        r = res[int(k)]
+        assert (r["successes"], r["events"]) == (o["successes"], o["events"]), k
+
+
 @SPECULATE
 def test_fig3_bernoulli_sources(ctx, speculate):
     """Fig. 3's setting (99%, +-0.025) on Bernoulli sources of known p: the
