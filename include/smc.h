@@ -311,7 +311,9 @@ int smc_estimate_batch(smc_ctx *ctx, const smc_job *jobs, size_t n_jobs, smc_res
  * trajectories take as long either way), so pilot_widen = 1 (the batch as it
  * will run) is the faithful choice.  Candidates: 1, 2, 4, 8 and 16 lanes
  * (when the batch has automatic jobs of more than four channels; upwards until
- * a pilot takes 15 % longer than the best so far) at 16 waves per compute
+ * a pilot takes 15 % longer than the best so far; a request that gives the
+ * launch the same group size as the previous one, because the widest network
+ * needs more lanes, is not timed again) at 16 waves per compute
  * unit, then 8 and 32 waves per compute unit at the best lanes; the shortest
  * device time wins.  The choice
  * is recorded on the context for the batch's signature (the structures of its
@@ -323,7 +325,8 @@ int smc_estimate_batch(smc_ctx *ctx, const smc_job *jobs, size_t n_jobs, smc_res
  * SMC_TREE_SUMS: the same in distribution).  Errors: SMC_E_INVALID, and those
  * of smc_estimate_batch. */
 typedef struct {
-    int32_t lanes;           /* lanes per trajectory for the automatic wide jobs */
+    int32_t lanes;           /* lanes per trajectory for the automatic wide jobs
+                                (the launch's group size: 1, 2, 4, 8 or 16)    */
     int32_t waves_per_cu;    /* launch shape                                      */
     int32_t candidates;      /* configurations timed                              */
     int32_t pad_;

@@ -922,14 +922,23 @@ int smc_autotune_batch(smc_ctx *c, const smc_job *jobs, size_t n_jobs, double pi
     // coordinate search: lanes per trajectory at 16 waves per CU (upwards
     // until a pilot takes 15 % longer than the best so far), then the waves
     // per CU at the best lanes
+    int last_group = 0;
     for (int L : {1, 2, 4, 8, 16}) {
         if (L > 1 && !wide) break;
+        // the group size a launch would run with this request (the widest
+        // automatic job raises it): a request that gives the same group as
+        // the previous one runs the same launch
+        int group = 1;
+        for (size_t k = 0; k < n_jobs; ++k)
+            if (P[k].auto_lanes && !P[k].job.trace) group = std::max(group, lanes_for(L, P[k].M));
+        if (group == last_group) continue;
+        last_group = group;
         if (const int rc = pilot(L, 16, &t)) return rc;
         ++tried;
         if (L == 1) best.default_seconds = t;
         if (t < best.seconds) {
             best.seconds = t;
-            best.lanes = L;
+            best.lanes = group;   // the group the request gave
         } else if (t > 1.15 * best.seconds) {
             break;
         }

@@ -422,123 +422,10 @@ __global__ __launch_bounds__(256) void mlp_query(const float *x, long n, const f
     }
 }
 
-// ---------------------------------------------------------------------------
-// Inference + gate, persistent form for GPUs with 160 KB of LDS per CU: each
-// block stages W2 (bfloat16, 128 KB) in LDS once and then streams tiles of 32
-// points, so W2 is read from L2 once per block instead of once per tile.
-// Layer 1 into LDS as bfloat16; layer 2 on MFMA (wave w owns output columns
-// 64 w .. 64 w + 63, two 32 x 32 tiles); layer 3 reduced in registers: each
-// lane adds its two columns' products, the 32 lanes sharing a row group sum
-// with shuffles, and the four waves' partial sums are added in wave order.
-// Same gate as mlp_query.
-// ---------------------------------------------------------------------------
-// LDS rows (a column of W2, a row of h1) are padded by 8 bfloat16 values, so
-// that the 16-byte operand reads of the 32 lanes of a half-wave (one row each)
-// start on different banks instead of all on the same one.
+// LDS rows (a column of W2) are padded by 8 bfloat16 values, so that the
+// 16-byte operand reads of the 32 lanes of a half-wave (one row each) start
+// on different banks instead of all on the same one.
 constexpr int kQRow = kH + 8;
-constexpr size_t kQueryLds = (size_t)kH * kQRow * 2 + 32 * kQRow * 2 + 4 * 32 * 4 + 2 * 96 * 4 + 32 * 4;
-
-__global__ __launch_bounds__(256) void mlp_query_staged(const float *x, long n, const float *mu,
-                                                        const float *sigma, const uint16_t *W1b,
-                                                        const float *b1, const uint16_t *W2b,
-                                                        const float *b2, const uint16_t *W3b,
-                                                        const float *b3, const float *planes,
-                                                        int n_planes, float hull_tol, float threshold,
-                                                        float margin, float *p_out, uint8_t *use)
-{
-    extern __shared__ uint16_t qsm[];
-    uint16_t *W2s = qsm;                                  // [col][k] (row stride kQRow), as W2b
-    uint16_t *h1s = W2s + kH * kQRow;                     // [row][k] (row stride kQRow)
-    float *zpart = reinterpret_cast<float *>(h1s + 32 * kH);   // [wave][row]
-    float *xs = zpart + 4 * 32;                           // [row][3], as given
-    float *xn = xs + 96;                                  // [row][3], normalised, bfloat16-rounded
-    int *inside_s = reinterpret_cast<int *>(xn + 96);     // [row]
-    const int tid = (int)threadIdx.x;
-    {
-        const uint4 *src = reinterpret_cast<const uint4 *>(W2b);
-        uint4 *dst = reinterpret_cast<uint4 *>(W2s);
-        for (int i = tid; i < kH * kH / 8; i += 256) dst[(i / (kH / 8)) * (kQRow / 8) + i % (kH / 8)] = src[i];
-    }
-    const int lane = tid & 63, wave = tid >> 6;
-    const int rc = lane & 31, half = lane >> 5;
-    const float w0 = from_bf16(W1b[tid * 3]), w1 = from_bf16(W1b[tid * 3 + 1]), w2 = from_bf16(W1b[tid * 3 + 2]);
-    const float bj = b1[tid];
-    float b2c[2], w3c[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const int col = wave * 64 + t * 32 + rc;
-        b2c[t] = b2[col];
-        w3c[t] = from_bf16(W3b[col]);
-    }
-    const float bias3 = b3[0];
-    const long n_tiles = (n + 31) / 32;
-    for (long tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const long base = tile * 32;
-        __syncthreads();   // W2s staged; the previous tile's h1s, zpart and xs are consumed
-        if (tid < 96) {
-            const long row = base + tid / 3;
-            const int c = tid % 3;
-            const float v = row < n ? x[row * 3 + c] : 0.0f;
-            xs[tid] = v;
-            xn[tid] = from_bf16(to_bf16((v - mu[c]) / sigma[c]));
-        }
-        if (tid < 32) inside_s[tid] = 1;
-        __syncthreads();
-        for (int r = 0; r < 32; ++r) {
-            float acc = bj;
-            acc = fmaf(xn[r * 3 + 0], w0, acc);
-            acc = fmaf(xn[r * 3 + 1], w1, acc);
-            acc = fmaf(xn[r * 3 + 2], w2, acc);
-            h1s[r * kQRow + tid] = to_bf16(acc > 0.0f ? acc : 0.0f);
-        }
-        if (use) hull_test(xs, planes, n_planes, hull_tol, inside_s);
-        __syncthreads();
-        // the wave's two 32-column groups share each A operand read; their
-        // accumulators are independent, so the MFMAs overlap
-        floatx16 acc0 = {}, acc1 = {};
-        {
-            const uint16_t *arow = h1s + rc * kQRow + 8 * half;
-            const uint16_t *b0row = W2s + (wave * 64 + rc) * kQRow + 8 * half;
-            const uint16_t *b1row = b0row + 32 * kQRow;
-#pragma unroll 4
-            for (int kb = 0; kb < kH; kb += 16) {
-                const bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(arow + kb));
-                const bf16x8 b0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(b0row + kb));
-                const bf16x8 b1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(b1row + kb));
-                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
-            }
-        }
-        float part[16];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const float v0 = acc0[r] + b2c[0], v1 = acc1[r] + b2c[1];
-            part[r] = from_bf16(to_bf16(v0 > 0.0f ? v0 : 0.0f)) * w3c[0];
-            part[r] += from_bf16(to_bf16(v1 > 0.0f ? v1 : 0.0f)) * w3c[1];
-        }
-        // sum over the 32 columns of the lane's half: rows 8 (r / 4) + 4 half + r % 4
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            float v = part[r];
-#pragma unroll
-            for (int off = 16; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-            if (rc == 0) zpart[wave * 32 + 8 * (r / 4) + 4 * half + (r % 4)] = v;
-        }
-        __syncthreads();
-        if (tid < 32) {
-            const long row = base + tid;
-            const float z = bias3 + (((zpart[tid] + zpart[32 + tid]) + zpart[64 + tid]) + zpart[96 + tid]);
-            const float p = 1.0f / (1.0f + expf(-z));
-            if (row < n) {
-                p_out[row] = p;
-                if (use) {
-                    const bool inside = n_planes > 0 && inside_s[tid] != 0;
-                    use[row] = (inside && fabsf(p - threshold) >= margin) ? 1 : 0;
-                }
-            }
-        }
-    }
-}
 
 // ---------------------------------------------------------------------------
 // Inference + gate, one tile of 32 points per wave: each block (eight waves,
@@ -555,17 +442,30 @@ __global__ __launch_bounds__(256) void mlp_query_staged(const float *x, long n, 
 //  - the hull test spread over the two lanes of each point.
 // Same numeric contract and gate as the other query kernels.
 // ---------------------------------------------------------------------------
+// f rounded to bfloat16 (nearest, ties to even) and back, by the hardware
+// conversion (the same value as to_bf16 for finite f).
+__device__ __forceinline__ float rne_bf16(float f) { return (float)(__bf16)f; }
+
+// A lane's value moved across its 16-lane row by the DPP control ctrl.
+template <int ctrl>
+__device__ __forceinline__ float dpp_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, false));
+}
+
 constexpr int kQueryWaves = 8;
 constexpr size_t kWaveQueryLds = (size_t)kH * kQRow * 2 + (size_t)kH * 4 * sizeof(float);
+constexpr int kLdsPlanes = 1280;   // hull facets staged in LDS (a hull of n points has at most 2n - 4)
 
 __global__ __launch_bounds__(64 * kQueryWaves) void mlp_query_waves(
     const float *x, long n, const float *mu, const float *sigma, const uint16_t *W1b, const float *b1,
     const uint16_t *W2b, const float *b2, const uint16_t *W3b, const float *b3, const float *planes, int n_planes,
-    float hull_tol, float threshold, float margin, float *p_out, uint8_t *use)
+    int n_lds_planes, float hull_tol, float threshold, float margin, float *p_out, uint8_t *use)
 {
     extern __shared__ uint16_t qsm[];
     uint16_t *W2s = qsm;                                                // [col][k] (row stride kQRow)
     float4 *W1s = reinterpret_cast<float4 *>(W2s + kH * kQRow);         // [unit] = (w0, w1, w2, b1)
+    float4 *Ps = W1s + kH;                                              // facets 0 .. n_lds_planes - 1
     const int tid = (int)threadIdx.x;
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(W2b);
@@ -575,6 +475,8 @@ __global__ __launch_bounds__(64 * kQueryWaves) void mlp_query_waves(
         if (tid < kH)
             W1s[tid] = make_float4(from_bf16(W1b[tid * 3]), from_bf16(W1b[tid * 3 + 1]), from_bf16(W1b[tid * 3 + 2]),
                                    b1[tid]);
+        for (int f = tid; f < n_lds_planes; f += 64 * kQueryWaves)
+            Ps[f] = make_float4(planes[4 * f], planes[4 * f + 1], planes[4 * f + 2], planes[4 * f + 3]);
     }
     __syncthreads();
     const int lane = tid & 63, wave = tid >> 6;
@@ -583,17 +485,26 @@ __global__ __launch_bounds__(64 * kQueryWaves) void mlp_query_waves(
     const float mu0 = mu[0], mu1 = mu[1], mu2 = mu[2], sg0 = sigma[0], sg1 = sigma[1], sg2 = sigma[2];
     const long n_tiles = (n + 31) / 32;
     const long stride = (long)gridDim.x * kQueryWaves;
-    for (long tile = (long)blockIdx.x * kQueryWaves + wave; tile < n_tiles; tile += stride) {
+    // this lane's point of the wave's next tile, loaded one tile ahead
+    long tile = (long)blockIdx.x * kQueryWaves + wave;
+    float y0 = 0.0f, y1 = 0.0f, y2 = 0.0f;
+    if (tile * 32 + rc < n) {
+        y0 = x[(tile * 32 + rc) * 3];
+        y1 = x[(tile * 32 + rc) * 3 + 1];
+        y2 = x[(tile * 32 + rc) * 3 + 2];
+    }
+    for (; tile < n_tiles; tile += stride) {
         const long row = tile * 32 + rc;   // this lane's point (both halves hold it)
-        float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
-        if (row < n) {
-            x0 = x[row * 3];
-            x1 = x[row * 3 + 1];
-            x2 = x[row * 3 + 2];
+        const float x0 = y0, x1 = y1, x2 = y2;
+        const long nrow = (tile + stride) * 32 + rc;
+        if (nrow < n) {
+            y0 = x[nrow * 3];
+            y1 = x[nrow * 3 + 1];
+            y2 = x[nrow * 3 + 2];
         }
-        const float n0 = from_bf16(to_bf16((x0 - mu0) / sg0));
-        const float n1 = from_bf16(to_bf16((x1 - mu1) / sg1));
-        const float n2 = from_bf16(to_bf16((x2 - mu2) / sg2));
+        const float n0 = rne_bf16((x0 - mu0) / sg0);
+        const float n1 = rne_bf16((x1 - mu1) / sg1);
+        const float n2 = rne_bf16((x2 - mu2) / sg2);
         // layers 1 and 2, step by step along k: the step's A operand (layer 1
         // for the 8 hidden units this lane holds) feeds the eight 32-column
         // groups' accumulators
@@ -610,7 +521,7 @@ __global__ __launch_bounds__(64 * kQueryWaves) void mlp_query_waves(
                 h = fmaf(n0, w.x, h);
                 h = fmaf(n1, w.y, h);
                 h = fmaf(n2, w.z, h);
-                a[e] = __builtin_bit_cast(__bf16, to_bf16(h > 0.0f ? h : 0.0f));
+                a[e] = (__bf16)(h > 0.0f ? h : 0.0f);   // v_cvt_pk_bf16_f32: round to nearest even
             }
             const uint16_t *bcol = W2s + rc * kQRow + 8 * half + 16 * s;
 #pragma unroll
@@ -629,15 +540,21 @@ __global__ __launch_bounds__(64 * kQueryWaves) void mlp_query_waves(
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const float v = acc[g][r] + bg;
-                zr[r] += from_bf16(to_bf16(v > 0.0f ? v : 0.0f)) * wg;
+                zr[r] += rne_bf16(v > 0.0f ? v : 0.0f) * wg;
             }
         }
         // sum over the 32 columns of each half: then every lane of half h
-        // holds the sums of rows 8 (r / 4) + 4 h + r % 4
+        // holds the sums of rows 8 (r / 4) + 4 h + r % 4.  Within each 16-lane
+        // row by DPP moves (swap neighbours, swap pairs, mirror the 8-lane
+        // halves, mirror the row), then across the two rows of the half.
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-#pragma unroll
-            for (int off = 16; off >= 1; off >>= 1) zr[r] += __shfl_xor(zr[r], off, 64);
+            float v = zr[r];
+            v += dpp_f32<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+            v += dpp_f32<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+            v += dpp_f32<0x141>(v);   // row_half_mirror
+            v += dpp_f32<0x140>(v);   // row_mirror
+            zr[r] = v + __shfl_xor(v, 16, 64);
         }
         // row rc's sum is held by the half whose rows include it
         const int idx = 4 * (rc >> 3) + (rc & 3);
@@ -645,12 +562,22 @@ __global__ __launch_bounds__(64 * kQueryWaves) void mlp_query_waves(
 #pragma unroll
         for (int r = 1; r < 16; ++r) mine = idx == r ? zr[r] : mine;
         const float z = bias3 + __shfl(mine, ((rc >> 2) & 1) * 32 + rc, 64);
-        // hull: the two lanes of a point take alternate facets
+        // hull: the two lanes of a point take alternate facets (from LDS, the
+        // lanes of a half reading one facet at a time), without early exit
         bool ok = true;
-        for (int f = half; f < n_planes && ok; f += 2) {
-            const float *pl = planes + 4 * f;
-            const float v = pl[0] * x0 + pl[1] * x1 + pl[2] * x2;
-            ok = v <= pl[3] + hull_tol;
+        {
+            int f = half;
+#pragma unroll 4
+            for (; f < n_lds_planes; f += 2) {
+                const float4 pl = Ps[f];
+                const float v = pl.x * x0 + pl.y * x1 + pl.z * x2;
+                ok = ok && (v <= pl.w + hull_tol);
+            }
+            for (; f < n_planes; f += 2) {
+                const float *pl = planes + 4 * f;
+                const float v = pl[0] * x0 + pl[1] * x1 + pl[2] * x2;
+                ok = ok && (v <= pl[3] + hull_tol);
+            }
         }
         // (the shuffle runs on every lane: the partner's value must be written)
         const int other = __shfl(ok ? 1 : 0, lane ^ 32, 64);
@@ -841,7 +768,7 @@ hipError_t sg_query(hipStream_t s, const float *x, long n, const float *mu, cons
 {
     // the wave-tile form needs 139 KB of LDS per block; it runs where the
     // device allows it (CDNA4: 160 KB per CU), one block per CU over all tiles
-    static int staged = -1, n_blocks = 0;
+    static int staged = -1, n_blocks = 0, max_lds = 0;
     if (staged < 0) {
         int dev = 0, lds = 0, cus = 0;
         staged = 0;
@@ -849,18 +776,26 @@ hipError_t sg_query(hipStream_t s, const float *x, long n, const float *mu, cons
             hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
             (size_t)lds >= kWaveQueryLds &&
-            hipFuncSetAttribute((const void *)mlp_query_waves, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)kWaveQueryLds) == hipSuccess) {
+            hipFuncSetAttribute((const void *)mlp_query_waves, hipFuncAttributeMaxDynamicSharedMemorySize, lds) ==
+                hipSuccess) {
             staged = 1;
             n_blocks = cus;
+            max_lds = lds;
         }
     }
     if (staged == 1 && n >= 32L * 1024) {
         const long n_tiles = (n + 31) / 32;
         const long want = (n_tiles + kQueryWaves - 1) / kQueryWaves;
         const unsigned grid = (unsigned)(want < n_blocks ? want : n_blocks);
-        hipLaunchKernelGGL(mlp_query_waves, dim3(grid), dim3(64 * kQueryWaves), kWaveQueryLds, s, x, n, mu, sigma,
-                           W1b, b1, W2b, b2, W3b, b3, planes, n_planes, hull_tol, threshold, margin, p_out, use);
+        // the facets that fit the block's LDS are staged there (the rest are
+        // read from memory)
+        int lds_planes = n_planes < kLdsPlanes ? n_planes : kLdsPlanes;
+        const int room = (int)(((size_t)max_lds - kWaveQueryLds) / 16);
+        if (lds_planes > room) lds_planes = room;
+        const size_t lds = kWaveQueryLds + (size_t)lds_planes * 16;
+        hipLaunchKernelGGL(mlp_query_waves, dim3(grid), dim3(64 * kQueryWaves), lds, s, x, n, mu, sigma,
+                           W1b, b1, W2b, b2, W3b, b3, planes, n_planes, lds_planes, hull_tol, threshold, margin,
+                           p_out, use);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(mlp_query, dim3(blocks_for(n, 32)), dim3(256), 0, s, x, n, mu, sigma, W1b, b1, W2b, b2,

@@ -226,6 +226,24 @@ def test_c2_full_size_fixed(ctx):
     assert r["p_hat"] == 0.0 and r["lo"] == 0.0 and abs(r["hi"] - 1.0827e-5) < 1e-8
 
 
+def test_c2_full_size_sampled_trajectories(ctx):
+    """Configuration 2 at its full size in the launch bench.py times (the
+    autotuned configuration): 10^6 trajectories recorded on the device, 3000
+    of them, sampled, equal the oracle's trajectory for that index."""
+    B = _B()
+    net = W.michaelis_menten()
+    n = ctx.network(net)
+    f = ctx.formula(n, W.C2_FORMULA)
+    p = B.params(fixed_n=10**6, seed=1)
+    ctx.autotune(n, f, p)
+    ev, vd, rs = ctx.trajectories(n, f, p, 0, 10**6)
+    text = oracle.parse(W.C2_FORMULA, net)
+    rng = np.random.default_rng(11)
+    for i in rng.choice(10**6, size=3000, replace=False):
+        oev, ovd, ors = oracle.trajectories(net, text, int(i), 1, seed=1, model_id=0)
+        assert (ev[i], vd[i], rs[i]) == (oev[0], ovd[0], ors[0]), i
+
+
 @SPECULATE
 def test_batch_matches_single_jobs(ctx, speculate):
     B = _B()
@@ -819,7 +837,9 @@ def test_autotune_batch_keeps_the_estimates(ctx):
     tune = ctx.autotune_batch(jobs, pilot_widen=2.0)
     print(f"  {tune}", flush=True)
     assert tune["lanes"] in (1, 2, 4, 8, 16) and tune["waves_per_cu"] in (8, 16, 32)
-    assert 3 <= tune["candidates"] <= 7 and 0.0 < tune["seconds"] <= tune["default_seconds"]
+    # the widest sweep network needs 8 lanes: requests of 2 and 4 run as 8 and are not timed
+    assert 3 <= tune["candidates"] <= 5 and 0.0 < tune["seconds"] <= tune["default_seconds"]
+    assert tune["lanes"] in (1, 8, 16)
     assert ctx.autotune_batch(jobs, pilot_widen=2.0) == tune
     res = ctx.estimate_batch(jobs)
     expect = B.KERNEL_GENERIC if tune["lanes"] == 1 else B.KERNEL_GENERIC_GROUPED
