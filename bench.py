@@ -12,7 +12,9 @@ and the iterative-Wilson immigration-death run (95%, +-0.01).
 
 The surrogate section answers 10^6 Michaelis-Menten rate points (both the
 workload formula and F[0,60](P>=575)) with surrogate + fallback and reports
-the time against plain batched SMC at 95% +-0.01.
+the time against plain batched SMC at 95% +-0.01.  Further sections time a
+formula run as a trace program beside a compact one, and the SSA variants
+for wide networks (lane groups with sums in channel order or in a tree).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-surrogate]
        python bench.py --copy-calibration   (HBM counter calibration copy)
@@ -234,6 +236,57 @@ def batched_sweep_run(ctx, B, W):
                          "p_hat_in_0.2_0.8": sum(1 for r in nets if 0.2 <= r["p_hat"] <= 0.8)}}
 
 
+TRACE_FORMULA = "F[0,60]((S<=300) & F[1,5](P>=600))"
+
+
+def trace_program_run(ctx, B, W, n=100_000, cap=5_000):
+    """A formula outside the compact monitors (an F with a window not starting
+    at 0 inside an F), run as a trace program on the Michaelis-Menten network,
+    beside a compact formula of similar trajectory length (the companion F
+    formula) on the same network: events/s of each, fixed N."""
+    import torch
+    net = W.michaelis_menten()
+    nh = ctx.network(net)
+    out = {"workload": f"Michaelis-Menten, {n} trajectories, cap {cap}"}
+    for key, text in (("trace", TRACE_FORMULA), ("compact", W.MM_COMPANION_FORMULA)):
+        fh = ctx.formula(nh, text)
+        p = B.params(fixed_n=n, seed=1, max_events=cap)
+        ctx.estimate(nh, fh, B.params(fixed_n=256, seed=2, max_events=cap))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ctx.estimate(nh, fh, p)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[key] = {"formula": text, "kernel": ctx.last_kernel(), "seconds": wall,
+                    "device_seconds": r["device_seconds"], "events": r["events"],
+                    "events_per_s": r["events"] / wall, "p_hat": r["p_hat"], "truncated": r["truncated"]}
+    return out
+
+
+def tree_sums_run(ctx, B, W, n=100_000, lanes=8):
+    """The random-network workload (S = 64, M = 256, 10^5 trajectories) under
+    the SSA variants for wide networks: lane groups with sums in channel order
+    (bit-identical to one lane) and with tree-ordered sums (SMC_TREE_SUMS),
+    beside the one-lane specialised kernel."""
+    import torch
+    net = W.c3_network()
+    nh = ctx.network(net)
+    fh = ctx.formula(nh, W.c3_formula(net))
+    out = {"workload": f"random network S=64 M=256, {n} trajectories, {lanes} lanes per trajectory"}
+    for key, kw in (("one_lane_specialised", {}), ("group_channel_order", {"lanes": lanes}),
+                    ("group_tree_sums", {"lanes": lanes, "tree_sums": True})):
+        p = B.params(fixed_n=n, seed=1, max_events=W.C3_CAP, **kw)
+        ctx.estimate(nh, fh, B.params(fixed_n=256, seed=2, max_events=W.C3_CAP, **kw))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ctx.estimate(nh, fh, p)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[key] = {"kernel": ctx.last_kernel(), "seconds": wall, "events": r["events"],
+                    "events_per_s": r["events"] / wall, "p_hat": r["p_hat"], "successes": r["successes"]}
+    return out
+
+
 def fig3_sample_sizes(ctx, B, W, reps=32, eps=0.025, confidence=0.99):
     """Sample sizes of Fig. 3: for p = 0, 0.1, ..., 1, a one-molecule death
     process (rate 1) under F[0,T](X<=0) with T = -ln(1 - p) is a Bernoulli
@@ -389,7 +442,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-c1", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--no-large", action="store_true", help="skip the random-network and batched-sweep runs")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the random-network, batched-sweep, trace-program and wide-network runs")
     ap.add_argument("--no-c3", action="store_true", help="skip the random-network run")
     ap.add_argument("--no-c4", action="store_true", help="skip the batched-sweep run")
     ap.add_argument("--no-autotune", action="store_true", help="skip smc_autotune of the C2 launch")
@@ -526,6 +580,11 @@ def main():
     if not args.no_large and not args.no_c4:
         line["c4_batched_sweep"] = batched_sweep_run(ctx, B, W)
         progress("C4 batched sweep")
+    if not args.no_large:
+        line["trace_program"] = trace_program_run(ctx, B, W)
+        progress("trace program")
+        line["wide_network_variants"] = tree_sums_run(ctx, B, W)
+        progress("SSA variants for wide networks")
     if not args.no_surrogate:
         line["surrogate_vs_plain"] = []
         for t in (W.C2_FORMULA, W.MM_COMPANION_FORMULA):

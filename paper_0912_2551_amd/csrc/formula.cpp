@@ -484,19 +484,19 @@ class Compiler {
         case Node::FIN: {
             const int tt = trace_push(TN_TT, -1, -1, -1, 0.0, 0.0);
             const int b = trace_node(n->a.get());
-            return trace_push(TN_UNTIL, -1, tt, b, n->lo, n->hi);
+            return trace_push(TN_UNTIL, p_.tr_nskip++, tt, b, n->lo, n->hi);
         }
         case Node::GLOB: {
             const int tt = trace_push(TN_TT, -1, -1, -1, 0.0, 0.0);
             const int c = trace_node(n->a.get());
             const int nc = trace_push(TN_NOT, -1, c, -1, 0.0, 0.0);
-            const int u = trace_push(TN_UNTIL, -1, tt, nc, n->lo, n->hi);
+            const int u = trace_push(TN_UNTIL, p_.tr_nskip++, tt, nc, n->lo, n->hi);
             return trace_push(TN_NOT, -1, u, -1, 0.0, 0.0);
         }
         default: {
             const int a = trace_node(n->a.get());
             const int b = trace_node(n->b.get());
-            return trace_push(TN_UNTIL, -1, a, b, n->lo, n->hi);
+            return trace_push(TN_UNTIL, p_.tr_nskip++, a, b, n->lo, n->hi);
         }
         }
     }

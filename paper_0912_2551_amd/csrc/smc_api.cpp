@@ -438,7 +438,7 @@ int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult 
                 if (P[k].auto_lanes) P[k].job.lanes = lanes_for(it->second.lanes, P[k].M);
         }
     }
-    int s_max = 1, m_max = 1, n_iter = 0, group = 1, n_trace = 0, tr_nodes = 0;
+    int s_max = 1, m_max = 1, n_iter = 0, group = 1, n_trace = 0, tr_nodes = 0, tr_nskip = 0;
     uint32_t tr_cap = 0;
     Job *jobs = W.h_jobs;   // the previous call's copies have completed
     for (int k = 0; k < n; ++k) {
@@ -452,37 +452,41 @@ int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult 
             ++n_trace;
             tr_cap = std::max(tr_cap, jobs[k].max_events + 1u);
             tr_nodes = std::max(tr_nodes, (int)P[k].f->prog.tr_n);
+            tr_nskip = std::max(tr_nskip, (int)P[k].f->prog.tr_nskip);
         }
     }
     const size_t lds_wave = (size_t)(s_max + 1) * kWave * sizeof(int32_t);   // + the constant-1 row
     int wpb = (int)std::min<size_t>(4, std::max<size_t>(1, 65536 / lds_wave));
     if (lds_wave > 65536) return fail(ctx, SMC_E_INVALID, "network too large for one wave's LDS");
-    // Trace programs: one record area per lane of the launch, within a budget
+    // Trace programs: one record area per wave of the launch, within a budget
     // of device memory, which bounds the launch's waves; every job of such a
     // launch runs one lane per trajectory (on the trace-capable kernel).
-    unsigned long long tr_slots = 0;
+    unsigned long long tr_slots = 0;   // lanes with a record area
     if (n_trace > 0) {
         if (W.no_alloc)
             return fail(ctx, SMC_E_UNSUPPORTED, "trace programs need record areas, which an allocation-free call "
                                                 "does not allocate");
-        const unsigned long long stride = TraceArea::bytes(tr_cap, tr_nodes);
+        const unsigned long long stride = TraceArea::bytes(tr_cap, tr_nodes, tr_nskip);   // one wave
         const unsigned long long per_block = (unsigned long long)kWave * wpb;
         // no more lanes than the device holds, than the trajectories need, or
         // than the budget allows
         unsigned long long want = 0;
         for (int k = 0; k < n; ++k) want += P[k].capacity;
         want = (want + per_block - 1) / per_block * per_block;
-        tr_slots = std::min<unsigned long long>((unsigned long long)ctx->n_cu * 32ull * kWave, kTraceBudget / stride);
+        tr_slots = std::min<unsigned long long>((unsigned long long)ctx->n_cu * 32ull * kWave,
+                                                kTraceBudget / stride * kWave);
         tr_slots -= tr_slots % per_block;
         tr_slots = std::min(tr_slots, want);
         if (tr_slots == 0)
             return fail(ctx, SMC_E_NOMEM, "the record areas of one block of trace lanes exceed the 8 GiB budget "
                                           "(lower max_events)");
-        if (ensure(ctx, ctx->d_trace, ctx->cap_trace, (size_t)(tr_slots * stride))) return SMC_E_NOMEM;
+        if (ensure(ctx, ctx->d_trace, ctx->cap_trace, (size_t)(tr_slots / kWave * stride))) return SMC_E_NOMEM;
         for (int k = 0; k < n; ++k) {
             jobs[k].tr_base = ctx->d_trace;
             jobs[k].tr_stride = stride;
             jobs[k].tr_cap = tr_cap;
+            jobs[k].tr_nodes = (uint32_t)tr_nodes;
+            jobs[k].tr_nskip = (uint32_t)tr_nskip;
             jobs[k].lanes = 1;
             P[k].job.lanes = 1;
         }

@@ -98,8 +98,8 @@ struct Atom {
 
 // A node of a trace program: the formula itself as a tree (F I p written as
 // tt U I p, G I p as not(tt U I not p), Sec. 3.1), children before parents,
-// the root last.  pred: predicate id of TN_PRED; a, b: operands; [lo, hi]:
-// the interval of TN_NEXT and TN_UNTIL.
+// the root last.  pred: predicate id of TN_PRED, skip slot of TN_UNTIL; a, b:
+// operands; [lo, hi]: the interval of TN_NEXT and TN_UNTIL.
 struct TraceNode {
     int32_t kind, pred, a, b;
     double lo, hi;
@@ -122,7 +122,8 @@ struct MonProg {
     int32_t vvar[kMaxValOps];
     double vconst[kMaxValOps];
     double horizon;
-    int32_t trace, tr_n;
+    int32_t trace, tr_n, tr_nskip;   // tr_nskip: until nodes (TraceNode.pred is their skip slot)
+    int32_t tr_pad;
     TraceNode tnodes[kMaxTrace];
 };
 
@@ -154,20 +155,31 @@ struct NetDev {
     const ChanDev *chan;   // Mp entries
 };
 
-// The record area of one lane for a trace program of `cap` states and `n`
-// nodes (each part 256-byte aligned):
+// The record area of one wave for a trace program of `cap` states, `n` nodes
+// and `ns` until nodes, each part 256-byte aligned and interleaved over the
+// wave's 64 lanes (element e of lane l at index 64 e + l), so that lanes
+// reading the same position read adjacent words:
 //   double   t[cap + 1]        entry times; t[m + 1] is also the time state m is left
 //   uint32_t bits[cap]         predicate bits of each state (bit q: predicate q)
 //   int32_t  need[kMaxTrace]   how many positions each node is evaluated at
+//   int32_t  skip[ns][cap + 1] per until node: the next position that is not
+//                              neutral (left operand true, right one false)
 //   uint8_t  val[n][cap]       three-valued node values by position
 struct TraceArea {
     static constexpr unsigned long long align(unsigned long long x) { return (x + 255ull) & ~255ull; }
-    static constexpr unsigned long long bits_off(uint32_t cap) { return align(8ull * (cap + 1ull)); }
-    static constexpr unsigned long long need_off(uint32_t cap) { return bits_off(cap) + align(4ull * cap); }
-    static constexpr unsigned long long val_off(uint32_t cap) { return need_off(cap) + align(4ull * kMaxTrace); }
-    static constexpr unsigned long long bytes(uint32_t cap, int n)
+    static constexpr unsigned long long bits_off(uint32_t cap) { return align(8ull * 64ull * (cap + 1ull)); }
+    static constexpr unsigned long long need_off(uint32_t cap) { return bits_off(cap) + align(4ull * 64ull * cap); }
+    static constexpr unsigned long long skip_off(uint32_t cap)
     {
-        return val_off(cap) + align((unsigned long long)n * cap);
+        return need_off(cap) + align(4ull * 64ull * kMaxTrace);
+    }
+    static constexpr unsigned long long val_off(uint32_t cap, int ns)
+    {
+        return skip_off(cap) + align(4ull * 64ull * (unsigned long long)ns * (cap + 1ull));
+    }
+    static constexpr unsigned long long bytes(uint32_t cap, int n, int ns)   // one wave
+    {
+        return val_off(cap, ns) + align(64ull * (unsigned long long)n * cap);
     }
 };
 
@@ -220,11 +232,14 @@ struct Job {
     JobState *st;
     uint32_t *rec_events;         // optional per-index outputs (relative index)
     uint8_t *rec_vr;
-    // trace programs: one record area per lane of the launch (lane l at
-    // tr_base + l * tr_stride) for states 0 .. tr_cap - 1, see TraceArea
+    // trace programs: one record area per wave of the launch (wave w at
+    // tr_base + w * tr_stride) for states 0 .. tr_cap - 1 of up to tr_nodes
+    // nodes and tr_nskip until nodes, see TraceArea
     unsigned char *tr_base;
     unsigned long long tr_stride;
     uint32_t tr_cap;
+    uint32_t tr_nodes;
+    uint32_t tr_nskip;
     uint32_t tr_pad;
 };
 

@@ -253,9 +253,10 @@ struct JobView {
     int trace;    // the formula is a trace program
     uint32_t *rec_events;   // optional per-index outputs
     uint8_t *rec_vr;
-    unsigned char *tr_base;   // trace programs: the lanes' record areas
+    unsigned char *tr_base;   // trace programs: the waves' record areas
     unsigned long long tr_stride;
     uint32_t tr_cap;
+    int tr_nskip;
 
     __device__ void load(const Job *jobs, int j)
     {
@@ -296,6 +297,7 @@ struct JobView {
         tr_base = J->tr_base;
         tr_stride = J->tr_stride;
         tr_cap = J->tr_cap;
+        tr_nskip = (int)J->tr_nskip;
     }
 };
 
@@ -740,23 +742,35 @@ __device__ __forceinline__ uint8_t tv_or(uint8_t x, uint8_t y)
     return (x == TV_T || y == TV_T) ? TV_T : ((x == TV_F && y == TV_F) ? TV_F : TV_U);
 }
 
+// One lane's view of its wave's record area: element e of an array sits at
+// index 64 e of the lane's pointer (the lanes of a wave interleave).
 struct TraceRec {
     double *t;
     uint32_t *bits;
     int32_t *need;
+    int32_t *skip;
     uint8_t *val;
     uint32_t cap;
+    __device__ __forceinline__ double T(int i) const { return t[(long)i << 6]; }
+    __device__ __forceinline__ uint32_t B(int i) const { return bits[(long)i << 6]; }
+    __device__ __forceinline__ int32_t &N(int q) const { return need[(long)q << 6]; }
+    __device__ __forceinline__ int32_t &K(int slot, int i) const
+    {
+        return skip[((long)slot * (cap + 1) + i) << 6];
+    }
+    __device__ __forceinline__ uint8_t &Vq(int q, int i) const { return val[((long)q * cap + i) << 6]; }
 };
 
 __device__ __forceinline__ TraceRec trace_rec(unsigned char *base, unsigned long long stride, uint32_t cap,
-                                              unsigned long long slot)
+                                              int nskip, unsigned long long wave, int lane)
 {
-    unsigned char *a = base + slot * stride;
+    unsigned char *a = base + wave * stride;
     TraceRec R;
-    R.t = reinterpret_cast<double *>(a);
-    R.bits = reinterpret_cast<uint32_t *>(a + TraceArea::bits_off(cap));
-    R.need = reinterpret_cast<int32_t *>(a + TraceArea::need_off(cap));
-    R.val = a + TraceArea::val_off(cap);
+    R.t = reinterpret_cast<double *>(a) + lane;
+    R.bits = reinterpret_cast<uint32_t *>(a + TraceArea::bits_off(cap)) + lane;
+    R.need = reinterpret_cast<int32_t *>(a + TraceArea::need_off(cap)) + lane;
+    R.skip = reinterpret_cast<int32_t *>(a + TraceArea::skip_off(cap)) + lane;
+    R.val = a + TraceArea::val_off(cap, nskip) + lane;
     R.cap = cap;
     return R;
 }
@@ -766,92 +780,130 @@ __device__ __forceinline__ TraceRec trace_rec(unsigned char *base, unsigned long
 // evaluated children first, each at the positions its parents read: from
 // the root (position 0) down, a NOT, AND or OR reads its operands where it
 // is read, a NEXT one position further, an UNTIL every position its scans
-// reach (the scan from the last position reaches furthest).
+// reach (the scan from the last position reaches furthest).  An UNTIL's scan
+// jumps over positions where its left operand holds and its right one fails:
+// they change neither its result nor whether the left operand has held, so
+// only the window can end the scan there, and it does so iff the last of
+// them lies past the window.
 __device__ __noinline__ uint32_t trace_value(cptr<MonProg> mp, TraceRec R, int len, bool next_known)
 {
     const int nn = mp->tr_n;
-    for (int q = 0; q < nn; ++q) R.need[q] = 0;
-    R.need[nn - 1] = 1;
+    for (int q = 0; q < nn; ++q) R.N(q) = 0;
+    R.N(nn - 1) = 1;
     for (int q = nn - 1; q >= 0; --q) {
         const auto &N = mp->tnodes[q];
-        const int nq = R.need[q];
+        const int nq = R.N(q);
         if (nq == 0) continue;
         int e = nq;
         if (N.kind == TN_NEXT) {
             e = nq + 1 < len ? nq + 1 : len;
         } else if (N.kind == TN_UNTIL) {
-            const double ti = R.t[nq - 1];
-            int j = nq - 1;
-            while (j + 1 < len && !(R.t[j + 1] - ti > N.hi)) ++j;
-            e = j + 1;
+            // the last j with t_j - t_(nq-1) <= hi, by bisection (entry times
+            // do not decrease, so the test holds on a prefix of positions)
+            const double ti = R.T(nq - 1);
+            int lo_j = nq - 1, hi_j = len;   // t_lo_j - ti <= hi holds; hi_j: first known to fail (or len)
+            if (__builtin_isinf(N.hi)) lo_j = len - 1;
+            while (hi_j - lo_j > 1) {
+                const int mid = lo_j + (hi_j - lo_j) / 2;
+                if (R.T(mid) - ti > N.hi) hi_j = mid;
+                else lo_j = mid;
+            }
+            e = lo_j + 1;
         }
-        if (N.kind >= TN_NOT) R.need[N.a] = R.need[N.a] > e ? R.need[N.a] : e;
-        if (N.kind == TN_AND || N.kind == TN_OR || N.kind == TN_UNTIL)
-            R.need[N.b] = R.need[N.b] > e ? R.need[N.b] : e;
+        if (N.kind >= TN_NOT) R.N(N.a) = R.N(N.a) > e ? R.N(N.a) : e;
+        if (N.kind == TN_AND || N.kind == TN_OR || N.kind == TN_UNTIL) R.N(N.b) = R.N(N.b) > e ? R.N(N.b) : e;
     }
-    const unsigned long long cap = R.cap;
     for (int q = 0; q < nn; ++q) {
         const auto &N = mp->tnodes[q];
-        const int nq = R.need[q];
-        uint8_t *out = R.val + (unsigned long long)q * cap;
-        const uint8_t *va = N.a >= 0 ? R.val + (unsigned long long)N.a * cap : nullptr;
-        const uint8_t *vb = N.b >= 0 ? R.val + (unsigned long long)N.b * cap : nullptr;
-        for (int i = 0; i < nq; ++i) {
-            uint8_t r;
-            switch (N.kind) {
-            case TN_TT: r = TV_T; break;
-            case TN_FF: r = TV_F; break;
-            case TN_PRED: r = ((R.bits[i] >> N.pred) & 1u) ? TV_T : TV_F; break;
-            case TN_NOT: r = tv_not(va[i]); break;
-            case TN_AND: r = tv_and(va[i], vb[i]); break;
-            case TN_OR: r = tv_or(va[i], vb[i]); break;
-            case TN_NEXT: {
-                // X I a at i: the next state exists, is entered within I
-                // after state i, and satisfies a
+        const int kind = N.kind;
+        const int nq = R.N(q);
+        // this node's values and its operands' (distinct arrays: the loops
+        // below may keep several positions' loads in flight)
+        uint8_t *__restrict__ out = R.val + (((long)q * R.cap) << 6);
+        const uint8_t *__restrict__ va = N.a >= 0 ? R.val + (((long)N.a * R.cap) << 6) : nullptr;
+        const uint8_t *__restrict__ vb = N.b >= 0 ? R.val + (((long)N.b * R.cap) << 6) : nullptr;
+        const double *__restrict__ tt = R.t;
+        if (kind == TN_TT || kind == TN_FF) {
+            const uint8_t c = kind == TN_TT ? TV_T : TV_F;
+#pragma unroll 8
+            for (int i = 0; i < nq; ++i) out[(long)i << 6] = c;
+        } else if (kind == TN_PRED) {
+            const uint32_t *__restrict__ bb = R.bits;
+            const int bit = N.pred;
+#pragma unroll 8
+            for (int i = 0; i < nq; ++i) out[(long)i << 6] = ((bb[(long)i << 6] >> bit) & 1u) ? TV_T : TV_F;
+        } else if (kind == TN_NOT) {
+#pragma unroll 8
+            for (int i = 0; i < nq; ++i) out[(long)i << 6] = tv_not(va[(long)i << 6]);
+        } else if (kind == TN_AND) {
+#pragma unroll 8
+            for (int i = 0; i < nq; ++i) out[(long)i << 6] = tv_and(va[(long)i << 6], vb[(long)i << 6]);
+        } else if (kind == TN_OR) {
+#pragma unroll 8
+            for (int i = 0; i < nq; ++i) out[(long)i << 6] = tv_or(va[(long)i << 6], vb[(long)i << 6]);
+        } else if (kind == TN_NEXT) {
+            // X I a at i: the next state exists, is entered within I after
+            // state i, and satisfies a
+            for (int i = 0; i < nq; ++i) {
+                uint8_t r;
                 if (i + 1 < len) {
-                    const double d = R.t[i + 1] - R.t[i];
-                    r = (d >= N.lo && d <= N.hi) ? va[i + 1] : TV_F;
+                    const double d = tt[(long)(i + 1) << 6] - tt[(long)i << 6];
+                    r = (d >= N.lo && d <= N.hi) ? va[(long)(i + 1) << 6] : TV_F;
                 } else if (next_known) {
-                    const double tn = R.t[len];
-                    const double d = tn - R.t[i];
+                    const double tn = tt[(long)len << 6];
+                    const double d = tn - tt[(long)i << 6];
                     r = (__builtin_isinf(tn) || !(d >= N.lo && d <= N.hi)) ? TV_F : TV_U;
                 } else {
                     r = TV_U;
                 }
-                break;
+                out[(long)i << 6] = r;
             }
-            default: {
+        } else {
+            // skip[k]: the first position >= k, below the operands' range e,
+            // that is not neutral (e where there is none)
+            const int e = R.N(N.a);
+            int32_t *__restrict__ sk = R.skip + (((long)N.pred * (R.cap + 1)) << 6);
+            sk[(long)e << 6] = e;
+            for (int k = e - 1; k >= 0; --k) {
+                const bool neutral = va[(long)k << 6] == TV_T && vb[(long)k << 6] == TV_F;
+                sk[(long)k << 6] = neutral ? sk[(long)(k + 1) << 6] : k;
+            }
+            const double hi = N.hi, lo = N.lo;
+            for (int i = 0; i < nq; ++i) {
                 // a U I b at i: some j >= i entered within I after state i
                 // satisfies b, and a holds at i .. j - 1
+                const double ti = tt[(long)i << 6];
                 uint8_t res = TV_F, all = TV_T;
-                for (int j = i;; ++j) {
+                for (int j = i;;) {
                     if (j >= len) {
                         // state j lies past the prefix: it exists unless the
                         // last state is absorbing, and may be in the window
                         // unless its entry time is known to lie past it
                         bool none = false;
                         if (next_known) {
-                            const double tj = R.t[len];
-                            none = __builtin_isinf(tj) || tj - R.t[i] > N.hi;
+                            const double tj = tt[(long)len << 6];
+                            none = __builtin_isinf(tj) || tj - ti > hi;
                         }
                         if (!none && all != TV_F) res = tv_or(res, TV_U);
                         break;
                     }
-                    const double d = R.t[j] - R.t[i];
-                    if (d > N.hi) break;
-                    if (d >= N.lo) res = tv_or(res, tv_and(all, vb[j]));
+                    const double d = tt[(long)j << 6] - ti;
+                    if (d > hi) break;
+                    if (d >= lo) res = tv_or(res, tv_and(all, vb[(long)j << 6]));
                     if (res == TV_T) break;
-                    all = tv_and(all, va[j]);
+                    all = tv_and(all, va[(long)j << 6]);
                     if (all == TV_F) break;
+                    // positions j + 1 .. nj - 1 are neutral (nj = the range's
+                    // end when they run to it)
+                    const int nj = j + 1 < e ? sk[(long)(j + 1) << 6] : j + 1;
+                    if (nj > j + 1 && tt[(long)(nj - 1) << 6] - ti > hi) break;
+                    j = nj;
                 }
-                r = res;
-                break;
+                out[(long)i << 6] = res;
             }
-            }
-            out[i] = r;
         }
     }
-    return R.val[(unsigned long long)(nn - 1) * cap];
+    return R.Vq(nn - 1, 0);
 }
 
 // Is point p decided?  Then its verdict and reason.
@@ -862,10 +914,10 @@ __device__ __noinline__ bool trace_decided(cptr<MonProg> mp, TraceRec R, uint32_
     const uint32_t v = trace_value(mp, R, (int)m + 1, w != 0u);
     if (v != TV_U) {
         *verdict = v == TV_T ? 1u : 0u;
-        *reason = w == 0u ? (uint32_t)RS_STATE : (__builtin_isinf(R.t[m + 1]) ? (uint32_t)RS_ABSORB : (uint32_t)RS_TIME);
+        *reason = w == 0u ? (uint32_t)RS_STATE : (__builtin_isinf(R.T((int)m + 1)) ? (uint32_t)RS_ABSORB : (uint32_t)RS_TIME);
         return true;
     }
-    if (R.t[m + w] > t_max) {   // the pessimistic rule (Sec. 3.2)
+    if (R.T((int)(m + w)) > t_max) {   // the pessimistic rule (Sec. 3.2)
         *verdict = 0u;
         *reason = RS_TMAX;
         return true;
@@ -2007,12 +2059,12 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
             const bool ev_lane = active && !entered;
             typename Pol::Sel ch;
             const double tn = Pol::draw(V, X, dr, t, &ch, ev_lane);
-            const TraceRec R = trace_rec(V.tr_base, V.tr_stride, V.tr_cap,
-                                         (unsigned long long)gwave * kWave + (unsigned long long)lane);
+            const TraceRec R = trace_rec(V.tr_base, V.tr_stride, V.tr_cap, V.tr_nskip, (unsigned long long)gwave,
+                                         lane);
             bool tfin = false;
             uint32_t tk = k, tvd = 0, trs = 0;
             if (ev_lane) {
-                R.t[k + 1u] = tn;   // the time state k is left
+                R.t[(long)(k + 1u) << 6] = tn;   // the time state k is left
                 // absorption, or the t_max rule, decides point 2k + 1
                 if (__builtin_isinf(tn) || tn > V.t_max) {
                     trace_first(V.mon, R, tr_lo, 2u * k + 1u, V.t_max, V.max_events, &tk, &tvd, &trs);
@@ -2025,8 +2077,8 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
             k = applied ? k + 1u : k;
             entered = entered || applied;
             if (entered) {
-                R.t[k] = t;
-                R.bits[k] = eval_preds(V.mon, X);
+                R.t[(long)k << 6] = t;
+                R.bits[(long)k << 6] = eval_preds(V.mon, X);
                 // checkpoints: state index k + 1 a power of two from 16 on, and the cap
                 const bool cp = (V.max_events != 0u && k == V.max_events) || (k >= 15u && ((k + 1u) & k) == 0u);
                 if (cp) {
