@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import math
 import os
+import time
 from dataclasses import dataclass
 
 import numpy as np
@@ -314,14 +315,18 @@ class Context:
         return r.as_dict()
 
     def estimate_batch(self, jobs) -> list:
-        """jobs: list of (Network, Formula, Params)."""
+        """jobs: list of (Network, Formula, Params).  last_call_seconds holds
+        the wall time of the library call alone (without this marshalling)."""
         arr = (JobDesc * len(jobs))()
         for k, (n, f, p) in enumerate(jobs):
             arr[k].net = n.h
             arr[k].formula = f.h
             arr[k].params = p
         res = (Result * len(jobs))()
-        self._check(lib().smc_estimate_batch(self.h, arr, len(jobs), res))
+        t0 = time.perf_counter()
+        rc = lib().smc_estimate_batch(self.h, arr, len(jobs), res)
+        self.last_call_seconds = time.perf_counter() - t0
+        self._check(rc)
         return [r.as_dict() for r in res]
 
     def autotune_batch(self, jobs, pilot_widen=1.0) -> dict:
