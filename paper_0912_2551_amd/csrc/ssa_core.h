@@ -726,9 +726,10 @@ __device__ __forceinline__ void mon_init(MonState &ms)
 // point is decided when the formula's value at position 0 is known there, or
 // by the t_max rule (the latest known time lies past t_max) or the event
 // cap (m = max_events).  Decided stays decided as the prefix grows, so the
-// lane tests points only at checkpoints (m + 1 a power of two from 16 on,
-// the cap, absorption, t_max) and then finds the first decided point by
-// bisection: the trajectory's result is the one it would have at that point.
+// lane tests points only at checkpoints (16 and 32 states, every 64th
+// iteration of its wave for all lanes together, the cap, absorption, t_max)
+// and then finds the first decided point by bisection: the trajectory's
+// result is the one it would have at that point.
 // ---------------------------------------------------------------------------
 enum : uint8_t { TV_F = 0, TV_T = 1, TV_U = 2 };
 
@@ -2079,8 +2080,11 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
             if (entered) {
                 R.t[(long)k << 6] = t;
                 R.bits[(long)k << 6] = eval_preds(V.mon, X);
-                // checkpoints: state index k + 1 a power of two from 16 on, and the cap
-                const bool cp = (V.max_events != 0u && k == V.max_events) || (k >= 15u && ((k + 1u) & k) == 0u);
+                // checkpoints: the cap; 16 and 32 states (short trajectories);
+                // and every 64th iteration of the wave for all its lanes at
+                // once, so that one evaluation pass serves the whole wave
+                const bool sync = (it & 63u) == 63u;
+                const bool cp = (V.max_events != 0u && k == V.max_events) || k == 15u || k == 31u || sync;
                 if (cp) {
                     if (trace_decided(V.mon, R, 2u * k, V.t_max, V.max_events, &tvd, &trs)) {
                         trace_first(V.mon, R, tr_lo, 2u * k, V.t_max, V.max_events, &tk, &tvd, &trs);
