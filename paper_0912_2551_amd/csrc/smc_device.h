@@ -169,9 +169,12 @@ struct TraceArea {
     static constexpr unsigned long long align(unsigned long long x) { return (x + 255ull) & ~255ull; }
     static constexpr unsigned long long bits_off(uint32_t cap) { return align(8ull * 64ull * (cap + 1ull)); }
     static constexpr unsigned long long need_off(uint32_t cap) { return bits_off(cap) + align(4ull * 64ull * cap); }
+    // per node: the final-position counts, committed and being formed, and
+    // (until nodes) the start of the final neutral run
+    static constexpr unsigned long long fin_off(uint32_t cap) { return need_off(cap) + align(4ull * 64ull * kMaxTrace); }
     static constexpr unsigned long long skip_off(uint32_t cap)
     {
-        return need_off(cap) + align(4ull * 64ull * kMaxTrace);
+        return fin_off(cap) + align(4ull * 64ull * 3ull * kMaxTrace);
     }
     static constexpr unsigned long long val_off(uint32_t cap, int ns)
     {

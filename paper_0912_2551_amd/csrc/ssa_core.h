@@ -730,6 +730,13 @@ __device__ __forceinline__ void mon_init(MonState &ms)
 // iteration of its wave for all lanes together, the cap, absorption, t_max)
 // and then finds the first decided point by bisection: the trajectory's
 // result is the one it would have at that point.
+//
+// Evaluation is incremental.  After a test that leaves the formula open, each
+// node keeps the count of its leading positions whose values no longer
+// prefix can change (every state they depend on lies inside the tested
+// prefix); later tests, and the bisection, which only looks at longer
+// prefixes, recompute each node from that count on.  For a bounded window
+// that is the tail of the prefix within the window's reach of its end.
 // ---------------------------------------------------------------------------
 enum : uint8_t { TV_F = 0, TV_T = 1, TV_U = 2 };
 
@@ -749,12 +756,18 @@ struct TraceRec {
     double *t;
     uint32_t *bits;
     int32_t *need;
+    int32_t *fin;
     int32_t *skip;
     uint8_t *val;
     uint32_t cap;
     __device__ __forceinline__ double T(int i) const { return t[(long)i << 6]; }
     __device__ __forceinline__ uint32_t B(int i) const { return bits[(long)i << 6]; }
     __device__ __forceinline__ int32_t &N(int q) const { return need[(long)q << 6]; }
+    // final positions of node q: committed (F) and being formed (F2)
+    __device__ __forceinline__ int32_t &F(int q) const { return fin[(long)q << 6]; }
+    __device__ __forceinline__ int32_t &F2(int q) const { return fin[(long)(q + kMaxTrace) << 6]; }
+    // until node q: positions [RS(q), k0) are all neutral (and final)
+    __device__ __forceinline__ int32_t &RS(int q) const { return fin[(long)(q + 2 * kMaxTrace) << 6]; }
     __device__ __forceinline__ int32_t &K(int slot, int i) const
     {
         return skip[((long)slot * (cap + 1) + i) << 6];
@@ -770,6 +783,7 @@ __device__ __forceinline__ TraceRec trace_rec(unsigned char *base, unsigned long
     R.t = reinterpret_cast<double *>(a) + lane;
     R.bits = reinterpret_cast<uint32_t *>(a + TraceArea::bits_off(cap)) + lane;
     R.need = reinterpret_cast<int32_t *>(a + TraceArea::need_off(cap)) + lane;
+    R.fin = reinterpret_cast<int32_t *>(a + TraceArea::fin_off(cap)) + lane;
     R.skip = reinterpret_cast<int32_t *>(a + TraceArea::skip_off(cap)) + lane;
     R.val = a + TraceArea::val_off(cap, nskip) + lane;
     R.cap = cap;
@@ -785,7 +799,8 @@ __device__ __forceinline__ TraceRec trace_rec(unsigned char *base, unsigned long
 // jumps over positions where its left operand holds and its right one fails:
 // they change neither its result nor whether the left operand has held, so
 // only the window can end the scan there, and it does so iff the last of
-// them lies past the window.
+// them lies past the window.  Each node is recomputed from its committed
+// final count on; below that its values, and its until scans' jumps, stand.
 __device__ __noinline__ uint32_t trace_value(cptr<MonProg> mp, TraceRec R, int len, bool next_known)
 {
     const int nn = mp->tr_n;
@@ -818,6 +833,7 @@ __device__ __noinline__ uint32_t trace_value(cptr<MonProg> mp, TraceRec R, int l
         const auto &N = mp->tnodes[q];
         const int kind = N.kind;
         const int nq = R.N(q);
+        const int lo = R.F(q);
         // this node's values and its operands' (distinct arrays: the loops
         // below may keep several positions' loads in flight)
         uint8_t *__restrict__ out = R.val + (((long)q * R.cap) << 6);
@@ -827,25 +843,25 @@ __device__ __noinline__ uint32_t trace_value(cptr<MonProg> mp, TraceRec R, int l
         if (kind == TN_TT || kind == TN_FF) {
             const uint8_t c = kind == TN_TT ? TV_T : TV_F;
 #pragma unroll 8
-            for (int i = 0; i < nq; ++i) out[(long)i << 6] = c;
+            for (int i = lo; i < nq; ++i) out[(long)i << 6] = c;
         } else if (kind == TN_PRED) {
             const uint32_t *__restrict__ bb = R.bits;
             const int bit = N.pred;
 #pragma unroll 8
-            for (int i = 0; i < nq; ++i) out[(long)i << 6] = ((bb[(long)i << 6] >> bit) & 1u) ? TV_T : TV_F;
+            for (int i = lo; i < nq; ++i) out[(long)i << 6] = ((bb[(long)i << 6] >> bit) & 1u) ? TV_T : TV_F;
         } else if (kind == TN_NOT) {
 #pragma unroll 8
-            for (int i = 0; i < nq; ++i) out[(long)i << 6] = tv_not(va[(long)i << 6]);
+            for (int i = lo; i < nq; ++i) out[(long)i << 6] = tv_not(va[(long)i << 6]);
         } else if (kind == TN_AND) {
 #pragma unroll 8
-            for (int i = 0; i < nq; ++i) out[(long)i << 6] = tv_and(va[(long)i << 6], vb[(long)i << 6]);
+            for (int i = lo; i < nq; ++i) out[(long)i << 6] = tv_and(va[(long)i << 6], vb[(long)i << 6]);
         } else if (kind == TN_OR) {
 #pragma unroll 8
-            for (int i = 0; i < nq; ++i) out[(long)i << 6] = tv_or(va[(long)i << 6], vb[(long)i << 6]);
+            for (int i = lo; i < nq; ++i) out[(long)i << 6] = tv_or(va[(long)i << 6], vb[(long)i << 6]);
         } else if (kind == TN_NEXT) {
             // X I a at i: the next state exists, is entered within I after
             // state i, and satisfies a
-            for (int i = 0; i < nq; ++i) {
+            for (int i = lo; i < nq; ++i) {
                 uint8_t r;
                 if (i + 1 < len) {
                     const double d = tt[(long)(i + 1) << 6] - tt[(long)i << 6];
@@ -861,21 +877,43 @@ __device__ __noinline__ uint32_t trace_value(cptr<MonProg> mp, TraceRec R, int l
             }
         } else {
             // skip[k]: the first position >= k, below the operands' range e,
-            // that is not neutral (e where there is none)
+            // that is not neutral (e where there is none).  Below k0, where
+            // both operands are final, the entries stand; each points no
+            // further than the k0 of the commit that made it final, so a jump
+            // never crosses a position whose operands could still change
+            // (it may land on a neutral one, which the scan steps over).
             const int e = R.N(N.a);
             int32_t *__restrict__ sk = R.skip + (((long)N.pred * (R.cap + 1)) << 6);
+            const int fa = R.F(N.a), fb = R.F(N.b);
+            const int k0 = fa < fb ? fa : fb;
+            const int rs = R.RS(q);
             sk[(long)e << 6] = e;
-            for (int k = e - 1; k >= 0; --k) {
+            int nxt = e;
+            for (int k = e - 1; k >= k0; --k) {
                 const bool neutral = va[(long)k << 6] == TV_T && vb[(long)k << 6] == TV_F;
-                sk[(long)k << 6] = neutral ? sk[(long)(k + 1) << 6] : k;
+                nxt = neutral ? nxt : k;
+                sk[(long)k << 6] = nxt;
             }
-            const double hi = N.hi, lo = N.lo;
-            for (int i = 0; i < nq; ++i) {
+            const double whi = N.hi, wlo = N.lo;
+            // ws: the window's first position for i (the first j >= i with
+            // t_j - t_i >= lo; it does not decrease with i), and bad: the
+            // positions of [i, ws) where a is not known to hold.  With none,
+            // the scan from i changes nothing before ws, so it starts there.
+            int ws = lo, bad = 0;
+            for (int i = lo; i < nq; ++i) {
                 // a U I b at i: some j >= i entered within I after state i
                 // satisfies b, and a holds at i .. j - 1
                 const double ti = tt[(long)i << 6];
+                if (i > lo) {
+                    if (ws > i - 1) bad -= va[(long)(i - 1) << 6] != TV_T;
+                    else ws = i;
+                }
+                while (ws < len && tt[(long)ws << 6] - ti < wlo) {
+                    bad += va[(long)ws << 6] != TV_T;
+                    ++ws;
+                }
                 uint8_t res = TV_F, all = TV_T;
-                for (int j = i;;) {
+                for (int j = bad == 0 ? ws : i;;) {
                     if (j >= len) {
                         // state j lies past the prefix: it exists unless the
                         // last state is absorbing, and may be in the window
@@ -883,21 +921,23 @@ __device__ __noinline__ uint32_t trace_value(cptr<MonProg> mp, TraceRec R, int l
                         bool none = false;
                         if (next_known) {
                             const double tj = tt[(long)len << 6];
-                            none = __builtin_isinf(tj) || tj - ti > hi;
+                            none = __builtin_isinf(tj) || tj - ti > whi;
                         }
                         if (!none && all != TV_F) res = tv_or(res, TV_U);
                         break;
                     }
                     const double d = tt[(long)j << 6] - ti;
-                    if (d > hi) break;
-                    if (d >= lo) res = tv_or(res, tv_and(all, vb[(long)j << 6]));
+                    if (d > whi) break;
+                    if (d >= wlo) res = tv_or(res, tv_and(all, vb[(long)j << 6]));
                     if (res == TV_T) break;
                     all = tv_and(all, va[(long)j << 6]);
                     if (all == TV_F) break;
                     // positions j + 1 .. nj - 1 are neutral (nj = the range's
-                    // end when they run to it)
-                    const int nj = j + 1 < e ? sk[(long)(j + 1) << 6] : j + 1;
-                    if (nj > j + 1 && tt[(long)(nj - 1) << 6] - ti > hi) break;
+                    // end when they run to it); inside the final neutral run
+                    // the jump goes to its end at once
+                    int nj = j + 1 < e ? sk[(long)(j + 1) << 6] : j + 1;
+                    nj = (j + 1 >= rs && j + 1 < k0 && nj < k0) ? k0 : nj;
+                    if (nj > j + 1 && tt[(long)(nj - 1) << 6] - ti > whi) break;
                     j = nj;
                 }
                 out[(long)i << 6] = res;
@@ -905,6 +945,75 @@ __device__ __noinline__ uint32_t trace_value(cptr<MonProg> mp, TraceRec R, int l
         }
     }
     return R.Vq(nn - 1, 0);
+}
+
+// After a test of the prefix of `len` states (the time the last one is left
+// not yet known) that left the formula open: the new final counts, from the
+// need counts of that test, children first.  Position i of a node is final
+// when its value is the same on every longer prefix:
+//  - a predicate, TT or FF: i < len;
+//  - NOT, AND, OR: their operands are final at i;
+//  - NEXT: state i + 1 is known and its operand final there;
+//  - UNTIL over [lo, hi]: some position F' < len, below both operands' final
+//    counts, is entered more than hi after state i; then the scan from i ends
+//    at F' at the latest and reads only final values (an unbounded window
+//    never qualifies).  Entry times do not decrease, so these positions form
+//    a prefix, found by bisection.
+// Then the jump entries of each until that become final are bounded by the
+// new k0 (see trace_value), its final neutral run is extended over them or
+// restarted after the last of them that is not neutral, and the counts are
+// committed.
+__device__ __noinline__ void trace_commit(cptr<MonProg> mp, TraceRec R, int len)
+{
+    const int nn = mp->tr_n;
+    for (int q = 0; q < nn; ++q) {
+        const auto &N = mp->tnodes[q];
+        const int kind = N.kind;
+        const int nq = R.N(q);
+        int f = nq;
+        if (kind == TN_NOT) {
+            f = R.F2(N.a);
+        } else if (kind == TN_AND || kind == TN_OR) {
+            f = R.F2(N.a) < R.F2(N.b) ? R.F2(N.a) : R.F2(N.b);
+        } else if (kind == TN_NEXT) {
+            f = R.F2(N.a) - 1 < len - 1 ? R.F2(N.a) - 1 : len - 1;
+        } else if (kind == TN_UNTIL) {
+            int fp = R.F2(N.a) < R.F2(N.b) ? R.F2(N.a) : R.F2(N.b);
+            fp = fp < len - 1 ? fp : len - 1;
+            f = 0;
+            if (!__builtin_isinf(N.hi) && fp > 0) {
+                // the first i in [0, fp] with t_fp - t_i > hi false
+                const double tf = R.T(fp);
+                int a = 0, b = fp;
+                while (a < b) {
+                    const int mid = a + (b - a) / 2;
+                    if (tf - R.T(mid) > N.hi) a = mid + 1;
+                    else b = mid;
+                }
+                f = a;
+            }
+        }
+        f = f < nq ? f : nq;
+        R.F2(q) = f > 0 ? f : 0;
+    }
+    for (int q = 0; q < nn; ++q) {
+        const auto &N = mp->tnodes[q];
+        if (N.kind != TN_UNTIL) continue;
+        const int k0o = R.F(N.a) < R.F(N.b) ? R.F(N.a) : R.F(N.b);
+        const int k0n = R.F2(N.a) < R.F2(N.b) ? R.F2(N.a) : R.F2(N.b);
+        int32_t *sk = R.skip + (((long)N.pred * (R.cap + 1)) << 6);
+        const uint8_t *va = R.val + (((long)N.a * R.cap) << 6);
+        const uint8_t *vb = R.val + (((long)N.b * R.cap) << 6);
+        int rs = R.RS(q);
+        for (int k = k0o; k < k0n; ++k) {
+            const int v = sk[(long)k << 6];
+            sk[(long)k << 6] = v < k0n ? v : k0n;
+            const bool neutral = va[(long)k << 6] == TV_T && vb[(long)k << 6] == TV_F;
+            rs = neutral ? rs : k + 1;
+        }
+        R.RS(q) = rs;
+    }
+    for (int q = 0; q < nn; ++q) R.F(q) = R.F2(q);
 }
 
 // Is point p decided?  Then its verdict and reason.
@@ -2080,6 +2189,11 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
             if (entered) {
                 R.t[(long)k << 6] = t;
                 R.bits[(long)k << 6] = eval_preds(V.mon, X);
+                if (k == 0u)   // a new trajectory: nothing is final yet
+                    for (int q = 0; q < V.mon->tr_n; ++q) {
+                        R.F(q) = 0;
+                        R.RS(q) = 0;
+                    }
                 // checkpoints: the cap; 16 and 32 states (short trajectories);
                 // and every 64th iteration of the wave for all its lanes at
                 // once, so that one evaluation pass serves the whole wave
@@ -2091,6 +2205,7 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
                         tfin = true;
                     } else {
                         tr_lo = 2u * k + 1u;
+                        trace_commit(V.mon, R, (int)k + 1);
                     }
                 }
             }

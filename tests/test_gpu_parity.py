@@ -874,6 +874,13 @@ TRACE_CASES = [
     ("absorb", death_only, "F[0,100](G[1,5](X<=3))", {"max_events": 5000}),
     ("six-preds", W.isomerization, "(A>=1 & B<=45 & A+B>=2 & A>=10 & B<=40 & A<=50) U[0,2] (A<=18)",
      {"max_events": 5000}),
+    # long trajectories (hundreds to thousands of states, decided late): many
+    # tests that leave the formula open before the deciding one
+    ("long-nested", W.michaelis_menten, "F[0,60]((S<=300) & F[1,5](P>=600))", {"max_events": 5000}),
+    ("next-in-window", W.immigration_death, "F[5,60](X[0,0.2](X>=115) & G[0,1](X>=105))",
+     {"max_events": 20000}),
+    ("temporal-both", W.immigration_death, "(G[0,2](X<=118)) U[1,50] (F[0,1](X>=116))", {"max_events": 20000}),
+    ("long-G", W.immigration_death, "G[10,60](F[1,3](X>=85))", {"max_events": 20000}),
 ]
 
 
