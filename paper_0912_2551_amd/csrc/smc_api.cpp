@@ -591,6 +591,8 @@ int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult 
                        : variant == 10 ? SMC_KERNEL_GENERIC_TRACE
                        : tree ? SMC_KERNEL_GENERIC_TREE : SMC_KERNEL_GENERIC_GROUPED;
     for (int k = 0; k < n; ++k) res[k] = JobResult{};
+    unsigned long long room_max = 1;
+    for (int k = 0; k < n; ++k) room_max = std::max(room_max, (unsigned long long)jobs[k].capacity);
     double total_ms = 0.0;
     const auto t_start = std::chrono::steady_clock::now();
     unsigned long long last_progress = ~0ull;
@@ -610,10 +612,11 @@ int run_jobs_in(smc_ctx *ctx, Prepared *P, int n, const Workspace &W, JobResult 
         HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
         if (spec_fn)
             HIP_TRY(ctx, launch_module(spec_fn, grid, wpb, spec_lds, s, W.d_jobs, n, s_max, W.d_ctl,
-                                       ctx->cancel_dev, 1 << 18, static_first && launch == 0));
+                                       ctx->cancel_dev, 1 << 18, static_first && launch == 0, room_max));
         else
             HIP_TRY(ctx, launch_persistent(variant, n_iter > 0, grid, wpb, lds_wave * wpb, s, W.d_jobs, n, s_max,
-                                           W.d_ctl, ctx->cancel_dev, 1 << 18, static_first && launch == 0));
+                                           W.d_ctl, ctx->cancel_dev, 1 << 18, static_first && launch == 0,
+                                           room_max));
         if (speculative) {
             HIP_TRY(ctx, hipMemcpyAsync(W.d_jobs, jobs + n, n * sizeof(Job), hipMemcpyHostToDevice, s));
             HIP_TRY(ctx, launch_replay(s, W.d_jobs, n, W.d_results));

@@ -23,16 +23,18 @@ constexpr unsigned long long kTraceBudget = 8ull << 30;
 // formula.cpp
 void compile_formula(const std::string &text, const std::vector<std::string> &names, MonProg &out);
 
-// ssa_kernel.hip
+// ssa_kernel.hip (room_max: the largest capacity of the launch's jobs)
 hipError_t launch_persistent(int nb_variant, bool iterative, int grid, int waves_per_block, size_t lds_bytes,
                              hipStream_t stream, const Job *jobs, int n_jobs, int s_max,
-                             Control *ctl, const volatile int32_t *cancel, int spin_limit, int static_first);
+                             Control *ctl, const volatile int32_t *cancel, int spin_limit, int static_first,
+                             unsigned long long room_max);
 hipError_t launch_sample_state(int nb_variant, hipStream_t stream, const Job *job, double T,
                                unsigned long long count, int32_t *out, int s_max);
 // a specialised persistent kernel (spec.cpp) with the generic kernel's arguments
 hipError_t launch_module(hipFunction_t fn, int grid, int waves_per_block, size_t lds_bytes, hipStream_t stream,
                          const Job *jobs, int n_jobs, int s_max, Control *ctl,
-                         const volatile int32_t *cancel, int spin_limit, int static_first);
+                         const volatile int32_t *cancel, int spin_limit, int static_first,
+                         unsigned long long room_max);
 int persistent_blocks_per_cu(int variant, bool iterative, int waves_per_block, size_t lds_bytes);
 int module_blocks_per_cu(hipFunction_t fn, int waves_per_block, size_t lds_bytes);
 // Clears and sets up the jobs' state and the control block of the first

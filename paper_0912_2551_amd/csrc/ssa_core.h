@@ -1920,14 +1920,20 @@ __device__ __forceinline__ bool claimable(const Job *jobs, int j)
 // idle counts this wave's consecutive fruitless scans.  Without this, every
 // idle wave of a launch converges on the one job whose limit has just risen
 // (by a single index, say) and their claims serialise on its counter; the
-// idle term lets distant waves in when the nearby ones stay busy.  any: take
-// the first job with issuable indices, at any distance.
-__device__ int pick_job(const Job *jobs, int n_jobs, int start, int wph, int idle, bool any = false)
+// idle term lets distant waves in when the nearby ones stay busy.  No room
+// exceeds room_max (the launch's largest capacity), so the scan ends at the
+// first distance no job can qualify at.  any: take the first job with
+// issuable indices at distance q0 or more, at any distance, and report its
+// distance in *qf.
+__device__ int pick_job(const Job *jobs, int n_jobs, int start, int wph, int idle, unsigned long long room_max,
+                        bool any = false, int q0 = 0, int *qf = nullptr)
 {
     const int lane = lane_id();
     const unsigned long long w = (unsigned long long)wph;
     const unsigned long long age = 1ull + (unsigned long long)(idle < 4096 ? idle : 4096);
-    for (int base = 0; base < n_jobs; base += kWave) {
+    const unsigned long long reach = (room_max / 32ull + w) * age;
+    for (int base = q0; base < n_jobs; base += kWave) {
+        if (!any && (unsigned long long)base * w > reach) break;
         const int q = base + lane;
         int j = start + q;
         if (j >= n_jobs) j -= n_jobs;
@@ -1939,7 +1945,11 @@ __device__ int pick_job(const Job *jobs, int n_jobs, int start, int wph, int idl
                 ok = any || (unsigned long long)q * w <= ((lm - nx) / 32ull + w) * age;
         }
         const uint64_t m = __ballot(ok);
-        if (m) return __builtin_amdgcn_readlane(j, ffs64(m));
+        if (m) {
+            const int l = ffs64(m);
+            if (qf) *qf = base + l;
+            return __builtin_amdgcn_readlane(j, l);
+        }
     }
     return -1;
 }
@@ -1997,6 +2007,7 @@ struct KArgs {
     int spin_limit;
     int waves_per_block;
     int static_first;                 // first launch: waves start on their static shares
+    unsigned long long room_max;      // the largest capacity of the launch's jobs
 };
 
 // Add a wave's counts for batch b of its job to the sharded counters.
@@ -2042,6 +2053,11 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
     Draw dr{0.0, 0.0};   // random numbers of the lane's next event (index k)
     uint32_t tr_lo = 0;  // trace programs: every point below this one is undecided
     int spins = 0;
+    // scans that take any job: the jobs nearer than this (in this wave's scan
+    // order) had no issuable indices left.  Such scans run only once no
+    // iterative job is open, when no limit rises any more, so those jobs stay
+    // exhausted.
+    int any_from = 0;
     // wave-local pool of claimed, not yet started indices [pool_next, pool_end)
     unsigned long long pool_next = 0, pool_end = 0;
     // fixed-sample jobs: per-lane counts, added to the job once per wave
@@ -2085,12 +2101,13 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
             if (uniform_i(stop)) break;
         }
         if (__ballot(active) == 0ull && pool_next == pool_end) {
-            int j = pick_job(A.jobs, A.n_jobs, start, wph, spins);
+            int j = pick_job(A.jobs, A.n_jobs, start, wph, spins, A.room_max);
             // A launch of fixed-size jobs only: a wave leaves once nothing is
             // near its home, so before leaving it takes any job with indices
             // left, however far (with many more jobs than waves, some would
             // otherwise lie out of every wave's reach).
-            if (j < 0 && ld_relaxed(&A.ctl->open_jobs) <= 0) j = pick_job(A.jobs, A.n_jobs, start, wph, spins, true);
+            if (j < 0 && ld_relaxed(&A.ctl->open_jobs) <= 0)
+                j = pick_job(A.jobs, A.n_jobs, start, wph, spins, A.room_max, true, any_from, &any_from);
             if (j != cur && cur >= 0 && !V.iterative) {
                 // leaving a fixed-sample job: publish this wave's counts
                 const unsigned long long ny = wave_sum_u64(my_yes), nn = wave_sum_u64(my_no);

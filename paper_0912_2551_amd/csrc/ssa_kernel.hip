@@ -247,7 +247,8 @@ namespace smc {
 // the launch holds jobs with the Fig. 2 stopping rule
 hipError_t launch_persistent(int variant, bool iterative, int grid, int waves_per_block, size_t lds_bytes,
                              hipStream_t stream, const Job *jobs, int n_jobs, int s_max,
-                             Control *ctl, const volatile int32_t *cancel, int spin_limit, int static_first)
+                             Control *ctl, const volatile int32_t *cancel, int spin_limit, int static_first,
+                             unsigned long long room_max)
 {
     KArgs a;
     a.jobs = jobs;
@@ -258,6 +259,7 @@ hipError_t launch_persistent(int variant, bool iterative, int grid, int waves_pe
     a.spin_limit = spin_limit;
     a.waves_per_block = waves_per_block;
     a.static_first = static_first;
+    a.room_max = room_max;
     const dim3 block(kWave * waves_per_block);
     const void *fn = iterative ? persistent_kernel<true>(variant) : persistent_kernel<false>(variant);
     void *args[] = {&a};
@@ -286,7 +288,8 @@ int module_blocks_per_cu(hipFunction_t fn, int waves_per_block, size_t lds_bytes
 
 hipError_t launch_module(hipFunction_t fn, int grid, int waves_per_block, size_t lds_bytes, hipStream_t stream,
                          const Job *jobs, int n_jobs, int s_max, Control *ctl,
-                         const volatile int32_t *cancel, int spin_limit, int static_first)
+                         const volatile int32_t *cancel, int spin_limit, int static_first,
+                         unsigned long long room_max)
 {
     KArgs a;
     a.jobs = jobs;
@@ -297,6 +300,7 @@ hipError_t launch_module(hipFunction_t fn, int grid, int waves_per_block, size_t
     a.spin_limit = spin_limit;
     a.waves_per_block = waves_per_block;
     a.static_first = static_first;
+    a.room_max = room_max;
     void *params[] = {&a};
     return hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, (unsigned)(kWave * waves_per_block), 1, 1,
                                  (unsigned)lds_bytes, stream, params, nullptr);
