@@ -18,6 +18,7 @@ for wide networks (lane groups with sums in channel order or in a tree).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-surrogate]
        python bench.py --copy-calibration   (HBM counter calibration copy)
+       python bench.py --surrogate-query    (the 10^6-point query launch alone, for profiles)
 """
 import argparse
 import json
@@ -116,6 +117,51 @@ def copy_calibration():
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}))
+
+
+def surrogate_query_only(repeats=6):
+    """The surrogate's 10^6-point query alone, on device arrays, as the
+    surrogate section runs it for the workload formula: train on the 512-point
+    sweep's plain-SMC estimates (95% +-0.01), calibrate the gate on 1024
+    held-out points, then query the 10^6 rate points `repeats` times.  Prints
+    one JSON line with the wall time of each query."""
+    import numpy as np
+    import torch
+    from paper_0912_2551_amd import binding as B
+    from paper_0912_2551_amd import workloads as W
+    ctx = B.Context(0)
+    keep = []
+
+    def jobs_for(rates, seed):
+        jobs = []
+        for k, rr in enumerate(rates):
+            nh = ctx.network(W.michaelis_menten(*rr))
+            fh = ctx.formula(nh, W.C2_FORMULA)
+            keep.append((nh, fh))
+            jobs.append((nh, fh, B.params(confidence=0.95, half_width=0.01, seed=seed, model_id=k)))
+        return jobs
+
+    train = W.mm_sweep(512, seed=4)
+    res = ctx.estimate_batch(jobs_for(train, 1))
+    sg = B.Surrogate(ctx, seed=4)
+    sg.train(np.log10(train).astype(np.float32), np.array([r["p_hat"] for r in res], dtype=np.float32),
+             np.array([r["n"] for r in res], dtype=np.float32), steps=2000, lr=2e-3)
+    xc = W.surrogate_queries(1024, seed=7)
+    cal = ctx.estimate_batch(jobs_for(10.0 ** xc.astype(np.float64), 3))
+    sg.calibrate(xc, [r["lo"] for r in cal], [r["hi"] for r in cal], threshold=0.5, bound=0.01, min_margin=0.05)
+    n = 10 ** 6
+    q = torch.from_numpy(W.surrogate_queries(n, seed=6)).cuda()
+    p = torch.empty(n, dtype=torch.float32, device="cuda")
+    use = torch.empty(n, dtype=torch.uint8, device="cuda")
+    walls = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sg.query_device(q, n, p, use)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+    print(json.dumps({"surrogate_query_points": n, "wall_seconds": walls,
+                      "answered_share": float(use.float().mean().item())}))
 
 
 _T_START = time.perf_counter()
@@ -465,9 +511,14 @@ def main():
     ap.add_argument("--kernel", choices=["auto", "generic"], default="auto",
                     help="auto: kernel specialised to the network structure when supported")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--surrogate-query", action="store_true",
+                    help="only the surrogate's 10^6-point query launch (for profiles)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.surrogate_query:
+        surrogate_query_only()
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "

@@ -21,6 +21,7 @@ constexpr int kH = 256;   // hidden width
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 // FP32 -> BF16 bits, round to nearest, ties to even (finite inputs).
 __device__ __forceinline__ uint16_t to_bf16(float f)
@@ -432,10 +433,17 @@ constexpr int kQRow = kH + 8;
 // two per SIMD, so that one wave's vector work overlaps the other's matrix
 // work) stages W2 in LDS once; every wave then runs its own tiles from start
 // to end, with no block barrier after the staging.  Per tile:
-//  - layers 1 and 2 step by step along k: for step s, lane l computes the 8
-//    hidden units its A operand holds (row l % 32, units 16 s + 8 (l / 32) ..
-//    + 7), from W1 and b1 in LDS as (w0, w1, w2, b1), straight into registers;
-//    then v_mfma_f32_32x32x16_bf16 adds the step to each of the eight 32-column
+//  - layer 1 on the matrix cores, 32 hidden units at a time: one
+//    v_mfma_f32_32x32x16_bf16 of the units' rows (w0, w1, w2 and b1 split
+//    into three bfloat16 parts that add up to it, from LDS) by the tile's
+//    inputs (n0, n1, n2, 1, 1, 1); the inputs and weights are bfloat16
+//    values, so every product is exact and the sum is accumulated in FP32.
+//    Lane l then holds units 8 (r / 4) + 4 (l / 32) + r % 4 (r = 0 .. 15) of
+//    the block for point l % 32: after ReLU and rounding, the A operands of
+//    the block's two layer-2 steps, in an order of k that W2's staging
+//    follows (within every 16 k, the second and third groups of four trade
+//    places), so that no value moves between lanes;
+//  - layer 2: v_mfma_f32_32x32x16_bf16 adds each step to the eight 32-column
 //    groups' accumulators (B from LDS);
 //  - layer 3: every lane adds its columns' contributions to its 16 rows, then
 //    the 32 lanes of each half sum by shuffles;
@@ -454,7 +462,7 @@ __device__ __forceinline__ float dpp_f32(float v)
 }
 
 constexpr int kQueryWaves = 8;
-constexpr size_t kWaveQueryLds = (size_t)kH * kQRow * 2 + (size_t)kH * 4 * sizeof(float);
+constexpr size_t kWaveQueryLds = (size_t)kH * kQRow * 2 + (size_t)kH * 16;
 constexpr int kLdsPlanes = 1280;   // hull facets staged in LDS (a hull of n points has at most 2n - 4)
 
 __global__ __launch_bounds__(64 * kQueryWaves) void mlp_query_waves(
@@ -463,20 +471,41 @@ __global__ __launch_bounds__(64 * kQueryWaves) void mlp_query_waves(
     int n_lds_planes, float hull_tol, float threshold, float margin, float *p_out, uint8_t *use)
 {
     extern __shared__ uint16_t qsm[];
-    uint16_t *W2s = qsm;                                                // [col][k] (row stride kQRow)
-    float4 *W1s = reinterpret_cast<float4 *>(W2s + kH * kQRow);         // [unit] = (w0, w1, w2, b1)
-    float4 *Ps = W1s + kH;                                              // facets 0 .. n_lds_planes - 1
+    uint16_t *W2s = qsm;                                                // [col][k'] (row stride kQRow)
+    uint4 *W1s = reinterpret_cast<uint4 *>(W2s + kH * kQRow);           // [unit]: layer 1's A row
+    float4 *Ps = reinterpret_cast<float4 *>(W1s + kH);                  // facets 0 .. n_lds_planes - 1
     const int tid = (int)threadIdx.x;
     {
-        const uint4 *src = reinterpret_cast<const uint4 *>(W2b);
-        uint4 *dst = reinterpret_cast<uint4 *>(W2s);
-        for (int i = tid; i < kH * kH / 8; i += 64 * kQueryWaves)
-            dst[(i / (kH / 8)) * (kQRow / 8) + i % (kH / 8)] = src[i];
-        if (tid < kH)
-            W1s[tid] = make_float4(from_bf16(W1b[tid * 3]), from_bf16(W1b[tid * 3 + 1]), from_bf16(W1b[tid * 3 + 2]),
-                                   b1[tid]);
+        // W2 by groups of four k: within every 16, groups 1 and 2 trade places
+        const uint2 *src = reinterpret_cast<const uint2 *>(W2b);
+        uint2 *dst = reinterpret_cast<uint2 *>(W2s);
+        for (int i = tid; i < kH * kH / 4; i += 64 * kQueryWaves) {
+            const int c = i % (kH / 4), q = c & 3;
+            const int cd = (c & ~3) | (q == 1 ? 2 : q == 2 ? 1 : q);
+            dst[(i / (kH / 4)) * (kQRow / 4) + cd] = src[i];
+        }
+        if (tid < kH) {
+            // b1 = hi + lo + lo2, each a bfloat16 value (the two differences
+            // are exact in FP32)
+            const float b = b1[tid];
+            const __bf16 hi = (__bf16)b;
+            const float r1 = b - (float)hi;
+            const __bf16 lo = (__bf16)r1;
+            const __bf16 lo2 = (__bf16)(r1 - (float)lo);
+            bf16x8 a;
+            a[0] = __builtin_bit_cast(__bf16, W1b[tid * 3]);
+            a[1] = __builtin_bit_cast(__bf16, W1b[tid * 3 + 1]);
+            a[2] = __builtin_bit_cast(__bf16, W1b[tid * 3 + 2]);
+            a[3] = hi;
+            a[4] = lo;
+            a[5] = lo2;
+            a[6] = (__bf16)0.0f;
+            a[7] = (__bf16)0.0f;
+            W1s[tid] = __builtin_bit_cast(uint4, a);
+        }
+        // facets with the tolerance added to their offsets once
         for (int f = tid; f < n_lds_planes; f += 64 * kQueryWaves)
-            Ps[f] = make_float4(planes[4 * f], planes[4 * f + 1], planes[4 * f + 2], planes[4 * f + 3]);
+            Ps[f] = make_float4(planes[4 * f], planes[4 * f + 1], planes[4 * f + 2], planes[4 * f + 3] + hull_tol);
     }
     __syncthreads();
     const int lane = tid & 63, wave = tid >> 6;
@@ -505,42 +534,68 @@ __global__ __launch_bounds__(64 * kQueryWaves) void mlp_query_waves(
         const float n0 = rne_bf16((x0 - mu0) / sg0);
         const float n1 = rne_bf16((x1 - mu1) / sg1);
         const float n2 = rne_bf16((x2 - mu2) / sg2);
-        // layers 1 and 2, step by step along k: the step's A operand (layer 1
-        // for the 8 hidden units this lane holds) feeds the eight 32-column
-        // groups' accumulators
+        // layer 1's B operand: this point's inputs at k = 0 .. 5 (half 0);
+        // k = 8 .. 15 (half 1) are 0, as are the A rows there
+        bf16x8 xin;
+        xin[0] = (__bf16)(half ? 0.0f : n0);
+        xin[1] = (__bf16)(half ? 0.0f : n1);
+        xin[2] = (__bf16)(half ? 0.0f : n2);
+        xin[3] = (__bf16)(half ? 0.0f : 1.0f);
+        xin[4] = xin[3];
+        xin[5] = xin[3];
+        xin[6] = (__bf16)0.0f;
+        xin[7] = (__bf16)0.0f;
         floatx16 acc[8];
+        // units 32 bk .. 32 bk + 31 for the tile's 32 points, and the two
+        // layer-2 steps they feed (the first step starts the accumulators)
+        auto block = [&](int bk, bool first) {
+            const uint4 wr = W1s[32 * bk + rc];
+            const bf16x8 w = __builtin_bit_cast(bf16x8, half ? make_uint4(0u, 0u, 0u, 0u) : wr);
+            const floatx16 h1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, xin, floatx16{}, 0, 0, 0);
 #pragma unroll
-        for (int g = 0; g < 8; ++g) acc[g] = floatx16{};
-#pragma unroll 2
-        for (int s = 0; s < 16; ++s) {
-            bf16x8 a;
+            for (int t = 0; t < 2; ++t) {
+                bf16x8 a;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float4 w = W1s[16 * s + 8 * half + e];
-                float h = w.w;
-                h = fmaf(n0, w.x, h);
-                h = fmaf(n1, w.y, h);
-                h = fmaf(n2, w.z, h);
-                a[e] = (__bf16)(h > 0.0f ? h : 0.0f);   // v_cvt_pk_bf16_f32: round to nearest even
+                for (int e = 0; e < 8; ++e) {
+                    // ReLU as an integer max of the bit pattern (the same
+                    // value as max(h, 0) for every h that is not a NaN), then
+                    // v_cvt_pk_bf16_f32: round to nearest even
+                    const int hb = __float_as_int(h1[8 * t + e]);
+                    a[e] = (__bf16)__int_as_float(hb > 0 ? hb : 0);
+                }
+                const uint16_t *bcol = W2s + rc * kQRow + 8 * half + 16 * (2 * bk + t);
+#pragma unroll
+                for (int g = 0; g < 8; ++g) {
+                    const bf16x8 b =
+                        __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(bcol + g * 32 * kQRow));
+                    acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, first && t == 0 ? floatx16{} : acc[g],
+                                                                     0, 0, 0);
+                }
             }
-            const uint16_t *bcol = W2s + rc * kQRow + 8 * half + 16 * s;
-#pragma unroll
-            for (int g = 0; g < 8; ++g) {
-                const bf16x8 b = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(bcol + g * 32 * kQRow));
-                acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[g], 0, 0, 0);
-            }
-        }
-        // layer 3: rows 8 (r / 4) + 4 half + r % 4 of column 32 g + rc
+        };
+        block(0, true);
+#pragma unroll 1
+        for (int bk = 1; bk < 8; ++bk) block(bk, false);
+        // layer 3: rows 8 (r / 4) + 4 half + r % 4 of column 32 g + rc, two
+        // column groups at a time: the two rounded activations and their
+        // weights as bfloat16 pairs, one v_dot2_f32_bf16 (exact products,
+        // FP32 sum) per row
         float zr[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) zr[r] = 0.0f;
 #pragma unroll
-        for (int g = 0; g < 8; ++g) {
-            const float bg = b2[g * 32 + rc], wg = from_bf16(W3b[g * 32 + rc]);
+        for (int g = 0; g < 8; g += 2) {
+            const float b0 = b2[g * 32 + rc], b1v = b2[(g + 1) * 32 + rc];
+            bf16x2 w;
+            w[0] = __builtin_bit_cast(__bf16, W3b[g * 32 + rc]);
+            w[1] = __builtin_bit_cast(__bf16, W3b[(g + 1) * 32 + rc]);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const float v = acc[g][r] + bg;
-                zr[r] += rne_bf16(v > 0.0f ? v : 0.0f) * wg;
+                const float v0 = acc[g][r] + b0, v1 = acc[g + 1][r] + b1v;
+                bf16x2 h;
+                h[0] = (__bf16)(v0 > 0.0f ? v0 : 0.0f);
+                h[1] = (__bf16)(v1 > 0.0f ? v1 : 0.0f);
+                zr[r] = __builtin_amdgcn_fdot2_f32_bf16(h, w, zr[r], false);
             }
         }
         // sum over the 32 columns of each half: then every lane of half h
@@ -571,7 +626,7 @@ __global__ __launch_bounds__(64 * kQueryWaves) void mlp_query_waves(
             for (; f < n_lds_planes; f += 2) {
                 const float4 pl = Ps[f];
                 const float v = pl.x * x0 + pl.y * x1 + pl.z * x2;
-                ok = ok && (v <= pl.w + hull_tol);
+                ok = ok && (v <= pl.w);
             }
             for (; f < n_planes; f += 2) {
                 const float *pl = planes + 4 * f;
