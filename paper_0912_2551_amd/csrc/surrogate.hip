@@ -283,9 +283,7 @@ __global__ __launch_bounds__(kColBlock * kSlices) void layer1_backward(
 
 // out[0] = sum of the n per-row losses: thread t sums rows t, t + 256, ...
 // in order (FP64), then the 256 partial sums are added in thread order.
-// With step != nullptr the sum goes to out[*step] (a step counter in device
-// memory, for a training step captured once and replayed).
-__global__ __launch_bounds__(256) void loss_sum(const float *loss_row, int n, float *out, const int *step)
+__global__ __launch_bounds__(256) void loss_sum(const float *loss_row, int n, float *out)
 {
     __shared__ double part[256];
     const int t = (int)threadIdx.x;
@@ -296,31 +294,16 @@ __global__ __launch_bounds__(256) void loss_sum(const float *loss_row, int n, fl
     if (t == 0) {
         double s = 0.0;
         for (int r = 0; r < 256; ++r) s += part[r];
-        out[step ? *step : 0] = (float)s;
+        out[0] = (float)s;
     }
-}
-
-// The step counter of a replayed training step moves on (after the step's
-// other kernels, in stream order).
-__global__ void step_advance(int *step)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1;
 }
 
 // Adam on FP32 masters; BF16 copies of the weight matrices refreshed.
-// bc: with step != nullptr, the bias corrections (bc1, bc2) of each step of
-// the call, read at index *step (the host computes them exactly as for the
-// arguments), else unused.
 __global__ void adam_update(float *w, const float *g, float *m, float *v, uint16_t *wb, long count,
-                            float lr, float beta1, float beta2, float eps, float bc1, float bc2,
-                            const float *bc, const int *step)
+                            float lr, float beta1, float beta2, float eps, float bc1, float bc2)
 {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    if (step) {
-        bc1 = bc[2 * *step];
-        bc2 = bc[2 * *step + 1];
-    }
     const float gi = g[i];
     const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
     const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
@@ -750,24 +733,17 @@ hipError_t sg_layer1_backward(hipStream_t s, const float *dh1, const float *pre1
     return hipGetLastError();
 }
 
-hipError_t sg_loss_sum(hipStream_t s, const float *loss_row, int n, float *out, const int *step)
+hipError_t sg_loss_sum(hipStream_t s, const float *loss_row, int n, float *out)
 {
-    hipLaunchKernelGGL(loss_sum, dim3(1), dim3(256), 0, s, loss_row, n, out, step);
-    return hipGetLastError();
-}
-
-hipError_t sg_step_advance(hipStream_t s, int *step)
-{
-    hipLaunchKernelGGL(step_advance, dim3(1), dim3(64), 0, s, step);
+    hipLaunchKernelGGL(loss_sum, dim3(1), dim3(256), 0, s, loss_row, n, out);
     return hipGetLastError();
 }
 
 hipError_t sg_adam(hipStream_t s, float *w, const float *g, float *m, float *v, uint16_t *wb, long count,
-                   float lr, float beta1, float beta2, float eps, float bc1, float bc2, const float *bc,
-                   const int *step)
+                   float lr, float beta1, float beta2, float eps, float bc1, float bc2)
 {
     hipLaunchKernelGGL(adam_update, dim3(blocks_for(count, 256)), dim3(256), 0, s, w, g, m, v, wb, count, lr,
-                       beta1, beta2, eps, bc1, bc2, bc, step);
+                       beta1, beta2, eps, bc1, bc2);
     return hipGetLastError();
 }
 

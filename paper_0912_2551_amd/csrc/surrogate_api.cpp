@@ -30,11 +30,9 @@ hipError_t sg_layer3_backward(hipStream_t s, const uint16_t *h2b, const float *p
                               uint16_t *d2b);
 hipError_t sg_layer1_backward(hipStream_t s, const float *dh1, const float *pre1, const uint16_t *xb, int n,
                               float *dW1, float *db1);
-hipError_t sg_loss_sum(hipStream_t s, const float *loss_row, int n, float *out, const int *step);
-hipError_t sg_step_advance(hipStream_t s, int *step);
+hipError_t sg_loss_sum(hipStream_t s, const float *loss_row, int n, float *out);
 hipError_t sg_adam(hipStream_t s, float *w, const float *g, float *m, float *v, uint16_t *wb, long count,
-                   float lr, float beta1, float beta2, float eps, float bc1, float bc2, const float *bc,
-                   const int *step);
+                   float lr, float beta1, float beta2, float eps, float bc1, float bc2);
 hipError_t sg_round(hipStream_t s, const float *w, uint16_t *wb, long count);
 hipError_t sg_expand_neighbours(hipStream_t s, const float *x, long n, float delta, float *x6);
 hipError_t sg_confirm(hipStream_t s, const float *p, const unsigned long long *succ, const unsigned long long *trials,
@@ -58,7 +56,6 @@ constexpr long OFF_W1 = 0, OFF_B1 = OFF_W1 + H * 3, OFF_W2 = OFF_B1 + H, OFF_B2 
 struct smc_surrogate {
     smc_ctx *ctx = nullptr;
     hipStream_t stream = nullptr;
-    hipStream_t capture = nullptr;   // a stream of its own to capture training steps on
     float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;   // [N_PARAMS] each
     uint16_t *wb = nullptr;                                          // BF16 copies [N_PARAMS]
     float *norm = nullptr;                                           // mu[3], sigma[3]
@@ -171,10 +168,10 @@ int upload_batch(smc_surrogate *s, const float *x, const float *y, const float *
     return SMC_OK;
 }
 
-// Forward and backward over the uploaded batch, on stream st; gradients in
-// s->g.
-int forward_backward(smc_surrogate *s, hipStream_t st, int n, float inv_wsum)
+// Forward and backward over the uploaded batch; gradients in s->g.
+int forward_backward(smc_surrogate *s, int n, float inv_wsum)
 {
+    hipStream_t st = s->stream;
     const float *mu = s->norm, *sigma = s->norm + 3;
     float *w = s->w, *g = s->g;
     uint16_t *wb = s->wb;
@@ -190,70 +187,6 @@ int forward_backward(smc_surrogate *s, hipStream_t st, int n, float inv_wsum)
     // dh1[b][i] = sum_j d2b[b][j] W2b[j][i]
     SG_TRY(s, sg_gemm(st, s->d2b, H, 1, wb + OFF_W2, H, 1, s->dh1, H, n, H, H, 0));
     SG_TRY(s, sg_layer1_backward(st, s->dh1, s->pre1, s->xb, n, g + OFF_W1, g + OFF_B1));
-    return SMC_OK;
-}
-
-// Training steps as one HIP graph, replayed: a step is ten small launches
-// (about 45 us at n = 512 when launched one by one, most of it launch
-// overhead).  The step-dependent values (the bias corrections, the slot of
-// the loss history) are read through a step counter in device memory, which
-// the graph's last kernel advances, so one capture serves every step.  The
-// graph holds kernels only.  *used = false (and nothing run) where capture is
-// not available; the caller then launches the steps one by one.
-constexpr uint32_t kGraphMinSteps = 8;
-
-int train_graphed(smc_surrogate *s, int np, float inv, const smc_train_opts *opts, float b1, float b2, float eps,
-                  const std::vector<float> &bc, float *hist, bool *used)
-{
-    *used = false;
-    if (!s->capture && hipStreamCreateWithFlags(&s->capture, hipStreamNonBlocking) != hipSuccess) {
-        s->capture = nullptr;
-        return SMC_OK;
-    }
-    float *d_bc = nullptr;
-    int *d_step = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    struct Free {
-        float *&bc;
-        int *&step;
-        hipGraph_t &g;
-        hipGraphExec_t &e;
-        ~Free()
-        {
-            if (e) (void)hipGraphExecDestroy(e);
-            if (g) (void)hipGraphDestroy(g);
-            if (bc) (void)hipFree(bc);
-            if (step) (void)hipFree(step);
-        }
-    } release{d_bc, d_step, graph, exec};
-    SG_TRY(s, hipMalloc((void **)&d_bc, bc.size() * sizeof(float)));
-    SG_TRY(s, hipMalloc((void **)&d_step, sizeof(int)));
-    const int zero = 0;
-    SG_TRY(s, hipMemcpyAsync(d_bc, bc.data(), bc.size() * sizeof(float), hipMemcpyHostToDevice, s->stream));
-    SG_TRY(s, hipMemcpyAsync(d_step, &zero, sizeof(int), hipMemcpyHostToDevice, s->stream));
-    hipStream_t cs = s->capture;
-    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return SMC_OK;
-    int rc = forward_backward(s, cs, np, inv);
-    hipError_t e = hipSuccess;
-    if (rc == SMC_OK && hist) e = sg_loss_sum(cs, s->loss_row, np, hist, d_step);
-    if (rc == SMC_OK && e == hipSuccess)
-        e = sg_adam(cs, s->w, s->g, s->m, s->v, s->wb, N_PARAMS, opts->lr, b1, b2, eps, 1.0f, 1.0f, d_bc, d_step);
-    if (rc == SMC_OK && e == hipSuccess) e = sg_step_advance(cs, d_step);
-    const hipError_t ec = hipStreamEndCapture(cs, &graph);
-    if (rc != SMC_OK || e != hipSuccess || ec != hipSuccess || !graph) {
-        (void)hipGetLastError();
-        return SMC_OK;
-    }
-    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-        exec = nullptr;
-        (void)hipGetLastError();
-        return SMC_OK;
-    }
-    for (uint32_t it = 0; it < opts->steps; ++it) SG_TRY(s, hipGraphLaunch(exec, s->stream));
-    // the buffers above are freed on return: wait for the replays first
-    SG_TRY(s, hipStreamSynchronize(s->stream));
-    *used = true;
     return SMC_OK;
 }
 
@@ -349,7 +282,7 @@ int smc_surrogate_gradients(smc_surrogate *s, const float *x, const float *y, co
     int np = 0;
     float inv = 0.0f;
     int rc = upload_batch(s, x, y, w, n, &np, &inv);
-    if (rc == SMC_OK) rc = forward_backward(s, s->stream, np, inv);
+    if (rc == SMC_OK) rc = forward_backward(s, np, inv);
     if (rc == SMC_OK && loss) rc = sum_loss(s, np, loss);
     if (rc != SMC_OK) return rc;
     if (grads) {
@@ -398,28 +331,15 @@ int smc_surrogate_train(smc_surrogate *s, const float *x, const float *y, const 
         float *p;
         ~Free() { if (p) (void)hipFree(p); }
     } free_hist{hist};
-    // The bias corrections of each step, computed on the host.
-    std::vector<float> bc(2 * (size_t)opts->steps);
     for (uint32_t it = 0; it < opts->steps; ++it) {
-        const long k = s->step + 1 + (long)it;
-        bc[2 * it] = 1.0f - std::pow(b1, (float)k);
-        bc[2 * it + 1] = 1.0f - std::pow(b2, (float)k);
-    }
-    bool graphed = false;
-    if (opts->steps >= kGraphMinSteps) {
-        rc = train_graphed(s, np, inv, opts, b1, b2, eps, bc, hist, &graphed);
+        rc = forward_backward(s, np, inv);
         if (rc != SMC_OK) return rc;
+        if (hist) SG_TRY(s, sg_loss_sum(s->stream, s->loss_row, np, hist + it));
+        s->step += 1;
+        const float bc1 = 1.0f - std::pow(b1, (float)s->step);
+        const float bc2 = 1.0f - std::pow(b2, (float)s->step);
+        SG_TRY(s, sg_adam(s->stream, s->w, s->g, s->m, s->v, s->wb, N_PARAMS, opts->lr, b1, b2, eps, bc1, bc2));
     }
-    if (!graphed) {
-        for (uint32_t it = 0; it < opts->steps; ++it) {
-            rc = forward_backward(s, s->stream, np, inv);
-            if (rc != SMC_OK) return rc;
-            if (hist) SG_TRY(s, sg_loss_sum(s->stream, s->loss_row, np, hist + it, nullptr));
-            SG_TRY(s, sg_adam(s->stream, s->w, s->g, s->m, s->v, s->wb, N_PARAMS, opts->lr, b1, b2, eps,
-                              bc[2 * it], bc[2 * it + 1], nullptr, nullptr));
-        }
-    }
-    s->step += (long)opts->steps;
     if (hist)
         SG_TRY(s, hipMemcpyAsync(loss_out, hist, (size_t)opts->steps * sizeof(float), hipMemcpyDeviceToHost,
                                  s->stream));
@@ -613,7 +533,6 @@ void smc_surrogate_destroy(smc_surrogate *s)
     for (uint16_t *p : {s->wb, s->xb, s->h1b, s->h2b, s->d2b})
         if (p) (void)hipFree(p);
     if (s->quse) (void)hipFree(s->quse);
-    if (s->capture) (void)hipStreamDestroy(s->capture);
     delete s;
 }
 

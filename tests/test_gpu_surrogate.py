@@ -213,31 +213,6 @@ def test_query_matches_oracle_forward(ctx):
         assert not use.any()            # no training hull yet: never confident
 
 
-def test_training_graph_matches_eager(ctx):
-    """A training call of 8 or more steps replays one captured HIP graph of a
-    step; calls of one step launch its kernels one by one.  Twelve replayed
-    steps give the same per-step losses (every replay checked) and weights,
-    bit for bit, as twelve one-step calls; twice, with the program's own
-    eager work (a gradient evaluation, with its synchronisation) between."""
-    from paper_0912_2551_amd import binding as B
-    rng = np.random.default_rng(17)
-    x, _, _ = _sample(rng, 256)
-    c = x - np.log10(np.asarray(W.MM_RATES))
-    y = (1.0 / (1.0 + np.exp(-(3.0 * c[:, 2] - 1.5 * c[:, 0])))).astype(np.float32)
-    wt = np.full(len(x), 1000.0, np.float32)
-    graphed, eager = B.Surrogate(ctx, seed=11), B.Surrogate(ctx, seed=11)
-    la, lb = [], []
-    for rep in range(2):
-        print(f"graph replays, call {rep}", flush=True)
-        la.append(graphed.train(x, y, wt, steps=12, lr=2e-3))
-        lb.append(np.concatenate([eager.train(x, y, wt, steps=1, lr=2e-3) for _ in range(12)]))
-        assert np.array_equal(la[-1], lb[-1]), (rep, la[-1], lb[-1])
-        ga, gb = graphed.gradients(x[:64], y[:64], wt[:64]), eager.gradients(x[:64], y[:64], wt[:64])
-        assert ga[0] == gb[0] and np.array_equal(ga[1], gb[1])
-    assert np.array_equal(graphed.get_params(), eager.get_params())
-    assert la[1][-1] < la[0][0]
-
-
 def test_training_fits_and_gate(ctx):
     from paper_0912_2551_amd import binding as B
     rng = np.random.default_rng(9)
