@@ -309,27 +309,43 @@ def trace_program_run(ctx, B, W, n=100_000, cap=5_000):
     return out
 
 
-def tree_sums_run(ctx, B, W, n=100_000, lanes=8):
+def tree_sums_run(ctx, B, W, n=100_000, lanes=8, n_few=1024, lanes_few=16):
     """The random-network workload (S = 64, M = 256, 10^5 trajectories) under
     the SSA variants for wide networks: lane groups with sums in channel order
     (bit-identical to one lane) and with tree-ordered sums (SMC_TREE_SUMS),
-    beside the one-lane specialised kernel."""
+    beside the one-lane specialised kernel.  Then a latency-bound case: the
+    widest network of the batched sweep (S = 128, M = 512) with n_few
+    trajectories, far fewer than the device's lanes, where the wall time is
+    that of a trajectory's chain of events."""
     import torch
+
+    def runs(nh, fh, count, group, cap):
+        res = {}
+        for key, kw in (("one_lane_specialised", {}), ("group_channel_order", {"lanes": group}),
+                        ("group_tree_sums", {"lanes": group, "tree_sums": True})):
+            p = B.params(fixed_n=count, seed=1, max_events=cap, **kw)
+            ctx.estimate(nh, fh, B.params(fixed_n=256, seed=2, max_events=cap, **kw))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = ctx.estimate(nh, fh, p)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            res[key] = {"kernel": ctx.last_kernel(), "seconds": wall, "events": r["events"],
+                        "events_per_s": r["events"] / wall, "p_hat": r["p_hat"], "successes": r["successes"]}
+        return res
+
     net = W.c3_network()
     nh = ctx.network(net)
     fh = ctx.formula(nh, W.c3_formula(net))
     out = {"workload": f"random network S=64 M=256, {n} trajectories, {lanes} lanes per trajectory"}
-    for key, kw in (("one_lane_specialised", {}), ("group_channel_order", {"lanes": lanes}),
-                    ("group_tree_sums", {"lanes": lanes, "tree_sums": True})):
-        p = B.params(fixed_n=n, seed=1, max_events=W.C3_CAP, **kw)
-        ctx.estimate(nh, fh, B.params(fixed_n=256, seed=2, max_events=W.C3_CAP, **kw))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = ctx.estimate(nh, fh, p)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        out[key] = {"kernel": ctx.last_kernel(), "seconds": wall, "events": r["events"],
-                    "events_per_s": r["events"] / wall, "p_hat": r["p_hat"], "successes": r["successes"]}
+    out.update(runs(nh, fh, n, lanes, W.C3_CAP))
+    wide, text = max(W.c4_networks(), key=lambda nt: len(nt[0].rate))
+    nw = ctx.network(wide)
+    fw = ctx.formula(nw, text)
+    few = {"workload": f"the sweep's widest random network (S={len(wide.x0)} M={len(wide.rate)}), {n_few} "
+                       f"trajectories, {lanes_few} lanes per trajectory"}
+    few.update(runs(nw, fw, n_few, lanes_few, W.C3_CAP))
+    out["latency_bound"] = few
     return out
 
 
