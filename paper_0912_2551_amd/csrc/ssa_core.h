@@ -726,8 +726,9 @@ __device__ __forceinline__ void mon_init(MonState &ms)
 // point is decided when the formula's value at position 0 is known there, or
 // by the t_max rule (the latest known time lies past t_max) or the event
 // cap (m = max_events).  Decided stays decided as the prefix grows, so the
-// lane tests points only at checkpoints (16 and 32 states, every 64th
-// iteration of its wave for all lanes together, the cap, absorption, t_max)
+// lane tests points only at checkpoints (16 and 32 states, every 64th, 128th
+// or 256th iteration of its wave, as the positions a test recomputes grow,
+// for all lanes due together, the cap, absorption, t_max)
 // and then finds the first decided point by bisection: the trajectory's
 // result is the one it would have at that point.
 //
@@ -962,8 +963,8 @@ __device__ __noinline__ uint32_t trace_value(cptr<MonProg> mp, TraceRec R, int l
 // Then the jump entries of each until that become final are bounded by the
 // new k0 (see trace_value), its final neutral run is extended over them or
 // restarted after the last of them that is not neutral, and the counts are
-// committed.
-__device__ __noinline__ void trace_commit(cptr<MonProg> mp, TraceRec R, int len)
+// committed.  Returns the number of positions left open (over all nodes).
+__device__ __noinline__ uint32_t trace_commit(cptr<MonProg> mp, TraceRec R, int len)
 {
     const int nn = mp->tr_n;
     for (int q = 0; q < nn; ++q) {
@@ -1013,7 +1014,13 @@ __device__ __noinline__ void trace_commit(cptr<MonProg> mp, TraceRec R, int len)
         }
         R.RS(q) = rs;
     }
-    for (int q = 0; q < nn; ++q) R.F(q) = R.F2(q);
+    // the positions left open, which the next test recomputes at least
+    uint32_t open = 0;
+    for (int q = 0; q < nn; ++q) {
+        open += (uint32_t)(R.N(q) - R.F2(q));
+        R.F(q) = R.F2(q);
+    }
+    return open;
 }
 
 // Is point p decided?  Then its verdict and reason.
@@ -2052,6 +2059,7 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
     mon_init(ms);
     Draw dr{0.0, 0.0};   // random numbers of the lane's next event (index k)
     uint32_t tr_lo = 0;  // trace programs: every point below this one is undecided
+    uint32_t tr_every = 64;  // ... and the lane's interval between tests, in wave iterations
     int spins = 0;
     // scans that take any job: the jobs nearer than this (in this wave's scan
     // order) had no issuable indices left.  Such scans run only once no
@@ -2163,6 +2171,7 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
                 k = 0;
                 mon_init(ms);
                 tr_lo = 0;
+                tr_every = 64;
                 active = true;
                 entered = true;
             }
@@ -2212,9 +2221,13 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
                         R.RS(q) = 0;
                     }
                 // checkpoints: the cap; 16 and 32 states (short trajectories);
-                // and every 64th iteration of the wave for all its lanes at
-                // once, so that one evaluation pass serves the whole wave
-                const bool sync = (it & 63u) == 63u;
+                // and wave iterations at multiples of the lane's interval (64,
+                // 128 or 256), so that the lanes due together share one
+                // evaluation pass.  The interval follows the cost of a test:
+                // the positions the last open test left to recompute (few
+                // for short windows) against the events run past a decision
+                // before it is seen.
+                const bool sync = (it & (tr_every - 1u)) == tr_every - 1u;
                 const bool cp = (V.max_events != 0u && k == V.max_events) || k == 15u || k == 31u || sync;
                 if (cp) {
                     if (trace_decided(V.mon, R, 2u * k, V.t_max, V.max_events, &tvd, &trs)) {
@@ -2222,7 +2235,8 @@ __device__ __forceinline__ void persistent_body(KArgs A, int32_t *lds)
                         tfin = true;
                     } else {
                         tr_lo = 2u * k + 1u;
-                        trace_commit(V.mon, R, (int)k + 1);
+                        const uint32_t open = trace_commit(V.mon, R, (int)k + 1);
+                        tr_every = open < 128u ? 64u : (open < 256u ? 128u : 256u);
                     }
                 }
             }
