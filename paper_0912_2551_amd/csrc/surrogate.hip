@@ -502,6 +502,19 @@ __global__ __launch_bounds__(64 * kQueryWaves) void mlp_query_waves(
             a[6] = (__bf16)0.0f;
             a[7] = (__bf16)0.0f;
             W1s[tid] = __builtin_bit_cast(uint4, a);
+            // b2 the same way, in the padding of column tid's W2 row (k' = 256 ..
+            // 263), for one more layer-2 step against the constant input 1
+            const float c = b2[tid];
+            const __bf16 chi = (__bf16)c;
+            const float c1 = c - (float)chi;
+            const __bf16 clo = (__bf16)c1;
+            const __bf16 clo2 = (__bf16)(c1 - (float)clo);
+            bf16x8 bb;
+            bb[0] = chi;
+            bb[1] = clo;
+            bb[2] = clo2;
+            for (int e = 3; e < 8; ++e) bb[e] = (__bf16)0.0f;
+            *reinterpret_cast<uint4 *>(W2s + tid * kQRow + kH) = __builtin_bit_cast(uint4, bb);
         }
         // facets with the tolerance added to their offsets once
         for (int f = tid; f < n_lds_planes; f += 64 * kQueryWaves)
@@ -547,8 +560,8 @@ __global__ __launch_bounds__(64 * kQueryWaves) void mlp_query_waves(
         xin[7] = (__bf16)0.0f;
         floatx16 acc[8];
         // units 32 bk .. 32 bk + 31 for the tile's 32 points, and the two
-        // layer-2 steps they feed (the first step starts the accumulators)
-        auto block = [&](int bk, bool first) {
+        // layer-2 steps they feed
+        auto block = [&](int bk) {
             const uint4 wr = W1s[32 * bk + rc];
             const bf16x8 w = __builtin_bit_cast(bf16x8, half ? make_uint4(0u, 0u, 0u, 0u) : wr);
             const floatx16 h1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, xin, floatx16{}, 0, 0, 0);
@@ -568,33 +581,45 @@ __global__ __launch_bounds__(64 * kQueryWaves) void mlp_query_waves(
                 for (int g = 0; g < 8; ++g) {
                     const bf16x8 b =
                         __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(bcol + g * 32 * kQRow));
-                    acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, first && t == 0 ? floatx16{} : acc[g],
-                                                                     0, 0, 0);
+                    acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[g], 0, 0, 0);
                 }
             }
         };
-        block(0, true);
+        {
+            // the accumulators start with the layer-2 bias: inputs (1, 1, 1)
+            // against each column's three parts (half 1 holds zeros, so what
+            // its B operand reads past the padding does not count)
+            bf16x8 one;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) one[e] = (__bf16)(half == 0 && e < 3 ? 1.0f : 0.0f);
+            const uint16_t *bpad = W2s + rc * kQRow + kH + 8 * half;
+#pragma unroll
+            for (int g = 0; g < 8; ++g) {
+                const bf16x8 b = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(bpad + g * 32 * kQRow));
+                acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(one, b, floatx16{}, 0, 0, 0);
+            }
+        }
 #pragma unroll 1
-        for (int bk = 1; bk < 8; ++bk) block(bk, false);
-        // layer 3: rows 8 (r / 4) + 4 half + r % 4 of column 32 g + rc, two
-        // column groups at a time: the two rounded activations and their
-        // weights as bfloat16 pairs, one v_dot2_f32_bf16 (exact products,
-        // FP32 sum) per row
+        for (int bk = 0; bk < 8; ++bk) block(bk);
+        // layer 3: rows 8 (r / 4) + 4 half + r % 4 of column 32 g + rc (bias
+        // included), two column groups at a time: the two rounded activations
+        // and their weights as bfloat16 pairs, one v_dot2_f32_bf16 (exact
+        // products, FP32 sum) per row
         float zr[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) zr[r] = 0.0f;
 #pragma unroll
         for (int g = 0; g < 8; g += 2) {
-            const float b0 = b2[g * 32 + rc], b1v = b2[(g + 1) * 32 + rc];
             bf16x2 w;
             w[0] = __builtin_bit_cast(__bf16, W3b[g * 32 + rc]);
             w[1] = __builtin_bit_cast(__bf16, W3b[(g + 1) * 32 + rc]);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const float v0 = acc[g][r] + b0, v1 = acc[g + 1][r] + b1v;
+                // ReLU as an integer max of the bit pattern, as in layer 1
+                const int v0 = __float_as_int(acc[g][r]), v1 = __float_as_int(acc[g + 1][r]);
                 bf16x2 h;
-                h[0] = (__bf16)(v0 > 0.0f ? v0 : 0.0f);
-                h[1] = (__bf16)(v1 > 0.0f ? v1 : 0.0f);
+                h[0] = (__bf16)__int_as_float(v0 > 0 ? v0 : 0);
+                h[1] = (__bf16)__int_as_float(v1 > 0 ? v1 : 0);
                 zr[r] = __builtin_amdgcn_fdot2_f32_bf16(h, w, zr[r], false);
             }
         }
