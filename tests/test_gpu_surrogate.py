@@ -201,9 +201,10 @@ def test_query_matches_oracle_forward(ctx):
     params = mlp.init_params(12, mu=tuple(np.log10(W.MM_RATES)), sigma=(0.57, 0.57, 0.57))
     s = B.Surrogate(ctx)
     s.set_params(params.astype(np.float32))
-    # 5000 points take the per-tile kernel; 50000 the persistent one that
-    # stages W2 in LDS (where the device has the LDS for it)
-    for count in (5000, 50000):
+    # 5000 points take the per-tile kernel; from 32768 on the persistent one
+    # that stages W2 in LDS (where the device has the LDS for it): exactly
+    # 1024 full tiles, one point more (a tile of one), and a ragged 50000
+    for count in (5000, 32768, 32769, 50000):
         x = W.surrogate_queries(count, seed=5)
         p, use = s.query(x)
         ref = mlp.forward(params, x.astype(np.float64))["p"]
