@@ -901,6 +901,39 @@ def test_trace_program_parity(ctx, name, make, text, kw):
         assert np.array_equal(ev, oev), (name, np.nonzero(ev != oev)[0][:5])
 
 
+def test_random_formulas_parity(ctx):
+    """Seeded random nested formulas over X with bounded windows (every
+    operator; tests/formula_gen.py), whatever the library compiles them to (a
+    compact monitor or a trace program), per trajectory against the oracle:
+    24 formulas, 600 trajectories each."""
+    import random
+    from formula_gen import random_formula
+    B = _B()
+    net = W.immigration_death()
+    n = ctx.network(net)
+    r = random.Random(31)
+    kernels, done, tried = set(), 0, 0
+    while done < 24:
+        text = random_formula(r)
+        tried += 1
+        assert tried < 200
+        try:
+            f = ctx.formula(n, text)
+        except B.SmcError as e:   # beyond the trace programs' node or predicate limits
+            assert e.code == B.SMC_E_UNSUPPORTED, (text, e.code)
+            continue
+        print(f"case random formula {done}: {text}", flush=True)
+        kw = {"max_events": 5000}
+        ev, vd, rs = ctx.trajectories(n, f, B.params(seed=3, model_id=done, **kw), 0, 600)
+        kernels.add(ctx.last_kernel())
+        oev, ovd, ors = oracle.trajectories(net, oracle.parse(text, net), 0, 600, seed=3, model_id=done, **kw)
+        assert np.array_equal(rs, ors), (text, np.nonzero(rs != ors)[0][:5])
+        assert np.array_equal(vd, ovd), (text, np.nonzero(vd != ovd)[0][:5])
+        assert np.array_equal(ev, oev), (text, np.nonzero(ev != oev)[0][:5])
+        done += 1
+    assert B.KERNEL_GENERIC_TRACE in kernels and len(kernels) > 1, kernels
+
+
 def test_trace_programs_in_a_batch(ctx):
     """Trace programs and compact monitors in one iterative launch: every
     job's estimate equals the oracle's."""

@@ -34,6 +34,8 @@ import oracle
 from oracle import bltlc
 from paper_0912_2551_amd import workloads as W
 
+from formula_gen import random_formula
+
 U = 2   # the oracle's "unknown"
 
 
@@ -149,36 +151,13 @@ def test_final_positions_keep_their_values(make, text, steps):
         assert not bad, (text, idx, bad[:3])
 
 
-def _random_formula(r, depth=0):
-    """Random nested BLTLc text over X with bounded windows (every operator)."""
-    k = r.random()
-    if depth >= 3 or k < 0.25:
-        return f"X {r.choice(['<=', '>='])} {r.randint(40, 130)}"
-    sub = lambda: _random_formula(r, depth + 1)   # noqa: E731
-    lo = round(r.uniform(0.0, 2.0), 2)
-    hi = round(lo + r.uniform(0.1, 4.0), 2)
-    if k < 0.35:
-        return f"!({sub()})"
-    if k < 0.45:
-        return f"({sub()}) & ({sub()})"
-    if k < 0.55:
-        return f"({sub()}) | ({sub()})"
-    if k < 0.65:
-        return f"X[0,{round(r.uniform(0.05, 0.5), 2)}]({sub()})"
-    if k < 0.75:
-        return f"F[{lo},{hi}]({sub()})"
-    if k < 0.85:
-        return f"G[{lo},{hi}]({sub()})"
-    return f"({sub()}) U[{lo},{hi}] ({sub()})"
-
-
 def test_random_formulas_final_positions():
     """The rule on 40 random nested formulas (each on its own trajectory)."""
     import random
     r = random.Random(12)
     rng = np.random.default_rng(5)
     for q in range(40):
-        text = _random_formula(r)
+        text = random_formula(r)
         net, states, times, absorbed = _trace(W.immigration_death, 700, q)
         f = oracle.parse(text, net)
         bad = violations(f, states, times, absorbed, (2, 16, 64, 200, 500), per_node=20, rng=rng)
