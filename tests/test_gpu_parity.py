@@ -934,6 +934,44 @@ def test_random_formulas_parity(ctx):
     assert B.KERNEL_GENERIC_TRACE in kernels and len(kernels) > 1, kernels
 
 
+def test_random_networks_and_formulas_parity(ctx):
+    """Seeded random networks (2 to 12 species, S to 4 S reactions: uni- and
+    bimolecular, homodimers, 0 to 2 products) under seeded random formulas over
+    their species, per trajectory against the oracle on the default kernel
+    (specialised where supported), the generic kernel and 4-lane groups."""
+    import random
+    from formula_gen import random_formula
+    B = _B()
+    r = random.Random(77)
+    kw = {"max_events": 3000}
+    for q in range(8):
+        S = r.randint(2, 12)
+        net = W.random_network(S, r.randint(S, 4 * S), seed=900 + q)
+        nh = ctx.network(net)
+        for rep in range(2):
+            text = random_formula(r, names=net.names, lo=-40, hi=40,
+                                  around={nm: int(v) for nm, v in zip(net.names, net.x0)})
+            try:
+                fh = ctx.formula(nh, text)
+            except B.SmcError as e:   # beyond the trace programs' limits
+                assert e.code == B.SMC_E_UNSUPPORTED, (text, e.code)
+                continue
+            mid = 10 * q + rep
+            oev, ovd, ors = oracle.trajectories(net, oracle.parse(text, net), 0, 128, seed=4, model_id=mid, **kw)
+            for mode in ("default", "generic", "lanes4"):
+                print(f"case random network {net.label} formula {text} mode {mode}", flush=True)
+                if mode == "generic":
+                    ctx.set_specialization(B.SPECIALIZE_OFF)
+                try:
+                    p = B.params(seed=4, model_id=mid, lanes=4 if mode == "lanes4" else 0, **kw)
+                    ev, vd, rs = ctx.trajectories(nh, fh, p, 0, 128)
+                finally:
+                    ctx.set_specialization(B.SPECIALIZE_AUTO)
+                assert np.array_equal(rs, ors), (net.label, text, mode, np.nonzero(rs != ors)[0][:5])
+                assert np.array_equal(vd, ovd), (net.label, text, mode, np.nonzero(vd != ovd)[0][:5])
+                assert np.array_equal(ev, oev), (net.label, text, mode, np.nonzero(ev != oev)[0][:5])
+
+
 def test_trace_programs_in_a_batch(ctx):
     """Trace programs and compact monitors in one iterative launch: every
     job's estimate equals the oracle's."""
