@@ -337,6 +337,39 @@ def test_many_more_fixed_jobs_than_waves(ctx, kind):
         assert (r["successes"], r["events"]) == (o["successes"], o["events"]), k
 
 
+def test_many_fixed_jobs_beside_iterative_ones(ctx):
+    """Four iterative Wilson jobs and 5000 fixed-size jobs of 64 trajectories
+    in one launch on 256 waves: while an iterative job is open, waves only
+    take jobs near their homes; once none is, they take any job with indices
+    left, each resuming its scan past the jobs it found exhausted.  Every
+    fixed job runs in full, and the iterative estimates and sampled fixed
+    jobs give the oracle's results."""
+    B = _B()
+    net = W.isomerization()
+    text = "G[0,1](A>=22)"
+    nh = ctx.network(net)
+    fh = ctx.formula(nh, text)
+    jobs = [(nh, fh, B.params(seed=8, model_id=k, half_width=0.05)) for k in range(4)]
+    jobs += [(nh, fh, B.params(fixed_n=64, seed=8, model_id=4 + k)) for k in range(5000)]
+    ctx.set_waves_per_cu(1)
+    try:
+        print("case iterative and many fixed jobs", flush=True)
+        res = ctx.estimate_batch(jobs)
+    finally:
+        ctx.set_waves_per_cu(0)
+    assert all(r["n"] == 64 for r in res[4:])
+    for k in range(4):
+        o = oracle.estimate(net, text, eps=0.05, seed=8, model_id=k)
+        r = res[k]
+        assert (r["n"], r["successes"], r["events"], r["batches"]) == \
+            (o["n"], o["successes"], o["events"], len(o["bounds"])), (k, r, o)
+    rng = np.random.default_rng(4)
+    for k in rng.choice(5000, size=20, replace=False):
+        o = oracle.estimate(net, text, fixed_n=64, seed=8, model_id=4 + int(k))
+        r = res[4 + int(k)]
+        assert (r["successes"], r["events"]) == (o["successes"], o["events"]), k
+
+
 @SPECULATE
 def test_fig3_bernoulli_sources(ctx, speculate):
     """Fig. 3's setting (99%, +-0.025) on Bernoulli sources of known p: the
